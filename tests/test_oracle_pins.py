@@ -1,0 +1,278 @@
+"""Pins for the CPU oracle: checks against what the paper and mathematics fix.
+
+Every check here is independent of the oracle's own code path:
+  * the worked example printed in Fig. 1 (Section 2);
+  * brute force over explicit symbol tuples (exhaustive on tiny inputs);
+  * the suffix array of the concatenation S_0 S_1 ... with distinct integer
+    sentinels, built by prefix doubling (a textbook suffix-sorting method);
+  * closed forms: one read = the classic rotation-sort BWT; n identical
+    reads; homopolymers;
+  * invariants: symbol counts, the bare-terminator rows, the LF-walk inverse.
+Mutation tests plant plausible mistakes in a copy of the oracle source and
+require that some pin fails.
+"""
+import itertools
+import os
+import re
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+from conftest import ROOT, load_golden
+from oracle import invariants, oracle
+from paper_1401_7457_amd import datagen
+
+
+def _col(reads):
+    c = datagen.from_reads(reads)
+    return c.text, c.offsets
+
+
+# ---- Fig. 1 -----------------------------------------------------------------
+
+def test_fig1_worked_example():
+    g = load_golden("fig1.txt")
+    text, off = _col(g["reads"])
+    bwt, tp = oracle.bwt(text, off)
+    assert bwt.tobytes().decode() == g["bwt"][0]
+    assert tp.tolist() == [int(x) for x in g["term_pos"]]
+    pairs = oracle.sorted_suffixes(text, off)
+    shown = [g["reads"][i][k:] + "$" for i, k in pairs.tolist()]
+    assert shown == g["suffixes"]
+
+
+def test_fig1_bruteforce_agrees():
+    g = load_golden("fig1.txt")
+    b, tp = oracle.bwt_bruteforce(g["reads"])
+    assert b == g["bwt"][0]
+    assert tp == [int(x) for x in g["term_pos"]]
+
+
+# ---- brute force --------------------------------------------------------------
+
+def _all_strings(alpha, maxlen):
+    for L in range(maxlen + 1):
+        for t in itertools.product(alpha, repeat=L):
+            yield "".join(t)
+
+
+def test_exhaustive_tiny_over_AC():
+    small = list(_all_strings("AC", 4))   # 31 strings
+    tiny = list(_all_strings("AC", 2))    # 7 strings
+    cases = [[a] for a in small] + [[a, b] for a in small for b in small]
+    cases += [[a, b, c] for a in tiny for b in tiny for c in tiny]
+    for reads in cases:
+        text, off = _col(reads)
+        bwt, tp = oracle.bwt(text, off, threads=1)
+        eb, etp = oracle.bwt_bruteforce(reads)
+        assert bwt.tobytes().decode() == eb, reads
+        assert tp.tolist() == etp, reads
+
+
+@pytest.mark.parametrize("alpha", ["A", "AC", "ACGT"])
+def test_random_tiny_vs_bruteforce(alpha):
+    rng = np.random.default_rng(7 + len(alpha))
+    for _ in range(300):
+        n = int(rng.integers(1, 7))
+        reads = ["".join(rng.choice(list(alpha), size=int(rng.integers(0, 12)))) for _ in range(n)]
+        text, off = _col(reads)
+        for threads in (1, 3):
+            bwt, tp = oracle.bwt(text, off, threads=threads)
+            eb, etp = oracle.bwt_bruteforce(reads)
+            assert bwt.tobytes().decode() == eb, reads
+            assert tp.tolist() == etp, reads
+
+
+# ---- suffix array of the concatenation, by prefix doubling ------------------
+
+def _sa_prefix_doubling(s: np.ndarray) -> np.ndarray:
+    """Suffix array of an integer string by prefix doubling (Manber & Myers)."""
+    n = s.size
+    rank = s.astype(np.int64)
+    sa = np.arange(n)
+    h = 1
+    while True:
+        second = np.full(n, -1, dtype=np.int64)
+        second[: n - h] = rank[h:] if h < n else second[:0]
+        sa = np.lexsort((second, rank))
+        key = np.stack([rank[sa], second[sa]], axis=1)
+        diff = np.any(key[1:] != key[:-1], axis=1)
+        new = np.empty(n, dtype=np.int64)
+        new[sa] = np.concatenate([[0], np.cumsum(diff)])
+        rank = new
+        if rank.max() == n - 1:
+            return sa
+        h *= 2
+
+
+def _bwt_via_concatenation(reads):
+    """BWT from the suffix array of S_0 $_0 S_1 $_1 ... over integers.
+
+    $_i -> i (so terminators are distinct, ordered by read index and below
+    every base), bases -> n + rank(A<C<G<T).  A comparison of two suffixes of
+    the concatenation is decided at or before the first terminator, which
+    makes its suffix order the multi-string order.
+    """
+    n = len(reads)
+    rank = {"A": 0, "C": 1, "G": 2, "T": 3}
+    sym, src = [], []
+    for i, r in enumerate(reads):
+        sym += [n + rank[c] for c in r] + [i]
+        src += list(r) + ["$"]
+    sa = _sa_prefix_doubling(np.array(sym, dtype=np.int64))
+    starts = set()
+    p = 0
+    for r in reads:
+        starts.add(p)
+        p += len(r) + 1
+    out = []
+    term = [0] * n
+    read_of_start = {}
+    p = 0
+    for i, r in enumerate(reads):
+        read_of_start[p] = i
+        p += len(r) + 1
+    for row, pos in enumerate(sa.tolist()):
+        if pos in starts:
+            out.append("$")
+            term[read_of_start[pos]] = row
+        else:
+            out.append(src[pos - 1])
+    return "".join(out), term
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_oracle_matches_concatenation_suffix_array(seed):
+    rng = np.random.default_rng(seed)
+    col = datagen.random_collection(rng, 300, [0, 1, 2, 5, 17, 28, 29, 30, 57, 100])
+    reads = col.reads()
+    # add exact duplicates and shared prefixes to exercise terminator ties
+    reads = reads + reads[:40] + [r[:10] for r in reads[40:80]]
+    text, off = _col(reads)
+    bwt, tp = oracle.bwt(text, off, threads=4)
+    eb, etp = _bwt_via_concatenation(reads)
+    assert bwt.tobytes().decode() == eb
+    assert tp.tolist() == etp
+
+
+# ---- closed forms -----------------------------------------------------------------
+
+def _rotation_bwt(r: str):
+    """Textbook BWT of a single string r$ by sorting its rotations ($ smallest)."""
+    s = r + "\0"  # NUL stands for $ and sorts below A/C/G/T
+    rots = sorted(range(len(s)), key=lambda k: s[k:] + s[:k])
+    last = "".join(s[k - 1] for k in rots).replace("\0", "$")
+    return last, rots.index(0)
+
+
+@pytest.mark.parametrize("r", ["ACGT", "GATTACA", "AAAAAC", "TTTTT", "ACACACAC", "CGTACGTTAGCA" * 3, ""])
+def test_single_read_is_rotation_bwt(r):
+    text, off = _col([r])
+    bwt, tp = oracle.bwt(text, off)
+    eb, row0 = _rotation_bwt(r)
+    assert bwt.tobytes().decode() == eb
+    assert tp.tolist() == [row0]
+
+
+@pytest.mark.parametrize("r,n", [("ACGT", 5), ("GATTACA", 3), ("CCCA", 7), ("", 4)])
+def test_identical_reads_closed_form(r, n):
+    single, row0 = _rotation_bwt(r)
+    text, off = _col([r] * n)
+    bwt, tp = oracle.bwt(text, off, threads=2)
+    assert bwt.tobytes().decode() == "".join(ch * n for ch in single)
+    assert tp.tolist() == [row0 * n + i for i in range(n)]
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (1, 5), (7, 3), (40, 9)])
+def test_homopolymer_closed_form(m, n):
+    text, off = _col(["A" * m] * n)
+    bwt, tp = oracle.bwt(text, off)
+    assert bwt.tobytes().decode() == "A" * (n * m) + "$" * n
+    assert tp.tolist() == [n * m + i for i in range(n)]
+
+
+# ---- invariants at moderate size ------------------------------------------------
+
+def test_invariants_on_simulated_reads():
+    col = datagen.plain_config(0, scale=0.2)
+    bwt, tp = oracle.bwt(col.text, col.offsets)
+    invariants.check_counts(bwt, tp, col.text, col.offsets)
+    invariants.check_dollar_rows(bwt, col.text, col.offsets)
+    invariants.lf_reconstruct(bwt, tp, col.text, col.offsets)
+
+
+def test_thread_count_does_not_change_result():
+    col = datagen.plain_config(0, scale=0.05)
+    a, ta = oracle.bwt(col.text, col.offsets, threads=1)
+    b, tb = oracle.bwt(col.text, col.offsets, threads=7)
+    assert np.array_equal(a, b) and np.array_equal(ta, tb)
+
+
+def test_rejects_non_acgt():
+    with pytest.raises(ValueError):
+        oracle.bwt(np.frombuffer(b"ACNT", np.uint8), np.array([0, 4], np.uint64))
+
+
+# ---- packed input layout ----------------------------------------------------------
+
+def test_pack_layout_pins():
+    w = oracle.pack("ACGT")
+    assert w.tolist() == [0x1B00000000000000, 0]
+    w = oracle.pack("T" * 32 + "C")
+    assert w.tolist() == [0xFFFFFFFFFFFFFFFF, 0x4000000000000000, 0]
+    assert oracle.pack("").tolist() == [0]
+    w = oracle.pack("G" * 31 + "A" + "G")
+    assert w[0] == int("10" * 31 + "00", 2) and w[1] == 2 << 62
+
+
+# ---- mutation tests: planted mistakes in the oracle must be caught ----------
+
+MUTANTS = {
+    "terminator_order_reversed": ("return (a->read < b->read) ? -1 : (a->read > b->read) ? 1 : 0;",
+                                  "return (a->read < b->read) ? 1 : (a->read > b->read) ? -1 : 0;"),
+    "dollar_above_bases": ("if (a_end) return -1;", "if (a_end) return 1;"),
+    "preceding_symbol_off_by_one": ("bwt[row] = text[offsets[i] + k - 1];", "bwt[row] = text[offsets[i] + k];"),
+    "C_G_swapped": ("case 'C': return 2;", "case 'C': return 3;"),
+    "term_pos_dropped": ("term_pos[i] = row;", "term_pos[i] = row + 1;"),
+}
+
+
+def _pin_battery(lib):
+    """Run the cheap pins against a (possibly mutated) oracle build."""
+    failures = []
+    g = load_golden("fig1.txt")
+    text, off = _col(g["reads"])
+    try:
+        bwt, tp = oracle.bwt(text, off, lib=lib)
+        if bwt.tobytes().decode() != g["bwt"][0] or tp.tolist() != [int(x) for x in g["term_pos"]]:
+            failures.append("fig1")
+    except Exception:
+        failures.append("fig1-crash")
+    rng = np.random.default_rng(11)
+    reads = datagen.random_collection(rng, 50, [0, 3, 9, 20]).reads()
+    text, off = _col(reads)
+    bwt, tp = oracle.bwt(text, off, lib=lib)
+    eb, etp = _bwt_via_concatenation(reads)
+    if bwt.tobytes().decode() != eb or tp.tolist() != etp:
+        failures.append("concat-sa")
+    return failures
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_planted_mistake_is_caught(name):
+    old, new = MUTANTS[name]
+    src = open(os.path.join(ROOT, "oracle", "cx_oracle.c")).read()
+    assert src.count(old) == 1, f"mutation anchor for {name} not found exactly once"
+    with tempfile.TemporaryDirectory() as d:
+        p = os.path.join(d, "mut.c")
+        with open(p, "w") as f:
+            f.write(src.replace(old, new))
+        so = oracle.compile_oracle(p, os.path.join(d, "libmut.so"))
+        lib = oracle.load(so)
+        assert _pin_battery(lib), f"planted mistake '{name}' passed every pin"
+
+
+def test_unmutated_oracle_passes_battery():
+    assert _pin_battery(oracle.load()) == []
