@@ -1,0 +1,144 @@
+/*
+ * cxbwt.h -- C ABI of the MI355X (gfx950) multi-string BWT library.
+ *
+ * The library builds the Burrows-Wheeler transform of a collection of reads
+ * as defined in Section 2 of Liu, Luo & Lam, "GPU-Accelerated BWT
+ * Construction for Large Collection of Short Reads" (the CX1 method):
+ *
+ *   * read r_i (bases A<C<G<T) is extended to S_i = r_i $_i;
+ *   * the terminators sort below every base and $_i < $_j exactly when i < j;
+ *   * all sum_i (L_i + 1) suffixes of all S_i are sorted lexicographically;
+ *   * row rho of the BWT is the symbol before the rho-th suffix in its own
+ *     string, or '$' when that suffix starts at offset 0 (Fig. 1 shows the
+ *     collection {ACGT, TAGT, GGAA} giving TTAAG$TAG$CAGG$).
+ *
+ * Every step runs in HIP kernels on the device; the host code only checks
+ * arguments, sizes the workspace and sequences launches.
+ *
+ * Conventions shared by all entry points
+ *   * Pointers marked (device) must point to memory on the current HIP device;
+ *     (host) pointers to host memory.  The caller allocates and frees every
+ *     buffer, including the workspace; the library keeps no device memory
+ *     and frees nothing it was given.
+ *   * `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   * Return value: one of the CXBWT_* status codes below.  No C++ exception
+ *     crosses this interface.  cxbwt_status_str() gives a message.
+ *   * Calls on distinct streams with distinct workspaces may run concurrently
+ *     from different host threads.
+ */
+#ifndef CXBWT_H
+#define CXBWT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+#define CXBWT_OK 0
+#define CXBWT_EINVAL (-1)  /* a null pointer or inconsistent sizes            */
+#define CXBWT_ERANGE (-2)  /* a size the library does not support (below)     */
+#define CXBWT_ENOMEM (-3)  /* workspace smaller than cxbwt_workspace_bytes()  */
+#define CXBWT_EDEVICE (-4) /* a HIP launch or runtime call failed             */
+#define CXBWT_EDATA (-5)   /* the device found invalid input data: offsets not
+                              a non-decreasing partition of the bases, a read
+                              longer than max_read_len, or a non-ACGT byte     */
+
+/* Largest supported n_bases: suffix handles are 32-bit base positions. */
+#define CXBWT_MAX_BASES 4294967295ull
+/* Largest supported max_read_len. */
+#define CXBWT_MAX_READ_LEN 65535u
+
+/*
+ * Packed read layout (input of cxbwt_build), fixed by this library:
+ * base t of the reads concatenated in read order is the 2-bit code
+ * A=0, C=1, G=2, T=3 stored in 64-bit word t/32 at bits
+ * [62 - 2*(t%32), 63 - 2*(t%32)], i.e. the first base of a word in its two
+ * most significant bits.  A packed array holds cxbwt_packed_words(n_bases)
+ * words: ceil(n_bases/32) data words plus one zero pad word.
+ */
+uint64_t cxbwt_packed_words(uint64_t n_bases);
+
+/*
+ * cxbwt_pack -- read packing (the 2-bit representation of Section 3, used
+ * there to size the explicit-suffix alternative; here the device input form).
+ *
+ *   ascii     (device) n_bases bytes, each 'A', 'C', 'G' or 'T'.
+ *   n_bases   number of bases.
+ *   packed    (device, out) cxbwt_packed_words(n_bases) uint64 words in the
+ *             layout above; the pad word is written as zero.
+ *   d_status  (device, out, may be NULL) one uint32 set to 0 and then to a
+ *             non-zero value if any byte is not A/C/G/T (such bytes pack as
+ *             A).  Read it after the stream completes.
+ *   stream    hipStream_t as void*.
+ * Asynchronous on `stream`.  Returns CXBWT_EINVAL for null ascii/packed with
+ * n_bases > 0, CXBWT_ERANGE above CXBWT_MAX_BASES, CXBWT_EDEVICE on a launch
+ * failure.
+ */
+int cxbwt_pack(const uint8_t *ascii, uint64_t n_bases, uint64_t *packed, uint32_t *d_status,
+               void *stream);
+
+/*
+ * cxbwt_workspace_bytes -- device workspace cxbwt_build needs for these
+ * sizes (about 24 bytes per base plus small lists).  Pure host arithmetic:
+ * no device call, usable without a GPU.  Returns 0 when the sizes are out of
+ * range (see cxbwt_build).
+ */
+size_t cxbwt_workspace_bytes(uint64_t n_reads, uint64_t n_bases, uint32_t max_read_len);
+
+/*
+ * cxbwt_build -- the multi-string BWT of one read collection (Section 2;
+ * the suffix sort of Section 3.2 done entirely on the device).
+ *
+ * Inputs
+ *   packed        (device) cxbwt_packed_words(n_bases) words, layout above.
+ *   offsets       (device) n_reads + 1 uint64: read i is bases
+ *                 [offsets[i], offsets[i+1]) of the concatenation; offsets[0]
+ *                 must be 0, offsets must not decrease, offsets[n_reads] must
+ *                 equal n_bases.  Empty reads (equal neighbours) are allowed.
+ *   n_reads       number of reads n (>= 1, < 2^32).
+ *   n_bases       total bases B (<= CXBWT_MAX_BASES).
+ *   max_read_len  an upper bound on every read length (<= CXBWT_MAX_READ_LEN);
+ *                 it bounds the number of refinement windows.
+ * Outputs
+ *   bwt           (device, out) n_bases + n_reads bytes, ASCII over A/C/G/T/$:
+ *                 row rho is the symbol before the rho-th smallest suffix.
+ *   term_pos      (device, out) n_reads uint64: term_pos[i] is the row of the
+ *                 offset-0 suffix of read i, i.e. the '$' row standing for
+ *                 read i.  The '$' rows are exactly the values of term_pos.
+ * Workspace
+ *   workspace     (device) at least cxbwt_workspace_bytes(...) bytes, aligned
+ *                 to 256 bytes; contents on entry are ignored.
+ * Behaviour
+ *   Work is enqueued on `stream`; the call reads a few counters back between
+ *   sort levels, so it returns only after the device work is complete.
+ *   Returns CXBWT_EINVAL (null pointer, n_reads == 0), CXBWT_ERANGE (sizes
+ *   above the limits), CXBWT_ENOMEM (workspace too small), CXBWT_EDATA
+ *   (offsets invalid or a read longer than max_read_len, found on the device
+ *   before any sorting; outputs are then unspecified), CXBWT_EDEVICE.
+ */
+int cxbwt_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n_reads, uint64_t n_bases,
+                uint32_t max_read_len, uint8_t *bwt, uint64_t *term_pos, void *workspace,
+                size_t workspace_bytes, void *stream);
+
+/* Counters describing the last cxbwt_build on the calling host thread. */
+typedef struct cxbwt_stats {
+  uint32_t levels;        /* global sort levels run                               */
+  uint32_t max_window;    /* deepest 28-base key window used (0 = first window)   */
+  uint64_t chunks;        /* groups finished inside one workgroup                 */
+  uint64_t big_segments;  /* segment passes run through the global levels         */
+  uint64_t final_big;     /* groups of identical suffixes emitted from the levels */
+} cxbwt_stats;
+
+/* Copies the last build's counters (host) into *out; CXBWT_EINVAL on NULL. */
+int cxbwt_last_stats(cxbwt_stats *out);
+
+/* Static message for a status code. */
+const char *cxbwt_status_str(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CXBWT_H */

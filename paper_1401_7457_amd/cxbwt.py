@@ -1,0 +1,151 @@
+"""Thin Python binding of libcxbwt.so (argument marshalling only).
+
+Every step of the BWT construction runs in the library's HIP kernels; this
+module allocates device buffers with PyTorch, passes raw pointers and the
+current stream through the C ABI declared in include/cxbwt.h, and turns status
+codes into exceptions.  There is no CPU fallback: without the built library
+every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcxbwt.so")
+
+OK, EINVAL, ERANGE, ENOMEM, EDEVICE, EDATA = 0, -1, -2, -3, -4, -5
+STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ERANGE: "ERANGE", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", EDATA: "EDATA"}
+
+# Names the C ABI exports (include/cxbwt.h).
+ABI_FUNCTIONS = ("cxbwt_packed_words", "cxbwt_pack", "cxbwt_workspace_bytes", "cxbwt_build", "cxbwt_last_stats",
+                 "cxbwt_status_str")
+
+_lock = threading.Lock()
+_lib = None
+
+
+class CxbwtError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        msg = lib().cxbwt_status_str(status).decode() if _lib is not None else ""
+        super().__init__(f"{what}: {STATUS_NAMES.get(status, status)} ({msg})")
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_uint32), ("max_window", ctypes.c_uint32), ("chunks", ctypes.c_uint64),
+                ("big_segments", ctypes.c_uint64), ("final_big", ctypes.c_uint64)]
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                                   "(python -m paper_1401_7457_amd.build)")
+            L = ctypes.CDLL(LIB_PATH)
+            vp, u64, u32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32
+            L.cxbwt_packed_words.argtypes = [u64]
+            L.cxbwt_packed_words.restype = u64
+            L.cxbwt_pack.argtypes = [vp, u64, vp, vp, vp]
+            L.cxbwt_pack.restype = ctypes.c_int
+            L.cxbwt_workspace_bytes.argtypes = [u64, u64, u32]
+            L.cxbwt_workspace_bytes.restype = ctypes.c_size_t
+            L.cxbwt_build.argtypes = [vp, vp, u64, u64, u32, vp, vp, vp, ctypes.c_size_t, vp]
+            L.cxbwt_build.restype = ctypes.c_int
+            L.cxbwt_last_stats.argtypes = [ctypes.POINTER(Stats)]
+            L.cxbwt_last_stats.restype = ctypes.c_int
+            L.cxbwt_status_str.argtypes = [ctypes.c_int]
+            L.cxbwt_status_str.restype = ctypes.c_char_p
+            _lib = L
+        return _lib
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def packed_words(n_bases: int) -> int:
+    return int(lib().cxbwt_packed_words(n_bases))
+
+
+def workspace_bytes(n_reads: int, n_bases: int, max_read_len: int) -> int:
+    return int(lib().cxbwt_workspace_bytes(n_reads, n_bases, max_read_len))
+
+
+def pack(ascii_dev, stream=None):
+    """ASCII bases (uint8 CUDA tensor) -> packed words (int64 CUDA tensor holding uint64 bits)."""
+    import torch
+    if ascii_dev.dtype != torch.uint8 or not ascii_dev.is_cuda:
+        raise TypeError("pack expects a uint8 CUDA tensor")
+    ascii_dev = ascii_dev.contiguous()
+    nb = ascii_dev.numel()
+    out = torch.empty(packed_words(nb), dtype=torch.int64, device=ascii_dev.device)
+    status = torch.empty(1, dtype=torch.int32, device=ascii_dev.device)
+    st = lib().cxbwt_pack(ctypes.c_void_p(ascii_dev.data_ptr() if nb else 0), nb, ctypes.c_void_p(out.data_ptr()),
+                          ctypes.c_void_p(status.data_ptr()), _stream_ptr(stream))
+    if st != OK:
+        raise CxbwtError(st, "cxbwt_pack")
+    return out, status
+
+
+def alloc_workspace(n_reads: int, n_bases: int, max_read_len: int, device="cuda"):
+    import torch
+    nbytes = workspace_bytes(n_reads, n_bases, max_read_len)
+    if nbytes == 0:
+        raise CxbwtError(ERANGE, "cxbwt_workspace_bytes")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def build(packed, offsets, n_reads: int, n_bases: int, max_read_len: int, workspace=None, out=None, stream=None):
+    """BWT (uint8 CUDA tensor, n_bases + n_reads) and term_pos (int64 CUDA tensor, n_reads).
+
+    packed: int64 CUDA tensor of packed words; offsets: int64 CUDA tensor of n_reads + 1 base offsets.
+    """
+    import torch
+    dev = packed.device
+    if workspace is None:
+        workspace = alloc_workspace(n_reads, n_bases, max_read_len, dev)
+    if out is None:
+        bwt = torch.empty(n_bases + n_reads, dtype=torch.uint8, device=dev)
+        term = torch.empty(n_reads, dtype=torch.int64, device=dev)
+    else:
+        bwt, term = out
+    st = lib().cxbwt_build(ctypes.c_void_p(packed.data_ptr()), ctypes.c_void_p(offsets.data_ptr()), n_reads, n_bases,
+                           max_read_len, ctypes.c_void_p(bwt.data_ptr()), ctypes.c_void_p(term.data_ptr()),
+                           ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream_ptr(stream))
+    if st != OK:
+        raise CxbwtError(st, "cxbwt_build")
+    return bwt, term
+
+
+def last_stats() -> dict:
+    s = Stats()
+    lib().cxbwt_last_stats(ctypes.byref(s))
+    return {f: int(getattr(s, f)) for f, _ in Stats._fields_}
+
+
+def build_host(text: np.ndarray, offsets: np.ndarray, max_read_len: int | None = None, device="cuda"):
+    """Host arrays in, host arrays out: copy, pack and build on the device."""
+    import torch
+    text = np.ascontiguousarray(text, dtype=np.uint8)
+    offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+    n = offsets.size - 1
+    nb = int(offsets[-1])
+    if max_read_len is None:
+        max_read_len = int(np.max(np.diff(offsets.astype(np.int64)))) if n else 0
+    t_dev = torch.from_numpy(text).to(device) if nb else torch.empty(0, dtype=torch.uint8, device=device)
+    o_dev = torch.from_numpy(offsets.view(np.int64)).to(device)
+    packed, pstatus = pack(t_dev)
+    bwt, term = build(packed, o_dev, n, nb, max_read_len)
+    torch.cuda.synchronize()
+    if int(pstatus.item()) != 0:
+        raise CxbwtError(EDATA, "cxbwt_pack (non-ACGT byte)")
+    return bwt.cpu().numpy(), term.cpu().numpy().view(np.uint64)

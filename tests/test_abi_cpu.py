@@ -1,0 +1,86 @@
+"""The C ABI without a GPU: symbols, workspace sizing and host-side validation.
+
+Every call here returns before any HIP runtime call (argument checks come
+first), so it runs on a machine without a GPU.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+from paper_1401_7457_amd import cxbwt
+
+HEADER = os.path.join(ROOT, "include", "cxbwt.h")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(cxbwt_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = _declared_functions()
+    assert set(names) == set(cxbwt.ABI_FUNCTIONS)
+    L = cxbwt.lib()
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_packed_words():
+    assert cxbwt.packed_words(0) == 1
+    assert cxbwt.packed_words(1) == 2
+    assert cxbwt.packed_words(32) == 2
+    assert cxbwt.packed_words(33) == 3
+
+
+def test_workspace_bytes_scale_and_limits():
+    small = cxbwt.workspace_bytes(10, 1000, 100)
+    big = cxbwt.workspace_bytes(4_000_000, 400_000_000, 100)
+    assert small > 24 * 1000
+    assert 24 * 400_000_000 <= big <= 27 * 400_000_000
+    assert cxbwt.workspace_bytes(0, 10, 10) == 0            # no reads
+    assert cxbwt.workspace_bytes(1, 1 << 32, 10) == 0       # above 32-bit handles
+    assert cxbwt.workspace_bytes(1, 10, 70000) == 0         # read length bound
+
+
+def test_build_argument_validation_needs_no_gpu():
+    L = cxbwt.lib()
+    fake = ctypes.c_void_p(0x1000)
+    null = ctypes.c_void_p(0)
+    args = lambda **kw: [kw.get("packed", fake), kw.get("offsets", fake), kw.get("n", 3), kw.get("nb", 12),
+                         kw.get("maxlen", 4), kw.get("bwt", fake), kw.get("term", fake), kw.get("ws", fake),
+                         kw.get("wsb", 1 << 40), null]
+    assert L.cxbwt_build(*args(packed=null)) == cxbwt.EINVAL
+    assert L.cxbwt_build(*args(bwt=null)) == cxbwt.EINVAL
+    assert L.cxbwt_build(*args(term=null)) == cxbwt.EINVAL
+    assert L.cxbwt_build(*args(ws=null)) == cxbwt.EINVAL
+    assert L.cxbwt_build(*args(n=0)) == cxbwt.EINVAL
+    assert L.cxbwt_build(*args(nb=1 << 32)) == cxbwt.ERANGE
+    assert L.cxbwt_build(*args(maxlen=1 << 20)) == cxbwt.ERANGE
+    assert L.cxbwt_build(*args(wsb=10)) == cxbwt.ENOMEM
+    assert L.cxbwt_build(*args(ws=ctypes.c_void_p(0x1001))) == cxbwt.EINVAL  # misaligned workspace
+
+
+def test_pack_argument_validation_needs_no_gpu():
+    L = cxbwt.lib()
+    null = ctypes.c_void_p(0)
+    assert L.cxbwt_pack(null, 10, ctypes.c_void_p(0x1000), null, null) == cxbwt.EINVAL
+    assert L.cxbwt_pack(ctypes.c_void_p(0x1000), 10, null, null, null) == cxbwt.EINVAL
+    assert L.cxbwt_pack(ctypes.c_void_p(0x1000), 1 << 33, ctypes.c_void_p(0x1000), null, null) == cxbwt.ERANGE
+
+
+def test_status_strings():
+    L = cxbwt.lib()
+    for code in (0, -1, -2, -3, -4, -5):
+        assert L.cxbwt_status_str(code)
+    assert b"unknown" in L.cxbwt_status_str(42)
+
+
+def test_binding_has_no_cpu_fallback(monkeypatch, tmp_path):
+    monkeypatch.setattr(cxbwt, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(cxbwt, "_lib", None)
+    with pytest.raises(RuntimeError, match="missing"):
+        cxbwt.lib()
