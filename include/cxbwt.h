@@ -125,15 +125,33 @@ int cxbwt_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n_read
 
 /* Counters describing the last cxbwt_build on the calling host thread. */
 typedef struct cxbwt_stats {
-  uint32_t levels;        /* global sort levels run                               */
-  uint32_t max_window;    /* deepest 28-base key window used (0 = first window)   */
-  uint64_t chunks;        /* groups finished inside one workgroup                 */
-  uint64_t big_segments;  /* segment passes run through the global levels         */
-  uint64_t final_big;     /* groups of identical suffixes emitted from the levels */
+  uint32_t levels;             /* global sort levels run                               */
+  uint32_t max_window;         /* deepest 28-base key window used (0 = first window)   */
+  uint64_t chunks;             /* bucket sets finished inside one workgroup            */
+  uint64_t big_segments;       /* segment passes run through the global levels         */
+  uint64_t final_big;          /* groups of identical suffixes emitted from the levels */
+  uint64_t chunk_suffixes;     /* suffixes finished inside workgroups                  */
+  uint64_t level_suffixes;     /* suffix visits of the global histogram passes          */
+  uint64_t scattered_suffixes; /* suffixes moved by global scatters                    */
+  uint64_t regathered;         /* later-window keys fetched by the global levels        */
+  uint64_t window_fetches;     /* later-window keys fetched inside workgroups           */
+  /* With timing on (cxbwt_set_timing): summed kernel time in ms and launch
+   * count per kernel class: 0 prep, 1 key generation, 2 level histogram,
+   * 3 level scan, 4 level scatter, 5 in-workgroup finish, 6 final emit.      */
+  float ms[8];
+  uint32_t launches[8];
 } cxbwt_stats;
 
 /* Copies the last build's counters (host) into *out; CXBWT_EINVAL on NULL. */
 int cxbwt_last_stats(cxbwt_stats *out);
+
+/*
+ * cxbwt_set_timing -- for later cxbwt_build calls on the calling host thread,
+ * bracket every kernel class with HIP events recorded on the build's stream
+ * and sum their durations into cxbwt_stats.ms (enable != 0), or stop doing
+ * so (enable == 0, the default).  Returns the previous setting.
+ */
+int cxbwt_set_timing(int enable);
 
 /* Static message for a status code. */
 const char *cxbwt_status_str(int status);

@@ -14,24 +14,26 @@
 //   * handle  = the 32-bit global base position p of a suffix's first base;
 //               the n empty suffixes ($_i alone) are not sorted at all: they
 //               are rows 0..n-1 in read order.
-//   * key     = one 28-base window of the suffix: 56 bits of bases (zero past
-//               the end of the read), 5 bits holding min(remaining, 28), and
-//               3 bits carrying the symbol that precedes the suffix (0..3 a
-//               base, 4 = '$').  Ordering uses bits [3, 64) only.  Comparing
-//               (bases, clamped length) lexicographically is the order of
-//               Section 2 within one window: a suffix that ends inside the
-//               window is a proper prefix of, hence below, one that goes on;
-//               equal keys with a clamped length below 28 are identical
-//               suffixes, which stable passes keep in read order.
-//   * sort    = most-significant-digit first: global 8-bit digit levels split
-//               the key space until every bucket fits one workgroup (4096
-//               suffixes); each bucket set is then sorted, refined and emitted
-//               entirely in LDS.  A tie on a full window (clamped length 28)
-//               fetches the next window of the tied suffixes only.
+//   * key     = one 28-base window of the suffix (layout in device_common.h):
+//               bases zero-padded past the read end, then min(remaining, 28).
+//               Comparing (bases, clamped length) is the order of Section 2
+//               inside one window: a suffix that ends in the window is a
+//               proper prefix of, hence below, one that goes on; equal keys
+//               with a clamped length below 28 are identical suffixes, which
+//               stable passes keep in read order.
+//   * sort    = most-significant digit first.  Level 1 computes window-0 keys
+//               from the 2-bit reads and scatters them by their top 8 bits
+//               (keys are never stored unsorted); further 8-bit levels split
+//               every bucket larger than one workgroup's share (2048
+//               suffixes).  Runs of small buckets are then sorted on their
+//               remaining digits, tie-refined window by window and emitted
+//               inside one workgroup, in LDS.  A tie on a full window
+//               (clamped length 28) fetches the next window of the tied
+//               suffixes only.
 //
 // Every pass is stable and the initial order is read-major, so suffixes that
-// are equal through their terminators stay in read-index order (Section 3.2's
-// stability argument).
+// are equal through their terminators stay in read-index order (the stability
+// argument of Section 3.2).
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -41,29 +43,30 @@
 #include <vector>
 
 #include "cxbwt.h"
+#include "device_common.h"
 
 namespace {
 
-// ---------------------------------------------------------------------------
-// constants
-// ---------------------------------------------------------------------------
-constexpr int W = 28;                    // bases per key window
-constexpr int BLOCK = 256;               // threads per workgroup
-constexpr int WAVES = BLOCK / 64;        // wave64
-constexpr int ITEMS = 16;                // suffixes per thread in a tile
-constexpr int TILE = BLOCK * ITEMS;      // 4096: tile of a global level
-constexpr int WAVE_SPAN = 64 * ITEMS;    // suffixes per wave in a tile
-constexpr int CHUNK = 4096;              // largest bucket set finished in LDS
-constexpr int RANK_COUNT_MAX = 256;      // live groups up to this size: all-pairs ranking
-constexpr uint32_t NODIGIT = 0xFFFFFFFFu;
+using namespace cxk;
+
+#ifndef CXBWT_TILE_ITEMS
+#define CXBWT_TILE_ITEMS 12
+#endif
+constexpr int TILE_ITEMS = CXBWT_TILE_ITEMS;   // suffixes per thread in a level tile
+constexpr int TILE = BLOCK * TILE_ITEMS;       // 4096
+#ifndef CXBWT_LOCAL_ITEMS
+#define CXBWT_LOCAL_ITEMS 4
+#endif
+constexpr int LOCAL_ITEMS = CXBWT_LOCAL_ITEMS; // suffixes per thread in a chunk
+constexpr int CHUNK = BLOCK * LOCAL_ITEMS;     // 2048: largest run finished in LDS
+constexpr int GROUP_TILES = 256;               // tiles per first-stage scan group
+constexpr int RANK_COUNT_MAX = 256;            // live groups up to this size: all-pairs ranking
 
 constexpr uint32_t ST_BAD_OFFSETS = 1u;
 constexpr uint32_t ST_TOO_LONG = 2u;
 constexpr uint32_t ST_BAD_CHAR = 4u;
 constexpr uint32_t ST_LIST_OVERFLOW = 8u;
 constexpr uint32_t ST_WINDOW_BOUND = 16u;
-
-static_assert(TILE == CHUNK, "tile and chunk share the register layout");
 
 // A run of suffixes [start, start+len) in key/handle buffer `buf`, whose keys
 // are for window r and agree on every digit before d.
@@ -74,7 +77,7 @@ struct Seg {
   uint8_t d;
   uint8_t buf;
   uint8_t regather;  // keys must be re-fetched for window r before use
-  uint8_t pad;
+  uint8_t unsplit;   // chunk only: suffixes are in read order, not yet split by digit d
 };
 
 struct Lists {
@@ -89,203 +92,40 @@ struct Lists {
   uint32_t cap_finals;
   uint32_t *status;
   uint32_t rmax;
+  unsigned long long *scattered;
 };
 
-// ---------------------------------------------------------------------------
-// key helpers
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t order_bits(uint64_t k) { return k & ~7ull; }
-__device__ __forceinline__ uint32_t clamp_of(uint64_t k) { return (uint32_t)(k >> 3) & 31u; }
-__device__ __forceinline__ uint32_t digit_of(uint64_t k, int j) {
-  return j < 7 ? (uint32_t)(k >> (56 - 8 * j)) & 0xFFu : (uint32_t)(k >> 3) & 0x1Fu;
-}
-__host__ __device__ __forceinline__ uint64_t digit_mask(int j) {
-  return j < 7 ? (0xFFull << (56 - 8 * j)) : (0x1Full << 3);
-}
-__device__ __forceinline__ uint32_t base_at(const uint64_t *packed, uint64_t t) {
-  return (uint32_t)(packed[t >> 5] >> (62 - 2 * (t & 31))) & 3u;
-}
-__device__ __forceinline__ bool end_bit(const uint64_t *endbits, uint64_t t) {
-  return (endbits[t >> 6] >> (t & 63)) & 1ull;
+// Number of read ends strictly before base p: the index of the read that
+// starts at p among the non-empty reads.  ebrank[w] counts the end bits of
+// words before w.
+__device__ __forceinline__ uint32_t end_rank(const uint64_t *__restrict__ endbits, const uint32_t *__restrict__ ebrank,
+                                             uint64_t p) {
+  const uint64_t w = endbits[p >> 6];
+  const uint64_t below = (p & 63) ? (w << (64 - (p & 63))) : 0ull;
+  return ebrank[p >> 6] + (uint32_t)__popcll(below);
 }
 
-// Key of window r of the suffix whose first base is p (the window starts at
-// base q = p + 28 r).  endbits marks the last base of every non-empty read.
-// For r >= 1 the caller guarantees the read still holds at least 28 r bases
-// from p, so the read's last base e satisfies e >= q - 1.
-__device__ uint64_t window_key(const uint64_t *__restrict__ packed, const uint64_t *__restrict__ endbits,
-                               uint64_t nb, uint64_t p, uint32_t r, uint32_t prev3) {
-  uint64_t q = p + (uint64_t)W * r;
-  uint64_t lo = r == 0 ? p : q - 1;
-  if (lo >= nb) return prev3;  // never taken for a live suffix; keeps reads in bounds
-  uint64_t w0 = endbits[lo >> 6] >> (lo & 63);
-  uint64_t e;
-  if (w0) {
-    e = lo + (uint64_t)__builtin_ctzll(w0);
-  } else {
-    uint64_t b1 = (lo | 63ull) + 1;
-    uint64_t w1 = endbits[b1 >> 6];
-    e = w1 ? b1 + (uint64_t)__builtin_ctzll(w1) : ~0ull;
-  }
-  uint32_t clamp = (e < q + W) ? (uint32_t)(e + 1 - q) : (uint32_t)W;
-  uint64_t chars = 0;
-  if (clamp > 0 && q < nb) {
-    uint64_t wi = q >> 5;
-    uint32_t b = 2u * (uint32_t)(q & 31);
-    uint64_t x = packed[wi] << b;
-    if (b) x |= packed[wi + 1] >> (64 - b);
-    chars = x & ~0xFFull;
-    if (clamp < (uint32_t)W) chars &= ~((1ull << (64 - 2 * clamp)) - 1);
-  }
-  return chars | ((uint64_t)clamp << 3) | prev3;
-}
-
-__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
-__device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
-
-__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t v) {
-  const uint32_t l = lane_id();
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    uint32_t t = __shfl_up(v, o, 64);
-    if (l >= (uint32_t)o) v += t;
-  }
-  return v;
-}
-
-__device__ __forceinline__ uint64_t wave_or(uint64_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
-  return v;
-}
-__device__ __forceinline__ uint64_t wave_and(uint64_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v &= __shfl_xor(v, o, 64);
-  return v;
-}
-__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor(v, o, 64));
-  return v;
-}
-
-// Exclusive prefix sum of one value per thread over the workgroup.
-__device__ uint32_t block_excl_sum(uint32_t v, uint32_t *tmp, uint32_t *total) {
-  uint32_t inc = wave_incl_sum(v);
-  const int w = threadIdx.x >> 6;
-  if (lane_id() == 63) tmp[w] = inc;
-  __syncthreads();
-  uint32_t pre = 0, tot = 0;
-#pragma unroll
-  for (int i = 0; i < WAVES; ++i) {
-    uint32_t x = tmp[i];
-    if (i < w) pre += x;
-    tot += x;
-  }
-  __syncthreads();
-  if (total) *total = tot;
-  return pre + inc - v;
-}
-
-__device__ uint64_t block_or(uint64_t v, uint64_t *tmp) {
-  v = wave_or(v);
-  if (lane_id() == 0) tmp[threadIdx.x >> 6] = v;
-  __syncthreads();
-  uint64_t r = 0;
-#pragma unroll
-  for (int i = 0; i < WAVES; ++i) r |= tmp[i];
-  __syncthreads();
-  return r;
-}
-__device__ uint64_t block_and(uint64_t v, uint64_t *tmp) {
-  v = wave_and(v);
-  if (lane_id() == 0) tmp[threadIdx.x >> 6] = v;
-  __syncthreads();
-  uint64_t r = ~0ull;
-#pragma unroll
-  for (int i = 0; i < WAVES; ++i) r &= tmp[i];
-  __syncthreads();
-  return r;
-}
-__device__ uint32_t block_max(uint32_t v, uint32_t *tmp) {
-  v = wave_max(v);
-  if (lane_id() == 0) tmp[threadIdx.x >> 6] = v;
-  __syncthreads();
-  uint32_t r = 0;
-#pragma unroll
-  for (int i = 0; i < WAVES; ++i) r = max(r, tmp[i]);
-  __syncthreads();
-  return r;
-}
-
-// Index of the ITEMS items of this thread in a tile: wave w owns
-// [w*WAVE_SPAN, (w+1)*WAVE_SPAN); item i of lane l is w*WAVE_SPAN + i*64 + l.
-__device__ __forceinline__ uint32_t item_index(int i) {
-  return (uint32_t)((threadIdx.x >> 6) * WAVE_SPAN + i * 64) + lane_id();
-}
-
-// Stable 256-way split of up to TILE items held in registers (layout of
-// item_index).  On return pos[i] is the destination of item i in [0, count);
-// dstart[d] is the first destination of digit d.  dig[i] == NODIGIT marks an
-// absent item.
-__device__ void block_multisplit(const uint32_t (&dig)[ITEMS], uint32_t (&pos)[ITEMS], uint32_t *wcount,
-                                 uint32_t *dstart, uint32_t *tmp) {
-  const int w = threadIdx.x >> 6;
-  for (int x = threadIdx.x; x < WAVES * 256; x += BLOCK) wcount[x] = 0;
-  __syncthreads();
-  uint32_t *wc = wcount + w * 256;
-  const uint64_t lt = lanemask_lt();
-#pragma unroll
-  for (int i = 0; i < ITEMS; ++i) {
-    const uint32_t d = dig[i];
-    const bool valid = d != NODIGIT;
-    uint64_t peers = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const uint64_t v = __ballot(bit);
-      peers &= bit ? v : ~v;
-    }
-    if (valid) {
-      const uint32_t before = wc[d];
-      pos[i] = before + (uint32_t)__popcll(peers & lt);
-      if ((peers & lt) == 0) wc[d] = before + (uint32_t)__popcll(peers);
-    }
-  }
-  __syncthreads();
-  const uint32_t d = threadIdx.x;  // BLOCK == 256 digits
-  uint32_t run = 0;
-#pragma unroll
-  for (int ww = 0; ww < WAVES; ++ww) {
-    const uint32_t c = wcount[ww * 256 + d];
-    wcount[ww * 256 + d] = run;
-    run += c;
-  }
-  const uint32_t ex = block_excl_sum(run, tmp, nullptr);
-  dstart[d] = ex;
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < ITEMS; ++i)
-    if (dig[i] != NODIGIT) pos[i] += dstart[dig[i]] + wc[dig[i]];
-}
-
-// Writes the BWT row of a sorted suffix and, for an offset-0 suffix, the
-// row into term_pos of its read (the read whose first base is p).
-__device__ __forceinline__ void emit_row(uint64_t row, uint64_t key, uint32_t p, const uint64_t *__restrict__ offsets,
-                                         uint64_t n, uint8_t *__restrict__ bwt, uint64_t *__restrict__ term_pos) {
+// Writes the BWT row of a sorted suffix; an offset-0 suffix also records its
+// row under its read's rank among the non-empty reads (k_term turns those
+// into term_pos).
+__device__ __forceinline__ void emit_row(uint64_t row, uint64_t key, uint32_t p, const uint64_t *__restrict__ endbits,
+                                         const uint32_t *__restrict__ ebrank, uint8_t *__restrict__ bwt,
+                                         uint64_t *__restrict__ start_row) {
   const uint32_t pv = (uint32_t)key & 7u;
   const uint32_t lut = 'A' | ('C' << 8) | ('G' << 16) | ('T' << 24);
   bwt[row] = pv == 4 ? (uint8_t)'$' : (uint8_t)((lut >> (8 * pv)) & 0xFFu);
-  if (pv == 4) {
-    // largest i with offsets[i] <= p: the read that starts at p
-    uint64_t lo = 0, hi = n;
-    while (hi - lo > 1) {
-      const uint64_t mid = (lo + hi) >> 1;
-      if (offsets[mid] <= (uint64_t)p) lo = mid;
-      else hi = mid;
-    }
-    term_pos[lo] = row;
+  if (pv == 4) start_row[end_rank(endbits, ebrank, p)] = row;
+}
+
+__device__ __forceinline__ uint32_t find_upper(const uint32_t *prefix, uint32_t count, uint32_t x) {
+  // largest s < count with prefix[s] <= x (prefix[0] == 0, non-decreasing)
+  uint32_t lo = 0, hi = count;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (prefix[mid] <= x) lo = mid;
+    else hi = mid;
   }
+  return lo;
 }
 
 // ---------------------------------------------------------------------------
@@ -338,7 +178,7 @@ __global__ void k_prep(const uint64_t *__restrict__ packed, const uint64_t *__re
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const uint64_t a = offsets[i], b = offsets[i + 1];
-  bool bad = b < a || b > nb || (i == 0 && a != 0) || (i == n - 1 && b != nb);
+  const bool bad = b < a || b > nb || (i == 0 && a != 0) || (i == n - 1 && b != nb);
   if (bad) {
     atomicOr(status, ST_BAD_OFFSETS);
     return;
@@ -359,31 +199,164 @@ __global__ void k_prep(const uint64_t *__restrict__ packed, const uint64_t *__re
 }
 
 // ---------------------------------------------------------------------------
-// a1: suffix listing + window-0 keys, read-major (handle = base position)
+// exclusive prefix counts of the read-end bits, per 64-bit word
+// ---------------------------------------------------------------------------
+constexpr int RANK_WPT = 16;                      // words per thread
+constexpr int RANK_BLOCK_WORDS = BLOCK * RANK_WPT;
+
+__global__ __launch_bounds__(BLOCK) void k_rank_count(const uint64_t *__restrict__ endbits, uint64_t nw,
+                                                      uint32_t *__restrict__ blocksum) {
+  __shared__ uint32_t tmp[WAVES];
+  const uint64_t w0 = (uint64_t)blockIdx.x * RANK_BLOCK_WORDS + (uint64_t)threadIdx.x * RANK_WPT;
+  uint32_t c = 0;
+#pragma unroll
+  for (int i = 0; i < RANK_WPT; ++i)
+    if (w0 + i < nw) c += (uint32_t)__popcll(endbits[w0 + i]);
+  uint32_t total;
+  block_excl_sum(c, tmp, &total);
+  if (threadIdx.x == 0) blocksum[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_rank_top(uint32_t *__restrict__ blocksum, uint32_t nblocks) {
+  __shared__ uint32_t tmp[WAVES];
+  uint32_t running = 0;
+  for (uint32_t base = 0; base < nblocks; base += BLOCK) {
+    const uint32_t i = base + threadIdx.x;
+    const uint32_t v = i < nblocks ? blocksum[i] : 0u;
+    uint32_t total;
+    const uint32_t ex = block_excl_sum(v, tmp, &total);
+    if (i < nblocks) blocksum[i] = running + ex;
+    running += total;
+  }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_rank_words(const uint64_t *__restrict__ endbits, uint64_t nw,
+                                                      const uint32_t *__restrict__ blocksum,
+                                                      uint32_t *__restrict__ ebrank) {
+  __shared__ uint32_t tmp[WAVES];
+  const uint64_t w0 = (uint64_t)blockIdx.x * RANK_BLOCK_WORDS + (uint64_t)threadIdx.x * RANK_WPT;
+  uint32_t c = 0;
+#pragma unroll
+  for (int i = 0; i < RANK_WPT; ++i)
+    if (w0 + i < nw) c += (uint32_t)__popcll(endbits[w0 + i]);
+  uint32_t run = blocksum[blockIdx.x] + block_excl_sum(c, tmp, nullptr);
+#pragma unroll
+  for (int i = 0; i < RANK_WPT; ++i) {
+    if (w0 + i < nw) {
+      ebrank[w0 + i] = run;
+      run += (uint32_t)__popcll(endbits[w0 + i]);
+    }
+  }
+}
+
+// term_pos of every non-empty read from the row its offset-0 suffix recorded.
+__global__ void k_term(const uint64_t *__restrict__ offsets, uint64_t n, const uint64_t *__restrict__ endbits,
+                       const uint32_t *__restrict__ ebrank, const uint64_t *__restrict__ start_row,
+                       uint64_t *__restrict__ term_pos) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t a = offsets[i], b = offsets[i + 1];
+  if (b > a) term_pos[i] = start_row[end_rank(endbits, ebrank, a)];
+}
+
+// ---------------------------------------------------------------------------
+// a1 for small inputs: suffix listing + window-0 keys, read-major
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(BLOCK) void k_gen(const uint64_t *__restrict__ packed, const uint64_t *__restrict__ endbits,
                                                uint64_t nb, uint64_t *__restrict__ keys, uint32_t *__restrict__ hdl) {
   const uint64_t p = (uint64_t)blockIdx.x * BLOCK + threadIdx.x;
   if (p >= nb) return;
-  uint32_t prev3;
-  if (p == 0 || end_bit(endbits, p - 1)) prev3 = 4;
-  else prev3 = base_at(packed, p - 1);
-  keys[p] = window_key(packed, endbits, nb, p, 0, prev3);
+  keys[p] = first_key(packed, endbits, nb, p);
   hdl[p] = (uint32_t)p;
 }
 
 // ---------------------------------------------------------------------------
-// a2/a3 global levels: split every oversized segment by one 8-bit digit
+// a1 + a2, level 1: window-0 keys of every suffix (read-major, from the 2-bit
+// reads) counted by their top digit, then recomputed and scattered
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t find_seg(const uint32_t *tile_prefix, uint32_t nsegs, uint32_t tile) {
-  uint32_t lo = 0, hi = nsegs;
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (tile_prefix[mid] <= tile) lo = mid;
-    else hi = mid;
+__global__ __launch_bounds__(BLOCK) void k_gen_hist(const uint64_t *__restrict__ packed,
+                                                    const uint64_t *__restrict__ endbits, uint64_t nb,
+                                                    uint32_t *__restrict__ tile_hist) {
+  __shared__ uint32_t hist[256];
+  const uint32_t tile = blockIdx.x;
+  const uint64_t t0 = (uint64_t)tile * TILE;
+  const uint64_t t1 = min(t0 + (uint64_t)TILE, nb);
+  hist[threadIdx.x] = 0;
+  __syncthreads();
+  for (uint64_t p = t0 + threadIdx.x; p < t1; p += BLOCK) {
+    const uint64_t k = first_key(packed, endbits, nb, p);
+    atomicAdd(&hist[digit_of(k, 0)], 1u);
   }
-  return lo;
+  __syncthreads();
+  tile_hist[(uint64_t)tile * 256 + threadIdx.x] = hist[threadIdx.x];
 }
+
+// Stable scatter of `m` items held in registers to global positions
+// base[digit] + rank-within-tile, staged through LDS so that each digit's run
+// is written contiguously.
+struct ScatterSmem {
+  uint64_t sk[TILE];
+  uint32_t sh[TILE];
+  uint32_t wcount[WAVES * 256];
+  uint32_t dstart[256];
+  uint64_t goff[256];
+  uint32_t tmp[WAVES];
+};
+
+__device__ __forceinline__ void tile_scatter(ScatterSmem &S, const uint64_t (&kr)[TILE_ITEMS],
+                                             const uint32_t (&hr)[TILE_ITEMS], const uint32_t (&dig)[TILE_ITEMS],
+                                             uint32_t m, int d, uint64_t *__restrict__ Ko, uint32_t *__restrict__ Ho) {
+  uint32_t pos[TILE_ITEMS];
+  block_multisplit<TILE_ITEMS>(dig, pos, S.wcount, S.dstart, S.tmp);
+#pragma unroll
+  for (int i = 0; i < TILE_ITEMS; ++i) {
+    if (dig[i] != NODIGIT) {
+      S.sk[pos[i]] = kr[i];
+      S.sh[pos[i]] = hr[i];
+    }
+  }
+  __syncthreads();
+  for (uint32_t q = threadIdx.x; q < m; q += BLOCK) {
+    const uint64_t k = S.sk[q];
+    const uint32_t dd = digit_of(k, d);
+    const uint64_t g = S.goff[dd] + (q - S.dstart[dd]);
+    Ko[g] = k;
+    Ho[g] = S.sh[q];
+  }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_gen_scatter(const uint64_t *__restrict__ packed,
+                                                       const uint64_t *__restrict__ endbits, uint64_t nb,
+                                                       const uint32_t *__restrict__ tile_hist,
+                                                       const uint32_t *__restrict__ gsum, uint64_t *__restrict__ Ko,
+                                                       uint32_t *__restrict__ Ho) {
+  __shared__ ScatterSmem S;
+  const uint32_t tile = blockIdx.x;
+  const uint64_t t0 = (uint64_t)tile * TILE;
+  const uint32_t m = (uint32_t)min((uint64_t)TILE, nb - t0);
+  uint64_t kr[TILE_ITEMS];
+  uint32_t hr[TILE_ITEMS], dig[TILE_ITEMS];
+#pragma unroll
+  for (int i = 0; i < TILE_ITEMS; ++i) {
+    const uint32_t li = item_index<TILE_ITEMS>(i);
+    if (li < m) {
+      kr[i] = first_key(packed, endbits, nb, t0 + li);
+      hr[i] = (uint32_t)(t0 + li);
+      dig[i] = digit_of(kr[i], 0);
+    } else {
+      kr[i] = 0;
+      hr[i] = 0;
+      dig[i] = NODIGIT;
+    }
+  }
+  const uint32_t g = tile / GROUP_TILES;
+  S.goff[threadIdx.x] = (uint64_t)gsum[(uint64_t)g * 256 + threadIdx.x] + tile_hist[(uint64_t)tile * 256 + threadIdx.x];
+  tile_scatter(S, kr, hr, dig, m, 0, Ko, Ho);
+}
+
+// ---------------------------------------------------------------------------
+// a2/a3 levels 2..: split every oversized segment by one 8-bit digit
+// ---------------------------------------------------------------------------
 
 // Per-tile digit histogram and per-segment OR/AND of the ordering bits.  A
 // segment flagged `regather` first re-fetches its keys for window r.
@@ -395,8 +368,9 @@ __global__ __launch_bounds__(BLOCK) void k_level_hist(const Seg *__restrict__ se
                                                       uint32_t *__restrict__ tile_hist, unsigned long long *seg_or,
                                                       unsigned long long *seg_and) {
   __shared__ uint32_t hist[256];
+  __shared__ uint64_t red[WAVES];
   const uint32_t tile = blockIdx.x;
-  const uint32_t s = find_seg(tile_prefix, nsegs, tile);
+  const uint32_t s = find_upper(tile_prefix, nsegs, tile);
   const Seg sg = segs[s];
   const uint64_t t0 = sg.start + (uint64_t)(tile - tile_prefix[s]) * TILE;
   const uint64_t t1 = min(t0 + (uint64_t)TILE, sg.start + sg.len);
@@ -415,14 +389,41 @@ __global__ __launch_bounds__(BLOCK) void k_level_hist(const Seg *__restrict__ se
     o |= k;
     a &= k;
   }
-  o = wave_or(o);
-  a = wave_and(a);
-  if (lane_id() == 0) {
+  o = block_or(o, red);
+  a = block_and(a, red);
+  if (threadIdx.x == 0) {
     atomicOr(&seg_or[s], (unsigned long long)order_bits(o));
     atomicAnd(&seg_and[s], (unsigned long long)(a | 7ull));
   }
-  __syncthreads();
   tile_hist[(uint64_t)tile * 256 + threadIdx.x] = hist[threadIdx.x];
+}
+
+// First scan stage: inside each group of at most GROUP_TILES consecutive
+// tiles of one segment, turn tile counts into exclusive prefixes per digit
+// and record the group totals.
+__global__ __launch_bounds__(BLOCK) void k_group_scan(const uint32_t *__restrict__ tile_prefix,
+                                                      const uint32_t *__restrict__ group_prefix, uint32_t nsegs,
+                                                      uint32_t *__restrict__ tile_hist, uint32_t *__restrict__ gsum) {
+  const uint32_t g = blockIdx.x;
+  const uint32_t s = find_upper(group_prefix, nsegs, g);
+  const uint32_t tb = tile_prefix[s] + (g - group_prefix[s]) * GROUP_TILES;
+  const uint32_t te = min(tb + (uint32_t)GROUP_TILES, tile_prefix[s + 1]);
+  const uint32_t d = threadIdx.x;
+  uint32_t run = 0;
+  for (uint32_t t = tb; t < te; ++t) {
+    const uint64_t at = (uint64_t)t * 256 + d;
+    const uint32_t c = tile_hist[at];
+    tile_hist[at] = run;
+    run += c;
+  }
+  gsum[(uint64_t)g * 256 + d] = run;
+}
+
+__device__ void copy_out(Seg *list, uint32_t cap, const Seg *staged, uint32_t count, uint32_t base, uint32_t *status) {
+  for (uint32_t i = threadIdx.x; i < count; i += BLOCK) {
+    if (base + i < cap) list[base + i] = staged[i];
+    else atomicOr(status, ST_LIST_OVERFLOW);
+  }
 }
 
 __device__ void push_seg(Seg *list, uint32_t *count, uint32_t cap, const Seg &s, uint32_t *status) {
@@ -431,31 +432,34 @@ __device__ void push_seg(Seg *list, uint32_t *count, uint32_t cap, const Seg &s,
   else atomicOr(status, ST_LIST_OVERFLOW);
 }
 
-// One workgroup per segment: turn tile counts into scatter offsets and sort
-// the resulting buckets into: groups finished in LDS (packed into chunks of
-// at most CHUNK suffixes), segments for the next level, and final groups of
-// identical suffixes.  A segment whose current digit is constant is not
-// scattered; it moves to its first varying digit, or, when all its ordering
-// bits agree, to the next window (full tie) or to the final list (ended tie).
-__global__ __launch_bounds__(BLOCK) void k_level_scan(const Seg *__restrict__ segs, const uint32_t *__restrict__ tile_prefix,
-                                                      uint32_t *__restrict__ tile_hist,
+// Second scan stage, one workgroup per segment: digit totals from the group
+// totals, bucket starts, group bases.  The buckets are then sorted into runs
+// finished in LDS (chunks of at most CHUNK suffixes), segments for the next
+// level and final groups of identical suffixes.  A segment whose current
+// digit is constant is not scattered: it moves to its first varying digit,
+// or, when all its ordering bits agree, to the next window (a full tie) or
+// to the final list (an ended tie).
+__global__ __launch_bounds__(BLOCK) void k_level_scan(const Seg *__restrict__ segs, const uint32_t *__restrict__ group_prefix,
+                                                      uint32_t *__restrict__ gsum,
                                                       const unsigned long long *__restrict__ seg_or,
                                                       const unsigned long long *__restrict__ seg_and,
-                                                      uint8_t *__restrict__ seg_split, Lists L) {
+                                                      uint8_t *__restrict__ seg_split, Lists L, int force_split) {
   __shared__ uint32_t tot[256];
   __shared__ uint32_t bstart[256];
   __shared__ uint32_t tmp[WAVES];
   __shared__ int single;
+  __shared__ Seg st_chunk[256], st_big[256], st_fin[256];
+  __shared__ uint32_t cnt3[3], base3[3];
   const uint32_t s = blockIdx.x;
   const Seg sg = segs[s];
-  const uint32_t tp0 = tile_prefix[s], tp1 = tile_prefix[s + 1];
+  const uint32_t gp0 = group_prefix[s], gp1 = group_prefix[s + 1];
   const uint32_t dg = threadIdx.x;
   uint32_t total = 0;
-  for (uint32_t t = tp0; t < tp1; ++t) total += tile_hist[(uint64_t)t * 256 + dg];
+  for (uint32_t g = gp0; g < gp1; ++g) total += gsum[(uint64_t)g * 256 + dg];
   tot[dg] = total;
   if (dg == 0) single = 0;
   __syncthreads();
-  if ((uint64_t)total == sg.len) single = 1;
+  if ((uint64_t)total == sg.len && !force_split) single = 1;
   __syncthreads();
   if (single) {
     if (dg == 0) {
@@ -485,15 +489,19 @@ __global__ __launch_bounds__(BLOCK) void k_level_scan(const Seg *__restrict__ se
   const uint32_t ex = block_excl_sum(total, tmp, nullptr);
   bstart[dg] = ex;
   uint32_t run = (uint32_t)sg.start + ex;
-  for (uint32_t t = tp0; t < tp1; ++t) {
-    const uint64_t at = (uint64_t)t * 256 + dg;
-    const uint32_t c = tile_hist[at];
-    tile_hist[at] = run;
+  for (uint32_t g = gp0; g < gp1; ++g) {
+    const uint64_t at = (uint64_t)g * 256 + dg;
+    const uint32_t c = gsum[at];
+    gsum[at] = run;
     run += c;
   }
   __syncthreads();
+  // thread 0 classifies the buckets into LDS lists; one atomic per list
+  // reserves the global slots, then the workgroup copies the entries out
   if (dg == 0) {
     seg_split[s] = 1;
+    atomicAdd(L.scattered, (unsigned long long)sg.len);
+    uint32_t nc = 0, nbg = 0, nf = 0;
     Seg cur{};
     bool have = false;
     for (int b = 0; b < 256; ++b) {
@@ -502,67 +510,75 @@ __global__ __launch_bounds__(BLOCK) void k_level_scan(const Seg *__restrict__ se
       const uint64_t st = sg.start + bstart[b];
       if (c > (uint32_t)CHUNK) {
         if (have) {
-          push_seg(L.chunks, L.n_chunks, L.cap_chunks, cur, L.status);
+          st_chunk[nc++] = cur;
           have = false;
         }
         Seg nx{st, c, sg.r, (uint8_t)(sg.d + 1), (uint8_t)(sg.buf ^ 1), 0, 0};
         if (sg.d == 7) {
           // bucket value b is the clamped length; all ordering bits agree
           if (b < W) {
-            push_seg(L.finals, L.n_finals, L.cap_finals, nx, L.status);
+            st_fin[nf++] = nx;
           } else if (sg.r + 1 > L.rmax) {
             atomicOr(L.status, ST_WINDOW_BOUND);
           } else {
             nx.r = sg.r + 1;
             nx.d = 0;
             nx.regather = 1;
-            push_seg(L.big_next, L.n_big_next, L.cap_big, nx, L.status);
+            st_big[nbg++] = nx;
           }
         } else {
-          push_seg(L.big_next, L.n_big_next, L.cap_big, nx, L.status);
+          st_big[nbg++] = nx;
         }
         continue;
       }
       if (have && cur.len + c <= (uint64_t)CHUNK) {
         cur.len += c;
       } else {
-        if (have) push_seg(L.chunks, L.n_chunks, L.cap_chunks, cur, L.status);
+        if (have) st_chunk[nc++] = cur;
         cur = Seg{st, c, sg.r, sg.d, (uint8_t)(sg.buf ^ 1), 0, 0};
         have = true;
       }
     }
-    if (have) push_seg(L.chunks, L.n_chunks, L.cap_chunks, cur, L.status);
+    if (have) st_chunk[nc++] = cur;
+    cnt3[0] = nc;
+    cnt3[1] = nbg;
+    cnt3[2] = nf;
+    base3[0] = nc ? atomicAdd(L.n_chunks, nc) : 0u;
+    base3[1] = nbg ? atomicAdd(L.n_big_next, nbg) : 0u;
+    base3[2] = nf ? atomicAdd(L.n_finals, nf) : 0u;
   }
+  __syncthreads();
+  copy_out(L.chunks, L.cap_chunks, st_chunk, cnt3[0], base3[0], L.status);
+  copy_out(L.big_next, L.cap_big, st_big, cnt3[1], base3[1], L.status);
+  copy_out(L.finals, L.cap_finals, st_fin, cnt3[2], base3[2], L.status);
 }
 
-// Stable scatter of one tile by the segment's digit into the other buffer.
+// Stable scatter of one tile by its segment's digit into the other buffer.
 __global__ __launch_bounds__(BLOCK) void k_level_scatter(const Seg *__restrict__ segs,
-                                                         const uint32_t *__restrict__ tile_prefix, uint32_t nsegs,
+                                                         const uint32_t *__restrict__ tile_prefix,
+                                                         const uint32_t *__restrict__ group_prefix, uint32_t nsegs,
                                                          const uint8_t *__restrict__ seg_split,
-                                                         const uint32_t *__restrict__ tile_off, uint64_t *keys0,
+                                                         const uint32_t *__restrict__ tile_hist,
+                                                         const uint32_t *__restrict__ gsum, uint64_t *keys0,
                                                          uint64_t *keys1, uint32_t *hdl0, uint32_t *hdl1) {
-  __shared__ uint64_t sk[TILE];
-  __shared__ uint32_t sh[TILE];
-  __shared__ uint32_t wcount[WAVES * 256];
-  __shared__ uint32_t dstart[256];
-  __shared__ uint32_t goff[256];
-  __shared__ uint32_t tmp[WAVES];
+  __shared__ ScatterSmem S;
   const uint32_t tile = blockIdx.x;
-  const uint32_t s = find_seg(tile_prefix, nsegs, tile);
+  const uint32_t s = find_upper(tile_prefix, nsegs, tile);
   if (!seg_split[s]) return;
   const Seg sg = segs[s];
-  const uint64_t t0 = sg.start + (uint64_t)(tile - tile_prefix[s]) * TILE;
+  const uint32_t tl = tile - tile_prefix[s];
+  const uint64_t t0 = sg.start + (uint64_t)tl * TILE;
   const uint32_t m = (uint32_t)min((uint64_t)TILE, sg.start + sg.len - t0);
   const uint64_t *Ki = sg.buf ? keys1 : keys0;
   const uint32_t *Hi = sg.buf ? hdl1 : hdl0;
   uint64_t *Ko = sg.buf ? keys0 : keys1;
   uint32_t *Ho = sg.buf ? hdl0 : hdl1;
   const int d = sg.d;
-  uint64_t kr[ITEMS];
-  uint32_t hr[ITEMS], dig[ITEMS], pos[ITEMS];
+  uint64_t kr[TILE_ITEMS];
+  uint32_t hr[TILE_ITEMS], dig[TILE_ITEMS];
 #pragma unroll
-  for (int i = 0; i < ITEMS; ++i) {
-    const uint32_t li = item_index(i);
+  for (int i = 0; i < TILE_ITEMS; ++i) {
+    const uint32_t li = item_index<TILE_ITEMS>(i);
     if (li < m) {
       kr[i] = Ki[t0 + li];
       hr[i] = Hi[t0 + li];
@@ -573,39 +589,26 @@ __global__ __launch_bounds__(BLOCK) void k_level_scatter(const Seg *__restrict__
       dig[i] = NODIGIT;
     }
   }
-  goff[threadIdx.x] = tile_off[(uint64_t)tile * 256 + threadIdx.x];
-  block_multisplit(dig, pos, wcount, dstart, tmp);
-#pragma unroll
-  for (int i = 0; i < ITEMS; ++i) {
-    if (dig[i] != NODIGIT) {
-      sk[pos[i]] = kr[i];
-      sh[pos[i]] = hr[i];
-    }
-  }
-  __syncthreads();
-  for (uint32_t q = threadIdx.x; q < m; q += BLOCK) {
-    const uint64_t k = sk[q];
-    const uint32_t dd = digit_of(k, d);
-    const uint64_t g = (uint64_t)goff[dd] + (q - dstart[dd]);
-    Ko[g] = k;
-    Ho[g] = sh[q];
-  }
+  const uint32_t g = group_prefix[s] + tl / GROUP_TILES;
+  S.goff[threadIdx.x] = (uint64_t)gsum[(uint64_t)g * 256 + threadIdx.x] + tile_hist[(uint64_t)tile * 256 + threadIdx.x];
+  tile_scatter(S, kr, hr, dig, m, d, Ko, Ho);
 }
 
 // Groups of identical suffixes too large for one workgroup: emit in place.
 __global__ __launch_bounds__(BLOCK) void k_emit_final(const Seg *__restrict__ segs, const uint32_t *__restrict__ tile_prefix,
                                                       uint32_t nsegs, const uint64_t *__restrict__ keys0,
                                                       const uint64_t *__restrict__ keys1, const uint32_t *__restrict__ hdl0,
-                                                      const uint32_t *__restrict__ hdl1, const uint64_t *__restrict__ offsets,
-                                                      uint64_t n, uint8_t *__restrict__ bwt, uint64_t *__restrict__ term_pos) {
+                                                      const uint32_t *__restrict__ hdl1, const uint64_t *__restrict__ endbits,
+                                                      const uint32_t *__restrict__ ebrank, uint64_t n,
+                                                      uint8_t *__restrict__ bwt, uint64_t *__restrict__ start_row) {
   const uint32_t tile = blockIdx.x;
-  const uint32_t s = find_seg(tile_prefix, nsegs, tile);
+  const uint32_t s = find_upper(tile_prefix, nsegs, tile);
   const Seg sg = segs[s];
   const uint64_t t0 = sg.start + (uint64_t)(tile - tile_prefix[s]) * TILE;
   const uint64_t t1 = min(t0 + (uint64_t)TILE, sg.start + sg.len);
   const uint64_t *K = sg.buf ? keys1 : keys0;
   const uint32_t *H = sg.buf ? hdl1 : hdl0;
-  for (uint64_t j = t0 + threadIdx.x; j < t1; j += BLOCK) emit_row(n + j, K[j], H[j], offsets, n, bwt, term_pos);
+  for (uint64_t j = t0 + threadIdx.x; j < t1; j += BLOCK) emit_row(n + j, K[j], H[j], endbits, ebrank, bwt, start_row);
 }
 
 // ---------------------------------------------------------------------------
@@ -614,11 +617,11 @@ __global__ __launch_bounds__(BLOCK) void k_emit_final(const Seg *__restrict__ se
 struct LocalSmem {
   uint64_t K[2][CHUNK];
   uint32_t H[2][CHUNK];
-  uint16_t G[2][CHUNK];      // group start carried through composite passes
-  uint16_t gr[CHUNK];        // group rank of each position
-  uint16_t hp[CHUNK + 1];    // start of each group
-  uint8_t head[CHUNK];       // position starts a group
-  uint8_t fin[CHUNK];        // position's group is final
+  uint16_t G[2][CHUNK];    // group start carried through composite passes
+  uint16_t gr[CHUNK];      // group rank of each position
+  uint16_t hp[CHUNK + 1];  // start of each group
+  uint8_t head[CHUNK];     // position starts a group
+  uint8_t fin[CHUNK];      // position's group is final
   uint32_t wcount[WAVES * 256];
   uint32_t dstart[256];
   uint32_t tmp[WAVES];
@@ -626,18 +629,16 @@ struct LocalSmem {
   uint32_t scan_tmp[WAVES];
 };
 
-// Stable LDS pass of m items from buffer `src` to 1-src by digit `sel`:
-// 0..7 key digits (items whose group is final contribute digit 0 when
-// zero_final is set, through their zeroed ordering bits), 8/9 the low/high
-// byte of the carried group start.
+// Stable LDS pass of m items from buffer `src` to src^1 by digit `sel`:
+// 0..7 key digits, 8/9 the low/high byte of the carried group start.
 template <bool WITH_G>
 __device__ void lds_pass(LocalSmem &S, int src, uint32_t m, int sel) {
-  uint64_t kr[ITEMS];
-  uint32_t hr[ITEMS], dig[ITEMS], pos[ITEMS];
-  uint16_t gg[ITEMS];
+  uint64_t kr[LOCAL_ITEMS];
+  uint32_t hr[LOCAL_ITEMS], dig[LOCAL_ITEMS], pos[LOCAL_ITEMS];
+  uint16_t gg[LOCAL_ITEMS];
 #pragma unroll
-  for (int i = 0; i < ITEMS; ++i) {
-    const uint32_t li = item_index(i);
+  for (int i = 0; i < LOCAL_ITEMS; ++i) {
+    const uint32_t li = item_index<LOCAL_ITEMS>(i);
     if (li < m) {
       kr[i] = S.K[src][li];
       hr[i] = S.H[src][li];
@@ -652,9 +653,9 @@ __device__ void lds_pass(LocalSmem &S, int src, uint32_t m, int sel) {
       dig[i] = NODIGIT;
     }
   }
-  block_multisplit(dig, pos, S.wcount, S.dstart, S.tmp);
+  block_multisplit<LOCAL_ITEMS>(dig, pos, S.wcount, S.dstart, S.tmp);
 #pragma unroll
-  for (int i = 0; i < ITEMS; ++i) {
+  for (int i = 0; i < LOCAL_ITEMS; ++i) {
     if (dig[i] != NODIGIT) {
       S.K[src ^ 1][pos[i]] = kr[i];
       S.H[src ^ 1][pos[i]] = hr[i];
@@ -664,14 +665,16 @@ __device__ void lds_pass(LocalSmem &S, int src, uint32_t m, int sel) {
   __syncthreads();
 }
 
-__global__ __launch_bounds__(BLOCK) void k_local(const Seg *__restrict__ chunks, const uint64_t *__restrict__ keys0,
-                                                 const uint64_t *__restrict__ keys1, const uint32_t *__restrict__ hdl0,
-                                                 const uint32_t *__restrict__ hdl1, const uint64_t *__restrict__ packed,
-                                                 const uint64_t *__restrict__ endbits, const uint64_t *__restrict__ offsets,
-                                                 uint64_t n, uint64_t nb, uint32_t rmax, uint8_t *__restrict__ bwt,
-                                                 uint64_t *__restrict__ term_pos, uint32_t *status) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  LocalSmem &S = *reinterpret_cast<LocalSmem *>(smem_raw);
+// two workgroups per CU at 8 items per thread, four at 4, eight at 2
+__global__ __launch_bounds__(BLOCK, 16 / LOCAL_ITEMS) void k_local(const Seg *__restrict__ chunks, const uint64_t *__restrict__ keys0,
+                                                    const uint64_t *__restrict__ keys1, const uint32_t *__restrict__ hdl0,
+                                                    const uint32_t *__restrict__ hdl1, const uint64_t *__restrict__ packed,
+                                                    const uint64_t *__restrict__ endbits,
+                                                    const uint32_t *__restrict__ ebrank, uint64_t n, uint64_t nb,
+                                                    uint32_t rmax, uint8_t *__restrict__ bwt,
+                                                    uint64_t *__restrict__ start_row, uint32_t *status,
+                                                    unsigned long long *fetches) {
+  __shared__ LocalSmem S;
   const Seg ch = chunks[blockIdx.x];
   const uint32_t m = (uint32_t)ch.len;
   const uint64_t *Kg = ch.buf ? keys1 : keys0;
@@ -682,44 +685,36 @@ __global__ __launch_bounds__(BLOCK) void k_local(const Seg *__restrict__ chunks,
   }
   __syncthreads();
   int cur = 0;
-  // sort by the digits d..7 that vary inside the chunk (least significant first)
-  {
-    uint64_t o = 0, a = ~0ull;
-    for (uint32_t j = threadIdx.x; j < m; j += BLOCK) {
-      o |= S.K[0][j];
-      a &= S.K[0][j];
-    }
-    o = block_or(o, S.tmp64);
-    a = block_and(a, S.tmp64);
-    const uint64_t diff = (o ^ a) & ~7ull;
-    for (int j = 7; j >= (int)ch.d; --j) {
-      if (diff & digit_mask(j)) {
-        lds_pass<false>(S, cur, m, j);
-        cur ^= 1;
-      }
-    }
+  // The chunk is a run of buckets that differ in digit d and agree before
+  // it.  Each bucket is a group still to be sorted on its current key; after
+  // that, groups are runs of equal keys, refined window by window.
+  const int d0 = ch.d;
+  if (ch.unsplit) {
+    lds_pass<false>(S, cur, m, d0);
+    cur ^= 1;
   }
-  // refinement of ties, window by window
   for (uint32_t j = threadIdx.x; j < m; j += BLOCK) {
-    S.head[j] = (j == 0) || (order_bits(S.K[cur][j]) != order_bits(S.K[cur][j - 1]));
+    S.head[j] = (j == 0) || (digit_of(S.K[cur][j], d0) != digit_of(S.K[cur][j - 1], d0));
     S.fin[j] = 0;
   }
   __syncthreads();
   uint32_t r = ch.r;
+  uint32_t nfetch = 0;
+  bool fetch_round = false;
   for (;;) {
     // group ranks (inclusive count of heads - 1) and group starts
     {
-      const uint32_t base = threadIdx.x * ITEMS;
+      const uint32_t base = threadIdx.x * LOCAL_ITEMS;
       uint32_t cnt = 0;
 #pragma unroll
-      for (int i = 0; i < ITEMS; ++i) {
+      for (int i = 0; i < LOCAL_ITEMS; ++i) {
         const uint32_t j = base + i;
         if (j < m) cnt += S.head[j];
       }
       uint32_t total;
       uint32_t pre = block_excl_sum(cnt, S.scan_tmp, &total);
 #pragma unroll
-      for (int i = 0; i < ITEMS; ++i) {
+      for (int i = 0; i < LOCAL_ITEMS; ++i) {
         const uint32_t j = base + i;
         if (j < m) {
           pre += S.head[j];
@@ -727,31 +722,46 @@ __global__ __launch_bounds__(BLOCK) void k_local(const Seg *__restrict__ chunks,
           if (S.head[j]) S.hp[pre - 1] = (uint16_t)j;
         }
       }
-      if (threadIdx.x == 0) S.hp[total] = (uint16_t)m;  // m <= CHUNK fits when CHUNK <= 65535
+      if (threadIdx.x == 0) S.hp[total] = (uint16_t)m;
     }
     __syncthreads();
+    // a group is finished when it is a single suffix, or (after the first
+    // sort) when its equal keys end inside the window: identical suffixes
     uint32_t live_max = 0;
     for (uint32_t j = threadIdx.x; j < m; j += BLOCK) {
       if (S.fin[j]) continue;
       const uint32_t g = S.gr[j];
-      const uint32_t a = S.hp[g], e = S.hp[g + 1];
-      if (e - a == 1 || clamp_of(S.K[cur][a]) < (uint32_t)W) S.fin[j] = 1;
-      else live_max = max(live_max, e - a);
+      const uint32_t size = (uint32_t)S.hp[g + 1] - S.hp[g];
+      if (size == 1 || (fetch_round && clamp_of(S.K[cur][j]) < (uint32_t)W)) S.fin[j] = 1;
+      else live_max = max(live_max, size);
     }
     live_max = block_max(live_max, S.tmp);
     if (live_max == 0) break;
-    if (r + 1 > rmax) {
-      if (threadIdx.x == 0) atomicOr(status, ST_WINDOW_BOUND);
-      break;
+    if (fetch_round) {
+      if (r + 1 > rmax) {
+        if (threadIdx.x == 0) atomicOr(status, ST_WINDOW_BOUND);
+        break;
+      }
+      ++r;
+      // fetch the next window of every live suffix: all loads first
+      WinWords ww[LOCAL_ITEMS];
+      bool act[LOCAL_ITEMS];
+#pragma unroll
+      for (int i = 0; i < LOCAL_ITEMS; ++i) {
+        const uint32_t j = threadIdx.x + i * BLOCK;
+        act[i] = j < m && !S.fin[j];
+        if (act[i]) ww[i] = window_load(packed, endbits, nb, S.H[cur][j], r);
+      }
+#pragma unroll
+      for (int i = 0; i < LOCAL_ITEMS; ++i) {
+        const uint32_t j = threadIdx.x + i * BLOCK;
+        if (act[i]) {
+          S.K[cur][j] = window_combine(ww[i], nb, S.H[cur][j], r, (uint32_t)S.K[cur][j] & 7u);
+          ++nfetch;
+        }
+      }
+      __syncthreads();
     }
-    ++r;
-    // fetch the next window of every live suffix
-    for (uint32_t j = threadIdx.x; j < m; j += BLOCK) {
-      if (S.fin[j]) continue;
-      const uint64_t k = S.K[cur][j];
-      S.K[cur][j] = window_key(packed, endbits, nb, S.H[cur][j], r, (uint32_t)k & 7u);
-    }
-    __syncthreads();
     if (live_max <= (uint32_t)RANK_COUNT_MAX) {
       // stable rank inside each live group by all-pairs comparison
       for (uint32_t j = threadIdx.x; j < m; j += BLOCK) {
@@ -764,10 +774,24 @@ __global__ __launch_bounds__(BLOCK) void k_local(const Seg *__restrict__ chunks,
         const uint32_t g = S.gr[j];
         const uint32_t a = S.hp[g], e = S.hp[g + 1];
         const uint64_t oj = order_bits(kj);
+        // rank = #{t < j : key_t <= key_j} + #{t > j : key_t < key_j} (t = j
+        // adds nothing); four independent LDS reads per step keep the loop
+        // off the load-latency chain
         uint32_t c = 0;
-        for (uint32_t t = a; t < e; ++t) {
+        uint32_t t = a;
+        for (; t + 4 <= e; t += 4) {
+          const uint64_t o0 = order_bits(S.K[cur][t]);
+          const uint64_t o1 = order_bits(S.K[cur][t + 1]);
+          const uint64_t o2 = order_bits(S.K[cur][t + 2]);
+          const uint64_t o3 = order_bits(S.K[cur][t + 3]);
+          c += (t < j) ? (o0 <= oj) : (o0 < oj);
+          c += (t + 1 < j) ? (o1 <= oj) : (o1 < oj);
+          c += (t + 2 < j) ? (o2 <= oj) : (o2 < oj);
+          c += (t + 3 < j) ? (o3 <= oj) : (o3 < oj);
+        }
+        for (; t < e; ++t) {
           const uint64_t ot = order_bits(S.K[cur][t]);
-          c += (ot < oj) || (ot == oj && t < j);
+          c += (t < j) ? (ot <= oj) : (ot < oj);
         }
         S.K[cur ^ 1][a + c] = kj;
         S.H[cur ^ 1][a + c] = S.H[cur][j];
@@ -775,10 +799,11 @@ __global__ __launch_bounds__(BLOCK) void k_local(const Seg *__restrict__ chunks,
       __syncthreads();
       cur ^= 1;
     } else {
-      // composite stable LSD: new key digits, then the group start
+      // composite stable LSD over the whole chunk: key digits, then the
+      // group start (finished groups have zeroed ordering bits and stay put)
       for (uint32_t j = threadIdx.x; j < m; j += BLOCK) {
         S.G[cur][j] = S.hp[S.gr[j]];
-        if (S.fin[j]) S.K[cur][j] &= 7ull;  // final groups keep their place
+        if (S.fin[j]) S.K[cur][j] &= 7ull;
       }
       __syncthreads();
       uint64_t o = 0, a = ~0ull;
@@ -800,48 +825,57 @@ __global__ __launch_bounds__(BLOCK) void k_local(const Seg *__restrict__ chunks,
       lds_pass<true>(S, cur, m, 9);
       cur ^= 1;
     }
-    // new group heads inside live groups
+    // new group heads inside live groups: changes of the full key
     for (uint32_t j = threadIdx.x; j < m; j += BLOCK) {
       if (S.fin[j]) continue;
       const uint32_t a = S.hp[S.gr[j]];
       if (j > a && order_bits(S.K[cur][j]) != order_bits(S.K[cur][j - 1])) S.head[j] = 1;
     }
     __syncthreads();
+    fetch_round = true;
   }
   // a4: emit
   for (uint32_t j = threadIdx.x; j < m; j += BLOCK)
-    emit_row(n + ch.start + j, S.K[cur][j], S.H[cur][j], offsets, n, bwt, term_pos);
+    emit_row(n + ch.start + j, S.K[cur][j], S.H[cur][j], endbits, ebrank, bwt, start_row);
+  nfetch = wave_incl_sum(nfetch);
+  if (lane_id() == 63 && nfetch) atomicAdd(fetches, (unsigned long long)nfetch);
 }
+
+static_assert(CHUNK <= 65535, "group starts are 16-bit");
+static_assert(sizeof(LocalSmem) * (16 / LOCAL_ITEMS) <= 160 * 1024, "chunk workgroups per CU fit the LDS");
 
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 thread_local cxbwt_stats g_stats;
+thread_local int g_timing = 0;
 
 inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 inline uint64_t align_up(uint64_t x) { return (x + 255) & ~255ull; }
 
 struct Layout {
-  uint64_t keys0, keys1, hdl0, hdl1, endbits, tile_hist, segs, tile_prefix, seg_or, seg_and, seg_split, big_next,
-      chunks, finals, counters, total;
-  uint64_t cap_big, cap_chunks, cap_finals, max_tiles, endbit_words;
+  uint64_t keys0, keys1, hdl0, hdl1, endbits, ebrank, rank_blocks, start_row, tile_hist, gsum, segs, tile_prefix,
+      group_prefix, seg_or, seg_and, seg_split, big_next, chunks, finals, counters, total;
+  uint64_t cap_big, cap_chunks, cap_finals, max_tiles, max_groups, endbit_words, n_rank_blocks;
 };
 
 bool sizes_ok(uint64_t n_reads, uint64_t n_bases, uint32_t max_read_len) {
   return n_reads >= 1 && n_reads < (1ull << 32) && n_bases <= CXBWT_MAX_BASES && max_read_len <= CXBWT_MAX_READ_LEN;
 }
 
-Layout make_layout(uint64_t n_reads, uint64_t nb, uint32_t maxlen) {
-  (void)n_reads;
+Layout make_layout(uint64_t n_reads, uint64_t nb) {
   Layout L{};
-  const uint64_t windows = (uint64_t)maxlen / W + 2;
+  // segments of one level are disjoint and each holds more than CHUNK suffixes
   L.cap_big = nb / (CHUNK + 1) + 2;
   L.cap_finals = L.cap_big;
-  // every chunk but the last of a run holds more than CHUNK/2 suffixes on
-  // average with its successor; runs end at a big bucket or a parent's end
-  L.cap_chunks = 2 * ceil_div(nb, CHUNK) + 2 * (8 * windows + 1) * L.cap_big + 2;
+  // chunks of one level: two neighbouring chunks of a run hold more than
+  // CHUNK suffixes together, and a run ends at an oversized bucket or at the
+  // end of its parent (both at most cap_big per level)
+  L.cap_chunks = 2 * ceil_div(nb, CHUNK) + 2 * L.cap_big + 2;
   L.max_tiles = ceil_div(nb, TILE) + L.cap_big + 1;
+  L.max_groups = ceil_div(L.max_tiles, GROUP_TILES) + L.cap_big + 1;
   L.endbit_words = nb / 64 + 2;
+  L.n_rank_blocks = ceil_div(L.endbit_words, RANK_BLOCK_WORDS);
   uint64_t off = 0;
   auto take = [&](uint64_t bytes) {
     uint64_t at = off;
@@ -853,9 +887,14 @@ Layout make_layout(uint64_t n_reads, uint64_t nb, uint32_t maxlen) {
   L.hdl0 = take(4 * nb);
   L.hdl1 = take(4 * nb);
   L.endbits = take(8 * L.endbit_words);
+  L.ebrank = take(4 * L.endbit_words);
+  L.rank_blocks = take(4 * L.n_rank_blocks);
+  L.start_row = take(8 * n_reads);
   L.tile_hist = take(4 * 256 * L.max_tiles);
+  L.gsum = take(4 * 256 * L.max_groups);
   L.segs = take(sizeof(Seg) * L.cap_big);
   L.tile_prefix = take(4 * (L.cap_big + 1));
+  L.group_prefix = take(4 * (L.cap_big + 1));
   L.seg_or = take(8 * L.cap_big);
   L.seg_and = take(8 * L.cap_big);
   L.seg_split = take(L.cap_big);
@@ -867,12 +906,12 @@ Layout make_layout(uint64_t n_reads, uint64_t nb, uint32_t maxlen) {
   return L;
 }
 
-#define CX_CHECK(x)                                  \
-  do {                                               \
-    if ((x) != hipSuccess) return CXBWT_EDEVICE;     \
+#define CX_CHECK(x)                              \
+  do {                                           \
+    if ((x) != hipSuccess) return CXBWT_EDEVICE; \
   } while (0)
-#define CX_LAUNCHED()                                \
-  do {                                               \
+#define CX_LAUNCHED()                                          \
+  do {                                                         \
     if (hipGetLastError() != hipSuccess) return CXBWT_EDEVICE; \
   } while (0)
 
@@ -900,117 +939,288 @@ int fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st) {
   return CXBWT_OK;
 }
 
-// counters block layout (uint32 slots)
-enum { C_STATUS = 0, C_NBIG = 1, C_NCHUNK = 2, C_NFINAL = 3, C_COUNT = 16 };
+// Kernel classes timed by PhaseTimer (indices of cxbwt_stats.ms).
+enum Phase { PH_PREP = 0, PH_GEN, PH_HIST, PH_SCAN, PH_SCATTER, PH_LOCAL, PH_FINAL };
+
+// Brackets kernel launches with HIP events on the build's stream when timing
+// is on; durations are summed at the host synchronisation points.
+struct PhaseTimer {
+  hipStream_t st;
+  bool on;
+  struct Pending {
+    int phase;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  hipEvent_t open_ev = nullptr;
+  static std::vector<hipEvent_t> &pool() {
+    thread_local std::vector<hipEvent_t> p;
+    return p;
+  }
+  hipEvent_t get() {
+    auto &p = pool();
+    if (!p.empty()) {
+      hipEvent_t e = p.back();
+      p.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  void begin() {
+    if (!on) return;
+    open_ev = get();
+    if (open_ev) (void)hipEventRecord(open_ev, st);
+  }
+  void end(int phase) {
+    if (!on || !open_ev) return;
+    hipEvent_t b = get();
+    if (!b) return;
+    (void)hipEventRecord(b, st);
+    pending.push_back({phase, open_ev, b});
+    open_ev = nullptr;
+  }
+  // call only after the stream has been synchronised
+  void collect() {
+    for (auto &q : pending) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, q.a, q.b) == hipSuccess) g_stats.ms[q.phase] += ms;
+      g_stats.launches[q.phase]++;
+      pool().push_back(q.a);
+      pool().push_back(q.b);
+    }
+    pending.clear();
+  }
+  ~PhaseTimer() {
+    for (auto &q : pending) {
+      pool().push_back(q.a);
+      pool().push_back(q.b);
+    }
+    if (open_ev) pool().push_back(open_ev);
+  }
+};
+
+// counters block layout (uint32 slots; 64-bit counters on even slots)
+enum { C_STATUS = 0, C_NBIG = 1, C_NCHUNK = 2, C_NFINAL = 3, C_FETCH = 8, C_SCATTERED = 10, C_COUNT = 16 };
+
+struct Buffers {
+  uint64_t *keys0, *keys1, *endbits, *start_row;
+  uint32_t *hdl0, *hdl1, *ebrank, *rank_blocks, *tile_hist, *gsum, *tile_prefix, *group_prefix, *counters;
+  Seg *segs, *big_next, *chunks, *finals;
+  unsigned long long *seg_or, *seg_and;
+  uint8_t *seg_split;
+};
+
+// Finish the chunks and final groups a level produced.
+int finish_level(const Buffers &B, const Layout &Lo, const uint64_t *packed, const uint64_t *offsets, uint64_t n,
+                 uint64_t nb, uint32_t rmax, uint8_t *bwt, uint64_t *term_pos, uint32_t n_chunks, uint32_t n_finals,
+                 std::vector<uint32_t> &tprefix, PhaseTimer &T, hipStream_t st) {
+  if (n_chunks > Lo.cap_chunks || n_finals > Lo.cap_finals) return CXBWT_EDEVICE;
+  if (n_chunks) {
+    T.begin();
+    k_local<<<n_chunks, BLOCK, 0, st>>>(B.chunks, B.keys0, B.keys1, B.hdl0, B.hdl1, packed, B.endbits, B.ebrank, n, nb,
+                                        rmax, bwt, B.start_row, B.counters + C_STATUS,
+                                        (unsigned long long *)(B.counters + C_FETCH));
+    CX_LAUNCHED();
+    T.end(PH_LOCAL);
+    g_stats.chunks += n_chunks;
+  }
+  if (n_finals) {
+    std::vector<Seg> fin(n_finals);
+    CX_CHECK(hipMemcpyAsync(fin.data(), B.finals, sizeof(Seg) * n_finals, hipMemcpyDeviceToHost, st));
+    CX_CHECK(hipStreamSynchronize(st));
+    tprefix.assign(n_finals + 1, 0);
+    uint64_t suffixes = 0;
+    for (uint32_t i = 0; i < n_finals; ++i) {
+      tprefix[i + 1] = tprefix[i] + (uint32_t)ceil_div(fin[i].len, TILE);
+      suffixes += fin[i].len;
+    }
+    CX_CHECK(hipMemcpyAsync(B.tile_prefix, tprefix.data(), 4 * (n_finals + 1), hipMemcpyHostToDevice, st));
+    T.begin();
+    k_emit_final<<<tprefix[n_finals], BLOCK, 0, st>>>(B.finals, B.tile_prefix, n_finals, B.keys0, B.keys1, B.hdl0,
+                                                      B.hdl1, B.endbits, B.ebrank, n, bwt, B.start_row);
+    CX_LAUNCHED();
+    T.end(PH_FINAL);
+    g_stats.final_big += n_finals;
+    g_stats.chunk_suffixes -= suffixes;
+  }
+  return CXBWT_OK;
+}
 
 int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint64_t nb, uint32_t maxlen, uint8_t *bwt,
               uint64_t *term_pos, unsigned char *ws, hipStream_t st) {
   g_stats = cxbwt_stats{};
-  const Layout Lo = make_layout(n, nb, maxlen);
-  uint64_t *keys0 = (uint64_t *)(ws + Lo.keys0);
-  uint64_t *keys1 = (uint64_t *)(ws + Lo.keys1);
-  uint32_t *hdl0 = (uint32_t *)(ws + Lo.hdl0);
-  uint32_t *hdl1 = (uint32_t *)(ws + Lo.hdl1);
-  uint64_t *endbits = (uint64_t *)(ws + Lo.endbits);
-  uint32_t *tile_hist = (uint32_t *)(ws + Lo.tile_hist);
-  Seg *segs = (Seg *)(ws + Lo.segs);
-  uint32_t *tile_prefix = (uint32_t *)(ws + Lo.tile_prefix);
-  unsigned long long *seg_or = (unsigned long long *)(ws + Lo.seg_or);
-  unsigned long long *seg_and = (unsigned long long *)(ws + Lo.seg_and);
-  uint8_t *seg_split = (uint8_t *)(ws + Lo.seg_split);
-  Seg *big_next = (Seg *)(ws + Lo.big_next);
-  Seg *chunks = (Seg *)(ws + Lo.chunks);
-  Seg *finals = (Seg *)(ws + Lo.finals);
-  uint32_t *counters = (uint32_t *)(ws + Lo.counters);
+  PhaseTimer T{st, g_timing != 0, {}};
+  const Layout Lo = make_layout(n, nb);
+  Buffers B;
+  B.keys0 = (uint64_t *)(ws + Lo.keys0);
+  B.keys1 = (uint64_t *)(ws + Lo.keys1);
+  B.hdl0 = (uint32_t *)(ws + Lo.hdl0);
+  B.hdl1 = (uint32_t *)(ws + Lo.hdl1);
+  B.endbits = (uint64_t *)(ws + Lo.endbits);
+  B.ebrank = (uint32_t *)(ws + Lo.ebrank);
+  B.rank_blocks = (uint32_t *)(ws + Lo.rank_blocks);
+  B.start_row = (uint64_t *)(ws + Lo.start_row);
+  B.tile_hist = (uint32_t *)(ws + Lo.tile_hist);
+  B.gsum = (uint32_t *)(ws + Lo.gsum);
+  B.segs = (Seg *)(ws + Lo.segs);
+  B.tile_prefix = (uint32_t *)(ws + Lo.tile_prefix);
+  B.group_prefix = (uint32_t *)(ws + Lo.group_prefix);
+  B.seg_or = (unsigned long long *)(ws + Lo.seg_or);
+  B.seg_and = (unsigned long long *)(ws + Lo.seg_and);
+  B.seg_split = (uint8_t *)(ws + Lo.seg_split);
+  B.big_next = (Seg *)(ws + Lo.big_next);
+  B.chunks = (Seg *)(ws + Lo.chunks);
+  B.finals = (Seg *)(ws + Lo.finals);
+  B.counters = (uint32_t *)(ws + Lo.counters);
   const uint32_t rmax = maxlen / W + 1;
+  uint32_t *counters = B.counters;
 
   int rc;
   if ((rc = fill_u32(counters, C_COUNT, 0, st))) return rc;
-  if ((rc = fill_u64(endbits, Lo.endbit_words, 0, st))) return rc;
-  k_prep<<<grid_for(n, 256), 256, 0, st>>>(packed, offsets, n, nb, maxlen, (unsigned long long *)endbits, bwt, term_pos,
-                                          counters + C_STATUS);
+  if ((rc = fill_u64(B.endbits, Lo.endbit_words, 0, st))) return rc;
+  T.begin();
+  k_prep<<<grid_for(n, 256), 256, 0, st>>>(packed, offsets, n, nb, maxlen, (unsigned long long *)B.endbits, bwt,
+                                          term_pos, counters + C_STATUS);
   CX_LAUNCHED();
+  T.end(PH_PREP);
   uint32_t hc[C_COUNT];
   CX_CHECK(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, st));
   CX_CHECK(hipStreamSynchronize(st));
+  T.collect();
   if (hc[C_STATUS] & (ST_BAD_OFFSETS | ST_TOO_LONG)) return CXBWT_EDATA;
   if (nb == 0) return CXBWT_OK;
-
-  k_gen<<<grid_for(nb, BLOCK), BLOCK, 0, st>>>(packed, endbits, nb, keys0, hdl0);
+  g_stats.chunk_suffixes = nb;
+  // ranks of the read ends, for term_pos
+  T.begin();
+  k_rank_count<<<(unsigned)Lo.n_rank_blocks, BLOCK, 0, st>>>(B.endbits, Lo.endbit_words, B.rank_blocks);
   CX_LAUNCHED();
+  k_rank_top<<<1, BLOCK, 0, st>>>(B.rank_blocks, (uint32_t)Lo.n_rank_blocks);
+  CX_LAUNCHED();
+  k_rank_words<<<(unsigned)Lo.n_rank_blocks, BLOCK, 0, st>>>(B.endbits, Lo.endbit_words, B.rank_blocks, B.ebrank);
+  CX_LAUNCHED();
+  T.end(PH_PREP);
 
-  Lists Ls{big_next, counters + C_NBIG, (uint32_t)Lo.cap_big, chunks, counters + C_NCHUNK, (uint32_t)Lo.cap_chunks,
-           finals, counters + C_NFINAL, (uint32_t)Lo.cap_finals, counters + C_STATUS, rmax};
-  std::vector<Seg> big;
-  uint32_t n_chunks = 0;
-  if (nb > (uint64_t)CHUNK) {
-    big.push_back(Seg{0, nb, 0, 0, 0, 0, 0});
+  Lists Ls{B.big_next, counters + C_NBIG, (uint32_t)Lo.cap_big, B.chunks, counters + C_NCHUNK, (uint32_t)Lo.cap_chunks,
+           B.finals, counters + C_NFINAL, (uint32_t)Lo.cap_finals, counters + C_STATUS, rmax,
+           (unsigned long long *)(counters + C_SCATTERED)};
+  std::vector<uint32_t> tprefix, gprefix;
+
+  if (nb <= (uint64_t)CHUNK) {
+    // one workgroup finishes everything
+    T.begin();
+    k_gen<<<grid_for(nb, BLOCK), BLOCK, 0, st>>>(packed, B.endbits, nb, B.keys0, B.hdl0);
+    CX_LAUNCHED();
+    T.end(PH_GEN);
+    Seg one{0, nb, 0, 0, 0, 0, 1};
+    CX_CHECK(hipMemcpyAsync(B.chunks, &one, sizeof(Seg), hipMemcpyHostToDevice, st));
+    if ((rc = finish_level(B, Lo, packed, offsets, n, nb, rmax, bwt, term_pos, 1, 0, tprefix, T, st))) return rc;
   } else {
-    Seg one{0, nb, 0, 0, 0, 0, 0};
-    CX_CHECK(hipMemcpyAsync(chunks, &one, sizeof(Seg), hipMemcpyHostToDevice, st));
-    n_chunks = 1;
-  }
-  std::vector<uint32_t> tprefix;
-  while (!big.empty()) {
-    const uint32_t ns = (uint32_t)big.size();
-    if (ns > Lo.cap_big) return CXBWT_EDEVICE;
-    tprefix.assign(ns + 1, 0);
-    for (uint32_t i = 0; i < ns; ++i) tprefix[i + 1] = tprefix[i] + (uint32_t)ceil_div(big[i].len, TILE);
-    const uint32_t ntiles = tprefix[ns];
-    if (ntiles > Lo.max_tiles) return CXBWT_EDEVICE;
-    CX_CHECK(hipMemcpyAsync(segs, big.data(), sizeof(Seg) * ns, hipMemcpyHostToDevice, st));
-    CX_CHECK(hipMemcpyAsync(tile_prefix, tprefix.data(), 4 * (ns + 1), hipMemcpyHostToDevice, st));
-    if ((rc = fill_u64((uint64_t *)seg_or, ns, 0, st))) return rc;
-    if ((rc = fill_u64((uint64_t *)seg_and, ns, ~0ull, st))) return rc;
-    if ((rc = fill_u32(counters + C_NBIG, 1, 0, st))) return rc;
-    k_level_hist<<<ntiles, BLOCK, 0, st>>>(segs, tile_prefix, ns, keys0, keys1, hdl0, hdl1, packed, endbits, nb,
-                                           tile_hist, seg_or, seg_and);
+    // level 1: keys computed from the 2-bit reads, counted, recomputed, scattered
+    const uint32_t ntiles = (uint32_t)ceil_div(nb, TILE);
+    const uint32_t ngroups = (uint32_t)ceil_div(ntiles, GROUP_TILES);
+    Seg all{0, nb, 0, 0, 0, 0, 0};
+    tprefix = {0, ntiles};
+    gprefix = {0, ngroups};
+    CX_CHECK(hipMemcpyAsync(B.segs, &all, sizeof(Seg), hipMemcpyHostToDevice, st));
+    CX_CHECK(hipMemcpyAsync(B.tile_prefix, tprefix.data(), 8, hipMemcpyHostToDevice, st));
+    CX_CHECK(hipMemcpyAsync(B.group_prefix, gprefix.data(), 8, hipMemcpyHostToDevice, st));
+    T.begin();
+    k_gen_hist<<<ntiles, BLOCK, 0, st>>>(packed, B.endbits, nb, B.tile_hist);
     CX_LAUNCHED();
-    k_level_scan<<<ns, BLOCK, 0, st>>>(segs, tile_prefix, tile_hist, seg_or, seg_and, seg_split, Ls);
+    T.end(PH_GEN);
+    T.begin();
+    k_group_scan<<<ngroups, BLOCK, 0, st>>>(B.tile_prefix, B.group_prefix, 1, B.tile_hist, B.gsum);
     CX_LAUNCHED();
-    k_level_scatter<<<ntiles, BLOCK, 0, st>>>(segs, tile_prefix, ns, seg_split, tile_hist, keys0, keys1, hdl0, hdl1);
+    k_level_scan<<<1, BLOCK, 0, st>>>(B.segs, B.group_prefix, B.gsum, B.seg_or, B.seg_and, B.seg_split, Ls, 1);
     CX_LAUNCHED();
+    T.end(PH_SCAN);
+    T.begin();
+    k_gen_scatter<<<ntiles, BLOCK, 0, st>>>(packed, B.endbits, nb, B.tile_hist, B.gsum, B.keys1, B.hdl1);
+    CX_LAUNCHED();
+    T.end(PH_SCATTER);
+    g_stats.level_suffixes += nb;
+    g_stats.levels = 1;
+    g_stats.big_segments = 1;
     CX_CHECK(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, st));
     CX_CHECK(hipStreamSynchronize(st));
+    T.collect();
     if (hc[C_STATUS]) return CXBWT_EDEVICE;
-    g_stats.levels++;
-    g_stats.big_segments += ns;
-    const uint32_t nn = hc[C_NBIG];
-    big.resize(nn);
-    if (nn) {
-      CX_CHECK(hipMemcpyAsync(big.data(), big_next, sizeof(Seg) * nn, hipMemcpyDeviceToHost, st));
+    std::vector<Seg> big(hc[C_NBIG]);
+    if (!big.empty()) {
+      CX_CHECK(hipMemcpyAsync(big.data(), B.big_next, sizeof(Seg) * big.size(), hipMemcpyDeviceToHost, st));
       CX_CHECK(hipStreamSynchronize(st));
-      for (const Seg &s : big) g_stats.max_window = std::max(g_stats.max_window, s.r);
     }
-    n_chunks = hc[C_NCHUNK];
+    if ((rc = finish_level(B, Lo, packed, offsets, n, nb, rmax, bwt, term_pos, hc[C_NCHUNK], hc[C_NFINAL], tprefix, T,
+                           st)))
+      return rc;
+    // levels 2..
+    while (!big.empty()) {
+      const uint32_t ns = (uint32_t)big.size();
+      if (ns > Lo.cap_big) return CXBWT_EDEVICE;
+      tprefix.assign(ns + 1, 0);
+      gprefix.assign(ns + 1, 0);
+      for (uint32_t i = 0; i < ns; ++i) {
+        const uint32_t nt = (uint32_t)ceil_div(big[i].len, TILE);
+        tprefix[i + 1] = tprefix[i] + nt;
+        gprefix[i + 1] = gprefix[i] + (uint32_t)ceil_div(nt, GROUP_TILES);
+        g_stats.level_suffixes += big[i].len;
+        if (big[i].regather) g_stats.regathered += big[i].len;
+        g_stats.max_window = std::max(g_stats.max_window, big[i].r);
+      }
+      const uint32_t nt = tprefix[ns], ng = gprefix[ns];
+      if (nt > Lo.max_tiles || ng > Lo.max_groups) return CXBWT_EDEVICE;
+      CX_CHECK(hipMemcpyAsync(B.segs, big.data(), sizeof(Seg) * ns, hipMemcpyHostToDevice, st));
+      CX_CHECK(hipMemcpyAsync(B.tile_prefix, tprefix.data(), 4 * (ns + 1), hipMemcpyHostToDevice, st));
+      CX_CHECK(hipMemcpyAsync(B.group_prefix, gprefix.data(), 4 * (ns + 1), hipMemcpyHostToDevice, st));
+      if ((rc = fill_u64((uint64_t *)B.seg_or, ns, 0, st))) return rc;
+      if ((rc = fill_u64((uint64_t *)B.seg_and, ns, ~0ull, st))) return rc;
+      if ((rc = fill_u32(counters + C_NBIG, 3, 0, st))) return rc;  // big, chunk and final counts
+      T.begin();
+      k_level_hist<<<nt, BLOCK, 0, st>>>(B.segs, B.tile_prefix, ns, B.keys0, B.keys1, B.hdl0, B.hdl1, packed, B.endbits,
+                                         nb, B.tile_hist, B.seg_or, B.seg_and);
+      CX_LAUNCHED();
+      T.end(PH_HIST);
+      T.begin();
+      k_group_scan<<<ng, BLOCK, 0, st>>>(B.tile_prefix, B.group_prefix, ns, B.tile_hist, B.gsum);
+      CX_LAUNCHED();
+      k_level_scan<<<ns, BLOCK, 0, st>>>(B.segs, B.group_prefix, B.gsum, B.seg_or, B.seg_and, B.seg_split, Ls, 0);
+      CX_LAUNCHED();
+      T.end(PH_SCAN);
+      T.begin();
+      k_level_scatter<<<nt, BLOCK, 0, st>>>(B.segs, B.tile_prefix, B.group_prefix, ns, B.seg_split, B.tile_hist, B.gsum,
+                                            B.keys0, B.keys1, B.hdl0, B.hdl1);
+      CX_LAUNCHED();
+      T.end(PH_SCATTER);
+      CX_CHECK(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, st));
+      CX_CHECK(hipStreamSynchronize(st));
+      T.collect();
+      if (hc[C_STATUS]) return CXBWT_EDEVICE;
+      g_stats.levels++;
+      g_stats.big_segments += ns;
+      big.resize(hc[C_NBIG]);
+      if (!big.empty()) {
+        CX_CHECK(hipMemcpyAsync(big.data(), B.big_next, sizeof(Seg) * big.size(), hipMemcpyDeviceToHost, st));
+        CX_CHECK(hipStreamSynchronize(st));
+      }
+      if ((rc = finish_level(B, Lo, packed, offsets, n, nb, rmax, bwt, term_pos, hc[C_NCHUNK], hc[C_NFINAL], tprefix,
+                             T, st)))
+        return rc;
+    }
   }
-  if (n_chunks) {
-    const size_t smem = sizeof(LocalSmem);
-    k_local<<<n_chunks, BLOCK, smem, st>>>(chunks, keys0, keys1, hdl0, hdl1, packed, endbits, offsets, n, nb, rmax,
-                                           bwt, term_pos, counters + C_STATUS);
-    CX_LAUNCHED();
-  }
-  g_stats.chunks = n_chunks;
-  const uint32_t nfin = hc[C_NFINAL];
-  if (nfin) {
-    std::vector<Seg> fin(nfin);
-    CX_CHECK(hipMemcpyAsync(fin.data(), finals, sizeof(Seg) * nfin, hipMemcpyDeviceToHost, st));
-    CX_CHECK(hipStreamSynchronize(st));
-    tprefix.assign(nfin + 1, 0);
-    for (uint32_t i = 0; i < nfin; ++i) tprefix[i + 1] = tprefix[i] + (uint32_t)ceil_div(fin[i].len, TILE);
-    CX_CHECK(hipMemcpyAsync(tile_prefix, tprefix.data(), 4 * (nfin + 1), hipMemcpyHostToDevice, st));
-    k_emit_final<<<tprefix[nfin], BLOCK, 0, st>>>(finals, tile_prefix, nfin, keys0, keys1, hdl0, hdl1, offsets, n, bwt,
-                                                  term_pos);
-    CX_LAUNCHED();
-  }
-  g_stats.final_big = nfin;
+  T.begin();
+  k_term<<<grid_for(n, 256), 256, 0, st>>>(offsets, n, B.endbits, B.ebrank, B.start_row, term_pos);
+  CX_LAUNCHED();
+  T.end(PH_FINAL);
   CX_CHECK(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, st));
   CX_CHECK(hipStreamSynchronize(st));
+  T.collect();
+  g_stats.window_fetches = (uint64_t)hc[C_FETCH] | ((uint64_t)hc[C_FETCH + 1] << 32);
+  g_stats.scattered_suffixes = (uint64_t)hc[C_SCATTERED] | ((uint64_t)hc[C_SCATTERED + 1] << 32);
   if (hc[C_STATUS]) return CXBWT_EDEVICE;
   return CXBWT_OK;
 }
-
-bool local_smem_configured = false;
 
 }  // namespace
 
@@ -1037,7 +1247,7 @@ int cxbwt_pack(const uint8_t *ascii, uint64_t n_bases, uint64_t *packed, uint32_
 
 size_t cxbwt_workspace_bytes(uint64_t n_reads, uint64_t n_bases, uint32_t max_read_len) {
   if (!sizes_ok(n_reads, n_bases, max_read_len)) return 0;
-  return (size_t)make_layout(n_reads, n_bases, max_read_len).total;
+  return (size_t)make_layout(n_reads, n_bases).total;
 }
 
 int cxbwt_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n_reads, uint64_t n_bases,
@@ -1047,13 +1257,6 @@ int cxbwt_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n_read
   if (!sizes_ok(n_reads, n_bases, max_read_len)) return CXBWT_ERANGE;
   if (workspace_bytes < cxbwt_workspace_bytes(n_reads, n_bases, max_read_len)) return CXBWT_ENOMEM;
   if (((uintptr_t)workspace & 255u) != 0) return CXBWT_EINVAL;
-  if (!local_smem_configured) {
-    // raise the dynamic LDS limit where the runtime asks for it; a launch
-    // that still does not fit reports an error through hipGetLastError
-    (void)hipFuncSetAttribute((const void *)k_local, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)sizeof(LocalSmem));
-    local_smem_configured = true;
-  }
   return run_build(packed, offsets, n_reads, n_bases, max_read_len, bwt, term_pos, (unsigned char *)workspace,
                    (hipStream_t)stream);
 }
@@ -1062,6 +1265,12 @@ int cxbwt_last_stats(cxbwt_stats *out) {
   if (!out) return CXBWT_EINVAL;
   *out = g_stats;
   return CXBWT_OK;
+}
+
+int cxbwt_set_timing(int enable) {
+  const int prev = g_timing;
+  g_timing = enable ? 1 : 0;
+  return prev;
 }
 
 const char *cxbwt_status_str(int status) {

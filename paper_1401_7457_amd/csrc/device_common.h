@@ -1,0 +1,243 @@
+// device_common.h -- key layout, window fetch and workgroup primitives shared
+// by the kernels of cxbwt.hip (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cxk {
+
+constexpr int W = 28;              // bases per key window
+constexpr int BLOCK = 256;         // threads per workgroup
+constexpr int WAVES = BLOCK / 64;  // wave64
+constexpr uint32_t NODIGIT = 0xFFFFFFFFu;
+
+// ---------------------------------------------------------------------------
+// Suffix key of one 28-base window (see cxbwt.hip for why this order is the
+// suffix order):
+//   bits 63..8  the 28 bases, 2 bits each, first base highest; zero past the
+//               end of the read
+//   bits  7..3  clamped length: min(bases left in the read from the window
+//               start, 28)
+//   bits  2..0  symbol preceding the suffix: 0..3 = A,C,G,T, 4 = '$'
+// Only bits [3, 64) take part in comparisons.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t order_bits(uint64_t k) { return k & ~7ull; }
+__device__ __forceinline__ uint32_t clamp_of(uint64_t k) { return (uint32_t)(k >> 3) & 31u; }
+// 8-bit digit j (0 = most significant) of the ordering bits; digit 7 is the
+// 5-bit clamped length
+__device__ __forceinline__ uint32_t digit_of(uint64_t k, int j) {
+  return j < 7 ? (uint32_t)(k >> (56 - 8 * j)) & 0xFFu : (uint32_t)(k >> 3) & 0x1Fu;
+}
+__host__ __device__ __forceinline__ uint64_t digit_mask(int j) {
+  return j < 7 ? (0xFFull << (56 - 8 * j)) : (0x1Full << 3);
+}
+__device__ __forceinline__ uint32_t base_at(const uint64_t *packed, uint64_t t) {
+  return (uint32_t)(packed[t >> 5] >> (62 - 2 * (t & 31))) & 3u;
+}
+__device__ __forceinline__ bool end_bit(const uint64_t *endbits, uint64_t t) {
+  return (endbits[t >> 6] >> (t & 63)) & 1ull;
+}
+
+// The four words a window key is built from; every load is issued before any
+// is used so many windows can be in flight per thread.  Addresses are clamped
+// into the arrays (a clamped read is never used): endbits holds nb/64 + 2
+// words, packed holds ceil(nb/32) + 1 words, and nb >= 1.
+struct WinWords {
+  uint64_t e0, e1, c0, c1;
+};
+
+__device__ __forceinline__ WinWords window_load(const uint64_t *__restrict__ packed,
+                                                const uint64_t *__restrict__ endbits, uint64_t nb, uint64_t p,
+                                                uint32_t r) {
+  const uint64_t q = p + (uint64_t)W * r;
+  uint64_t lo = r == 0 ? p : q - 1;
+  lo = lo < nb ? lo : nb - 1;
+  const uint64_t qc = q < nb ? q : nb - 1;
+  WinWords w;
+  w.e0 = endbits[lo >> 6];
+  w.e1 = endbits[(lo >> 6) + 1];
+  w.c0 = packed[qc >> 5];
+  w.c1 = packed[(qc >> 5) + 1];
+  return w;
+}
+
+// Key of window r of the suffix starting at base p (the window starts at
+// q = p + 28 r).  endbits marks the last base of every non-empty read.  For
+// r >= 1 the suffix is live: its read holds at least 28 r bases from p, so
+// the read's last base e is at least q - 1.
+__device__ __forceinline__ uint64_t window_combine(const WinWords &w, uint64_t nb, uint64_t p, uint32_t r,
+                                                   uint32_t prev3) {
+  const uint64_t q = p + (uint64_t)W * r;
+  const uint64_t lo = r == 0 ? p : q - 1;
+  if (lo >= nb) return prev3;  // never taken for a live suffix
+  const uint64_t w0 = w.e0 >> (lo & 63);
+  uint64_t e;
+  if (w0) e = lo + (uint64_t)__builtin_ctzll(w0);
+  else e = w.e1 ? ((lo | 63ull) + 1) + (uint64_t)__builtin_ctzll(w.e1) : ~0ull;
+  const uint32_t clamp = (e < q + W) ? (uint32_t)(e + 1 - q) : (uint32_t)W;
+  uint64_t chars = 0;
+  if (clamp > 0 && q < nb) {
+    const uint32_t b = 2u * (uint32_t)(q & 31);
+    uint64_t x = w.c0 << b;
+    if (b) x |= w.c1 >> (64 - b);
+    chars = x & ~0xFFull;
+    if (clamp < (uint32_t)W) chars &= ~((1ull << (64 - 2 * clamp)) - 1);
+  }
+  return chars | ((uint64_t)clamp << 3) | prev3;
+}
+
+__device__ __forceinline__ uint64_t window_key(const uint64_t *__restrict__ packed,
+                                               const uint64_t *__restrict__ endbits, uint64_t nb, uint64_t p,
+                                               uint32_t r, uint32_t prev3) {
+  return window_combine(window_load(packed, endbits, nb, p, r), nb, p, r, prev3);
+}
+
+// Window-0 key of the suffix starting at base p, with its preceding symbol:
+// '$' when p starts a read (p == 0 or base p-1 ends a read).
+__device__ __forceinline__ uint64_t first_key(const uint64_t *__restrict__ packed,
+                                              const uint64_t *__restrict__ endbits, uint64_t nb, uint64_t p) {
+  const WinWords w = window_load(packed, endbits, nb, p, 0);
+  uint32_t prev3 = 4;
+  if (p > 0 && !end_bit(endbits, p - 1)) prev3 = base_at(packed, p - 1);
+  return window_combine(w, nb, p, 0, prev3);
+}
+
+// ---------------------------------------------------------------------------
+// wave / workgroup primitives
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+__device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t v) {
+  const uint32_t l = lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(v, o, 64);
+    if (l >= (uint32_t)o) v += t;
+  }
+  return v;
+}
+__device__ __forceinline__ uint64_t wave_or(uint64_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ uint64_t wave_and(uint64_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v &= __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor(v, o, 64));
+  return v;
+}
+
+// Exclusive prefix sum of one value per thread over the workgroup.
+__device__ __forceinline__ uint32_t block_excl_sum(uint32_t v, uint32_t *tmp, uint32_t *total) {
+  const uint32_t inc = wave_incl_sum(v);
+  const int w = threadIdx.x >> 6;
+  if (lane_id() == 63) tmp[w] = inc;
+  __syncthreads();
+  uint32_t pre = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < WAVES; ++i) {
+    const uint32_t x = tmp[i];
+    if (i < w) pre += x;
+    tot += x;
+  }
+  __syncthreads();
+  if (total) *total = tot;
+  return pre + inc - v;
+}
+
+__device__ __forceinline__ uint64_t block_or(uint64_t v, uint64_t *tmp) {
+  v = wave_or(v);
+  if (lane_id() == 0) tmp[threadIdx.x >> 6] = v;
+  __syncthreads();
+  uint64_t r = 0;
+#pragma unroll
+  for (int i = 0; i < WAVES; ++i) r |= tmp[i];
+  __syncthreads();
+  return r;
+}
+__device__ __forceinline__ uint64_t block_and(uint64_t v, uint64_t *tmp) {
+  v = wave_and(v);
+  if (lane_id() == 0) tmp[threadIdx.x >> 6] = v;
+  __syncthreads();
+  uint64_t r = ~0ull;
+#pragma unroll
+  for (int i = 0; i < WAVES; ++i) r &= tmp[i];
+  __syncthreads();
+  return r;
+}
+__device__ __forceinline__ uint32_t block_max(uint32_t v, uint32_t *tmp) {
+  v = wave_max(v);
+  if (lane_id() == 0) tmp[threadIdx.x >> 6] = v;
+  __syncthreads();
+  uint32_t r = 0;
+#pragma unroll
+  for (int i = 0; i < WAVES; ++i) r = max(r, tmp[i]);
+  __syncthreads();
+  return r;
+}
+
+// Position of item i of this thread when a workgroup holds NI items per
+// thread: wave w owns [w*64*NI, (w+1)*64*NI); item i of lane l sits at
+// w*64*NI + i*64 + l (consecutive lanes touch consecutive elements).
+template <int NI>
+__device__ __forceinline__ uint32_t item_index(int i) {
+  return (uint32_t)((threadIdx.x >> 6) * (64 * NI) + i * 64) + lane_id();
+}
+
+// Stable 256-way split of up to BLOCK*NI items held in registers (layout of
+// item_index<NI>).  On return pos[i] is the destination of item i in
+// [0, count) and dstart[d] the first destination of digit d.  dig[i] ==
+// NODIGIT marks an absent item.  Ranks inside a wave come from ballot-matched
+// peer masks; waves are ordered by a digit-major scan of per-wave counts.
+template <int NI>
+__device__ __forceinline__ void block_multisplit(const uint32_t (&dig)[NI], uint32_t (&pos)[NI], uint32_t *wcount,
+                                                 uint32_t *dstart, uint32_t *tmp) {
+  const int w = threadIdx.x >> 6;
+  for (int x = threadIdx.x; x < WAVES * 256; x += BLOCK) wcount[x] = 0;
+  __syncthreads();
+  uint32_t *wc = wcount + w * 256;
+  const uint64_t lt = lanemask_lt();
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    const uint32_t d = dig[i];
+    const bool valid = d != NODIGIT;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t v = __ballot(bit);
+      peers &= bit ? v : ~v;
+    }
+    if (valid) {
+      const uint32_t before = wc[d];
+      pos[i] = before + (uint32_t)__popcll(peers & lt);
+      if ((peers & lt) == 0) wc[d] = before + (uint32_t)__popcll(peers);
+    }
+  }
+  __syncthreads();
+  const uint32_t d = threadIdx.x;  // one digit per thread (BLOCK == 256)
+  uint32_t run = 0;
+#pragma unroll
+  for (int ww = 0; ww < WAVES; ++ww) {
+    const uint32_t c = wcount[ww * 256 + d];
+    wcount[ww * 256 + d] = run;
+    run += c;
+  }
+  const uint32_t ex = block_excl_sum(run, tmp, nullptr);
+  dstart[d] = ex;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NI; ++i)
+    if (dig[i] != NODIGIT) pos[i] += dstart[dig[i]] + wc[dig[i]];
+}
+
+static_assert(BLOCK == 256, "block_multisplit assigns one digit per thread");
+
+}  // namespace cxk

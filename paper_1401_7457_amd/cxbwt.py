@@ -22,7 +22,10 @@ STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ERANGE: "ERANGE", ENOMEM: "ENOMEM", 
 
 # Names the C ABI exports (include/cxbwt.h).
 ABI_FUNCTIONS = ("cxbwt_packed_words", "cxbwt_pack", "cxbwt_workspace_bytes", "cxbwt_build", "cxbwt_last_stats",
-                 "cxbwt_status_str")
+                 "cxbwt_set_timing", "cxbwt_status_str")
+
+# kernel classes of cxbwt_stats.ms / launches
+KERNEL_CLASSES = ("prep", "gen", "level_hist", "level_scan", "level_scatter", "local", "final_emit", "unused")
 
 _lock = threading.Lock()
 _lib = None
@@ -37,7 +40,10 @@ class CxbwtError(RuntimeError):
 
 class Stats(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_uint32), ("max_window", ctypes.c_uint32), ("chunks", ctypes.c_uint64),
-                ("big_segments", ctypes.c_uint64), ("final_big", ctypes.c_uint64)]
+                ("big_segments", ctypes.c_uint64), ("final_big", ctypes.c_uint64),
+                ("chunk_suffixes", ctypes.c_uint64), ("level_suffixes", ctypes.c_uint64),
+                ("scattered_suffixes", ctypes.c_uint64), ("regathered", ctypes.c_uint64),
+                ("window_fetches", ctypes.c_uint64), ("ms", ctypes.c_float * 8), ("launches", ctypes.c_uint32 * 8)]
 
 
 def lib():
@@ -60,6 +66,8 @@ def lib():
             L.cxbwt_build.restype = ctypes.c_int
             L.cxbwt_last_stats.argtypes = [ctypes.POINTER(Stats)]
             L.cxbwt_last_stats.restype = ctypes.c_int
+            L.cxbwt_set_timing.argtypes = [ctypes.c_int]
+            L.cxbwt_set_timing.restype = ctypes.c_int
             L.cxbwt_status_str.argtypes = [ctypes.c_int]
             L.cxbwt_status_str.restype = ctypes.c_char_p
             _lib = L
@@ -80,15 +88,19 @@ def workspace_bytes(n_reads: int, n_bases: int, max_read_len: int) -> int:
     return int(lib().cxbwt_workspace_bytes(n_reads, n_bases, max_read_len))
 
 
-def pack(ascii_dev, stream=None):
+def pack(ascii_dev, stream=None, out=None, status=None):
     """ASCII bases (uint8 CUDA tensor) -> packed words (int64 CUDA tensor holding uint64 bits)."""
     import torch
     if ascii_dev.dtype != torch.uint8 or not ascii_dev.is_cuda:
         raise TypeError("pack expects a uint8 CUDA tensor")
     ascii_dev = ascii_dev.contiguous()
     nb = ascii_dev.numel()
-    out = torch.empty(packed_words(nb), dtype=torch.int64, device=ascii_dev.device)
-    status = torch.empty(1, dtype=torch.int32, device=ascii_dev.device)
+    if out is None:
+        out = torch.empty(packed_words(nb), dtype=torch.int64, device=ascii_dev.device)
+    elif out.numel() < packed_words(nb):
+        raise ValueError("packed output too small")
+    if status is None:
+        status = torch.empty(1, dtype=torch.int32, device=ascii_dev.device)
     st = lib().cxbwt_pack(ctypes.c_void_p(ascii_dev.data_ptr() if nb else 0), nb, ctypes.c_void_p(out.data_ptr()),
                           ctypes.c_void_p(status.data_ptr()), _stream_ptr(stream))
     if st != OK:
@@ -129,7 +141,15 @@ def build(packed, offsets, n_reads: int, n_bases: int, max_read_len: int, worksp
 def last_stats() -> dict:
     s = Stats()
     lib().cxbwt_last_stats(ctypes.byref(s))
-    return {f: int(getattr(s, f)) for f, _ in Stats._fields_}
+    out = {f: int(getattr(s, f)) for f, _ in Stats._fields_ if f not in ("ms", "launches")}
+    out["ms"] = {k: float(s.ms[i]) for i, k in enumerate(KERNEL_CLASSES) if s.launches[i]}
+    out["launches"] = {k: int(s.launches[i]) for i, k in enumerate(KERNEL_CLASSES) if s.launches[i]}
+    return out
+
+
+def set_timing(enable: bool) -> bool:
+    """Per-kernel-class HIP-event timing of later builds on this host thread."""
+    return bool(lib().cxbwt_set_timing(1 if enable else 0))
 
 
 def build_host(text: np.ndarray, offsets: np.ndarray, max_read_len: int | None = None, device="cuda"):

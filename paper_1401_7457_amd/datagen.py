@@ -67,8 +67,10 @@ def random_genome(rng: np.random.Generator, length: int) -> np.ndarray:
 def mutate(rng: np.random.Generator, codes: np.ndarray, rate: float) -> np.ndarray:
     """Substitute each symbol with probability `rate` by one of the other three."""
     out = codes.copy()
-    hit = rng.random(out.size) < rate
-    k = int(hit.sum())
+    if rate <= 0 or out.size == 0:
+        return out
+    hit = rng.random(out.size, dtype=np.float32) < np.float32(rate)
+    k = int(np.count_nonzero(hit))
     if k:
         out[hit] = (out[hit] + rng.integers(1, 4, size=k, dtype=np.uint8)) & 3
     return out
@@ -135,25 +137,27 @@ def sample_reads(rng: np.random.Generator, genome: np.ndarray, n: int, read_len,
     text = np.empty(int(offsets[-1]), dtype=np.uint8)
     starts = rng.integers(0, G - lens + 1)
     strand = rng.random(n) < 0.5 if both_strands else np.zeros(n, dtype=bool)
+    idx_t = np.int32 if G < (1 << 31) - 1 else np.int64
     for c0 in range(0, n, _CHUNK):
         c1 = min(n, c0 + _CHUNK)
-        L = lens[c0:c1]
-        s = starts[c0:c1]
-        rev = strand[c0:c1]
-        tot = int(L.sum())
-        if tot == 0:
+        L = lens[c0:c1].astype(idx_t)
+        if int(L.sum()) == 0:
             continue
-        read_of = np.repeat(np.arange(c1 - c0), L)
-        local = np.arange(tot) - np.repeat(np.cumsum(L) - L, L)
-        fwd_idx = s[read_of] + local
-        rev_idx = s[read_of] + L[read_of] - 1 - local
-        r = rev[read_of]
-        idx = np.where(r, rev_idx, fwd_idx)
-        codes = genome[idx]
-        codes = np.where(r, 3 - codes, codes).astype(np.uint8)  # complement A<->T, C<->G
+        s = starts[c0:c1].astype(idx_t)
+        rev = strand[c0:c1]
+        maxL = int(L.max())
+        j = np.arange(maxL, dtype=idx_t)[None, :]
+        # base j of a forward read is genome[s + j]; of a reverse read, the
+        # complement of genome[s + L - 1 - j]
+        pos = np.where(rev[:, None], (s + L - 1)[:, None] - j, s[:, None] + j)
+        valid = j < L[:, None]
+        np.clip(pos, 0, G - 1, out=pos)
+        codes = genome[pos]
+        codes = np.where(rev[:, None], 3 - codes, codes).astype(np.uint8)
+        codes = codes[valid] if maxL and not bool(valid.all()) else codes.reshape(-1)
         codes = mutate(rng, codes, error_rate)
         b0 = int(offsets[c0])
-        text[b0:b0 + tot] = ASCII[codes]
+        text[b0:b0 + codes.size] = ASCII[codes]
     return Collection(text, offsets)
 
 
