@@ -35,23 +35,29 @@ WORKLOADS = {
 def algorithmic_bytes(stats: dict, n_reads: int, n_bases: int) -> dict:
     """Bytes each kernel class must move, by the per-suffix model of the design.
 
-    gen          12.375 B/base: write 8 B key + 4 B handle, read 2-bit bases and end bits
-    level_hist   8 B per suffix visit (key read) + 12 B per later-window fetch
-    level_scan   4 B per tile counter, read and written (~0.25 B/suffix visit per pass)
-    level_scatter 24 B per moved suffix: key + handle read and written
-    local        13 B per suffix (key + handle read, 1 B BWT written) + 16 B per
-                 later-window fetch (8 B of bases, 8 B of end bits) + 8 B per read start
-    final_emit   13 B per suffix
-    prep         17 B per read (two offsets, one BWT byte)
+    gen           0.375 B per base: read the 2-bit bases and the end bits
+                  (level 1 counts keys computed from the reads)
+    level_hist    8 B per suffix visit (key read) + 12 B per later-window re-key
+    level_scan    4 B per tile counter read and written (1 KB per 3072-suffix tile)
+    level_scatter level 1: 12.375 B per base (bases + end bits read, key + handle
+                  written); later levels: 24 B per moved suffix (key + handle
+                  read and written)
+    local         13 B per suffix (key + handle read, 1 B BWT written) + 16 B per
+                  later-window fetch (8 B of bases, 8 B of end bits) + 8 B per read
+    final_emit    13 B per suffix
+    prep          17 B per read (two offsets, one BWT byte) + 0.19 B per base
+                  (end-bit ranks)
     """
     cs = stats.get("chunk_suffixes", 0)
     fin = n_bases - cs
+    scattered = stats.get("scattered_suffixes", 0)
+    level1 = n_bases if stats.get("levels", 0) >= 1 and scattered >= n_bases else 0
     return {
-        "prep": 17.0 * n_reads,
-        "gen": 12.375 * n_bases,
-        "level_hist": 8.0 * stats.get("level_suffixes", 0) + 12.0 * stats.get("regathered", 0),
-        "level_scan": 2.0 * stats.get("level_suffixes", 0) / 4096 * 256 * 4 / 2,
-        "level_scatter": 24.0 * stats.get("scattered_suffixes", 0),
+        "prep": 17.0 * n_reads + 0.1875 * n_bases,
+        "gen": 0.375 * n_bases,
+        "level_hist": 8.0 * stats.get("level_suffixes", 0) - 8.0 * level1 + 12.0 * stats.get("regathered", 0),
+        "level_scan": 2.0 * 1024 * stats.get("level_suffixes", 0) / 3072,
+        "level_scatter": 12.375 * level1 + 24.0 * (scattered - level1),
         "local": 13.0 * cs + 16.0 * stats.get("window_fetches", 0) + 8.0 * n_reads,
         "final_emit": 13.0 * fin,
     }
@@ -71,13 +77,123 @@ def cpu_baseline(scale: float, threads: int) -> dict:
             "seconds": dt}
 
 
+def _batch_mode(args) -> dict:
+    """Many collections: one batched build per wave against one build per collection."""
+    import numpy as np
+    import torch
+
+    from paper_1401_7457_amd import cxbwt, datagen, serve
+    cols = datagen.batch_collections(count=args.batch_count, scale=args.scale)
+    sizes = [(c.n_reads, c.n_bases) for c in cols]
+    waves = serve.plan_waves(sizes, budget_bytes=int(args.budget_gb * 2 ** 30))
+    total = sum(nb for _, nb in sizes)
+    print(f"[bench] batch: {len(cols)} collections, {total} bases, {len(waves)} wave(s)", file=sys.stderr,
+          flush=True)
+    dev = [(torch.from_numpy(c.text).cuda(), torch.from_numpy(c.offsets.view(np.int64)).cuda()) for c in cols]
+
+    def batched():
+        for w in waves:
+            texts = [dev[i][0] for i in w]
+            parts = [torch.zeros(1, dtype=torch.int64, device="cuda")]
+            base = 0
+            for i in w:
+                parts.append(dev[i][1][1:] + base)
+                base += cols[i].n_bases
+            text = torch.cat(texts)
+            offs = torch.cat(parts)
+            cr = np.concatenate([[0], np.cumsum([cols[i].n_reads for i in w])]).astype(np.uint64)
+            maxlen = max(cols[i].max_read_len for i in w)
+            packed, _ = cxbwt.pack(text)
+            cxbwt.build_batch(packed, offs, int(cr[-1]), base, maxlen, cr)
+
+    def sequential():
+        for i, c in enumerate(cols):
+            packed, _ = cxbwt.pack(dev[i][0])
+            cxbwt.build(packed, dev[i][1], c.n_reads, c.n_bases, c.max_read_len)
+
+    out = {}
+    for name, fn in (("batched", batched), ("one_at_a_time", sequential)):
+        fn()  # warm-up (allocator, code objects)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        out[name] = {"seconds": dt, "gbases_per_s": total / dt / 1e9}
+    return {
+        "metric": "batched BWT build aggregate Gbases/s at 1 GPU",
+        "value": out["batched"]["gbases_per_s"],
+        "unit": "Gbases/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "higher_is_better": True,
+        "data": "synthetic",
+        "config": {"workload": f"batched: {len(cols)} collections, log-uniform 5k-2M reads x{args.scale:g}, "
+                               f"L in {{75,100,150}}, 1-10 Mb genomes x{args.scale:g}, 0.5% subst",
+                   "bases": total, "waves": len(waves)},
+        "one_at_a_time_gbases_per_s": out["one_at_a_time"]["gbases_per_s"],
+        "speedup_vs_one_at_a_time": out["batched"]["gbases_per_s"] / out["one_at_a_time"]["gbases_per_s"],
+    }
+
+
+def _serve_mode(args) -> dict:
+    """Poisson job stream: continuous batching against one job at a time on the same trace."""
+    import numpy as np
+    import torch
+
+    from paper_1401_7457_amd import cxbwt, datagen, serve
+    jobs = datagen.job_stream(count=args.jobs, rate_per_s=1.0, scale=args.scale)
+    mean_bases = float(np.mean([j.collection.n_bases for j in jobs]))
+    # capacity: throughput of one-at-a-time builds of these jobs
+    ex = serve.DeviceExecutor()
+    probe = jobs[: min(8, len(jobs))]
+    rep0, _ = serve.replay([(0.0, j.collection) for j in probe], ex, int(args.budget_gb * 2 ** 30),
+                           max_batch_jobs=1)
+    capacity = rep0["gbases_per_s"] * 1e9  # bases per second
+    rate = args.load * capacity / mean_bases
+    arrivals = [(j.arrival_s / rate, j.collection) for j in jobs]
+    total = sum(j.collection.n_bases for j in jobs)
+    print(f"[bench] serve: {len(jobs)} jobs, {total} bases, rate {rate:.1f}/s (load {args.load})",
+          file=sys.stderr, flush=True)
+    res = {}
+    for name, kw in (("continuous", {}), ("one_at_a_time", {"max_batch_jobs": 1})):
+        torch.cuda.synchronize()
+        rep, _ = serve.replay(arrivals, ex, int(args.budget_gb * 2 ** 30), **kw)
+        res[name] = rep
+    c, b = res["continuous"], res["one_at_a_time"]
+    return {
+        "metric": "served BWT build aggregate Gbases/s and p50/p99 job latency at 1 GPU",
+        "value": c["gbases_per_s"],
+        "unit": "Gbases/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "data": "synthetic",
+        "config": {"workload": f"served: Poisson arrivals at {args.load:g} x measured capacity, {len(jobs)} jobs, "
+                               f"log-uniform 10k-5M reads x{args.scale:g}, L uniform 100-250, 1% subst",
+                   "bases": total, "budget_gb": args.budget_gb},
+        "latency_p50_s": c["latency_p50_s"],
+        "latency_p99_s": c["latency_p99_s"],
+        "mean_jobs_per_batch": c["mean_jobs_per_batch"],
+        "one_at_a_time": {"gbases_per_s": b["gbases_per_s"], "latency_p50_s": b["latency_p50_s"],
+                          "latency_p99_s": b["latency_p99_s"]},
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve"],
+                    help="plain: one collection (the headline line); batch / serve: the batched and served forms")
+    ap.add_argument("--scale", type=float, default=0.05, help="batch/serve: size scale of the collections")
+    ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--jobs", type=int, default=60)
+    ap.add_argument("--load", type=float, default=0.8, help="serve: offered load relative to measured capacity")
+    ap.add_argument("--budget-gb", type=float, default=250.0)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="plain1", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-scale", type=float, default=0.25, help="oracle sample: plain1 recipe at this scale")
+    ap.add_argument("--cpu-scale", type=float, default=0.1, help="oracle sample: plain1 recipe at this scale")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one device copy of this size (for counter calibration under rocprofv3)")
@@ -99,6 +215,10 @@ def main() -> int:
         return 1
     torch.cuda.set_device(0)
     cxbwt.lib()
+    if args.mode != "plain":
+        res = _batch_mode(args) if args.mode == "batch" else _serve_mode(args)
+        print(json.dumps(res), flush=True)
+        return 0
     k, label = WORKLOADS[args.workload]
     col = datagen.plain_config(k)
     n, nb, maxlen = col.n_reads, col.n_bases, col.max_read_len
@@ -117,9 +237,12 @@ def main() -> int:
         cxbwt.build(packed, offsets, n, nb, maxlen, workspace=ws, out=(bwt, term))
 
     if args.copy_calibration_mib:
-        src = torch.empty(args.copy_calibration_mib << 20, dtype=torch.uint8, device="cuda")
+        # a plain streaming kernel of known traffic (reads and writes
+        # copy_calibration_mib MiB each) for scaling the HBM byte counters
+        src = torch.ones((args.copy_calibration_mib << 20) // 4, dtype=torch.int32, device="cuda")
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.cuda.synchronize()
+        torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
 

@@ -123,6 +123,46 @@ int cxbwt_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n_read
                 uint32_t max_read_len, uint8_t *bwt, uint64_t *term_pos, void *workspace,
                 size_t workspace_bytes, void *stream);
 
+/*
+ * cxbwt_batch_workspace_bytes -- workspace of cxbwt_build_batch for these
+ * totals (same per-base cost as cxbwt_workspace_bytes plus per-collection
+ * tables).  Pure host arithmetic; 0 when out of range or n_coll is 0 or
+ * larger than n_reads.
+ */
+size_t cxbwt_batch_workspace_bytes(uint64_t n_reads, uint64_t n_bases, uint32_t max_read_len, uint32_t n_coll);
+
+/*
+ * cxbwt_build_batch -- the BWTs of n_coll independent collections in one
+ * pass of the device pipeline: every sort level and every finishing launch
+ * covers all collections at once (each collection is its own segment from
+ * the first level on, so suffixes of different collections never meet).
+ * Each result is exactly the cxbwt_build result of that collection alone
+ * (Section 2 applied per collection).
+ *
+ * Inputs
+ *   packed, offsets, n_reads, n_bases, max_read_len
+ *                 the reads of all collections concatenated, collection
+ *                 after collection, as for cxbwt_build (n_bases is the
+ *                 total, at most CXBWT_MAX_BASES; offsets are global).
+ *   coll_reads    (host) n_coll + 1 uint64: collection c holds reads
+ *                 [coll_reads[c], coll_reads[c+1]); coll_reads[0] == 0,
+ *                 strictly increasing (no empty collection), coll_reads[n_coll]
+ *                 == n_reads.
+ * Outputs
+ *   bwt           (device, out) n_bases + n_reads bytes: the collections'
+ *                 BWTs concatenated in order; collection c's BWT (n_c + B_c
+ *                 bytes) starts at byte (reads before c) + (bases before c).
+ *   term_pos      (device, out) n_reads uint64: for global read i of
+ *                 collection c, the row inside collection c's BWT of the '$'
+ *                 standing for read i - coll_reads[c].
+ * Workspace, stream, return codes: as cxbwt_build, with CXBWT_EINVAL also
+ * for inconsistent coll_reads and CXBWT_ENOMEM below
+ * cxbwt_batch_workspace_bytes().  Returns after the device work completes.
+ */
+int cxbwt_build_batch(const uint64_t *packed, const uint64_t *offsets, uint64_t n_reads, uint64_t n_bases,
+                      uint32_t max_read_len, const uint64_t *coll_reads, uint32_t n_coll, uint8_t *bwt,
+                      uint64_t *term_pos, void *workspace, size_t workspace_bytes, void *stream);
+
 /* Counters describing the last cxbwt_build on the calling host thread. */
 typedef struct cxbwt_stats {
   uint32_t levels;             /* global sort levels run                               */

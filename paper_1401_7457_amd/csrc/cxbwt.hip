@@ -78,6 +78,16 @@ struct Seg {
   uint8_t buf;
   uint8_t regather;  // keys must be re-fetched for window r before use
   uint8_t unsplit;   // chunk only: suffixes are in read order, not yet split by digit d
+  uint32_t coll;     // collection the suffixes belong to
+};
+
+// Where collection c's rows go.  Suffix position j (a base position of the
+// whole batch) of collection c is BWT row j + row_shift of that collection,
+// stored at output byte j + out_shift (the outputs of the collections are
+// concatenated, each n_c + B_c bytes).
+struct CollMap {
+  uint64_t out_shift;  // reads in collections 0..c
+  int64_t row_shift;   // n_c - (first base of c)
 };
 
 struct Lists {
@@ -108,13 +118,13 @@ __device__ __forceinline__ uint32_t end_rank(const uint64_t *__restrict__ endbit
 // Writes the BWT row of a sorted suffix; an offset-0 suffix also records its
 // row under its read's rank among the non-empty reads (k_term turns those
 // into term_pos).
-__device__ __forceinline__ void emit_row(uint64_t row, uint64_t key, uint32_t p, const uint64_t *__restrict__ endbits,
-                                         const uint32_t *__restrict__ ebrank, uint8_t *__restrict__ bwt,
-                                         uint64_t *__restrict__ start_row) {
+__device__ __forceinline__ void emit_row(uint64_t j, const CollMap &cm, uint64_t key, uint32_t p,
+                                         const uint64_t *__restrict__ endbits, const uint32_t *__restrict__ ebrank,
+                                         uint8_t *__restrict__ bwt, uint64_t *__restrict__ start_row) {
   const uint32_t pv = (uint32_t)key & 7u;
   const uint32_t lut = 'A' | ('C' << 8) | ('G' << 16) | ('T' << 24);
-  bwt[row] = pv == 4 ? (uint8_t)'$' : (uint8_t)((lut >> (8 * pv)) & 0xFFu);
-  if (pv == 4) start_row[end_rank(endbits, ebrank, p)] = row;
+  bwt[j + cm.out_shift] = pv == 4 ? (uint8_t)'$' : (uint8_t)((lut >> (8 * pv)) & 0xFFu);
+  if (pv == 4) start_row[end_rank(endbits, ebrank, p)] = (uint64_t)((int64_t)j + cm.row_shift);
 }
 
 __device__ __forceinline__ uint32_t find_upper(const uint32_t *prefix, uint32_t count, uint32_t x) {
@@ -173,10 +183,19 @@ __global__ void k_pack(const uint8_t *__restrict__ ascii, uint64_t nb, uint64_t 
 // bare terminators (row i = $_i, preceded by the last base of read i)
 // ---------------------------------------------------------------------------
 __global__ void k_prep(const uint64_t *__restrict__ packed, const uint64_t *__restrict__ offsets, uint64_t n, uint64_t nb,
-                       uint32_t maxlen, unsigned long long *endbits, uint8_t *__restrict__ bwt,
-                       uint64_t *__restrict__ term_pos, uint32_t *status) {
+                       uint32_t maxlen, const uint64_t *__restrict__ coll_reads, uint32_t ncoll,
+                       unsigned long long *endbits, uint8_t *__restrict__ bwt, uint64_t *__restrict__ term_pos,
+                       uint32_t *status) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  // collection of read i: largest c with coll_reads[c] <= i
+  uint32_t clo = 0, chi = ncoll;
+  while (chi - clo > 1) {
+    const uint32_t mid = (clo + chi) >> 1;
+    if (coll_reads[mid] <= i) clo = mid;
+    else chi = mid;
+  }
+  const uint64_t first_read = coll_reads[clo];
   const uint64_t a = offsets[i], b = offsets[i + 1];
   const bool bad = b < a || b > nb || (i == 0 && a != 0) || (i == n - 1 && b != nb);
   if (bad) {
@@ -187,15 +206,25 @@ __global__ void k_prep(const uint64_t *__restrict__ packed, const uint64_t *__re
     atomicOr(status, ST_TOO_LONG);
     return;
   }
+  // row (i - first_read) of the collection, whose output starts at byte
+  // (bases before it) + (reads before it): byte offsets[first_read] + i
+  const uint64_t out = offsets[first_read] + i;
   if (b > a) {
     const uint64_t e = b - 1;
     atomicOr(&endbits[e >> 6], 1ull << (e & 63));
     const uint32_t lut = 'A' | ('C' << 8) | ('G' << 16) | ('T' << 24);
-    bwt[i] = (uint8_t)((lut >> (8 * base_at(packed, e))) & 0xFFu);
+    bwt[out] = (uint8_t)((lut >> (8 * base_at(packed, e))) & 0xFFu);
   } else {
-    bwt[i] = (uint8_t)'$';
-    term_pos[i] = i;
+    bwt[out] = (uint8_t)'$';
+    term_pos[i] = i - first_read;
   }
+}
+
+// First base of every collection (host needs them to lay out segments).
+__global__ void k_coll_bases(const uint64_t *__restrict__ offsets, const uint64_t *__restrict__ coll_reads,
+                             uint32_t ncoll, uint64_t *__restrict__ bases) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c <= ncoll) bases[c] = offsets[coll_reads[c]];
 }
 
 // ---------------------------------------------------------------------------
@@ -260,27 +289,39 @@ __global__ void k_term(const uint64_t *__restrict__ offsets, uint64_t n, const u
 }
 
 // ---------------------------------------------------------------------------
-// a1 for small inputs: suffix listing + window-0 keys, read-major
+// a1 for collections that fit one chunk: window-0 keys in read order
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(BLOCK) void k_gen(const uint64_t *__restrict__ packed, const uint64_t *__restrict__ endbits,
-                                               uint64_t nb, uint64_t *__restrict__ keys, uint32_t *__restrict__ hdl) {
-  const uint64_t p = (uint64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (p >= nb) return;
-  keys[p] = first_key(packed, endbits, nb, p);
-  hdl[p] = (uint32_t)p;
+
+__global__ __launch_bounds__(BLOCK) void k_gen(const Seg *__restrict__ segs, const uint32_t *__restrict__ tile_prefix,
+                                               uint32_t nsegs, const uint64_t *__restrict__ packed,
+                                               const uint64_t *__restrict__ endbits, uint64_t nb,
+                                               uint64_t *__restrict__ keys, uint32_t *__restrict__ hdl) {
+  const uint32_t tile = blockIdx.x;
+  const uint32_t s = find_upper(tile_prefix, nsegs, tile);
+  const Seg sg = segs[s];
+  const uint64_t t0 = sg.start + (uint64_t)(tile - tile_prefix[s]) * TILE;
+  const uint64_t t1 = min(t0 + (uint64_t)TILE, sg.start + sg.len);
+  for (uint64_t p = t0 + threadIdx.x; p < t1; p += BLOCK) {
+    keys[p] = first_key(packed, endbits, nb, p);
+    hdl[p] = (uint32_t)p;
+  }
 }
 
 // ---------------------------------------------------------------------------
-// a1 + a2, level 1: window-0 keys of every suffix (read-major, from the 2-bit
-// reads) counted by their top digit, then recomputed and scattered
+// a1 + a2, level 1: window-0 keys of every suffix of a collection (read
+// order, from the 2-bit reads) counted by their top digit, then recomputed
+// and scattered; keys are never stored unsorted.  One segment per collection.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(BLOCK) void k_gen_hist(const uint64_t *__restrict__ packed,
+__global__ __launch_bounds__(BLOCK) void k_gen_hist(const Seg *__restrict__ segs, const uint32_t *__restrict__ tile_prefix,
+                                                    uint32_t nsegs, const uint64_t *__restrict__ packed,
                                                     const uint64_t *__restrict__ endbits, uint64_t nb,
                                                     uint32_t *__restrict__ tile_hist) {
   __shared__ uint32_t hist[256];
   const uint32_t tile = blockIdx.x;
-  const uint64_t t0 = (uint64_t)tile * TILE;
-  const uint64_t t1 = min(t0 + (uint64_t)TILE, nb);
+  const uint32_t s = find_upper(tile_prefix, nsegs, tile);
+  const Seg sg = segs[s];
+  const uint64_t t0 = sg.start + (uint64_t)(tile - tile_prefix[s]) * TILE;
+  const uint64_t t1 = min(t0 + (uint64_t)TILE, sg.start + sg.len);
   hist[threadIdx.x] = 0;
   __syncthreads();
   for (uint64_t p = t0 + threadIdx.x; p < t1; p += BLOCK) {
@@ -325,15 +366,21 @@ __device__ __forceinline__ void tile_scatter(ScatterSmem &S, const uint64_t (&kr
   }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_gen_scatter(const uint64_t *__restrict__ packed,
+__global__ __launch_bounds__(BLOCK) void k_gen_scatter(const Seg *__restrict__ segs,
+                                                       const uint32_t *__restrict__ tile_prefix,
+                                                       const uint32_t *__restrict__ group_prefix, uint32_t nsegs,
+                                                       const uint64_t *__restrict__ packed,
                                                        const uint64_t *__restrict__ endbits, uint64_t nb,
                                                        const uint32_t *__restrict__ tile_hist,
                                                        const uint32_t *__restrict__ gsum, uint64_t *__restrict__ Ko,
                                                        uint32_t *__restrict__ Ho) {
   __shared__ ScatterSmem S;
   const uint32_t tile = blockIdx.x;
-  const uint64_t t0 = (uint64_t)tile * TILE;
-  const uint32_t m = (uint32_t)min((uint64_t)TILE, nb - t0);
+  const uint32_t s = find_upper(tile_prefix, nsegs, tile);
+  const Seg sg = segs[s];
+  const uint32_t tl = tile - tile_prefix[s];
+  const uint64_t t0 = sg.start + (uint64_t)tl * TILE;
+  const uint32_t m = (uint32_t)min((uint64_t)TILE, sg.start + sg.len - t0);
   uint64_t kr[TILE_ITEMS];
   uint32_t hr[TILE_ITEMS], dig[TILE_ITEMS];
 #pragma unroll
@@ -349,7 +396,7 @@ __global__ __launch_bounds__(BLOCK) void k_gen_scatter(const uint64_t *__restric
       dig[i] = NODIGIT;
     }
   }
-  const uint32_t g = tile / GROUP_TILES;
+  const uint32_t g = group_prefix[s] + tl / GROUP_TILES;
   S.goff[threadIdx.x] = (uint64_t)gsum[(uint64_t)g * 256 + threadIdx.x] + tile_hist[(uint64_t)tile * 256 + threadIdx.x];
   tile_scatter(S, kr, hr, dig, m, 0, Ko, Ho);
 }
@@ -513,7 +560,7 @@ __global__ __launch_bounds__(BLOCK) void k_level_scan(const Seg *__restrict__ se
           st_chunk[nc++] = cur;
           have = false;
         }
-        Seg nx{st, c, sg.r, (uint8_t)(sg.d + 1), (uint8_t)(sg.buf ^ 1), 0, 0};
+        Seg nx{st, c, sg.r, (uint8_t)(sg.d + 1), (uint8_t)(sg.buf ^ 1), 0, 0, sg.coll};
         if (sg.d == 7) {
           // bucket value b is the clamped length; all ordering bits agree
           if (b < W) {
@@ -535,7 +582,7 @@ __global__ __launch_bounds__(BLOCK) void k_level_scan(const Seg *__restrict__ se
         cur.len += c;
       } else {
         if (have) st_chunk[nc++] = cur;
-        cur = Seg{st, c, sg.r, sg.d, (uint8_t)(sg.buf ^ 1), 0, 0};
+        cur = Seg{st, c, sg.r, sg.d, (uint8_t)(sg.buf ^ 1), 0, 0, sg.coll};
         have = true;
       }
     }
@@ -599,8 +646,9 @@ __global__ __launch_bounds__(BLOCK) void k_emit_final(const Seg *__restrict__ se
                                                       uint32_t nsegs, const uint64_t *__restrict__ keys0,
                                                       const uint64_t *__restrict__ keys1, const uint32_t *__restrict__ hdl0,
                                                       const uint32_t *__restrict__ hdl1, const uint64_t *__restrict__ endbits,
-                                                      const uint32_t *__restrict__ ebrank, uint64_t n,
-                                                      uint8_t *__restrict__ bwt, uint64_t *__restrict__ start_row) {
+                                                      const uint32_t *__restrict__ ebrank,
+                                                      const CollMap *__restrict__ cmap, uint8_t *__restrict__ bwt,
+                                                      uint64_t *__restrict__ start_row) {
   const uint32_t tile = blockIdx.x;
   const uint32_t s = find_upper(tile_prefix, nsegs, tile);
   const Seg sg = segs[s];
@@ -608,7 +656,8 @@ __global__ __launch_bounds__(BLOCK) void k_emit_final(const Seg *__restrict__ se
   const uint64_t t1 = min(t0 + (uint64_t)TILE, sg.start + sg.len);
   const uint64_t *K = sg.buf ? keys1 : keys0;
   const uint32_t *H = sg.buf ? hdl1 : hdl0;
-  for (uint64_t j = t0 + threadIdx.x; j < t1; j += BLOCK) emit_row(n + j, K[j], H[j], endbits, ebrank, bwt, start_row);
+  const CollMap cm = cmap[sg.coll];
+  for (uint64_t j = t0 + threadIdx.x; j < t1; j += BLOCK) emit_row(j, cm, K[j], H[j], endbits, ebrank, bwt, start_row);
 }
 
 // ---------------------------------------------------------------------------
@@ -670,8 +719,9 @@ __global__ __launch_bounds__(BLOCK, 16 / LOCAL_ITEMS) void k_local(const Seg *__
                                                     const uint64_t *__restrict__ keys1, const uint32_t *__restrict__ hdl0,
                                                     const uint32_t *__restrict__ hdl1, const uint64_t *__restrict__ packed,
                                                     const uint64_t *__restrict__ endbits,
-                                                    const uint32_t *__restrict__ ebrank, uint64_t n, uint64_t nb,
-                                                    uint32_t rmax, uint8_t *__restrict__ bwt,
+                                                    const uint32_t *__restrict__ ebrank,
+                                                    const CollMap *__restrict__ cmap, uint64_t nb, uint32_t rmax,
+                                                    uint8_t *__restrict__ bwt,
                                                     uint64_t *__restrict__ start_row, uint32_t *status,
                                                     unsigned long long *fetches) {
   __shared__ LocalSmem S;
@@ -835,8 +885,9 @@ __global__ __launch_bounds__(BLOCK, 16 / LOCAL_ITEMS) void k_local(const Seg *__
     fetch_round = true;
   }
   // a4: emit
+  const CollMap cm = cmap[ch.coll];
   for (uint32_t j = threadIdx.x; j < m; j += BLOCK)
-    emit_row(n + ch.start + j, S.K[cur][j], S.H[cur][j], endbits, ebrank, bwt, start_row);
+    emit_row(ch.start + j, cm, S.K[cur][j], S.H[cur][j], endbits, ebrank, bwt, start_row);
   nfetch = wave_incl_sum(nfetch);
   if (lane_id() == 63 && nfetch) atomicAdd(fetches, (unsigned long long)nfetch);
 }
@@ -855,7 +906,8 @@ inline uint64_t align_up(uint64_t x) { return (x + 255) & ~255ull; }
 
 struct Layout {
   uint64_t keys0, keys1, hdl0, hdl1, endbits, ebrank, rank_blocks, start_row, tile_hist, gsum, segs, tile_prefix,
-      group_prefix, seg_or, seg_and, seg_split, big_next, chunks, finals, counters, total;
+      group_prefix, seg_or, seg_and, seg_split, big_next, chunks, finals, coll_reads, coll_bases, cmap, counters,
+      total;
   uint64_t cap_big, cap_chunks, cap_finals, max_tiles, max_groups, endbit_words, n_rank_blocks;
 };
 
@@ -863,17 +915,19 @@ bool sizes_ok(uint64_t n_reads, uint64_t n_bases, uint32_t max_read_len) {
   return n_reads >= 1 && n_reads < (1ull << 32) && n_bases <= CXBWT_MAX_BASES && max_read_len <= CXBWT_MAX_READ_LEN;
 }
 
-Layout make_layout(uint64_t n_reads, uint64_t nb) {
+Layout make_layout(uint64_t n_reads, uint64_t nb, uint32_t n_coll) {
   Layout L{};
-  // segments of one level are disjoint and each holds more than CHUNK suffixes
+  // segments of one level are disjoint and each holds more than CHUNK
+  // suffixes; level 1 starts with one segment per collection
   L.cap_big = nb / (CHUNK + 1) + 2;
   L.cap_finals = L.cap_big;
   // chunks of one level: two neighbouring chunks of a run hold more than
   // CHUNK suffixes together, and a run ends at an oversized bucket or at the
-  // end of its parent (both at most cap_big per level)
-  L.cap_chunks = 2 * ceil_div(nb, CHUNK) + 2 * L.cap_big + 2;
-  L.max_tiles = ceil_div(nb, TILE) + L.cap_big + 1;
-  L.max_groups = ceil_div(L.max_tiles, GROUP_TILES) + L.cap_big + 1;
+  // end of its parent (both at most cap_big per level); level 1 adds one
+  // chunk per collection that fits a chunk
+  L.cap_chunks = 2 * ceil_div(nb, CHUNK) + 2 * L.cap_big + n_coll + 2;
+  L.max_tiles = ceil_div(nb, TILE) + L.cap_big + n_coll + 1;
+  L.max_groups = ceil_div(L.max_tiles, GROUP_TILES) + L.cap_big + n_coll + 1;
   L.endbit_words = nb / 64 + 2;
   L.n_rank_blocks = ceil_div(L.endbit_words, RANK_BLOCK_WORDS);
   uint64_t off = 0;
@@ -882,6 +936,7 @@ Layout make_layout(uint64_t n_reads, uint64_t nb) {
     off = align_up(off + bytes);
     return at;
   };
+  const uint64_t seg_slots = std::max<uint64_t>(L.cap_big, n_coll + 1);
   L.keys0 = take(8 * nb);
   L.keys1 = take(8 * nb);
   L.hdl0 = take(4 * nb);
@@ -892,15 +947,18 @@ Layout make_layout(uint64_t n_reads, uint64_t nb) {
   L.start_row = take(8 * n_reads);
   L.tile_hist = take(4 * 256 * L.max_tiles);
   L.gsum = take(4 * 256 * L.max_groups);
-  L.segs = take(sizeof(Seg) * L.cap_big);
-  L.tile_prefix = take(4 * (L.cap_big + 1));
-  L.group_prefix = take(4 * (L.cap_big + 1));
-  L.seg_or = take(8 * L.cap_big);
-  L.seg_and = take(8 * L.cap_big);
-  L.seg_split = take(L.cap_big);
+  L.segs = take(sizeof(Seg) * seg_slots);
+  L.tile_prefix = take(4 * (seg_slots + 1));
+  L.group_prefix = take(4 * (seg_slots + 1));
+  L.seg_or = take(8 * seg_slots);
+  L.seg_and = take(8 * seg_slots);
+  L.seg_split = take(seg_slots);
   L.big_next = take(sizeof(Seg) * L.cap_big);
   L.chunks = take(sizeof(Seg) * L.cap_chunks);
   L.finals = take(sizeof(Seg) * L.cap_finals);
+  L.coll_reads = take(8 * ((uint64_t)n_coll + 1));
+  L.coll_bases = take(8 * ((uint64_t)n_coll + 1));
+  L.cmap = take(sizeof(CollMap) * (uint64_t)n_coll);
   L.counters = take(64);
   L.total = off;
   return L;
@@ -1005,22 +1063,44 @@ struct PhaseTimer {
 enum { C_STATUS = 0, C_NBIG = 1, C_NCHUNK = 2, C_NFINAL = 3, C_FETCH = 8, C_SCATTERED = 10, C_COUNT = 16 };
 
 struct Buffers {
-  uint64_t *keys0, *keys1, *endbits, *start_row;
+  uint64_t *keys0, *keys1, *endbits, *start_row, *coll_reads, *coll_bases;
   uint32_t *hdl0, *hdl1, *ebrank, *rank_blocks, *tile_hist, *gsum, *tile_prefix, *group_prefix, *counters;
   Seg *segs, *big_next, *chunks, *finals;
+  CollMap *cmap;
   unsigned long long *seg_or, *seg_and;
   uint8_t *seg_split;
 };
 
+// Upload a segment list with its tile and group prefixes; returns the tile
+// and group totals.
+int upload_segments(const Buffers &B, const Layout &Lo, const std::vector<Seg> &segs, std::vector<uint32_t> &tprefix,
+                    std::vector<uint32_t> &gprefix, uint32_t &ntiles, uint32_t &ngroups, hipStream_t st) {
+  const uint32_t ns = (uint32_t)segs.size();
+  tprefix.assign(ns + 1, 0);
+  gprefix.assign(ns + 1, 0);
+  for (uint32_t i = 0; i < ns; ++i) {
+    const uint32_t nt = (uint32_t)ceil_div(segs[i].len, TILE);
+    tprefix[i + 1] = tprefix[i] + nt;
+    gprefix[i + 1] = gprefix[i] + (uint32_t)ceil_div(nt, GROUP_TILES);
+  }
+  ntiles = tprefix[ns];
+  ngroups = gprefix[ns];
+  if (ntiles > Lo.max_tiles || ngroups > Lo.max_groups) return CXBWT_EDEVICE;
+  CX_CHECK(hipMemcpyAsync(B.segs, segs.data(), sizeof(Seg) * ns, hipMemcpyHostToDevice, st));
+  CX_CHECK(hipMemcpyAsync(B.tile_prefix, tprefix.data(), 4 * (ns + 1), hipMemcpyHostToDevice, st));
+  CX_CHECK(hipMemcpyAsync(B.group_prefix, gprefix.data(), 4 * (ns + 1), hipMemcpyHostToDevice, st));
+  return CXBWT_OK;
+}
+
 // Finish the chunks and final groups a level produced.
-int finish_level(const Buffers &B, const Layout &Lo, const uint64_t *packed, const uint64_t *offsets, uint64_t n,
-                 uint64_t nb, uint32_t rmax, uint8_t *bwt, uint64_t *term_pos, uint32_t n_chunks, uint32_t n_finals,
-                 std::vector<uint32_t> &tprefix, PhaseTimer &T, hipStream_t st) {
+int finish_level(const Buffers &B, const Layout &Lo, const uint64_t *packed, uint64_t nb, uint32_t rmax, uint8_t *bwt,
+                 uint32_t n_chunks, uint32_t n_finals, std::vector<uint32_t> &tprefix, PhaseTimer &T,
+                 hipStream_t st) {
   if (n_chunks > Lo.cap_chunks || n_finals > Lo.cap_finals) return CXBWT_EDEVICE;
   if (n_chunks) {
     T.begin();
-    k_local<<<n_chunks, BLOCK, 0, st>>>(B.chunks, B.keys0, B.keys1, B.hdl0, B.hdl1, packed, B.endbits, B.ebrank, n, nb,
-                                        rmax, bwt, B.start_row, B.counters + C_STATUS,
+    k_local<<<n_chunks, BLOCK, 0, st>>>(B.chunks, B.keys0, B.keys1, B.hdl0, B.hdl1, packed, B.endbits, B.ebrank, B.cmap,
+                                        nb, rmax, bwt, B.start_row, B.counters + C_STATUS,
                                         (unsigned long long *)(B.counters + C_FETCH));
     CX_LAUNCHED();
     T.end(PH_LOCAL);
@@ -1039,7 +1119,7 @@ int finish_level(const Buffers &B, const Layout &Lo, const uint64_t *packed, con
     CX_CHECK(hipMemcpyAsync(B.tile_prefix, tprefix.data(), 4 * (n_finals + 1), hipMemcpyHostToDevice, st));
     T.begin();
     k_emit_final<<<tprefix[n_finals], BLOCK, 0, st>>>(B.finals, B.tile_prefix, n_finals, B.keys0, B.keys1, B.hdl0,
-                                                      B.hdl1, B.endbits, B.ebrank, n, bwt, B.start_row);
+                                                      B.hdl1, B.endbits, B.ebrank, B.cmap, bwt, B.start_row);
     CX_LAUNCHED();
     T.end(PH_FINAL);
     g_stats.final_big += n_finals;
@@ -1048,11 +1128,14 @@ int finish_level(const Buffers &B, const Layout &Lo, const uint64_t *packed, con
   return CXBWT_OK;
 }
 
-int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint64_t nb, uint32_t maxlen, uint8_t *bwt,
-              uint64_t *term_pos, unsigned char *ws, hipStream_t st) {
+// The whole build for ncoll collections laid end to end (a single build is
+// one collection).  coll_reads (host) holds ncoll + 1 read boundaries.
+int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint64_t nb, uint32_t maxlen,
+              const uint64_t *coll_reads, uint32_t ncoll, uint8_t *bwt, uint64_t *term_pos, unsigned char *ws,
+              hipStream_t st) {
   g_stats = cxbwt_stats{};
   PhaseTimer T{st, g_timing != 0, {}};
-  const Layout Lo = make_layout(n, nb);
+  const Layout Lo = make_layout(n, nb, ncoll);
   Buffers B;
   B.keys0 = (uint64_t *)(ws + Lo.keys0);
   B.keys1 = (uint64_t *)(ws + Lo.keys1);
@@ -1073,6 +1156,9 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
   B.big_next = (Seg *)(ws + Lo.big_next);
   B.chunks = (Seg *)(ws + Lo.chunks);
   B.finals = (Seg *)(ws + Lo.finals);
+  B.coll_reads = (uint64_t *)(ws + Lo.coll_reads);
+  B.coll_bases = (uint64_t *)(ws + Lo.coll_bases);
+  B.cmap = (CollMap *)(ws + Lo.cmap);
   B.counters = (uint32_t *)(ws + Lo.counters);
   const uint32_t rmax = maxlen / W + 1;
   uint32_t *counters = B.counters;
@@ -1080,17 +1166,37 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
   int rc;
   if ((rc = fill_u32(counters, C_COUNT, 0, st))) return rc;
   if ((rc = fill_u64(B.endbits, Lo.endbit_words, 0, st))) return rc;
+  CX_CHECK(hipMemcpyAsync(B.coll_reads, coll_reads, 8 * ((uint64_t)ncoll + 1), hipMemcpyHostToDevice, st));
   T.begin();
-  k_prep<<<grid_for(n, 256), 256, 0, st>>>(packed, offsets, n, nb, maxlen, (unsigned long long *)B.endbits, bwt,
-                                          term_pos, counters + C_STATUS);
+  k_prep<<<grid_for(n, 256), 256, 0, st>>>(packed, offsets, n, nb, maxlen, B.coll_reads, ncoll,
+                                          (unsigned long long *)B.endbits, bwt, term_pos, counters + C_STATUS);
   CX_LAUNCHED();
   T.end(PH_PREP);
+  k_coll_bases<<<grid_for((uint64_t)ncoll + 1, 256), 256, 0, st>>>(offsets, B.coll_reads, ncoll, B.coll_bases);
+  CX_LAUNCHED();
   uint32_t hc[C_COUNT];
+  std::vector<uint64_t> cbase(ncoll + 1);
   CX_CHECK(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, st));
+  CX_CHECK(hipMemcpyAsync(cbase.data(), B.coll_bases, 8 * ((uint64_t)ncoll + 1), hipMemcpyDeviceToHost, st));
   CX_CHECK(hipStreamSynchronize(st));
   T.collect();
   if (hc[C_STATUS] & (ST_BAD_OFFSETS | ST_TOO_LONG)) return CXBWT_EDATA;
-  if (nb == 0) return CXBWT_OK;
+  // offsets are valid, so the collection bases are non-decreasing and end at nb
+  std::vector<CollMap> cm(ncoll);
+  std::vector<Seg> big, small;
+  for (uint32_t c = 0; c < ncoll; ++c) {
+    const uint64_t nc = coll_reads[c + 1] - coll_reads[c];
+    const uint64_t bc = cbase[c + 1] - cbase[c];
+    cm[c].out_shift = coll_reads[c + 1];
+    cm[c].row_shift = (int64_t)nc - (int64_t)cbase[c];
+    if (bc > (uint64_t)CHUNK) big.push_back(Seg{cbase[c], bc, 0, 0, 0, 0, 0, c});
+    else if (bc > 0) small.push_back(Seg{cbase[c], bc, 0, 0, 0, 0, 1, c});
+  }
+  if (ncoll) CX_CHECK(hipMemcpyAsync(B.cmap, cm.data(), sizeof(CollMap) * ncoll, hipMemcpyHostToDevice, st));
+  if (nb == 0) {
+    CX_CHECK(hipStreamSynchronize(st));
+    return CXBWT_OK;
+  }
   g_stats.chunk_suffixes = nb;
   // ranks of the read ends, for term_pos
   T.begin();
@@ -1106,91 +1212,85 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
            B.finals, counters + C_NFINAL, (uint32_t)Lo.cap_finals, counters + C_STATUS, rmax,
            (unsigned long long *)(counters + C_SCATTERED)};
   std::vector<uint32_t> tprefix, gprefix;
+  uint32_t ntiles = 0, ngroups = 0;
 
-  if (nb <= (uint64_t)CHUNK) {
-    // one workgroup finishes everything
+  // collections that fit one chunk: keys in read order, one unsplit chunk each
+  if (!small.empty()) {
+    if ((rc = upload_segments(B, Lo, small, tprefix, gprefix, ntiles, ngroups, st))) return rc;
     T.begin();
-    k_gen<<<grid_for(nb, BLOCK), BLOCK, 0, st>>>(packed, B.endbits, nb, B.keys0, B.hdl0);
+    k_gen<<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, (uint32_t)small.size(), packed, B.endbits, nb, B.keys0,
+                                    B.hdl0);
     CX_LAUNCHED();
     T.end(PH_GEN);
-    Seg one{0, nb, 0, 0, 0, 0, 1};
-    CX_CHECK(hipMemcpyAsync(B.chunks, &one, sizeof(Seg), hipMemcpyHostToDevice, st));
-    if ((rc = finish_level(B, Lo, packed, offsets, n, nb, rmax, bwt, term_pos, 1, 0, tprefix, T, st))) return rc;
-  } else {
+    CX_CHECK(hipMemcpyAsync(B.chunks, small.data(), sizeof(Seg) * small.size(), hipMemcpyHostToDevice, st));
+    if (big.empty()) {
+      if ((rc = finish_level(B, Lo, packed, nb, rmax, bwt, (uint32_t)small.size(), 0, tprefix, T, st))) return rc;
+    } else {
+      // level 1 appends its chunks after these
+      const uint32_t nsmall = (uint32_t)small.size();
+      CX_CHECK(hipMemcpyAsync(counters + C_NCHUNK, &nsmall, 4, hipMemcpyHostToDevice, st));
+      CX_CHECK(hipStreamSynchronize(st));  // host values above must stay alive until copied
+    }
+  }
+  if (!big.empty()) {
     // level 1: keys computed from the 2-bit reads, counted, recomputed, scattered
-    const uint32_t ntiles = (uint32_t)ceil_div(nb, TILE);
-    const uint32_t ngroups = (uint32_t)ceil_div(ntiles, GROUP_TILES);
-    Seg all{0, nb, 0, 0, 0, 0, 0};
-    tprefix = {0, ntiles};
-    gprefix = {0, ngroups};
-    CX_CHECK(hipMemcpyAsync(B.segs, &all, sizeof(Seg), hipMemcpyHostToDevice, st));
-    CX_CHECK(hipMemcpyAsync(B.tile_prefix, tprefix.data(), 8, hipMemcpyHostToDevice, st));
-    CX_CHECK(hipMemcpyAsync(B.group_prefix, gprefix.data(), 8, hipMemcpyHostToDevice, st));
+    const uint32_t ns = (uint32_t)big.size();
+    if ((rc = upload_segments(B, Lo, big, tprefix, gprefix, ntiles, ngroups, st))) return rc;
     T.begin();
-    k_gen_hist<<<ntiles, BLOCK, 0, st>>>(packed, B.endbits, nb, B.tile_hist);
+    k_gen_hist<<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, ns, packed, B.endbits, nb, B.tile_hist);
     CX_LAUNCHED();
     T.end(PH_GEN);
     T.begin();
-    k_group_scan<<<ngroups, BLOCK, 0, st>>>(B.tile_prefix, B.group_prefix, 1, B.tile_hist, B.gsum);
+    k_group_scan<<<ngroups, BLOCK, 0, st>>>(B.tile_prefix, B.group_prefix, ns, B.tile_hist, B.gsum);
     CX_LAUNCHED();
-    k_level_scan<<<1, BLOCK, 0, st>>>(B.segs, B.group_prefix, B.gsum, B.seg_or, B.seg_and, B.seg_split, Ls, 1);
+    k_level_scan<<<ns, BLOCK, 0, st>>>(B.segs, B.group_prefix, B.gsum, B.seg_or, B.seg_and, B.seg_split, Ls, 1);
     CX_LAUNCHED();
     T.end(PH_SCAN);
     T.begin();
-    k_gen_scatter<<<ntiles, BLOCK, 0, st>>>(packed, B.endbits, nb, B.tile_hist, B.gsum, B.keys1, B.hdl1);
+    k_gen_scatter<<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, B.group_prefix, ns, packed, B.endbits, nb,
+                                            B.tile_hist, B.gsum, B.keys1, B.hdl1);
     CX_LAUNCHED();
     T.end(PH_SCATTER);
-    g_stats.level_suffixes += nb;
+    for (const Seg &g : big) g_stats.level_suffixes += g.len;
     g_stats.levels = 1;
-    g_stats.big_segments = 1;
+    g_stats.big_segments = ns;
     CX_CHECK(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, st));
     CX_CHECK(hipStreamSynchronize(st));
     T.collect();
     if (hc[C_STATUS]) return CXBWT_EDEVICE;
-    std::vector<Seg> big(hc[C_NBIG]);
+    big.resize(hc[C_NBIG]);
     if (!big.empty()) {
       CX_CHECK(hipMemcpyAsync(big.data(), B.big_next, sizeof(Seg) * big.size(), hipMemcpyDeviceToHost, st));
       CX_CHECK(hipStreamSynchronize(st));
     }
-    if ((rc = finish_level(B, Lo, packed, offsets, n, nb, rmax, bwt, term_pos, hc[C_NCHUNK], hc[C_NFINAL], tprefix, T,
-                           st)))
-      return rc;
+    if ((rc = finish_level(B, Lo, packed, nb, rmax, bwt, hc[C_NCHUNK], hc[C_NFINAL], tprefix, T, st))) return rc;
     // levels 2..
     while (!big.empty()) {
-      const uint32_t ns = (uint32_t)big.size();
-      if (ns > Lo.cap_big) return CXBWT_EDEVICE;
-      tprefix.assign(ns + 1, 0);
-      gprefix.assign(ns + 1, 0);
-      for (uint32_t i = 0; i < ns; ++i) {
-        const uint32_t nt = (uint32_t)ceil_div(big[i].len, TILE);
-        tprefix[i + 1] = tprefix[i] + nt;
-        gprefix[i + 1] = gprefix[i] + (uint32_t)ceil_div(nt, GROUP_TILES);
+      const uint32_t nsg = (uint32_t)big.size();
+      if (nsg > Lo.cap_big) return CXBWT_EDEVICE;
+      for (uint32_t i = 0; i < nsg; ++i) {
         g_stats.level_suffixes += big[i].len;
         if (big[i].regather) g_stats.regathered += big[i].len;
         g_stats.max_window = std::max(g_stats.max_window, big[i].r);
       }
-      const uint32_t nt = tprefix[ns], ng = gprefix[ns];
-      if (nt > Lo.max_tiles || ng > Lo.max_groups) return CXBWT_EDEVICE;
-      CX_CHECK(hipMemcpyAsync(B.segs, big.data(), sizeof(Seg) * ns, hipMemcpyHostToDevice, st));
-      CX_CHECK(hipMemcpyAsync(B.tile_prefix, tprefix.data(), 4 * (ns + 1), hipMemcpyHostToDevice, st));
-      CX_CHECK(hipMemcpyAsync(B.group_prefix, gprefix.data(), 4 * (ns + 1), hipMemcpyHostToDevice, st));
-      if ((rc = fill_u64((uint64_t *)B.seg_or, ns, 0, st))) return rc;
-      if ((rc = fill_u64((uint64_t *)B.seg_and, ns, ~0ull, st))) return rc;
+      if ((rc = upload_segments(B, Lo, big, tprefix, gprefix, ntiles, ngroups, st))) return rc;
+      if ((rc = fill_u64((uint64_t *)B.seg_or, nsg, 0, st))) return rc;
+      if ((rc = fill_u64((uint64_t *)B.seg_and, nsg, ~0ull, st))) return rc;
       if ((rc = fill_u32(counters + C_NBIG, 3, 0, st))) return rc;  // big, chunk and final counts
       T.begin();
-      k_level_hist<<<nt, BLOCK, 0, st>>>(B.segs, B.tile_prefix, ns, B.keys0, B.keys1, B.hdl0, B.hdl1, packed, B.endbits,
-                                         nb, B.tile_hist, B.seg_or, B.seg_and);
+      k_level_hist<<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, nsg, B.keys0, B.keys1, B.hdl0, B.hdl1, packed,
+                                             B.endbits, nb, B.tile_hist, B.seg_or, B.seg_and);
       CX_LAUNCHED();
       T.end(PH_HIST);
       T.begin();
-      k_group_scan<<<ng, BLOCK, 0, st>>>(B.tile_prefix, B.group_prefix, ns, B.tile_hist, B.gsum);
+      k_group_scan<<<ngroups, BLOCK, 0, st>>>(B.tile_prefix, B.group_prefix, nsg, B.tile_hist, B.gsum);
       CX_LAUNCHED();
-      k_level_scan<<<ns, BLOCK, 0, st>>>(B.segs, B.group_prefix, B.gsum, B.seg_or, B.seg_and, B.seg_split, Ls, 0);
+      k_level_scan<<<nsg, BLOCK, 0, st>>>(B.segs, B.group_prefix, B.gsum, B.seg_or, B.seg_and, B.seg_split, Ls, 0);
       CX_LAUNCHED();
       T.end(PH_SCAN);
       T.begin();
-      k_level_scatter<<<nt, BLOCK, 0, st>>>(B.segs, B.tile_prefix, B.group_prefix, ns, B.seg_split, B.tile_hist, B.gsum,
-                                            B.keys0, B.keys1, B.hdl0, B.hdl1);
+      k_level_scatter<<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, B.group_prefix, nsg, B.seg_split, B.tile_hist,
+                                                B.gsum, B.keys0, B.keys1, B.hdl0, B.hdl1);
       CX_LAUNCHED();
       T.end(PH_SCATTER);
       CX_CHECK(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, st));
@@ -1198,15 +1298,13 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
       T.collect();
       if (hc[C_STATUS]) return CXBWT_EDEVICE;
       g_stats.levels++;
-      g_stats.big_segments += ns;
+      g_stats.big_segments += nsg;
       big.resize(hc[C_NBIG]);
       if (!big.empty()) {
         CX_CHECK(hipMemcpyAsync(big.data(), B.big_next, sizeof(Seg) * big.size(), hipMemcpyDeviceToHost, st));
         CX_CHECK(hipStreamSynchronize(st));
       }
-      if ((rc = finish_level(B, Lo, packed, offsets, n, nb, rmax, bwt, term_pos, hc[C_NCHUNK], hc[C_NFINAL], tprefix,
-                             T, st)))
-        return rc;
+      if ((rc = finish_level(B, Lo, packed, nb, rmax, bwt, hc[C_NCHUNK], hc[C_NFINAL], tprefix, T, st))) return rc;
     }
   }
   T.begin();
@@ -1247,7 +1345,12 @@ int cxbwt_pack(const uint8_t *ascii, uint64_t n_bases, uint64_t *packed, uint32_
 
 size_t cxbwt_workspace_bytes(uint64_t n_reads, uint64_t n_bases, uint32_t max_read_len) {
   if (!sizes_ok(n_reads, n_bases, max_read_len)) return 0;
-  return (size_t)make_layout(n_reads, n_bases).total;
+  return (size_t)make_layout(n_reads, n_bases, 1).total;
+}
+
+size_t cxbwt_batch_workspace_bytes(uint64_t n_reads, uint64_t n_bases, uint32_t max_read_len, uint32_t n_coll) {
+  if (!sizes_ok(n_reads, n_bases, max_read_len) || n_coll == 0 || n_coll > n_reads) return 0;
+  return (size_t)make_layout(n_reads, n_bases, n_coll).total;
 }
 
 int cxbwt_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n_reads, uint64_t n_bases,
@@ -1257,8 +1360,25 @@ int cxbwt_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n_read
   if (!sizes_ok(n_reads, n_bases, max_read_len)) return CXBWT_ERANGE;
   if (workspace_bytes < cxbwt_workspace_bytes(n_reads, n_bases, max_read_len)) return CXBWT_ENOMEM;
   if (((uintptr_t)workspace & 255u) != 0) return CXBWT_EINVAL;
-  return run_build(packed, offsets, n_reads, n_bases, max_read_len, bwt, term_pos, (unsigned char *)workspace,
+  const uint64_t one[2] = {0, n_reads};
+  return run_build(packed, offsets, n_reads, n_bases, max_read_len, one, 1, bwt, term_pos, (unsigned char *)workspace,
                    (hipStream_t)stream);
+}
+
+int cxbwt_build_batch(const uint64_t *packed, const uint64_t *offsets, uint64_t n_reads, uint64_t n_bases,
+                      uint32_t max_read_len, const uint64_t *coll_reads, uint32_t n_coll, uint8_t *bwt,
+                      uint64_t *term_pos, void *workspace, size_t workspace_bytes, void *stream) {
+  if (!packed || !offsets || !bwt || !term_pos || !workspace || !coll_reads || n_reads == 0 || n_coll == 0)
+    return CXBWT_EINVAL;
+  if (!sizes_ok(n_reads, n_bases, max_read_len)) return CXBWT_ERANGE;
+  if (n_coll > n_reads) return CXBWT_EINVAL;
+  if (coll_reads[0] != 0 || coll_reads[n_coll] != n_reads) return CXBWT_EINVAL;
+  for (uint32_t c = 0; c < n_coll; ++c)
+    if (coll_reads[c + 1] <= coll_reads[c]) return CXBWT_EINVAL;  // every collection holds a read
+  if (workspace_bytes < cxbwt_batch_workspace_bytes(n_reads, n_bases, max_read_len, n_coll)) return CXBWT_ENOMEM;
+  if (((uintptr_t)workspace & 255u) != 0) return CXBWT_EINVAL;
+  return run_build(packed, offsets, n_reads, n_bases, max_read_len, coll_reads, n_coll, bwt, term_pos,
+                   (unsigned char *)workspace, (hipStream_t)stream);
 }
 
 int cxbwt_last_stats(cxbwt_stats *out) {

@@ -21,8 +21,9 @@ OK, EINVAL, ERANGE, ENOMEM, EDEVICE, EDATA = 0, -1, -2, -3, -4, -5
 STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ERANGE: "ERANGE", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", EDATA: "EDATA"}
 
 # Names the C ABI exports (include/cxbwt.h).
-ABI_FUNCTIONS = ("cxbwt_packed_words", "cxbwt_pack", "cxbwt_workspace_bytes", "cxbwt_build", "cxbwt_last_stats",
-                 "cxbwt_set_timing", "cxbwt_status_str")
+ABI_FUNCTIONS = ("cxbwt_packed_words", "cxbwt_pack", "cxbwt_workspace_bytes", "cxbwt_build",
+                 "cxbwt_batch_workspace_bytes", "cxbwt_build_batch", "cxbwt_last_stats", "cxbwt_set_timing",
+                 "cxbwt_status_str")
 
 # kernel classes of cxbwt_stats.ms / launches
 KERNEL_CLASSES = ("prep", "gen", "level_hist", "level_scan", "level_scatter", "local", "final_emit", "unused")
@@ -64,6 +65,10 @@ def lib():
             L.cxbwt_workspace_bytes.restype = ctypes.c_size_t
             L.cxbwt_build.argtypes = [vp, vp, u64, u64, u32, vp, vp, vp, ctypes.c_size_t, vp]
             L.cxbwt_build.restype = ctypes.c_int
+            L.cxbwt_batch_workspace_bytes.argtypes = [u64, u64, u32, u32]
+            L.cxbwt_batch_workspace_bytes.restype = ctypes.c_size_t
+            L.cxbwt_build_batch.argtypes = [vp, vp, u64, u64, u32, vp, u32, vp, vp, vp, ctypes.c_size_t, vp]
+            L.cxbwt_build_batch.restype = ctypes.c_int
             L.cxbwt_last_stats.argtypes = [ctypes.POINTER(Stats)]
             L.cxbwt_last_stats.restype = ctypes.c_int
             L.cxbwt_set_timing.argtypes = [ctypes.c_int]
@@ -136,6 +141,88 @@ def build(packed, offsets, n_reads: int, n_bases: int, max_read_len: int, worksp
     if st != OK:
         raise CxbwtError(st, "cxbwt_build")
     return bwt, term
+
+
+def batch_workspace_bytes(n_reads: int, n_bases: int, max_read_len: int, n_coll: int) -> int:
+    return int(lib().cxbwt_batch_workspace_bytes(n_reads, n_bases, max_read_len, n_coll))
+
+
+def build_batch(packed, offsets, n_reads: int, n_bases: int, max_read_len: int, coll_reads, workspace=None,
+                out=None, stream=None):
+    """BWTs of several collections laid end to end (see cxbwt_build_batch).
+
+    coll_reads: host sequence of n_coll + 1 read boundaries.  Returns the
+    concatenated BWTs (uint8 CUDA tensor) and per-read term_pos rows local to
+    each collection (int64 CUDA tensor).
+    """
+    import torch
+    cr = np.ascontiguousarray(np.asarray(coll_reads, dtype=np.uint64))
+    n_coll = cr.size - 1
+    dev = packed.device
+    if workspace is None:
+        nbytes = batch_workspace_bytes(n_reads, n_bases, max_read_len, n_coll)
+        if nbytes == 0:
+            raise CxbwtError(ERANGE, "cxbwt_batch_workspace_bytes")
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    if out is None:
+        bwt = torch.empty(n_bases + n_reads, dtype=torch.uint8, device=dev)
+        term = torch.empty(n_reads, dtype=torch.int64, device=dev)
+    else:
+        bwt, term = out
+    st = lib().cxbwt_build_batch(ctypes.c_void_p(packed.data_ptr()), ctypes.c_void_p(offsets.data_ptr()), n_reads,
+                                 n_bases, max_read_len, cr.ctypes.data_as(ctypes.c_void_p), n_coll,
+                                 ctypes.c_void_p(bwt.data_ptr()), ctypes.c_void_p(term.data_ptr()),
+                                 ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream_ptr(stream))
+    if st != OK:
+        raise CxbwtError(st, "cxbwt_build_batch")
+    return bwt, term
+
+
+def concat_collections(cols):
+    """Host-side concatenation: (text, global offsets, coll_reads, max_read_len)."""
+    texts = [np.asarray(c.text, dtype=np.uint8) for c in cols]
+    text = np.concatenate(texts) if texts else np.zeros(0, np.uint8)
+    offs = [np.zeros(1, dtype=np.uint64)]
+    base = 0
+    coll_reads = [0]
+    maxlen = 0
+    for c in cols:
+        o = np.asarray(c.offsets, dtype=np.uint64)
+        offs.append(o[1:] + np.uint64(base))
+        base += int(o[-1])
+        coll_reads.append(coll_reads[-1] + o.size - 1)
+        if o.size > 1:
+            maxlen = max(maxlen, int(np.max(np.diff(o.astype(np.int64)))))
+    return text, np.concatenate(offs), np.array(coll_reads, dtype=np.uint64), maxlen
+
+
+def split_batch_output(bwt: np.ndarray, term: np.ndarray, cols):
+    """Per-collection (bwt, term_pos) views of a batch result (host arrays)."""
+    out = []
+    b0 = 0
+    r0 = 0
+    for c in cols:
+        n, nb = c.n_reads, c.n_bases
+        out.append((bwt[b0:b0 + n + nb], term[r0:r0 + n]))
+        b0 += n + nb
+        r0 += n
+    return out
+
+
+def build_batch_host(cols, device="cuda"):
+    """Host collections in, per-collection host (bwt, term_pos) out."""
+    import torch
+    text, offsets, coll_reads, maxlen = concat_collections(cols)
+    n = offsets.size - 1
+    nb = int(offsets[-1])
+    t_dev = torch.from_numpy(text).to(device) if nb else torch.empty(0, dtype=torch.uint8, device=device)
+    o_dev = torch.from_numpy(offsets.view(np.int64)).to(device)
+    packed, pstatus = pack(t_dev)
+    bwt, term = build_batch(packed, o_dev, n, nb, maxlen, coll_reads)
+    torch.cuda.synchronize()
+    if int(pstatus.item()) != 0:
+        raise CxbwtError(EDATA, "cxbwt_pack (non-ACGT byte)")
+    return split_batch_output(bwt.cpu().numpy(), term.cpu().numpy().view(np.uint64), cols)
 
 
 def last_stats() -> dict:

@@ -84,3 +84,22 @@ def test_binding_has_no_cpu_fallback(monkeypatch, tmp_path):
     monkeypatch.setattr(cxbwt, "_lib", None)
     with pytest.raises(RuntimeError, match="missing"):
         cxbwt.lib()
+
+
+def test_batch_argument_validation_needs_no_gpu():
+    L = cxbwt.lib()
+    fake = ctypes.c_void_p(0x1000)
+    null = ctypes.c_void_p(0)
+
+    def call(coll, n=4, nb=40, wsb=1 << 40, ws=fake):
+        arr = (ctypes.c_uint64 * len(coll))(*coll)
+        return L.cxbwt_build_batch(fake, fake, n, nb, 10, arr, len(coll) - 1, fake, fake, ws, wsb, null)
+
+    assert call([0, 2, 3]) == cxbwt.EINVAL          # does not end at n_reads
+    assert call([1, 2, 4]) == cxbwt.EINVAL          # does not start at 0
+    assert call([0, 2, 2, 4]) == cxbwt.EINVAL       # empty collection
+    assert call([0, 2, 4], wsb=10) == cxbwt.ENOMEM
+    assert call([0, 2, 4], nb=1 << 32) == cxbwt.ERANGE
+    assert cxbwt.batch_workspace_bytes(4, 40, 10, 2) >= cxbwt.workspace_bytes(4, 40, 10)
+    assert cxbwt.batch_workspace_bytes(4, 40, 10, 0) == 0
+    assert cxbwt.batch_workspace_bytes(4, 40, 10, 5) == 0

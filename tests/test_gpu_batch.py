@@ -1,0 +1,76 @@
+"""Batched builds: every collection of a batch equals its build alone.
+
+Each collection's slice of cxbwt_build_batch output is compared bit for bit
+with the oracle on that collection alone and with cxbwt_build on that
+collection alone.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle
+from paper_1401_7457_amd import cxbwt, datagen
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    cxbwt.lib()
+
+
+def _check_batch(cols, label, alone=True):
+    _say(f"{label}: {len(cols)} collections, {sum(c.n_bases for c in cols)} bases")
+    outs = cxbwt.build_batch_host(cols)
+    for i, (c, (b, t)) in enumerate(zip(cols, outs)):
+        eb, et = oracle.bwt(c.text, c.offsets)
+        assert np.array_equal(b, eb), f"{label}: collection {i} BWT differs from the oracle"
+        assert np.array_equal(t, et), f"{label}: collection {i} term_pos differs from the oracle"
+        if alone:
+            ab, at = cxbwt.build_host(c.text, c.offsets)
+            assert np.array_equal(b, ab) and np.array_equal(t, at), f"{label}: collection {i} differs alone"
+
+
+def test_batch_of_mixed_sizes():
+    rng = np.random.default_rng(21)
+    cols = []
+    for k in range(24):
+        kind = k % 4
+        if kind == 0:
+            cols.append(datagen.random_collection(rng, int(rng.integers(1, 20)), [0, 1, 5, 28, 29, 57]))
+        elif kind == 1:
+            g = datagen.random_genome(rng, 5000)
+            cols.append(datagen.sample_reads(rng, g, int(rng.integers(50, 400)), 100, 0.01))
+        elif kind == 2:
+            cols.append(datagen.from_reads(["ACGT" * 10] * int(rng.integers(1, 80))))
+        else:
+            cols.append(datagen.from_reads([""] * 3 + ["A"] + [""]))
+    _check_batch(cols, "mixed")
+
+
+def test_single_collection_batch_equals_build():
+    col = datagen.plain_config(0, scale=0.2)
+    _check_batch([col], "one collection")
+
+
+def test_batch_shaped_like_the_batched_workload():
+    cols = datagen.batch_collections(count=12, scale=0.01)
+    _check_batch(cols, "batch recipe x0.01", alone=False)
+
+
+def test_batch_repeat_runs_identical():
+    cols = datagen.batch_collections(count=6, scale=0.005)
+    _say("batch determinism")
+    a = cxbwt.build_batch_host(cols)
+    b = cxbwt.build_batch_host(cols)
+    for (x, y), (u, v) in zip(a, b):
+        assert np.array_equal(x, u) and np.array_equal(y, v)
