@@ -63,6 +63,47 @@ def algorithmic_bytes(stats: dict, n_reads: int, n_bases: int) -> dict:
     }
 
 
+KERNELS_OF_CLASS = {
+    "prep": ["k_prep", "k_text_bases", "k_rank_count", "k_rank_top", "k_rank_words"],
+    "gen": ["k_gen_hist", "k_gen"],
+    "level_hist": ["k_level_hist"],
+    "level_scan": ["k_group_scan", "k_level_scan"],
+    "level_scatter": ["k_gen_scatter", "k_level_scatter"],
+    "local": ["k_local"],
+    "final_emit": ["k_emit_final", "k_term"],
+}
+
+
+def kernel_sources_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("cxbwt.hip", "device_common.h"):
+        with open(os.path.join(ROOT, "paper_1401_7457_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, kclass: str, launches_per_build: int):
+    """HBM bytes per launch of a kernel class from the committed counter runs.
+
+    None when no counter run exists for this workload, or when the kernel
+    sources changed since it was taken.
+    """
+    import json as _json
+    path = os.path.join(ROOT, "profiles", f"{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = _json.load(open(path))
+    if rec.get("kernel_sources_sha256_16") != kernel_sources_hash():
+        return None
+    tot = 0.0
+    for k in KERNELS_OF_CLASS.get(kclass, []):
+        e = rec["kernels"].get(k)
+        if e:
+            tot += (e["fetch_MB_per_dispatch"] + e["write_MB_per_dispatch"]) * 1e6 * e["dispatches_per_build"]
+    return tot / max(1, launches_per_build) if tot else None
+
+
 def cpu_baseline(scale: float, threads: int) -> dict:
     from oracle import oracle  # the CPU baseline leg is the oracle itself
     from paper_1401_7457_amd import datagen
@@ -146,7 +187,7 @@ def _serve_mode(args) -> dict:
     jobs = datagen.job_stream(count=args.jobs, rate_per_s=1.0, scale=args.scale)
     mean_bases = float(np.mean([j.collection.n_bases for j in jobs]))
     # capacity: throughput of one-at-a-time builds of these jobs
-    ex = serve.DeviceExecutor()
+    ex = serve.DeviceExecutor(keep_on_device=True)
     probe = jobs[: min(8, len(jobs))]
     rep0, _ = serve.replay([(0.0, j.collection) for j in probe], ex, int(args.budget_gb * 2 ** 30),
                            max_batch_jobs=1)
@@ -172,6 +213,7 @@ def _serve_mode(args) -> dict:
         "config": {"workload": f"served: Poisson arrivals at {args.load:g} x measured capacity, {len(jobs)} jobs, "
                                f"log-uniform 10k-5M reads x{args.scale:g}, L uniform 100-250, 1% subst",
                    "bases": total, "budget_gb": args.budget_gb},
+        "latency_note": "arrival to BWT complete on the device (device-to-host copy not included)",
         "latency_p50_s": c["latency_p50_s"],
         "latency_p99_s": c["latency_p99_s"],
         "mean_jobs_per_batch": c["mean_jobs_per_batch"],
@@ -301,7 +343,8 @@ def main() -> int:
         "config": {"workload": label, "reads": n, "bases": nb, "read_len": maxlen, "seed": col.seed,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(args.workload, dom, per_launch[dom]),
                      "avg_launch_ms": dom_ms / max(1, per_launch[dom]), "launches_per_step": per_launch[dom],
                      "algorithmic_bytes_per_step": model[dom]},
         "kernel_ms": per_ms,

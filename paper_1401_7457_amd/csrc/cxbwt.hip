@@ -105,26 +105,30 @@ struct Lists {
   unsigned long long *scattered;
 };
 
-// Number of read ends strictly before base p: the index of the read that
-// starts at p among the non-empty reads.  ebrank[w] counts the end bits of
-// words before w.
-__device__ __forceinline__ uint32_t end_rank(const uint64_t *__restrict__ endbits, const uint32_t *__restrict__ ebrank,
-                                             uint64_t p) {
-  const uint64_t w = endbits[p >> 6];
-  const uint64_t below = (p & 63) ? (w << (64 - (p & 63))) : 0ull;
-  return ebrank[p >> 6] + (uint32_t)__popcll(below);
+// Number of read starts strictly before base p: for the first base of a
+// read, the index of that read among the non-empty reads.  srank[w] counts
+// the start bits of records before w.
+__device__ __forceinline__ uint32_t start_rank(const TextRec *__restrict__ text, const uint32_t *__restrict__ srank,
+                                               uint64_t p) {
+  const uint32_t below = text[p >> 5].starts & ((1u << (p & 31)) - 1u);
+  return srank[p >> 5] + (uint32_t)__popc(below);
 }
 
 // Writes the BWT row of a sorted suffix; an offset-0 suffix also records its
 // row under its read's rank among the non-empty reads (k_term turns those
 // into term_pos).
 __device__ __forceinline__ void emit_row(uint64_t j, const CollMap &cm, uint64_t key, uint32_t p,
-                                         const uint64_t *__restrict__ endbits, const uint32_t *__restrict__ ebrank,
+                                         const TextRec *__restrict__ text, const uint32_t *__restrict__ srank,
                                          uint8_t *__restrict__ bwt, uint64_t *__restrict__ start_row) {
   const uint32_t pv = (uint32_t)key & 7u;
   const uint32_t lut = 'A' | ('C' << 8) | ('G' << 16) | ('T' << 24);
   bwt[j + cm.out_shift] = pv == 4 ? (uint8_t)'$' : (uint8_t)((lut >> (8 * pv)) & 0xFFu);
-  if (pv == 4) start_row[end_rank(endbits, ebrank, p)] = (uint64_t)((int64_t)j + cm.row_shift);
+  if (pv == 4) start_row[start_rank(text, srank, p)] = (uint64_t)((int64_t)j + cm.row_shift);
+}
+
+// Base t of the packed input (2 bits, first base of a word highest).
+__device__ __forceinline__ uint32_t base_at(const uint64_t *__restrict__ packed, uint64_t t) {
+  return (uint32_t)(packed[t >> 5] >> (62 - 2 * (t & 31))) & 3u;
 }
 
 __device__ __forceinline__ uint32_t find_upper(const uint32_t *prefix, uint32_t count, uint32_t x) {
@@ -184,7 +188,7 @@ __global__ void k_pack(const uint8_t *__restrict__ ascii, uint64_t nb, uint64_t 
 // ---------------------------------------------------------------------------
 __global__ void k_prep(const uint64_t *__restrict__ packed, const uint64_t *__restrict__ offsets, uint64_t n, uint64_t nb,
                        uint32_t maxlen, const uint64_t *__restrict__ coll_reads, uint32_t ncoll,
-                       unsigned long long *endbits, uint8_t *__restrict__ bwt, uint64_t *__restrict__ term_pos,
+                       TextRec *text, uint8_t *__restrict__ bwt, uint64_t *__restrict__ term_pos,
                        uint32_t *status) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -209,15 +213,23 @@ __global__ void k_prep(const uint64_t *__restrict__ packed, const uint64_t *__re
   // row (i - first_read) of the collection, whose output starts at byte
   // (bases before it) + (reads before it): byte offsets[first_read] + i
   const uint64_t out = offsets[first_read] + i;
+  if (i == n - 1) atomicOr(&text[nb >> 5].starts, 1u << (nb & 31));  // end of the text
   if (b > a) {
     const uint64_t e = b - 1;
-    atomicOr(&endbits[e >> 6], 1ull << (e & 63));
+    atomicOr(&text[a >> 5].starts, 1u << (a & 31));
     const uint32_t lut = 'A' | ('C' << 8) | ('G' << 16) | ('T' << 24);
     bwt[out] = (uint8_t)((lut >> (8 * base_at(packed, e))) & 0xFFu);
   } else {
     bwt[out] = (uint8_t)'$';
     term_pos[i] = i - first_read;
   }
+}
+
+// Bases of the text records (read starts were set by k_prep).
+__global__ void k_text_bases(const uint64_t *__restrict__ packed, uint64_t nwords, TextRec *__restrict__ text,
+                             uint64_t nrec) {
+  const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w < nrec) text[w].bases = w < nwords ? packed[w] : 0ull;
 }
 
 // First base of every collection (host needs them to lay out segments).
@@ -233,14 +245,14 @@ __global__ void k_coll_bases(const uint64_t *__restrict__ offsets, const uint64_
 constexpr int RANK_WPT = 16;                      // words per thread
 constexpr int RANK_BLOCK_WORDS = BLOCK * RANK_WPT;
 
-__global__ __launch_bounds__(BLOCK) void k_rank_count(const uint64_t *__restrict__ endbits, uint64_t nw,
+__global__ __launch_bounds__(BLOCK) void k_rank_count(const TextRec *__restrict__ text, uint64_t nw,
                                                       uint32_t *__restrict__ blocksum) {
   __shared__ uint32_t tmp[WAVES];
   const uint64_t w0 = (uint64_t)blockIdx.x * RANK_BLOCK_WORDS + (uint64_t)threadIdx.x * RANK_WPT;
   uint32_t c = 0;
 #pragma unroll
   for (int i = 0; i < RANK_WPT; ++i)
-    if (w0 + i < nw) c += (uint32_t)__popcll(endbits[w0 + i]);
+    if (w0 + i < nw) c += (uint32_t)__popc(text[w0 + i].starts);
   uint32_t total;
   block_excl_sum(c, tmp, &total);
   if (threadIdx.x == 0) blocksum[blockIdx.x] = total;
@@ -259,33 +271,34 @@ __global__ __launch_bounds__(BLOCK) void k_rank_top(uint32_t *__restrict__ block
   }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_rank_words(const uint64_t *__restrict__ endbits, uint64_t nw,
+__global__ __launch_bounds__(BLOCK) void k_rank_words(const TextRec *__restrict__ text, uint64_t nw,
                                                       const uint32_t *__restrict__ blocksum,
-                                                      uint32_t *__restrict__ ebrank) {
+                                                      uint32_t *__restrict__ srank) {
   __shared__ uint32_t tmp[WAVES];
   const uint64_t w0 = (uint64_t)blockIdx.x * RANK_BLOCK_WORDS + (uint64_t)threadIdx.x * RANK_WPT;
+  uint32_t cnt[RANK_WPT];
   uint32_t c = 0;
 #pragma unroll
-  for (int i = 0; i < RANK_WPT; ++i)
-    if (w0 + i < nw) c += (uint32_t)__popcll(endbits[w0 + i]);
+  for (int i = 0; i < RANK_WPT; ++i) {
+    cnt[i] = w0 + i < nw ? (uint32_t)__popc(text[w0 + i].starts) : 0u;
+    c += cnt[i];
+  }
   uint32_t run = blocksum[blockIdx.x] + block_excl_sum(c, tmp, nullptr);
 #pragma unroll
   for (int i = 0; i < RANK_WPT; ++i) {
-    if (w0 + i < nw) {
-      ebrank[w0 + i] = run;
-      run += (uint32_t)__popcll(endbits[w0 + i]);
-    }
+    if (w0 + i < nw) srank[w0 + i] = run;
+    run += cnt[i];
   }
 }
 
 // term_pos of every non-empty read from the row its offset-0 suffix recorded.
-__global__ void k_term(const uint64_t *__restrict__ offsets, uint64_t n, const uint64_t *__restrict__ endbits,
-                       const uint32_t *__restrict__ ebrank, const uint64_t *__restrict__ start_row,
+__global__ void k_term(const uint64_t *__restrict__ offsets, uint64_t n, const TextRec *__restrict__ text,
+                       const uint32_t *__restrict__ srank, const uint64_t *__restrict__ start_row,
                        uint64_t *__restrict__ term_pos) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const uint64_t a = offsets[i], b = offsets[i + 1];
-  if (b > a) term_pos[i] = start_row[end_rank(endbits, ebrank, a)];
+  if (b > a) term_pos[i] = start_row[start_rank(text, srank, a)];
 }
 
 // ---------------------------------------------------------------------------
@@ -293,8 +306,7 @@ __global__ void k_term(const uint64_t *__restrict__ offsets, uint64_t n, const u
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(BLOCK) void k_gen(const Seg *__restrict__ segs, const uint32_t *__restrict__ tile_prefix,
-                                               uint32_t nsegs, const uint64_t *__restrict__ packed,
-                                               const uint64_t *__restrict__ endbits, uint64_t nb,
+                                               uint32_t nsegs, const TextRec *__restrict__ text, uint64_t nb,
                                                uint64_t *__restrict__ keys, uint32_t *__restrict__ hdl) {
   const uint32_t tile = blockIdx.x;
   const uint32_t s = find_upper(tile_prefix, nsegs, tile);
@@ -302,7 +314,7 @@ __global__ __launch_bounds__(BLOCK) void k_gen(const Seg *__restrict__ segs, con
   const uint64_t t0 = sg.start + (uint64_t)(tile - tile_prefix[s]) * TILE;
   const uint64_t t1 = min(t0 + (uint64_t)TILE, sg.start + sg.len);
   for (uint64_t p = t0 + threadIdx.x; p < t1; p += BLOCK) {
-    keys[p] = first_key(packed, endbits, nb, p);
+    keys[p] = first_key(text, nb, p);
     hdl[p] = (uint32_t)p;
   }
 }
@@ -313,8 +325,7 @@ __global__ __launch_bounds__(BLOCK) void k_gen(const Seg *__restrict__ segs, con
 // and scattered; keys are never stored unsorted.  One segment per collection.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(BLOCK) void k_gen_hist(const Seg *__restrict__ segs, const uint32_t *__restrict__ tile_prefix,
-                                                    uint32_t nsegs, const uint64_t *__restrict__ packed,
-                                                    const uint64_t *__restrict__ endbits, uint64_t nb,
+                                                    uint32_t nsegs, const TextRec *__restrict__ text, uint64_t nb,
                                                     uint32_t *__restrict__ tile_hist) {
   __shared__ uint32_t hist[256];
   const uint32_t tile = blockIdx.x;
@@ -325,7 +336,7 @@ __global__ __launch_bounds__(BLOCK) void k_gen_hist(const Seg *__restrict__ segs
   hist[threadIdx.x] = 0;
   __syncthreads();
   for (uint64_t p = t0 + threadIdx.x; p < t1; p += BLOCK) {
-    const uint64_t k = first_key(packed, endbits, nb, p);
+    const uint64_t k = first_key(text, nb, p);
     atomicAdd(&hist[digit_of(k, 0)], 1u);
   }
   __syncthreads();
@@ -369,8 +380,7 @@ __device__ __forceinline__ void tile_scatter(ScatterSmem &S, const uint64_t (&kr
 __global__ __launch_bounds__(BLOCK) void k_gen_scatter(const Seg *__restrict__ segs,
                                                        const uint32_t *__restrict__ tile_prefix,
                                                        const uint32_t *__restrict__ group_prefix, uint32_t nsegs,
-                                                       const uint64_t *__restrict__ packed,
-                                                       const uint64_t *__restrict__ endbits, uint64_t nb,
+                                                       const TextRec *__restrict__ text, uint64_t nb,
                                                        const uint32_t *__restrict__ tile_hist,
                                                        const uint32_t *__restrict__ gsum, uint64_t *__restrict__ Ko,
                                                        uint32_t *__restrict__ Ho) {
@@ -387,7 +397,7 @@ __global__ __launch_bounds__(BLOCK) void k_gen_scatter(const Seg *__restrict__ s
   for (int i = 0; i < TILE_ITEMS; ++i) {
     const uint32_t li = item_index<TILE_ITEMS>(i);
     if (li < m) {
-      kr[i] = first_key(packed, endbits, nb, t0 + li);
+      kr[i] = first_key(text, nb, t0 + li);
       hr[i] = (uint32_t)(t0 + li);
       dig[i] = digit_of(kr[i], 0);
     } else {
@@ -410,8 +420,7 @@ __global__ __launch_bounds__(BLOCK) void k_gen_scatter(const Seg *__restrict__ s
 __global__ __launch_bounds__(BLOCK) void k_level_hist(const Seg *__restrict__ segs, const uint32_t *__restrict__ tile_prefix,
                                                       uint32_t nsegs, uint64_t *keys0, uint64_t *keys1,
                                                       const uint32_t *__restrict__ hdl0, const uint32_t *__restrict__ hdl1,
-                                                      const uint64_t *__restrict__ packed,
-                                                      const uint64_t *__restrict__ endbits, uint64_t nb,
+                                                      const TextRec *__restrict__ text, uint64_t nb,
                                                       uint32_t *__restrict__ tile_hist, unsigned long long *seg_or,
                                                       unsigned long long *seg_and) {
   __shared__ uint32_t hist[256];
@@ -429,7 +438,7 @@ __global__ __launch_bounds__(BLOCK) void k_level_hist(const Seg *__restrict__ se
   for (uint64_t j = t0 + threadIdx.x; j < t1; j += BLOCK) {
     uint64_t k = K[j];
     if (sg.regather) {
-      k = window_key(packed, endbits, nb, H[j], sg.r, (uint32_t)k & 7u);
+      k = window_key(text, nb, H[j], sg.r, (uint32_t)k & 7u);
       K[j] = k;
     }
     atomicAdd(&hist[digit_of(k, sg.d)], 1u);
@@ -645,8 +654,8 @@ __global__ __launch_bounds__(BLOCK) void k_level_scatter(const Seg *__restrict__
 __global__ __launch_bounds__(BLOCK) void k_emit_final(const Seg *__restrict__ segs, const uint32_t *__restrict__ tile_prefix,
                                                       uint32_t nsegs, const uint64_t *__restrict__ keys0,
                                                       const uint64_t *__restrict__ keys1, const uint32_t *__restrict__ hdl0,
-                                                      const uint32_t *__restrict__ hdl1, const uint64_t *__restrict__ endbits,
-                                                      const uint32_t *__restrict__ ebrank,
+                                                      const uint32_t *__restrict__ hdl1, const TextRec *__restrict__ text,
+                                                      const uint32_t *__restrict__ srank,
                                                       const CollMap *__restrict__ cmap, uint8_t *__restrict__ bwt,
                                                       uint64_t *__restrict__ start_row) {
   const uint32_t tile = blockIdx.x;
@@ -657,7 +666,7 @@ __global__ __launch_bounds__(BLOCK) void k_emit_final(const Seg *__restrict__ se
   const uint64_t *K = sg.buf ? keys1 : keys0;
   const uint32_t *H = sg.buf ? hdl1 : hdl0;
   const CollMap cm = cmap[sg.coll];
-  for (uint64_t j = t0 + threadIdx.x; j < t1; j += BLOCK) emit_row(j, cm, K[j], H[j], endbits, ebrank, bwt, start_row);
+  for (uint64_t j = t0 + threadIdx.x; j < t1; j += BLOCK) emit_row(j, cm, K[j], H[j], text, srank, bwt, start_row);
 }
 
 // ---------------------------------------------------------------------------
@@ -714,12 +723,16 @@ __device__ void lds_pass(LocalSmem &S, int src, uint32_t m, int sel) {
   __syncthreads();
 }
 
-// two workgroups per CU at 8 items per thread, four at 4, eight at 2
-__global__ __launch_bounds__(BLOCK, 16 / LOCAL_ITEMS) void k_local(const Seg *__restrict__ chunks, const uint64_t *__restrict__ keys0,
+// chunk workgroups resident per CU (also waves per SIMD: 4 waves each)
+#ifndef CXBWT_LOCAL_OCCUPANCY
+#define CXBWT_LOCAL_OCCUPANCY (16 / CXBWT_LOCAL_ITEMS)
+#endif
+constexpr int LOCAL_OCCUPANCY = CXBWT_LOCAL_OCCUPANCY;
+
+__global__ __launch_bounds__(BLOCK, LOCAL_OCCUPANCY) void k_local(const Seg *__restrict__ chunks, const uint64_t *__restrict__ keys0,
                                                     const uint64_t *__restrict__ keys1, const uint32_t *__restrict__ hdl0,
-                                                    const uint32_t *__restrict__ hdl1, const uint64_t *__restrict__ packed,
-                                                    const uint64_t *__restrict__ endbits,
-                                                    const uint32_t *__restrict__ ebrank,
+                                                    const uint32_t *__restrict__ hdl1, const TextRec *__restrict__ text,
+                                                    const uint32_t *__restrict__ srank,
                                                     const CollMap *__restrict__ cmap, uint64_t nb, uint32_t rmax,
                                                     uint8_t *__restrict__ bwt,
                                                     uint64_t *__restrict__ start_row, uint32_t *status,
@@ -800,7 +813,7 @@ __global__ __launch_bounds__(BLOCK, 16 / LOCAL_ITEMS) void k_local(const Seg *__
       for (int i = 0; i < LOCAL_ITEMS; ++i) {
         const uint32_t j = threadIdx.x + i * BLOCK;
         act[i] = j < m && !S.fin[j];
-        if (act[i]) ww[i] = window_load(packed, endbits, nb, S.H[cur][j], r);
+        if (act[i]) ww[i] = window_load(text, nb, S.H[cur][j], r);
       }
 #pragma unroll
       for (int i = 0; i < LOCAL_ITEMS; ++i) {
@@ -887,13 +900,13 @@ __global__ __launch_bounds__(BLOCK, 16 / LOCAL_ITEMS) void k_local(const Seg *__
   // a4: emit
   const CollMap cm = cmap[ch.coll];
   for (uint32_t j = threadIdx.x; j < m; j += BLOCK)
-    emit_row(ch.start + j, cm, S.K[cur][j], S.H[cur][j], endbits, ebrank, bwt, start_row);
+    emit_row(ch.start + j, cm, S.K[cur][j], S.H[cur][j], text, srank, bwt, start_row);
   nfetch = wave_incl_sum(nfetch);
   if (lane_id() == 63 && nfetch) atomicAdd(fetches, (unsigned long long)nfetch);
 }
 
 static_assert(CHUNK <= 65535, "group starts are 16-bit");
-static_assert(sizeof(LocalSmem) * (16 / LOCAL_ITEMS) <= 160 * 1024, "chunk workgroups per CU fit the LDS");
+static_assert(sizeof(LocalSmem) * LOCAL_OCCUPANCY <= 160 * 1024, "chunk workgroups per CU fit the LDS");
 
 // ---------------------------------------------------------------------------
 // host side
@@ -905,10 +918,10 @@ inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 inline uint64_t align_up(uint64_t x) { return (x + 255) & ~255ull; }
 
 struct Layout {
-  uint64_t keys0, keys1, hdl0, hdl1, endbits, ebrank, rank_blocks, start_row, tile_hist, gsum, segs, tile_prefix,
+  uint64_t keys0, keys1, hdl0, hdl1, text, srank, rank_blocks, start_row, tile_hist, gsum, segs, tile_prefix,
       group_prefix, seg_or, seg_and, seg_split, big_next, chunks, finals, coll_reads, coll_bases, cmap, counters,
       total;
-  uint64_t cap_big, cap_chunks, cap_finals, max_tiles, max_groups, endbit_words, n_rank_blocks;
+  uint64_t cap_big, cap_chunks, cap_finals, max_tiles, max_groups, n_rec, n_rank_blocks;
 };
 
 bool sizes_ok(uint64_t n_reads, uint64_t n_bases, uint32_t max_read_len) {
@@ -928,8 +941,8 @@ Layout make_layout(uint64_t n_reads, uint64_t nb, uint32_t n_coll) {
   L.cap_chunks = 2 * ceil_div(nb, CHUNK) + 2 * L.cap_big + n_coll + 2;
   L.max_tiles = ceil_div(nb, TILE) + L.cap_big + n_coll + 1;
   L.max_groups = ceil_div(L.max_tiles, GROUP_TILES) + L.cap_big + n_coll + 1;
-  L.endbit_words = nb / 64 + 2;
-  L.n_rank_blocks = ceil_div(L.endbit_words, RANK_BLOCK_WORDS);
+  L.n_rec = ceil_div(nb, 32) + 2;
+  L.n_rank_blocks = ceil_div(L.n_rec, RANK_BLOCK_WORDS);
   uint64_t off = 0;
   auto take = [&](uint64_t bytes) {
     uint64_t at = off;
@@ -941,8 +954,8 @@ Layout make_layout(uint64_t n_reads, uint64_t nb, uint32_t n_coll) {
   L.keys1 = take(8 * nb);
   L.hdl0 = take(4 * nb);
   L.hdl1 = take(4 * nb);
-  L.endbits = take(8 * L.endbit_words);
-  L.ebrank = take(4 * L.endbit_words);
+  L.text = take(sizeof(TextRec) * L.n_rec);
+  L.srank = take(4 * L.n_rec);
   L.rank_blocks = take(4 * L.n_rank_blocks);
   L.start_row = take(8 * n_reads);
   L.tile_hist = take(4 * 256 * L.max_tiles);
@@ -1063,8 +1076,9 @@ struct PhaseTimer {
 enum { C_STATUS = 0, C_NBIG = 1, C_NCHUNK = 2, C_NFINAL = 3, C_FETCH = 8, C_SCATTERED = 10, C_COUNT = 16 };
 
 struct Buffers {
-  uint64_t *keys0, *keys1, *endbits, *start_row, *coll_reads, *coll_bases;
-  uint32_t *hdl0, *hdl1, *ebrank, *rank_blocks, *tile_hist, *gsum, *tile_prefix, *group_prefix, *counters;
+  uint64_t *keys0, *keys1, *start_row, *coll_reads, *coll_bases;
+  TextRec *text;
+  uint32_t *hdl0, *hdl1, *srank, *rank_blocks, *tile_hist, *gsum, *tile_prefix, *group_prefix, *counters;
   Seg *segs, *big_next, *chunks, *finals;
   CollMap *cmap;
   unsigned long long *seg_or, *seg_and;
@@ -1093,13 +1107,13 @@ int upload_segments(const Buffers &B, const Layout &Lo, const std::vector<Seg> &
 }
 
 // Finish the chunks and final groups a level produced.
-int finish_level(const Buffers &B, const Layout &Lo, const uint64_t *packed, uint64_t nb, uint32_t rmax, uint8_t *bwt,
+int finish_level(const Buffers &B, const Layout &Lo, uint64_t nb, uint32_t rmax, uint8_t *bwt,
                  uint32_t n_chunks, uint32_t n_finals, std::vector<uint32_t> &tprefix, PhaseTimer &T,
                  hipStream_t st) {
   if (n_chunks > Lo.cap_chunks || n_finals > Lo.cap_finals) return CXBWT_EDEVICE;
   if (n_chunks) {
     T.begin();
-    k_local<<<n_chunks, BLOCK, 0, st>>>(B.chunks, B.keys0, B.keys1, B.hdl0, B.hdl1, packed, B.endbits, B.ebrank, B.cmap,
+    k_local<<<n_chunks, BLOCK, 0, st>>>(B.chunks, B.keys0, B.keys1, B.hdl0, B.hdl1, B.text, B.srank, B.cmap,
                                         nb, rmax, bwt, B.start_row, B.counters + C_STATUS,
                                         (unsigned long long *)(B.counters + C_FETCH));
     CX_LAUNCHED();
@@ -1119,7 +1133,7 @@ int finish_level(const Buffers &B, const Layout &Lo, const uint64_t *packed, uin
     CX_CHECK(hipMemcpyAsync(B.tile_prefix, tprefix.data(), 4 * (n_finals + 1), hipMemcpyHostToDevice, st));
     T.begin();
     k_emit_final<<<tprefix[n_finals], BLOCK, 0, st>>>(B.finals, B.tile_prefix, n_finals, B.keys0, B.keys1, B.hdl0,
-                                                      B.hdl1, B.endbits, B.ebrank, B.cmap, bwt, B.start_row);
+                                                      B.hdl1, B.text, B.srank, B.cmap, bwt, B.start_row);
     CX_LAUNCHED();
     T.end(PH_FINAL);
     g_stats.final_big += n_finals;
@@ -1141,8 +1155,8 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
   B.keys1 = (uint64_t *)(ws + Lo.keys1);
   B.hdl0 = (uint32_t *)(ws + Lo.hdl0);
   B.hdl1 = (uint32_t *)(ws + Lo.hdl1);
-  B.endbits = (uint64_t *)(ws + Lo.endbits);
-  B.ebrank = (uint32_t *)(ws + Lo.ebrank);
+  B.text = (TextRec *)(ws + Lo.text);
+  B.srank = (uint32_t *)(ws + Lo.srank);
   B.rank_blocks = (uint32_t *)(ws + Lo.rank_blocks);
   B.start_row = (uint64_t *)(ws + Lo.start_row);
   B.tile_hist = (uint32_t *)(ws + Lo.tile_hist);
@@ -1165,11 +1179,11 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
 
   int rc;
   if ((rc = fill_u32(counters, C_COUNT, 0, st))) return rc;
-  if ((rc = fill_u64(B.endbits, Lo.endbit_words, 0, st))) return rc;
+  if ((rc = fill_u64((uint64_t *)B.text, 2 * Lo.n_rec, 0, st))) return rc;
   CX_CHECK(hipMemcpyAsync(B.coll_reads, coll_reads, 8 * ((uint64_t)ncoll + 1), hipMemcpyHostToDevice, st));
   T.begin();
-  k_prep<<<grid_for(n, 256), 256, 0, st>>>(packed, offsets, n, nb, maxlen, B.coll_reads, ncoll,
-                                          (unsigned long long *)B.endbits, bwt, term_pos, counters + C_STATUS);
+  k_prep<<<grid_for(n, 256), 256, 0, st>>>(packed, offsets, n, nb, maxlen, B.coll_reads, ncoll, B.text, bwt,
+                                          term_pos, counters + C_STATUS);
   CX_LAUNCHED();
   T.end(PH_PREP);
   k_coll_bases<<<grid_for((uint64_t)ncoll + 1, 256), 256, 0, st>>>(offsets, B.coll_reads, ncoll, B.coll_bases);
@@ -1200,11 +1214,13 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
   g_stats.chunk_suffixes = nb;
   // ranks of the read ends, for term_pos
   T.begin();
-  k_rank_count<<<(unsigned)Lo.n_rank_blocks, BLOCK, 0, st>>>(B.endbits, Lo.endbit_words, B.rank_blocks);
+  k_text_bases<<<grid_for(Lo.n_rec, 256), 256, 0, st>>>(packed, cxbwt_packed_words(nb), B.text, Lo.n_rec);
+  CX_LAUNCHED();
+  k_rank_count<<<(unsigned)Lo.n_rank_blocks, BLOCK, 0, st>>>(B.text, Lo.n_rec, B.rank_blocks);
   CX_LAUNCHED();
   k_rank_top<<<1, BLOCK, 0, st>>>(B.rank_blocks, (uint32_t)Lo.n_rank_blocks);
   CX_LAUNCHED();
-  k_rank_words<<<(unsigned)Lo.n_rank_blocks, BLOCK, 0, st>>>(B.endbits, Lo.endbit_words, B.rank_blocks, B.ebrank);
+  k_rank_words<<<(unsigned)Lo.n_rank_blocks, BLOCK, 0, st>>>(B.text, Lo.n_rec, B.rank_blocks, B.srank);
   CX_LAUNCHED();
   T.end(PH_PREP);
 
@@ -1218,13 +1234,13 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
   if (!small.empty()) {
     if ((rc = upload_segments(B, Lo, small, tprefix, gprefix, ntiles, ngroups, st))) return rc;
     T.begin();
-    k_gen<<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, (uint32_t)small.size(), packed, B.endbits, nb, B.keys0,
+    k_gen<<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, (uint32_t)small.size(), B.text, nb, B.keys0,
                                     B.hdl0);
     CX_LAUNCHED();
     T.end(PH_GEN);
     CX_CHECK(hipMemcpyAsync(B.chunks, small.data(), sizeof(Seg) * small.size(), hipMemcpyHostToDevice, st));
     if (big.empty()) {
-      if ((rc = finish_level(B, Lo, packed, nb, rmax, bwt, (uint32_t)small.size(), 0, tprefix, T, st))) return rc;
+      if ((rc = finish_level(B, Lo, nb, rmax, bwt, (uint32_t)small.size(), 0, tprefix, T, st))) return rc;
     } else {
       // level 1 appends its chunks after these
       const uint32_t nsmall = (uint32_t)small.size();
@@ -1237,7 +1253,7 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
     const uint32_t ns = (uint32_t)big.size();
     if ((rc = upload_segments(B, Lo, big, tprefix, gprefix, ntiles, ngroups, st))) return rc;
     T.begin();
-    k_gen_hist<<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, ns, packed, B.endbits, nb, B.tile_hist);
+    k_gen_hist<<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, ns, B.text, nb, B.tile_hist);
     CX_LAUNCHED();
     T.end(PH_GEN);
     T.begin();
@@ -1247,7 +1263,7 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
     CX_LAUNCHED();
     T.end(PH_SCAN);
     T.begin();
-    k_gen_scatter<<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, B.group_prefix, ns, packed, B.endbits, nb,
+    k_gen_scatter<<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, B.group_prefix, ns, B.text, nb,
                                             B.tile_hist, B.gsum, B.keys1, B.hdl1);
     CX_LAUNCHED();
     T.end(PH_SCATTER);
@@ -1263,7 +1279,7 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
       CX_CHECK(hipMemcpyAsync(big.data(), B.big_next, sizeof(Seg) * big.size(), hipMemcpyDeviceToHost, st));
       CX_CHECK(hipStreamSynchronize(st));
     }
-    if ((rc = finish_level(B, Lo, packed, nb, rmax, bwt, hc[C_NCHUNK], hc[C_NFINAL], tprefix, T, st))) return rc;
+    if ((rc = finish_level(B, Lo, nb, rmax, bwt, hc[C_NCHUNK], hc[C_NFINAL], tprefix, T, st))) return rc;
     // levels 2..
     while (!big.empty()) {
       const uint32_t nsg = (uint32_t)big.size();
@@ -1278,8 +1294,8 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
       if ((rc = fill_u64((uint64_t *)B.seg_and, nsg, ~0ull, st))) return rc;
       if ((rc = fill_u32(counters + C_NBIG, 3, 0, st))) return rc;  // big, chunk and final counts
       T.begin();
-      k_level_hist<<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, nsg, B.keys0, B.keys1, B.hdl0, B.hdl1, packed,
-                                             B.endbits, nb, B.tile_hist, B.seg_or, B.seg_and);
+      k_level_hist<<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, nsg, B.keys0, B.keys1, B.hdl0, B.hdl1, B.text,
+                                             nb, B.tile_hist, B.seg_or, B.seg_and);
       CX_LAUNCHED();
       T.end(PH_HIST);
       T.begin();
@@ -1304,11 +1320,11 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
         CX_CHECK(hipMemcpyAsync(big.data(), B.big_next, sizeof(Seg) * big.size(), hipMemcpyDeviceToHost, st));
         CX_CHECK(hipStreamSynchronize(st));
       }
-      if ((rc = finish_level(B, Lo, packed, nb, rmax, bwt, hc[C_NCHUNK], hc[C_NFINAL], tprefix, T, st))) return rc;
+      if ((rc = finish_level(B, Lo, nb, rmax, bwt, hc[C_NCHUNK], hc[C_NFINAL], tprefix, T, st))) return rc;
     }
   }
   T.begin();
-  k_term<<<grid_for(n, 256), 256, 0, st>>>(offsets, n, B.endbits, B.ebrank, B.start_row, term_pos);
+  k_term<<<grid_for(n, 256), 256, 0, st>>>(offsets, n, B.text, B.srank, B.start_row, term_pos);
   CX_LAUNCHED();
   T.end(PH_FINAL);
   CX_CHECK(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, st));

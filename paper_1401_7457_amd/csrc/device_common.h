@@ -32,74 +32,81 @@ __device__ __forceinline__ uint32_t digit_of(uint64_t k, int j) {
 __host__ __device__ __forceinline__ uint64_t digit_mask(int j) {
   return j < 7 ? (0xFFull << (56 - 8 * j)) : (0x1Full << 3);
 }
-__device__ __forceinline__ uint32_t base_at(const uint64_t *packed, uint64_t t) {
-  return (uint32_t)(packed[t >> 5] >> (62 - 2 * (t & 31))) & 3u;
-}
-__device__ __forceinline__ bool end_bit(const uint64_t *endbits, uint64_t t) {
-  return (endbits[t >> 6] >> (t & 63)) & 1ull;
-}
-
-// The four words a window key is built from; every load is issued before any
-// is used so many windows can be in flight per thread.  Addresses are clamped
-// into the arrays (a clamped read is never used): endbits holds nb/64 + 2
-// words, packed holds ceil(nb/32) + 1 words, and nb >= 1.
-struct WinWords {
-  uint64_t e0, e1, c0, c1;
+// ---------------------------------------------------------------------------
+// Text records: the 2-bit bases interleaved with read-start bits, 16 bytes
+// per 32 bases, so that one window of any suffix is a single 32-byte read.
+//   bases   32 bases, first base in the top two bits (the packed input word)
+//   starts  bit t set when base 32*w + t is the first base of a non-empty
+//           read; one extra start bit marks position B (the end of the text)
+// A record array holds ceil(B/32) + 2 records; the last ones are padding.
+// ---------------------------------------------------------------------------
+struct alignas(16) TextRec {
+  uint64_t bases;
+  uint32_t starts;
+  uint32_t pad;
 };
 
-__device__ __forceinline__ WinWords window_load(const uint64_t *__restrict__ packed,
-                                                const uint64_t *__restrict__ endbits, uint64_t nb, uint64_t p,
+__device__ __forceinline__ uint32_t rec_base(const TextRec *__restrict__ text, uint64_t t) {
+  return (uint32_t)(text[t >> 5].bases >> (62 - 2 * (t & 31))) & 3u;
+}
+__device__ __forceinline__ bool rec_start(const TextRec *__restrict__ text, uint64_t t) {
+  return (text[t >> 5].starts >> (t & 31)) & 1u;
+}
+
+// The two records a window key is built from, loaded before use so many
+// windows can be in flight per thread.  The record index is clamped into the
+// array (a clamped read is never used).
+struct WinWords {
+  TextRec a, b;
+};
+
+__device__ __forceinline__ WinWords window_load(const TextRec *__restrict__ text, uint64_t nb, uint64_t p,
                                                 uint32_t r) {
   const uint64_t q = p + (uint64_t)W * r;
-  uint64_t lo = r == 0 ? p : q - 1;
-  lo = lo < nb ? lo : nb - 1;
-  const uint64_t qc = q < nb ? q : nb - 1;
+  const uint64_t qc = q <= nb ? q : nb;
   WinWords w;
-  w.e0 = endbits[lo >> 6];
-  w.e1 = endbits[(lo >> 6) + 1];
-  w.c0 = packed[qc >> 5];
-  w.c1 = packed[(qc >> 5) + 1];
+  w.a = text[qc >> 5];
+  w.b = text[(qc >> 5) + 1];
   return w;
 }
 
 // Key of window r of the suffix starting at base p (the window starts at
-// q = p + 28 r).  endbits marks the last base of every non-empty read.  For
-// r >= 1 the suffix is live: its read holds at least 28 r bases from p, so
-// the read's last base e is at least q - 1.
+// q = p + 28 r).  The suffix's read ends just before the first read start s
+// after p; the window holds min(s - q, 28) bases.  For r >= 1 the suffix is
+// live: its read holds at least 28 r bases from p, so s >= q.
 __device__ __forceinline__ uint64_t window_combine(const WinWords &w, uint64_t nb, uint64_t p, uint32_t r,
                                                    uint32_t prev3) {
   const uint64_t q = p + (uint64_t)W * r;
-  const uint64_t lo = r == 0 ? p : q - 1;
-  if (lo >= nb) return prev3;  // never taken for a live suffix
-  const uint64_t w0 = w.e0 >> (lo & 63);
-  uint64_t e;
-  if (w0) e = lo + (uint64_t)__builtin_ctzll(w0);
-  else e = w.e1 ? ((lo | 63ull) + 1) + (uint64_t)__builtin_ctzll(w.e1) : ~0ull;
-  const uint32_t clamp = (e < q + W) ? (uint32_t)(e + 1 - q) : (uint32_t)W;
+  if (q > nb) return prev3;  // never taken for a live suffix
+  const uint64_t lo = r == 0 ? p + 1 : q;          // first position a start may sit at
+  const uint32_t o = (uint32_t)(lo - ((q >> 5) << 5));  // 0..32, offset of lo in the record pair
+  const uint64_t st = ((uint64_t)w.b.starts << 32) | w.a.starts;
+  const uint64_t from = o < 64 ? st >> o : 0ull;
+  const uint64_t s_rel = from ? (uint64_t)o + (uint64_t)__builtin_ctzll(from) : ~0ull;  // start - 32*(q>>5)
+  const uint64_t q_rel = q & 31;
+  const uint32_t clamp = (s_rel != ~0ull && s_rel < q_rel + W) ? (uint32_t)(s_rel - q_rel) : (uint32_t)W;
   uint64_t chars = 0;
-  if (clamp > 0 && q < nb) {
-    const uint32_t b = 2u * (uint32_t)(q & 31);
-    uint64_t x = w.c0 << b;
-    if (b) x |= w.c1 >> (64 - b);
+  if (clamp > 0) {
+    const uint32_t b = 2u * (uint32_t)q_rel;
+    uint64_t x = w.a.bases << b;
+    if (b) x |= w.b.bases >> (64 - b);
     chars = x & ~0xFFull;
     if (clamp < (uint32_t)W) chars &= ~((1ull << (64 - 2 * clamp)) - 1);
   }
   return chars | ((uint64_t)clamp << 3) | prev3;
 }
 
-__device__ __forceinline__ uint64_t window_key(const uint64_t *__restrict__ packed,
-                                               const uint64_t *__restrict__ endbits, uint64_t nb, uint64_t p,
-                                               uint32_t r, uint32_t prev3) {
-  return window_combine(window_load(packed, endbits, nb, p, r), nb, p, r, prev3);
+__device__ __forceinline__ uint64_t window_key(const TextRec *__restrict__ text, uint64_t nb, uint64_t p, uint32_t r,
+                                               uint32_t prev3) {
+  return window_combine(window_load(text, nb, p, r), nb, p, r, prev3);
 }
 
 // Window-0 key of the suffix starting at base p, with its preceding symbol:
-// '$' when p starts a read (p == 0 or base p-1 ends a read).
-__device__ __forceinline__ uint64_t first_key(const uint64_t *__restrict__ packed,
-                                              const uint64_t *__restrict__ endbits, uint64_t nb, uint64_t p) {
-  const WinWords w = window_load(packed, endbits, nb, p, 0);
+// '$' when p starts a read, else base p-1.
+__device__ __forceinline__ uint64_t first_key(const TextRec *__restrict__ text, uint64_t nb, uint64_t p) {
+  const WinWords w = window_load(text, nb, p, 0);
   uint32_t prev3 = 4;
-  if (p > 0 && !end_bit(endbits, p - 1)) prev3 = base_at(packed, p - 1);
+  if (!((w.a.starts >> (p & 31)) & 1u)) prev3 = rec_base(text, p - 1);
   return window_combine(w, nb, p, 0, prev3);
 }
 

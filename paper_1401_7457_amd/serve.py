@@ -80,9 +80,14 @@ def state_bytes(n_reads: int, n_bases: int) -> int:
 
 
 class DeviceExecutor(Executor):
-    """Stages jobs on the device and builds batches with cxbwt_build_batch."""
+    """Stages jobs on the device and builds batches with cxbwt_build_batch.
 
-    def __init__(self, device="cuda", max_read_len: Optional[int] = None):
+    keep_on_device: results stay as device tensors (latency = device
+    completion, the copy to the host is the caller's); otherwise they are
+    copied to host arrays before the job completes.
+    """
+
+    def __init__(self, device="cuda", keep_on_device: bool = False):
         import torch
 
         from . import cxbwt
@@ -90,7 +95,7 @@ class DeviceExecutor(Executor):
         self.cx = cxbwt
         self.device = torch.device(device)
         self.copy_stream = torch.cuda.Stream(device=self.device)
-        self.max_read_len = max_read_len
+        self.keep_on_device = keep_on_device
         cxbwt.lib()
 
     def footprint(self, col) -> int:
@@ -100,49 +105,48 @@ class DeviceExecutor(Executor):
         torch = self.torch
         col = job.collection
         with torch.cuda.stream(self.copy_stream):
-            text = torch.from_numpy(np.ascontiguousarray(col.text)).pin_memory()
-            offs = torch.from_numpy(np.ascontiguousarray(col.offsets).view(np.int64)).pin_memory()
-            t_dev = text.to(self.device, non_blocking=True)
-            o_dev = offs.to(self.device, non_blocking=True)
+            t_dev = torch.from_numpy(np.ascontiguousarray(col.text)).to(self.device, non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(self.copy_stream)
-        job.handle = (t_dev, o_dev, ev, col.max_read_len)
+        job.handle = (t_dev, ev)
 
     def run_batch(self, jobs: list[Job]) -> list[tuple]:
         torch, cx = self.torch, self.cx
         stream = torch.cuda.current_stream(self.device)
         for j in jobs:
-            stream.wait_event(j.handle[2])
+            stream.wait_event(j.handle[1])
+        cols = [j.collection for j in jobs]
+        _, offsets_h, coll_reads, maxlen = cx.concat_collections([_Shape(c) for c in cols])
+        nbs = [c.n_bases for c in cols]
+        ns = [c.n_reads for c in cols]
+        n, nb = int(coll_reads[-1]), int(offsets_h[-1])
         texts = [j.handle[0] for j in jobs]
-        nbs = [int(t.numel()) for t in texts]
-        ns = [int(j.handle[1].numel()) - 1 for j in jobs]
-        maxlen = max(j.handle[3] for j in jobs)
-        if self.max_read_len:
-            maxlen = max(maxlen, self.max_read_len)
-        text = torch.cat(texts) if sum(nbs) else torch.empty(0, dtype=torch.uint8, device=self.device)
-        parts = [torch.zeros(1, dtype=torch.int64, device=self.device)]
-        base = 0
-        for j, nb in zip(jobs, nbs):
-            parts.append(j.handle[1][1:] + base)
-            base += nb
-        offsets = torch.cat(parts)
-        coll_reads = np.concatenate([[0], np.cumsum(ns)]).astype(np.uint64)
-        n, nb = int(coll_reads[-1]), base
+        text = torch.cat(texts) if nb else torch.empty(0, dtype=torch.uint8, device=self.device)
+        offsets = torch.from_numpy(offsets_h.view(np.int64)).to(self.device)
         packed, pstatus = cx.pack(text)
         bwt, term = cx.build_batch(packed, offsets, n, nb, maxlen, coll_reads)
-        bwt_h = bwt.cpu().numpy()
-        term_h = term.cpu().numpy().view(np.uint64)
         if int(pstatus.item()) != 0:
             raise cx.CxbwtError(cx.EDATA, "cxbwt_pack (non-ACGT byte)")
+        if not self.keep_on_device:
+            bwt = bwt.cpu().numpy()
+            term = term.cpu().numpy().view(np.uint64)
         out, b0, r0 = [], 0, 0
         for nj, nbj in zip(ns, nbs):
-            out.append((bwt_h[b0:b0 + nj + nbj].copy(), term_h[r0:r0 + nj].copy()))
+            out.append((bwt[b0:b0 + nj + nbj], term[r0:r0 + nj]))
             b0 += nj + nbj
             r0 += nj
         return out
 
     def release(self, job: Job) -> None:
         job.handle = None
+
+
+class _Shape:
+    """Offsets-only view of a collection (the batch's text is already on the device)."""
+
+    def __init__(self, col):
+        self.offsets = col.offsets
+        self.text = np.zeros(0, dtype=np.uint8)
 
 
 class Server:
