@@ -43,7 +43,7 @@ def algorithmic_bytes(stats: dict, n_reads: int, n_bases: int) -> dict:
                   written); later levels: 24 B per moved suffix (key + handle
                   read and written)
     local         13 B per suffix (key + handle read, 1 B BWT written) + 16 B per
-                  later-window fetch (8 B of bases, 8 B of end bits) + 8 B per read
+                  later-window text read (bases and read starts) + 8 B per read
     final_emit    13 B per suffix
     prep          17 B per read (two offsets, one BWT byte) + 0.19 B per base
                   (end-bit ranks)

@@ -131,6 +131,20 @@ __device__ __forceinline__ uint32_t base_at(const uint64_t *__restrict__ packed,
   return (uint32_t)(packed[t >> 5] >> (62 - 2 * (t & 31))) & 3u;
 }
 
+// Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.  The
+// scatters give consecutive tiles to the same XCD (tile = xcd * (N/8) + k
+// for the k-th workgroup of an XCD), so that the partial cache lines that
+// neighbouring tiles write into one bucket meet in the same L2.
+#ifndef CXBWT_XCDS
+#define CXBWT_XCDS 8
+#endif
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t n) {
+  const uint32_t per = n / CXBWT_XCDS;
+  const uint32_t full = per * CXBWT_XCDS;
+  if (CXBWT_XCDS <= 1 || b >= full) return b;
+  return (b % CXBWT_XCDS) * per + b / CXBWT_XCDS;
+}
+
 __device__ __forceinline__ uint32_t find_upper(const uint32_t *prefix, uint32_t count, uint32_t x) {
   // largest s < count with prefix[s] <= x (prefix[0] == 0, non-decreasing)
   uint32_t lo = 0, hi = count;
@@ -385,7 +399,7 @@ __global__ __launch_bounds__(BLOCK) void k_gen_scatter(const Seg *__restrict__ s
                                                        const uint32_t *__restrict__ gsum, uint64_t *__restrict__ Ko,
                                                        uint32_t *__restrict__ Ho) {
   __shared__ ScatterSmem S;
-  const uint32_t tile = blockIdx.x;
+  const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
   const uint32_t s = find_upper(tile_prefix, nsegs, tile);
   const Seg sg = segs[s];
   const uint32_t tl = tile - tile_prefix[s];
@@ -466,6 +480,7 @@ __global__ __launch_bounds__(BLOCK) void k_group_scan(const uint32_t *__restrict
   const uint32_t te = min(tb + (uint32_t)GROUP_TILES, tile_prefix[s + 1]);
   const uint32_t d = threadIdx.x;
   uint32_t run = 0;
+#pragma unroll 8
   for (uint32_t t = tb; t < te; ++t) {
     const uint64_t at = (uint64_t)t * 256 + d;
     const uint32_t c = tile_hist[at];
@@ -511,6 +526,7 @@ __global__ __launch_bounds__(BLOCK) void k_level_scan(const Seg *__restrict__ se
   const uint32_t gp0 = group_prefix[s], gp1 = group_prefix[s + 1];
   const uint32_t dg = threadIdx.x;
   uint32_t total = 0;
+#pragma unroll 8
   for (uint32_t g = gp0; g < gp1; ++g) total += gsum[(uint64_t)g * 256 + dg];
   tot[dg] = total;
   if (dg == 0) single = 0;
@@ -545,6 +561,7 @@ __global__ __launch_bounds__(BLOCK) void k_level_scan(const Seg *__restrict__ se
   const uint32_t ex = block_excl_sum(total, tmp, nullptr);
   bstart[dg] = ex;
   uint32_t run = (uint32_t)sg.start + ex;
+#pragma unroll 8
   for (uint32_t g = gp0; g < gp1; ++g) {
     const uint64_t at = (uint64_t)g * 256 + dg;
     const uint32_t c = gsum[at];
@@ -618,7 +635,7 @@ __global__ __launch_bounds__(BLOCK) void k_level_scatter(const Seg *__restrict__
                                                          const uint32_t *__restrict__ gsum, uint64_t *keys0,
                                                          uint64_t *keys1, uint32_t *hdl0, uint32_t *hdl1) {
   __shared__ ScatterSmem S;
-  const uint32_t tile = blockIdx.x;
+  const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
   const uint32_t s = find_upper(tile_prefix, nsegs, tile);
   if (!seg_split[s]) return;
   const Seg sg = segs[s];

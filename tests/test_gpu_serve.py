@@ -23,9 +23,16 @@ def test_served_jobs_match_alone_and_oracle():
     print(f"[case] served: {len(jobs)} jobs, {sum(j.collection.n_bases for j in jobs)} bases", flush=True)
     sys.stdout.flush()
     ex = serve.DeviceExecutor()
-    rep, done = serve.replay([(j.arrival_s, j.collection) for j in jobs], ex, budget_bytes=8 << 30)
+    # a burst (every job arrives at once, staged in the loop): one batch holds them all
+    rep, done = serve.replay([(0.0, j.collection) for j in jobs], ex, budget_bytes=8 << 30,
+                             stage_in_background=False)
     assert rep["jobs_done"] == len(jobs)
-    assert rep["batches"] < len(jobs)  # some jobs were built together
+    assert rep["batches"] == 1
+    # the same jobs on their Poisson arrivals with the background stager
+    rep2, done2 = serve.replay([(j.arrival_s, j.collection) for j in jobs], ex, budget_bytes=8 << 30)
+    assert rep2["jobs_done"] == len(jobs)
+    for a, b in zip(done, done2):
+        assert np.array_equal(a.result[0], b.result[0]) and np.array_equal(a.result[1], b.result[1])
     for j in done:
         c = j.collection
         eb, et = oracle.bwt(c.text, c.offsets)
