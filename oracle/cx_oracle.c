@@ -257,3 +257,130 @@ int cx_oracle_bwt(const uint8_t *text, const uint64_t *offsets, uint64_t n_reads
   free(pairs);
   return ORACLE_OK;
 }
+
+/*
+ * cx_check_bwt: the properties every multi-string BWT satisfies, checked in
+ * O(N) memory for very large outputs (test infrastructure):
+ *   1. symbol counts: the input bases plus one '$' per read;
+ *   2. rows 0..n-1 are $_0..$_{n-1}: row i holds read i's last base ('$' if
+ *      the read is empty);
+ *   3. the LF walk from row i (LF(rho) = C[b] + #{rho' < rho : bwt[rho'] = b})
+ *      spells read i backwards and stops on row term_pos[i] holding '$'.
+ * Together these leave one possible string: the BWT.  Returns 0 when all
+ * hold, otherwise a positive code naming the first property that failed.
+ */
+typedef struct {
+  const uint8_t *bwt;
+  const uint64_t *term_pos;
+  const uint8_t *text;
+  const uint64_t *offsets;
+  const uint64_t *occ_base; /* per 64-row block: symbol counts before the block, 5 per block */
+  uint64_t C[5];
+  uint64_t r0, r1;          /* reads [r0, r1) */
+  int failed;
+} lf_job_t;
+
+/* symbol code: 0 = '$', then A, C, G, T in their sort order; -1 for any other
+ * byte (a table, filled once by cx_check_bwt before any worker starts) */
+static signed char sym_table[256];
+
+static void fill_sym_table(void) {
+  static const char order[5] = {'$', 'A', 'C', 'G', 'T'};
+  memset(sym_table, -1, sizeof(sym_table));
+  for (int s = 0; s < 5; ++s) sym_table[(uint8_t)order[s]] = (signed char)s;
+}
+
+static inline int sym_code(uint8_t c) { return sym_table[c]; }
+
+/* rank of symbol code s before row rho: block counts plus a scan inside the block */
+static uint64_t occ_before(const lf_job_t *j, int s, uint64_t rho) {
+  uint64_t blk = rho >> 6;
+  uint64_t c = j->occ_base[blk * 5 + (uint64_t)s];
+  for (uint64_t t = blk << 6; t < rho; ++t) c += (sym_code(j->bwt[t]) == s);
+  return c;
+}
+
+static void *lf_worker(void *p) {
+  lf_job_t *j = (lf_job_t *)p;
+  for (uint64_t i = j->r0; i < j->r1 && !j->failed; ++i) {
+    uint64_t a = j->offsets[i], b = j->offsets[i + 1];
+    uint64_t rho = i; /* row of the bare terminator $_i */
+    for (uint64_t step = 0;; ++step) {
+      int s = sym_code(j->bwt[rho]);
+      if (step == b - a) {
+        if (s != 0 || j->term_pos[i] != rho) j->failed = 3;
+        break;
+      }
+      uint8_t want = j->text[b - 1 - step];
+      if (j->bwt[rho] != want) {
+        j->failed = 3;
+        break;
+      }
+      rho = j->C[s] + occ_before(j, s, rho);
+    }
+  }
+  return NULL;
+}
+
+int cx_check_bwt(const uint8_t *bwt, const uint64_t *term_pos, const uint8_t *text, const uint64_t *offsets,
+                 uint64_t n_reads, uint64_t n_bases, int threads) {
+  uint64_t total = n_bases + n_reads;
+  uint64_t cnt[5] = {0, 0, 0, 0, 0}, want[5] = {0, 0, 0, 0, 0};
+  fill_sym_table();
+  /* 1. counts */
+  for (uint64_t t = 0; t < total; ++t) {
+    int s = sym_code(bwt[t]);
+    if (s < 0) return 1;
+    cnt[s]++;
+  }
+  for (uint64_t t = 0; t < n_bases; ++t) {
+    int s = sym_code(text[t]);
+    if (s < 1) return 1;
+    want[s]++;
+  }
+  want[0] = n_reads;
+  for (int s = 0; s < 5; ++s)
+    if (cnt[s] != want[s]) return 1;
+  /* 2. bare-terminator rows */
+  for (uint64_t i = 0; i < n_reads; ++i) {
+    uint8_t w = offsets[i + 1] > offsets[i] ? text[offsets[i + 1] - 1] : (uint8_t)'$';
+    if (bwt[i] != w) return 2;
+  }
+  /* 3. LF walks */
+  uint64_t nblk = total / 64 + 1;
+  uint64_t *occ = (uint64_t *)malloc(sizeof(uint64_t) * 5 * nblk);
+  if (!occ) return ORACLE_ENOMEM;
+  uint64_t run[5] = {0, 0, 0, 0, 0};
+  for (uint64_t blk = 0; blk < nblk; ++blk) {
+    for (int s = 0; s < 5; ++s) occ[blk * 5 + (uint64_t)s] = run[s];
+    uint64_t t1 = (blk + 1) * 64 < total ? (blk + 1) * 64 : total;
+    for (uint64_t t = blk * 64; t < t1; ++t) run[sym_code(bwt[t])]++;
+  }
+  if (threads <= 0) threads = 1;
+  lf_job_t *jobs = (lf_job_t *)calloc((size_t)threads, sizeof(lf_job_t));
+  pthread_t *tid = (pthread_t *)malloc(sizeof(pthread_t) * threads);
+  uint64_t C[5];
+  C[0] = 0;
+  for (int s = 1; s < 5; ++s) C[s] = C[s - 1] + cnt[s - 1];
+  for (int t = 0; t < threads; ++t) {
+    jobs[t].bwt = bwt;
+    jobs[t].term_pos = term_pos;
+    jobs[t].text = text;
+    jobs[t].offsets = offsets;
+    jobs[t].occ_base = occ;
+    memcpy(jobs[t].C, C, sizeof(C));
+    jobs[t].r0 = n_reads * (uint64_t)t / (uint64_t)threads;
+    jobs[t].r1 = n_reads * (uint64_t)(t + 1) / (uint64_t)threads;
+    jobs[t].failed = 0;
+    pthread_create(&tid[t], NULL, lf_worker, &jobs[t]);
+  }
+  int st = 0;
+  for (int t = 0; t < threads; ++t) {
+    pthread_join(tid[t], NULL);
+    if (jobs[t].failed && !st) st = jobs[t].failed;
+  }
+  free(tid);
+  free(jobs);
+  free(occ);
+  return st;
+}

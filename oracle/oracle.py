@@ -61,6 +61,9 @@ def _bind(lib):
     lib.cx_oracle_sorted_suffixes.restype = ctypes.c_int
     lib.cx_oracle_validate.argtypes = [u8p, u64p, ctypes.c_uint64, ctypes.c_uint64]
     lib.cx_oracle_validate.restype = ctypes.c_int
+    if hasattr(lib, "cx_check_bwt"):
+        lib.cx_check_bwt.argtypes = [u8p, u64p, u8p, u64p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int]
+        lib.cx_check_bwt.restype = ctypes.c_int
     return lib
 
 
@@ -119,6 +122,23 @@ def sorted_suffixes(text, offsets, threads: int | None = None, lib=None) -> np.n
     if st != 0:
         raise ValueError(f"oracle rejected the input (status {st})")
     return out
+
+
+def check_bwt(bwt, term_pos, text, offsets, threads: int | None = None, lib=None) -> int:
+    """Counts, bare-terminator rows and the LF walk of every read, in C (0 = all hold).
+
+    1: symbol counts wrong, 2: rows 0..n-1 wrong, 3: an LF walk diverged.
+    """
+    text, offsets = _as_inputs(text, offsets)
+    bwt = np.ascontiguousarray(bwt, dtype=np.uint8)
+    tp = np.ascontiguousarray(term_pos, dtype=np.uint64)
+    n = offsets.size - 1
+    nb = int(offsets[-1])
+    lib = lib or load()
+    tbuf = text if text.size else np.zeros(1, dtype=np.uint8)
+    return int(lib.cx_check_bwt(_ptr(bwt, ctypes.c_uint8), _ptr(tp if tp.size else np.zeros(1, np.uint64), ctypes.c_uint64),
+                                _ptr(tbuf, ctypes.c_uint8), _ptr(offsets, ctypes.c_uint64), n, nb,
+                                threads or default_threads()))
 
 
 def bwt_bruteforce(reads: list[str]):

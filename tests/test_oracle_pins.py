@@ -276,3 +276,33 @@ def test_planted_mistake_is_caught(name):
 
 def test_unmutated_oracle_passes_battery():
     assert _pin_battery(oracle.load()) == []
+
+
+# ---- the compiled invariant checker (used on full-size device outputs) ----
+
+def test_c_checker_accepts_true_bwts_and_rejects_damaged_ones():
+    col = datagen.plain_config(0, scale=0.3)
+    bwt, tp = oracle.bwt(col.text, col.offsets)
+    assert oracle.check_bwt(bwt, tp, col.text, col.offsets, threads=3) == 0
+    rng = np.random.default_rng(2)
+    # swap two different symbols: counts hold, the LF walk does not
+    for _ in range(5):
+        b = bwt.copy()
+        i, j = rng.integers(col.n_reads, b.size, size=2)
+        while b[i] == b[j]:
+            j = rng.integers(col.n_reads, b.size)
+        b[i], b[j] = b[j], b[i]
+        assert oracle.check_bwt(b, tp, col.text, col.offsets) != 0
+    b = bwt.copy()
+    b[5] = ord("A") if b[5] != ord("A") else ord("C")
+    assert oracle.check_bwt(b, tp, col.text, col.offsets) != 0
+    t = tp.copy()
+    t[0], t[1] = t[1], t[0]
+    assert oracle.check_bwt(bwt, t, col.text, col.offsets) != 0
+
+
+def test_c_checker_on_edge_collections():
+    for reads in (["ACGT", "TAGT", "GGAA"], ["", "A", ""], ["A" * 30] * 4, ["ACGTACGT"]):
+        c = datagen.from_reads(reads)
+        b, t = oracle.bwt(c.text, c.offsets)
+        assert oracle.check_bwt(b, t, c.text, c.offsets) == 0
