@@ -13,6 +13,8 @@ path both take its output as plain input.
 from __future__ import annotations
 
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass
 
 import numpy as np
@@ -20,7 +22,14 @@ import numpy as np
 ASCII = np.frombuffer(b"ACGT", dtype=np.uint8)
 BASE_SEED = 14017457
 
-_CHUNK = 1 << 20  # reads generated per vectorised chunk
+_CHUNK = 1 << 18  # reads generated per vectorised chunk
+
+
+def _workers() -> int:
+    try:
+        return max(1, min(16, len(os.sched_getaffinity(0))))
+    except AttributeError:  # pragma: no cover
+        return max(1, min(16, os.cpu_count() or 1))
 
 
 @dataclass
@@ -138,11 +147,18 @@ def sample_reads(rng: np.random.Generator, genome: np.ndarray, n: int, read_len,
     starts = rng.integers(0, G - lens + 1)
     strand = rng.random(n) < 0.5 if both_strands else np.zeros(n, dtype=bool)
     idx_t = np.int32 if G < (1 << 31) - 1 else np.int64
-    for c0 in range(0, n, _CHUNK):
+    # every chunk of reads draws its substitutions from a generator of its
+    # own, so chunks can be filled in parallel and the result does not
+    # depend on the thread count
+    n_chunks = (n + _CHUNK - 1) // _CHUNK
+    chunk_seeds = rng.integers(0, 1 << 63, size=n_chunks, dtype=np.int64)
+
+    def fill(ci: int) -> None:
+        c0 = ci * _CHUNK
         c1 = min(n, c0 + _CHUNK)
         L = lens[c0:c1].astype(idx_t)
         if int(L.sum()) == 0:
-            continue
+            return
         s = starts[c0:c1].astype(idx_t)
         rev = strand[c0:c1]
         maxL = int(L.max())
@@ -155,9 +171,17 @@ def sample_reads(rng: np.random.Generator, genome: np.ndarray, n: int, read_len,
         codes = genome[pos]
         codes = np.where(rev[:, None], 3 - codes, codes).astype(np.uint8)
         codes = codes[valid] if maxL and not bool(valid.all()) else codes.reshape(-1)
-        codes = mutate(rng, codes, error_rate)
+        codes = mutate(np.random.Generator(np.random.PCG64(int(chunk_seeds[ci]))), codes, error_rate)
         b0 = int(offsets[c0])
         text[b0:b0 + codes.size] = ASCII[codes]
+
+    workers = min(n_chunks, _workers())
+    if workers <= 1:
+        for ci in range(n_chunks):
+            fill(ci)
+    else:
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            list(ex.map(fill, range(n_chunks)))
     return Collection(text, offsets)
 
 

