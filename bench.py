@@ -64,7 +64,7 @@ def algorithmic_bytes(stats: dict, n_reads: int, n_bases: int) -> dict:
 
 
 KERNELS_OF_CLASS = {
-    "prep": ["k_prep", "k_text_bases", "k_rank_count", "k_rank_top", "k_rank_words"],
+    "prep": ["k_prep", "k_text_records", "k_rank_count", "k_rank_top", "k_rank_words"],
     "gen": ["k_gen_hist", "k_gen"],
     "level_hist": ["k_level_hist"],
     "level_scan": ["k_group_scan", "k_level_scan"],

@@ -82,7 +82,7 @@ int cxbwt_pack(const uint8_t *ascii, uint64_t n_bases, uint64_t *packed, uint32_
 
 /*
  * cxbwt_workspace_bytes -- device workspace cxbwt_build needs for these
- * sizes (about 24 bytes per base plus small lists).  Pure host arithmetic:
+ * sizes (about 28 bytes per base plus small lists).  Pure host arithmetic:
  * no device call, usable without a GPU.  Returns 0 when the sizes are out of
  * range (see cxbwt_build).
  */
@@ -166,20 +166,22 @@ int cxbwt_build_batch(const uint64_t *packed, const uint64_t *offsets, uint64_t 
 /* Counters describing the last cxbwt_build on the calling host thread. */
 typedef struct cxbwt_stats {
   uint32_t levels;             /* global sort levels run                               */
-  uint32_t max_window;         /* deepest 28-base key window used (0 = first window)   */
-  uint64_t chunks;             /* bucket sets finished inside one workgroup            */
+  uint32_t max_window;         /* deepest 27-base key window used (0 = first window)   */
+  uint64_t chunks;             /* bucket sets finished inside one wave                 */
   uint64_t big_segments;       /* segment passes run through the global levels         */
   uint64_t final_big;          /* groups of identical suffixes emitted from the levels */
-  uint64_t chunk_suffixes;     /* suffixes finished inside workgroups                  */
+  uint64_t chunk_suffixes;     /* suffixes finished inside waves                       */
   uint64_t level_suffixes;     /* suffix visits of the global histogram passes          */
   uint64_t scattered_suffixes; /* suffixes moved by global scatters                    */
   uint64_t regathered;         /* later-window keys fetched by the global levels        */
-  uint64_t window_fetches;     /* later-window keys fetched inside workgroups           */
+  uint64_t window_fetches;     /* later-window keys fetched inside waves                */
   /* With timing on (cxbwt_set_timing): summed kernel time in ms and launch
    * count per kernel class: 0 prep, 1 key generation, 2 level histogram,
-   * 3 level scan, 4 level scatter, 5 in-workgroup finish, 6 final emit.      */
+   * 3 level scan, 4 level scatter, 5 in-wave finish, 6 final emit.           */
   float ms[8];
   uint32_t launches[8];
+  uint32_t level_batches;      /* batches the levels after the first ran in            */
+  uint32_t reserved;
 } cxbwt_stats;
 
 /* Copies the last build's counters (host) into *out; CXBWT_EINVAL on NULL. */

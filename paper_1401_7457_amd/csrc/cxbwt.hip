@@ -14,22 +14,22 @@
 //   * handle  = the 32-bit global base position p of a suffix's first base;
 //               the n empty suffixes ($_i alone) are not sorted at all: they
 //               are rows 0..n-1 in read order.
-//   * key     = one 28-base window of the suffix (layout in device_common.h):
-//               bases zero-padded past the read end, then min(remaining, 28).
+//   * key     = one 27-base window of the suffix (layout in device_common.h):
+//               bases zero-padded past the read end, then min(remaining, 27).
 //               Comparing (bases, clamped length) is the order of Section 2
 //               inside one window: a suffix that ends in the window is a
 //               proper prefix of, hence below, one that goes on; equal keys
-//               with a clamped length below 28 are identical suffixes, which
+//               with a clamped length below 27 are identical suffixes, which
 //               stable passes keep in read order.
 //   * sort    = most-significant digit first.  Level 1 computes window-0 keys
 //               from the 2-bit reads and scatters them by their top 8 bits
 //               (keys are never stored unsorted); further 8-bit levels split
-//               every bucket larger than one workgroup's share (2048
+//               every bucket larger than one workgroup's share (1024
 //               suffixes).  Runs of small buckets are then sorted on their
 //               remaining digits, tie-refined window by window and emitted
 //               inside one workgroup, in LDS.  A tie on a full window
-//               (clamped length 28) fetches the next window of the tied
-//               suffixes only.
+//               (clamped length 27) fetches the next window of the tied
+//               suffixes only, one aligned 16-byte text record each.
 //
 // Every pass is stable and the initial order is read-major, so suffixes that
 // are equal through their terminators stay in read-index order (the stability
@@ -53,14 +53,15 @@ using namespace cxk;
 #define CXBWT_TILE_ITEMS 12
 #endif
 constexpr int TILE_ITEMS = CXBWT_TILE_ITEMS;   // suffixes per thread in a level tile
-constexpr int TILE = BLOCK * TILE_ITEMS;       // 4096
+constexpr int TILE = BLOCK * TILE_ITEMS;       // suffixes per level tile
 #ifndef CXBWT_LOCAL_ITEMS
-#define CXBWT_LOCAL_ITEMS 4
+#define CXBWT_LOCAL_ITEMS 8
 #endif
-constexpr int LOCAL_ITEMS = CXBWT_LOCAL_ITEMS; // suffixes per thread in a chunk
-constexpr int CHUNK = BLOCK * LOCAL_ITEMS;     // 2048: largest run finished in LDS
+constexpr int LOCAL_WG = 64;                   // one wave finishes a chunk
+constexpr int LOCAL_ITEMS = CXBWT_LOCAL_ITEMS; // suffixes per lane in a chunk
+constexpr int CHUNK = LOCAL_WG * LOCAL_ITEMS;  // largest run finished in LDS
 constexpr int GROUP_TILES = 256;               // tiles per first-stage scan group
-constexpr int RANK_COUNT_MAX = 256;            // live groups up to this size: all-pairs ranking
+constexpr uint64_t SEG_BATCH_MIN = 2048;       // segment size the level scratch is sized for
 
 constexpr uint32_t ST_BAD_OFFSETS = 1u;
 constexpr uint32_t ST_TOO_LONG = 2u;
@@ -70,16 +71,18 @@ constexpr uint32_t ST_WINDOW_BOUND = 16u;
 
 // A run of suffixes [start, start+len) in key/handle buffer `buf`, whose keys
 // are for window r and agree on every digit before d.
+// Positions fit 32 bits (at most CXBWT_MAX_BASES bases).
 struct Seg {
-  uint64_t start;
-  uint64_t len;
-  uint32_t r;
+  uint32_t start;
+  uint32_t len;
+  uint16_t r;
   uint8_t d;
-  uint8_t buf;
-  uint8_t regather;  // keys must be re-fetched for window r before use
-  uint8_t unsplit;   // chunk only: suffixes are in read order, not yet split by digit d
-  uint32_t coll;     // collection the suffixes belong to
+  uint8_t buf : 1;
+  uint8_t regather : 1;  // keys must be re-fetched for window r before use
+  uint8_t unsplit : 1;   // chunk only: suffixes are in read order, not yet split by digit d
+  uint32_t coll;         // collection the suffixes belong to
 };
+static_assert(sizeof(Seg) == 16, "segment records are 16 bytes");
 
 // Where collection c's rows go.  Suffix position j (a base position of the
 // whole batch) of collection c is BWT row j + row_shift of that collection,
@@ -107,11 +110,11 @@ struct Lists {
 
 // Number of read starts strictly before base p: for the first base of a
 // read, the index of that read among the non-empty reads.  srank[w] counts
-// the start bits of records before w.
+// the starts at positions below 16w.
 __device__ __forceinline__ uint32_t start_rank(const TextRec *__restrict__ text, const uint32_t *__restrict__ srank,
                                                uint64_t p) {
-  const uint32_t below = text[p >> 5].starts & ((1u << (p & 31)) - 1u);
-  return srank[p >> 5] + (uint32_t)__popc(below);
+  const uint64_t below = text[p >> 4].lo & ((1ull << (p & 15)) - 1ull);
+  return srank[p >> 4] + (uint32_t)__popcll(below);
 }
 
 // Writes the BWT row of a sorted suffix; an offset-0 suffix also records its
@@ -197,12 +200,13 @@ __global__ void k_pack(const uint8_t *__restrict__ ascii, uint64_t nb, uint64_t 
 }
 
 // ---------------------------------------------------------------------------
-// read preparation: validate offsets, mark read ends, emit the n rows of the
-// bare terminators (row i = $_i, preceded by the last base of read i)
+// read preparation: validate offsets, mark read starts in a bitmap (bit t of
+// word t/32 for position t), emit the n rows of the bare terminators (row i =
+// $_i, preceded by the last base of read i)
 // ---------------------------------------------------------------------------
 __global__ void k_prep(const uint64_t *__restrict__ packed, const uint64_t *__restrict__ offsets, uint64_t n, uint64_t nb,
                        uint32_t maxlen, const uint64_t *__restrict__ coll_reads, uint32_t ncoll,
-                       TextRec *text, uint8_t *__restrict__ bwt, uint64_t *__restrict__ term_pos,
+                       uint32_t *sbits, uint8_t *__restrict__ bwt, uint64_t *__restrict__ term_pos,
                        uint32_t *status) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -227,10 +231,10 @@ __global__ void k_prep(const uint64_t *__restrict__ packed, const uint64_t *__re
   // row (i - first_read) of the collection, whose output starts at byte
   // (bases before it) + (reads before it): byte offsets[first_read] + i
   const uint64_t out = offsets[first_read] + i;
-  if (i == n - 1) atomicOr(&text[nb >> 5].starts, 1u << (nb & 31));  // end of the text
+  if (i == n - 1) atomicOr(&sbits[nb >> 5], 1u << (nb & 31));  // end of the text
   if (b > a) {
     const uint64_t e = b - 1;
-    atomicOr(&text[a >> 5].starts, 1u << (a & 31));
+    atomicOr(&sbits[a >> 5], 1u << (a & 31));
     const uint32_t lut = 'A' | ('C' << 8) | ('G' << 16) | ('T' << 24);
     bwt[out] = (uint8_t)((lut >> (8 * base_at(packed, e))) & 0xFFu);
   } else {
@@ -239,11 +243,31 @@ __global__ void k_prep(const uint64_t *__restrict__ packed, const uint64_t *__re
   }
 }
 
-// Bases of the text records (read starts were set by k_prep).
-__global__ void k_text_bases(const uint64_t *__restrict__ packed, uint64_t nwords, TextRec *__restrict__ text,
-                             uint64_t nrec) {
+// 32 bases of the packed input starting at position t (a multiple of 16),
+// first base highest; words past the input read as zero.
+__device__ __forceinline__ uint64_t packed_at16(const uint64_t *__restrict__ packed, uint64_t nwords, uint64_t t) {
+  const uint64_t k = t >> 5;
+  const uint64_t w0 = k < nwords ? packed[k] : 0ull;
+  if (!(t & 31)) return w0;
+  const uint64_t w1 = k + 1 < nwords ? packed[k + 1] : 0ull;
+  return (w0 << 32) | (w1 >> 32);
+}
+
+// Text records from the packed bases and the read-start bitmap (k_prep);
+// the bitmap holds at least floor(B/32) + 4 zero-padded words.
+__global__ void k_text_records(const uint64_t *__restrict__ packed, uint64_t nwords, const uint32_t *__restrict__ sbits,
+                               TextRec *__restrict__ text, uint64_t nrec) {
   const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (w < nrec) text[w].bases = w < nwords ? packed[w] : 0ull;
+  if (w >= nrec) return;
+  const uint64_t t = 16 * w;
+  TextRec r;
+  r.hi = packed_at16(packed, nwords, t);
+  const uint64_t tail = packed_at16(packed, nwords, t + 32) & ~((1ull << 44) - 1);  // bases t+32 .. t+41
+  const uint64_t prev = w ? (packed_at16(packed, nwords, t - 16) >> 32) & 3ull : 0ull;  // base t-1
+  const uint64_t k = t >> 5;
+  const uint64_t bits = (((uint64_t)sbits[k + 1] << 32) | sbits[k]) >> (t & 31);
+  r.lo = tail | (prev << 42) | (bits & REC_STARTS);
+  text[w] = r;
 }
 
 // First base of every collection (host needs them to lay out segments).
@@ -254,7 +278,8 @@ __global__ void k_coll_bases(const uint64_t *__restrict__ offsets, const uint64_
 }
 
 // ---------------------------------------------------------------------------
-// exclusive prefix counts of the read-end bits, per 64-bit word
+// exclusive prefix counts of the read starts, per text record (each record
+// owns the start bits of its first 16 positions)
 // ---------------------------------------------------------------------------
 constexpr int RANK_WPT = 16;                      // words per thread
 constexpr int RANK_BLOCK_WORDS = BLOCK * RANK_WPT;
@@ -266,7 +291,7 @@ __global__ __launch_bounds__(BLOCK) void k_rank_count(const TextRec *__restrict_
   uint32_t c = 0;
 #pragma unroll
   for (int i = 0; i < RANK_WPT; ++i)
-    if (w0 + i < nw) c += (uint32_t)__popc(text[w0 + i].starts);
+    if (w0 + i < nw) c += (uint32_t)__popc((uint32_t)text[w0 + i].lo & 0xFFFFu);
   uint32_t total;
   block_excl_sum(c, tmp, &total);
   if (threadIdx.x == 0) blocksum[blockIdx.x] = total;
@@ -294,7 +319,7 @@ __global__ __launch_bounds__(BLOCK) void k_rank_words(const TextRec *__restrict_
   uint32_t c = 0;
 #pragma unroll
   for (int i = 0; i < RANK_WPT; ++i) {
-    cnt[i] = w0 + i < nw ? (uint32_t)__popc(text[w0 + i].starts) : 0u;
+    cnt[i] = w0 + i < nw ? (uint32_t)__popc((uint32_t)text[w0 + i].lo & 0xFFFFu) : 0u;
     c += cnt[i];
   }
   uint32_t run = blocksum[blockIdx.x] + block_excl_sum(c, tmp, nullptr);
@@ -586,7 +611,7 @@ __global__ __launch_bounds__(BLOCK) void k_level_scan(const Seg *__restrict__ se
           st_chunk[nc++] = cur;
           have = false;
         }
-        Seg nx{st, c, sg.r, (uint8_t)(sg.d + 1), (uint8_t)(sg.buf ^ 1), 0, 0, sg.coll};
+        Seg nx{(uint32_t)st, c, sg.r, (uint8_t)(sg.d + 1), (uint8_t)(sg.buf ^ 1), 0, 0, sg.coll};
         if (sg.d == 7) {
           // bucket value b is the clamped length; all ordering bits agree
           if (b < W) {
@@ -608,7 +633,7 @@ __global__ __launch_bounds__(BLOCK) void k_level_scan(const Seg *__restrict__ se
         cur.len += c;
       } else {
         if (have) st_chunk[nc++] = cur;
-        cur = Seg{st, c, sg.r, sg.d, (uint8_t)(sg.buf ^ 1), 0, 0, sg.coll};
+        cur = Seg{(uint32_t)st, c, sg.r, sg.d, (uint8_t)(sg.buf ^ 1), 0, 0, sg.coll};
         have = true;
       }
     }
@@ -687,243 +712,236 @@ __global__ __launch_bounds__(BLOCK) void k_emit_final(const Seg *__restrict__ se
 }
 
 // ---------------------------------------------------------------------------
-// a2/a3/a4 in one workgroup: finish a chunk of at most CHUNK suffixes
+// a2/a3/a4 in one wave: finish a chunk of at most CHUNK suffixes in LDS.
+// A chunk is small enough that every group in it is ranked by all-pairs
+// comparison, so the kernel needs no multisplit and no cross-wave barrier;
+// many independent one-wave workgroups per CU hide each other's latency.
+// Each round works on the list of live positions only (the members of
+// groups that are not finished), so the rounds that refine a few tied
+// groups cost little.
 // ---------------------------------------------------------------------------
 struct LocalSmem {
-  uint64_t K[2][CHUNK];
-  uint32_t H[2][CHUNK];
-  uint16_t G[2][CHUNK];    // group start carried through composite passes
-  uint16_t gr[CHUNK];      // group rank of each position
-  uint16_t hp[CHUNK + 1];  // start of each group
+  uint64_t K[CHUNK];       // key of each position
+  uint32_t H[CHUNK];       // handle of each position
+  uint16_t live[CHUNK];    // live positions, ascending
+  uint16_t gr[CHUNK];      // group of each live-list entry
+  uint16_t hp[CHUNK + 1];  // first live-list entry of each group
+  uint16_t dst[CHUNK];     // new position of each live-list entry
   uint8_t head[CHUNK];     // position starts a group
-  uint8_t fin[CHUNK];      // position's group is final
-  uint32_t wcount[WAVES * 256];
-  uint32_t dstart[256];
-  uint32_t tmp[WAVES];
-  uint64_t tmp64[WAVES];
-  uint32_t scan_tmp[WAVES];
 };
 
-// Stable LDS pass of m items from buffer `src` to src^1 by digit `sel`:
-// 0..7 key digits, 8/9 the low/high byte of the carried group start.
-template <bool WITH_G>
-__device__ void lds_pass(LocalSmem &S, int src, uint32_t m, int sel) {
-  uint64_t kr[LOCAL_ITEMS];
-  uint32_t hr[LOCAL_ITEMS], dig[LOCAL_ITEMS], pos[LOCAL_ITEMS];
-  uint16_t gg[LOCAL_ITEMS];
+// waves per SIMD the chunk kernel is compiled for (bounds its registers)
+#ifndef CXBWT_LOCAL_OCCUPANCY
+#define CXBWT_LOCAL_OCCUPANCY 3
+#endif
+constexpr int LOCAL_OCCUPANCY = CXBWT_LOCAL_OCCUPANCY;
+constexpr int LOCAL_SLOTS = LOCAL_ITEMS;  // 64-entry slots of a full live list
+#ifndef CXBWT_FETCH_BATCH
+#define CXBWT_FETCH_BATCH 2
+#endif
+constexpr int FETCH_BATCH = CXBWT_FETCH_BATCH < LOCAL_SLOTS ? CXBWT_FETCH_BATCH : LOCAL_SLOTS;
+
+// Groups of the live list from the head flags of its positions: gr[x] and
+// hp[g] (hp[number of groups] = n).  One ballot per 64 entries.
+__device__ __forceinline__ void live_groups(LocalSmem &S, uint32_t n, uint32_t lane, uint64_t le) {
+  uint32_t run = 0;
 #pragma unroll
-  for (int i = 0; i < LOCAL_ITEMS; ++i) {
-    const uint32_t li = item_index<LOCAL_ITEMS>(i);
-    if (li < m) {
-      kr[i] = S.K[src][li];
-      hr[i] = S.H[src][li];
-      gg[i] = WITH_G ? S.G[src][li] : (uint16_t)0;
-      if (sel < 8) dig[i] = digit_of(kr[i], sel);
-      else if (sel == 8) dig[i] = gg[i] & 0xFFu;
-      else dig[i] = (uint32_t)gg[i] >> 8;
-    } else {
-      kr[i] = 0;
-      hr[i] = 0;
-      gg[i] = 0;
-      dig[i] = NODIGIT;
+  for (int i = 0; i < LOCAL_SLOTS; ++i) {
+    const uint32_t x = i * LOCAL_WG + lane;
+    if (i * LOCAL_WG >= (int)n) break;
+    const bool in = x < n;
+    const bool h = in && S.head[S.live[x]];
+    const uint64_t hb = __ballot(h);
+    const uint32_t g = run + (uint32_t)__popcll(hb & le) - 1u;
+    if (in) {
+      S.gr[x] = (uint16_t)g;
+      if (h) S.hp[g] = (uint16_t)x;
     }
+    run += (uint32_t)__popcll(hb);
   }
-  block_multisplit<LOCAL_ITEMS>(dig, pos, S.wcount, S.dstart, S.tmp);
-#pragma unroll
-  for (int i = 0; i < LOCAL_ITEMS; ++i) {
-    if (dig[i] != NODIGIT) {
-      S.K[src ^ 1][pos[i]] = kr[i];
-      S.H[src ^ 1][pos[i]] = hr[i];
-      if (WITH_G) S.G[src ^ 1][pos[i]] = gg[i];
-    }
-  }
+  if (lane == 0) S.hp[run] = (uint16_t)n;
   __syncthreads();
 }
 
-// chunk workgroups resident per CU (also waves per SIMD: 4 waves each)
-#ifndef CXBWT_LOCAL_OCCUPANCY
-#define CXBWT_LOCAL_OCCUPANCY (16 / CXBWT_LOCAL_ITEMS)
-#endif
-constexpr int LOCAL_OCCUPANCY = CXBWT_LOCAL_OCCUPANCY;
-
-__global__ __launch_bounds__(BLOCK, LOCAL_OCCUPANCY) void k_local(const Seg *__restrict__ chunks, const uint64_t *__restrict__ keys0,
-                                                    const uint64_t *__restrict__ keys1, const uint32_t *__restrict__ hdl0,
-                                                    const uint32_t *__restrict__ hdl1, const TextRec *__restrict__ text,
-                                                    const uint32_t *__restrict__ srank,
-                                                    const CollMap *__restrict__ cmap, uint64_t nb, uint32_t rmax,
-                                                    uint8_t *__restrict__ bwt,
-                                                    uint64_t *__restrict__ start_row, uint32_t *status,
-                                                    unsigned long long *fetches) {
+__global__ __launch_bounds__(LOCAL_WG, LOCAL_OCCUPANCY) void k_local(
+    const Seg *__restrict__ chunks, const uint64_t *__restrict__ keys0, const uint64_t *__restrict__ keys1,
+    const uint32_t *__restrict__ hdl0, const uint32_t *__restrict__ hdl1, const TextRec *__restrict__ text,
+    const uint32_t *__restrict__ srank, const CollMap *__restrict__ cmap, uint64_t nb, uint32_t rmax,
+    uint8_t *__restrict__ bwt, uint64_t *__restrict__ start_row, uint32_t *status, unsigned long long *fetches) {
   __shared__ LocalSmem S;
   const Seg ch = chunks[blockIdx.x];
   const uint32_t m = (uint32_t)ch.len;
+  const uint32_t lane = threadIdx.x;
+  const uint64_t le = lanemask_lt() | (1ull << lane);
   const uint64_t *Kg = ch.buf ? keys1 : keys0;
   const uint32_t *Hg = ch.buf ? hdl1 : hdl0;
-  for (uint32_t j = threadIdx.x; j < m; j += BLOCK) {
-    S.K[0][j] = Kg[ch.start + j];
-    S.H[0][j] = Hg[ch.start + j];
+  // entry x of a list is handled by lane x % 64 in slot x / 64: neighbouring
+  // lanes hold neighbouring positions, which mostly share a group
+#pragma unroll
+  for (int i = 0; i < LOCAL_SLOTS; ++i) {
+    const uint32_t j = i * LOCAL_WG + lane;
+    if (j < m) {
+      S.K[j] = Kg[ch.start + j];
+      S.H[j] = Hg[ch.start + j];
+    }
   }
   __syncthreads();
-  int cur = 0;
   // The chunk is a run of buckets that differ in digit d and agree before
-  // it.  Each bucket is a group still to be sorted on its current key; after
-  // that, groups are runs of equal keys, refined window by window.
+  // it (or, unsplit, one group to be sorted on its whole key).  Each group is
+  // sorted on its current key; after that, groups are runs of equal keys,
+  // refined window by window.
   const int d0 = ch.d;
-  if (ch.unsplit) {
-    lds_pass<false>(S, cur, m, d0);
-    cur ^= 1;
-  }
-  for (uint32_t j = threadIdx.x; j < m; j += BLOCK) {
-    S.head[j] = (j == 0) || (digit_of(S.K[cur][j], d0) != digit_of(S.K[cur][j - 1], d0));
-    S.fin[j] = 0;
+#pragma unroll
+  for (int i = 0; i < LOCAL_SLOTS; ++i) {
+    const uint32_t j = i * LOCAL_WG + lane;
+    if (j < m) {
+      S.head[j] = (j == 0) || (!ch.unsplit && digit_of(S.K[j], d0) != digit_of(S.K[j - 1], d0));
+      S.live[j] = (uint16_t)j;
+    }
   }
   __syncthreads();
+  uint32_t n = m;  // live-list length
   uint32_t r = ch.r;
   uint32_t nfetch = 0;
   bool fetch_round = false;
   for (;;) {
-    // group ranks (inclusive count of heads - 1) and group starts
-    {
-      const uint32_t base = threadIdx.x * LOCAL_ITEMS;
-      uint32_t cnt = 0;
+    // drop the finished groups: single suffixes, and (after the first sort)
+    // runs of equal keys that end inside the window, i.e. identical suffixes
+    live_groups(S, n, lane, le);
+    uint32_t kept = 0;
 #pragma unroll
-      for (int i = 0; i < LOCAL_ITEMS; ++i) {
-        const uint32_t j = base + i;
-        if (j < m) cnt += S.head[j];
+    for (int i = 0; i < LOCAL_SLOTS; ++i) {
+      if (i * LOCAL_WG >= (int)n) break;
+      const uint32_t x = i * LOCAL_WG + lane;
+      bool keep = false;
+      uint16_t pos = 0;
+      if (x < n) {
+        pos = S.live[x];
+        const uint32_t g = S.gr[x];
+        const uint32_t size = (uint32_t)S.hp[g + 1] - S.hp[g];
+        keep = size >= 2 && (!fetch_round || clamp_of(S.K[pos]) == (uint32_t)W);
       }
-      uint32_t total;
-      uint32_t pre = block_excl_sum(cnt, S.scan_tmp, &total);
-#pragma unroll
-      for (int i = 0; i < LOCAL_ITEMS; ++i) {
-        const uint32_t j = base + i;
-        if (j < m) {
-          pre += S.head[j];
-          S.gr[j] = (uint16_t)(pre - 1);
-          if (S.head[j]) S.hp[pre - 1] = (uint16_t)j;
-        }
-      }
-      if (threadIdx.x == 0) S.hp[total] = (uint16_t)m;
+      const uint64_t kb = __ballot(keep);
+      // compaction moves entries down only, so slot i never overwrites an
+      // entry a later slot still has to read
+      if (keep) S.live[kept + (uint32_t)__popcll(kb & (le >> 1))] = pos;
+      kept += (uint32_t)__popcll(kb);
     }
+    n = kept;
+    if (n == 0) break;
     __syncthreads();
-    // a group is finished when it is a single suffix, or (after the first
-    // sort) when its equal keys end inside the window: identical suffixes
-    uint32_t live_max = 0;
-    for (uint32_t j = threadIdx.x; j < m; j += BLOCK) {
-      if (S.fin[j]) continue;
-      const uint32_t g = S.gr[j];
-      const uint32_t size = (uint32_t)S.hp[g + 1] - S.hp[g];
-      if (size == 1 || (fetch_round && clamp_of(S.K[cur][j]) < (uint32_t)W)) S.fin[j] = 1;
-      else live_max = max(live_max, size);
-    }
-    live_max = block_max(live_max, S.tmp);
-    if (live_max == 0) break;
+    live_groups(S, n, lane, le);
     if (fetch_round) {
       if (r + 1 > rmax) {
-        if (threadIdx.x == 0) atomicOr(status, ST_WINDOW_BOUND);
+        if (lane == 0) atomicOr(status, ST_WINDOW_BOUND);
         break;
       }
       ++r;
-      // fetch the next window of every live suffix: all loads first
-      WinWords ww[LOCAL_ITEMS];
-      bool act[LOCAL_ITEMS];
+      // fetch the next window of every live suffix, FETCH_BATCH loads in
+      // flight per lane
+      for (uint32_t x0 = 0; x0 < n; x0 += FETCH_BATCH * LOCAL_WG) {
+        TextRec tr[FETCH_BATCH];
+        uint32_t tp[FETCH_BATCH];
 #pragma unroll
-      for (int i = 0; i < LOCAL_ITEMS; ++i) {
-        const uint32_t j = threadIdx.x + i * BLOCK;
-        act[i] = j < m && !S.fin[j];
-        if (act[i]) ww[i] = window_load(text, nb, S.H[cur][j], r);
-      }
+        for (int i = 0; i < FETCH_BATCH; ++i) {
+          const uint32_t x = x0 + i * LOCAL_WG + lane;
+          if (x < n) {
+            tp[i] = S.live[x];
+            tr[i] = window_load(text, nb, S.H[tp[i]], r);
+          }
+        }
 #pragma unroll
-      for (int i = 0; i < LOCAL_ITEMS; ++i) {
-        const uint32_t j = threadIdx.x + i * BLOCK;
-        if (act[i]) {
-          S.K[cur][j] = window_combine(ww[i], nb, S.H[cur][j], r, (uint32_t)S.K[cur][j] & 7u);
-          ++nfetch;
+        for (int i = 0; i < FETCH_BATCH; ++i) {
+          const uint32_t x = x0 + i * LOCAL_WG + lane;
+          if (x < n) {
+            const uint32_t j = tp[i];
+            S.K[j] = window_combine(tr[i], nb, S.H[j], r, (uint32_t)S.K[j] & 7u);
+            ++nfetch;
+          }
         }
       }
       __syncthreads();
     }
-    if (live_max <= (uint32_t)RANK_COUNT_MAX) {
-      // stable rank inside each live group by all-pairs comparison
-      for (uint32_t j = threadIdx.x; j < m; j += BLOCK) {
-        const uint64_t kj = S.K[cur][j];
-        if (S.fin[j]) {
-          S.K[cur ^ 1][j] = kj;
-          S.H[cur ^ 1][j] = S.H[cur][j];
-          continue;
-        }
-        const uint32_t g = S.gr[j];
-        const uint32_t a = S.hp[g], e = S.hp[g + 1];
-        const uint64_t oj = order_bits(kj);
-        // rank = #{t < j : key_t <= key_j} + #{t > j : key_t < key_j} (t = j
-        // adds nothing); four independent LDS reads per step keep the loop
-        // off the load-latency chain
-        uint32_t c = 0;
-        uint32_t t = a;
-        for (; t + 4 <= e; t += 4) {
-          const uint64_t o0 = order_bits(S.K[cur][t]);
-          const uint64_t o1 = order_bits(S.K[cur][t + 1]);
-          const uint64_t o2 = order_bits(S.K[cur][t + 2]);
-          const uint64_t o3 = order_bits(S.K[cur][t + 3]);
-          c += (t < j) ? (o0 <= oj) : (o0 < oj);
-          c += (t + 1 < j) ? (o1 <= oj) : (o1 < oj);
-          c += (t + 2 < j) ? (o2 <= oj) : (o2 < oj);
-          c += (t + 3 < j) ? (o3 <= oj) : (o3 < oj);
-        }
-        for (; t < e; ++t) {
-          const uint64_t ot = order_bits(S.K[cur][t]);
-          c += (t < j) ? (ot <= oj) : (ot < oj);
-        }
-        S.K[cur ^ 1][a + c] = kj;
-        S.H[cur ^ 1][a + c] = S.H[cur][j];
+    // stable rank inside each live group by all-pairs comparison:
+    // rank = #{t < j : key_t <= key_j} + #{t > j : key_t < key_j}; every
+    // rank is taken before any entry moves
+    for (uint32_t x = lane; x < n; x += LOCAL_WG) {
+      const uint32_t j = S.live[x];
+      const uint32_t g = S.gr[x];
+      const uint32_t x0 = S.hp[g];
+      const uint32_t a = S.live[x0];
+      const uint32_t e = a + ((uint32_t)S.hp[g + 1] - x0);  // a group is a run of positions
+      const uint64_t kj = S.K[j];
+      const uint64_t oj = order_bits(kj);
+      // four independent LDS reads per step keep the loop off the
+      // load-latency chain
+      uint32_t c = 0;
+      uint32_t t = a;
+      for (; t + 4 <= e; t += 4) {
+        const uint64_t o0 = order_bits(S.K[t]);
+        const uint64_t o1 = order_bits(S.K[t + 1]);
+        const uint64_t o2 = order_bits(S.K[t + 2]);
+        const uint64_t o3 = order_bits(S.K[t + 3]);
+        c += (t < j) ? (o0 <= oj) : (o0 < oj);
+        c += (t + 1 < j) ? (o1 <= oj) : (o1 < oj);
+        c += (t + 2 < j) ? (o2 <= oj) : (o2 < oj);
+        c += (t + 3 < j) ? (o3 <= oj) : (o3 < oj);
       }
-      __syncthreads();
-      cur ^= 1;
-    } else {
-      // composite stable LSD over the whole chunk: key digits, then the
-      // group start (finished groups have zeroed ordering bits and stay put)
-      for (uint32_t j = threadIdx.x; j < m; j += BLOCK) {
-        S.G[cur][j] = S.hp[S.gr[j]];
-        if (S.fin[j]) S.K[cur][j] &= 7ull;
+      for (; t < e; ++t) {
+        const uint64_t ot = order_bits(S.K[t]);
+        c += (t < j) ? (ot <= oj) : (ot < oj);
       }
-      __syncthreads();
-      uint64_t o = 0, a = ~0ull;
-      for (uint32_t j = threadIdx.x; j < m; j += BLOCK) {
-        o |= S.K[cur][j];
-        a &= S.K[cur][j];
-      }
-      o = block_or(o, S.tmp64);
-      a = block_and(a, S.tmp64);
-      const uint64_t diff = (o ^ a) & ~7ull;
-      for (int jd = 7; jd >= 0; --jd) {
-        if (diff & digit_mask(jd)) {
-          lds_pass<true>(S, cur, m, jd);
-          cur ^= 1;
-        }
-      }
-      lds_pass<true>(S, cur, m, 8);
-      cur ^= 1;
-      lds_pass<true>(S, cur, m, 9);
-      cur ^= 1;
+      S.dst[x] = (uint16_t)(a + c);
     }
+    __syncthreads();
+    {
+      uint64_t sk[LOCAL_SLOTS];
+      uint32_t sh[LOCAL_SLOTS], sd[LOCAL_SLOTS];
+#pragma unroll
+      for (int i = 0; i < LOCAL_SLOTS; ++i) {
+        const uint32_t x = i * LOCAL_WG + lane;
+        if (x < n) {
+          const uint32_t j = S.live[x];
+          sk[i] = S.K[j];
+          sh[i] = S.H[j];
+          sd[i] = S.dst[x];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < LOCAL_SLOTS; ++i) {
+        const uint32_t x = i * LOCAL_WG + lane;
+        if (x < n) {
+          S.K[sd[i]] = sk[i];
+          S.H[sd[i]] = sh[i];
+        }
+      }
+    }
+    __syncthreads();
     // new group heads inside live groups: changes of the full key
-    for (uint32_t j = threadIdx.x; j < m; j += BLOCK) {
-      if (S.fin[j]) continue;
-      const uint32_t a = S.hp[S.gr[j]];
-      if (j > a && order_bits(S.K[cur][j]) != order_bits(S.K[cur][j - 1])) S.head[j] = 1;
+#pragma unroll
+    for (int i = 0; i < LOCAL_SLOTS; ++i) {
+      const uint32_t x = i * LOCAL_WG + lane;
+      if (i * LOCAL_WG >= (int)n) break;
+      if (x >= n) continue;
+      const uint32_t j = S.live[x];
+      if (!S.head[j] && order_bits(S.K[j]) != order_bits(S.K[j - 1])) S.head[j] = 1;
     }
     __syncthreads();
     fetch_round = true;
   }
   // a4: emit
   const CollMap cm = cmap[ch.coll];
-  for (uint32_t j = threadIdx.x; j < m; j += BLOCK)
-    emit_row(ch.start + j, cm, S.K[cur][j], S.H[cur][j], text, srank, bwt, start_row);
+#pragma unroll
+  for (int i = 0; i < LOCAL_SLOTS; ++i) {
+    const uint32_t j = i * LOCAL_WG + lane;
+    if (j < m) emit_row(ch.start + j, cm, S.K[j], S.H[j], text, srank, bwt, start_row);
+  }
   nfetch = wave_incl_sum(nfetch);
-  if (lane_id() == 63 && nfetch) atomicAdd(fetches, (unsigned long long)nfetch);
+  if (lane == 63 && nfetch) atomicAdd(fetches, (unsigned long long)nfetch);
 }
 
 static_assert(CHUNK <= 65535, "group starts are 16-bit");
-static_assert(sizeof(LocalSmem) * LOCAL_OCCUPANCY <= 160 * 1024, "chunk workgroups per CU fit the LDS");
 
 // ---------------------------------------------------------------------------
 // host side
@@ -938,7 +956,7 @@ struct Layout {
   uint64_t keys0, keys1, hdl0, hdl1, text, srank, rank_blocks, start_row, tile_hist, gsum, segs, tile_prefix,
       group_prefix, seg_or, seg_and, seg_split, big_next, chunks, finals, coll_reads, coll_bases, cmap, counters,
       total;
-  uint64_t cap_big, cap_chunks, cap_finals, max_tiles, max_groups, n_rec, n_rank_blocks;
+  uint64_t cap_big, cap_chunks, cap_finals, seg_slots, max_tiles, max_groups, n_rec, n_rank_blocks;
 };
 
 bool sizes_ok(uint64_t n_reads, uint64_t n_bases, uint32_t max_read_len) {
@@ -956,9 +974,14 @@ Layout make_layout(uint64_t n_reads, uint64_t nb, uint32_t n_coll) {
   // end of its parent (both at most cap_big per level); level 1 adds one
   // chunk per collection that fits a chunk
   L.cap_chunks = 2 * ceil_div(nb, CHUNK) + 2 * L.cap_big + n_coll + 2;
-  L.max_tiles = ceil_div(nb, TILE) + L.cap_big + n_coll + 1;
-  L.max_groups = ceil_div(L.max_tiles, GROUP_TILES) + L.cap_big + n_coll + 1;
-  L.n_rec = ceil_div(nb, 32) + 2;
+  // segments split in one batch of a level: the per-segment and per-tile
+  // scratch is sized for segments of more than SEG_BATCH_MIN suffixes; a
+  // level with more segments runs in several batches.  Level 1 (one segment
+  // per collection) always fits one batch.
+  L.seg_slots = std::max<uint64_t>(nb / (SEG_BATCH_MIN + 1) + 2, (uint64_t)n_coll + 1);
+  L.max_tiles = ceil_div(nb, TILE) + L.seg_slots + 1;
+  L.max_groups = ceil_div(nb, (uint64_t)TILE * GROUP_TILES) + L.seg_slots + 1;
+  L.n_rec = nb / 16 + 2;
   L.n_rank_blocks = ceil_div(L.n_rec, RANK_BLOCK_WORDS);
   uint64_t off = 0;
   auto take = [&](uint64_t bytes) {
@@ -966,7 +989,7 @@ Layout make_layout(uint64_t n_reads, uint64_t nb, uint32_t n_coll) {
     off = align_up(off + bytes);
     return at;
   };
-  const uint64_t seg_slots = std::max<uint64_t>(L.cap_big, n_coll + 1);
+  const uint64_t seg_slots = L.seg_slots;
   L.keys0 = take(8 * nb);
   L.keys1 = take(8 * nb);
   L.hdl0 = take(4 * nb);
@@ -1102,11 +1125,28 @@ struct Buffers {
   uint8_t *seg_split;
 };
 
+// End of the batch of segments starting at b0 that fits the per-segment and
+// per-tile scratch (at least one segment: a single segment always fits).
+size_t batch_end(const std::vector<Seg> &segs, size_t b0, const Layout &Lo) {
+  uint64_t tiles = 0, groups = 0;
+  size_t b1 = b0;
+  while (b1 < segs.size() && b1 - b0 < Lo.seg_slots) {
+    const uint64_t nt = ceil_div(segs[b1].len, TILE);
+    const uint64_t ng = ceil_div(nt, GROUP_TILES);
+    if (b1 > b0 && (tiles + nt > Lo.max_tiles || groups + ng > Lo.max_groups)) break;
+    tiles += nt;
+    groups += ng;
+    ++b1;
+  }
+  return b1;
+}
+
 // Upload a segment list with its tile and group prefixes; returns the tile
 // and group totals.
 int upload_segments(const Buffers &B, const Layout &Lo, const std::vector<Seg> &segs, std::vector<uint32_t> &tprefix,
                     std::vector<uint32_t> &gprefix, uint32_t &ntiles, uint32_t &ngroups, hipStream_t st) {
   const uint32_t ns = (uint32_t)segs.size();
+  if (ns > Lo.seg_slots) return CXBWT_EDEVICE;
   tprefix.assign(ns + 1, 0);
   gprefix.assign(ns + 1, 0);
   for (uint32_t i = 0; i < ns; ++i) {
@@ -1130,7 +1170,7 @@ int finish_level(const Buffers &B, const Layout &Lo, uint64_t nb, uint32_t rmax,
   if (n_chunks > Lo.cap_chunks || n_finals > Lo.cap_finals) return CXBWT_EDEVICE;
   if (n_chunks) {
     T.begin();
-    k_local<<<n_chunks, BLOCK, 0, st>>>(B.chunks, B.keys0, B.keys1, B.hdl0, B.hdl1, B.text, B.srank, B.cmap,
+    k_local<<<n_chunks, LOCAL_WG, 0, st>>>(B.chunks, B.keys0, B.keys1, B.hdl0, B.hdl1, B.text, B.srank, B.cmap,
                                         nb, rmax, bwt, B.start_row, B.counters + C_STATUS,
                                         (unsigned long long *)(B.counters + C_FETCH));
     CX_LAUNCHED();
@@ -1194,12 +1234,17 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
   const uint32_t rmax = maxlen / W + 1;
   uint32_t *counters = B.counters;
 
+  // the read-start bitmap lives in the tile histogram area, which is not
+  // used before level 1 (4 bytes per 32 bases against 1 KiB per 3072)
+  uint32_t *sbits = B.tile_hist;
+  const uint64_t n_sbits = nb / 32 + 4;
+  if (4 * n_sbits > 4 * 256 * Lo.max_tiles) return CXBWT_EDEVICE;
   int rc;
   if ((rc = fill_u32(counters, C_COUNT, 0, st))) return rc;
-  if ((rc = fill_u64((uint64_t *)B.text, 2 * Lo.n_rec, 0, st))) return rc;
+  if ((rc = fill_u32(sbits, n_sbits, 0, st))) return rc;
   CX_CHECK(hipMemcpyAsync(B.coll_reads, coll_reads, 8 * ((uint64_t)ncoll + 1), hipMemcpyHostToDevice, st));
   T.begin();
-  k_prep<<<grid_for(n, 256), 256, 0, st>>>(packed, offsets, n, nb, maxlen, B.coll_reads, ncoll, B.text, bwt,
+  k_prep<<<grid_for(n, 256), 256, 0, st>>>(packed, offsets, n, nb, maxlen, B.coll_reads, ncoll, sbits, bwt,
                                           term_pos, counters + C_STATUS);
   CX_LAUNCHED();
   T.end(PH_PREP);
@@ -1220,8 +1265,8 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
     const uint64_t bc = cbase[c + 1] - cbase[c];
     cm[c].out_shift = coll_reads[c + 1];
     cm[c].row_shift = (int64_t)nc - (int64_t)cbase[c];
-    if (bc > (uint64_t)CHUNK) big.push_back(Seg{cbase[c], bc, 0, 0, 0, 0, 0, c});
-    else if (bc > 0) small.push_back(Seg{cbase[c], bc, 0, 0, 0, 0, 1, c});
+    if (bc > (uint64_t)CHUNK) big.push_back(Seg{(uint32_t)cbase[c], (uint32_t)bc, 0, 0, 0, 0, 0, c});
+    else if (bc > 0) small.push_back(Seg{(uint32_t)cbase[c], (uint32_t)bc, 0, 0, 0, 0, 1, c});
   }
   if (ncoll) CX_CHECK(hipMemcpyAsync(B.cmap, cm.data(), sizeof(CollMap) * ncoll, hipMemcpyHostToDevice, st));
   if (nb == 0) {
@@ -1231,7 +1276,7 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
   g_stats.chunk_suffixes = nb;
   // ranks of the read ends, for term_pos
   T.begin();
-  k_text_bases<<<grid_for(Lo.n_rec, 256), 256, 0, st>>>(packed, cxbwt_packed_words(nb), B.text, Lo.n_rec);
+  k_text_records<<<grid_for(Lo.n_rec, 256), 256, 0, st>>>(packed, cxbwt_packed_words(nb), sbits, B.text, Lo.n_rec);
   CX_LAUNCHED();
   k_rank_count<<<(unsigned)Lo.n_rank_blocks, BLOCK, 0, st>>>(B.text, Lo.n_rec, B.rank_blocks);
   CX_LAUNCHED();
@@ -1297,47 +1342,58 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
       CX_CHECK(hipStreamSynchronize(st));
     }
     if ((rc = finish_level(B, Lo, nb, rmax, bwt, hc[C_NCHUNK], hc[C_NFINAL], tprefix, T, st))) return rc;
-    // levels 2..
+    // levels 2..: every segment of a level is split by one digit, in batches
+    // that fit the per-segment and per-tile scratch
     while (!big.empty()) {
-      const uint32_t nsg = (uint32_t)big.size();
-      if (nsg > Lo.cap_big) return CXBWT_EDEVICE;
-      for (uint32_t i = 0; i < nsg; ++i) {
+      const uint32_t nsg_all = (uint32_t)big.size();
+      if (nsg_all > Lo.cap_big) return CXBWT_EDEVICE;
+      for (uint32_t i = 0; i < nsg_all; ++i) {
         g_stats.level_suffixes += big[i].len;
         if (big[i].regather) g_stats.regathered += big[i].len;
-        g_stats.max_window = std::max(g_stats.max_window, big[i].r);
+        g_stats.max_window = std::max<uint32_t>(g_stats.max_window, big[i].r);
       }
-      if ((rc = upload_segments(B, Lo, big, tprefix, gprefix, ntiles, ngroups, st))) return rc;
-      if ((rc = fill_u64((uint64_t *)B.seg_or, nsg, 0, st))) return rc;
-      if ((rc = fill_u64((uint64_t *)B.seg_and, nsg, ~0ull, st))) return rc;
-      if ((rc = fill_u32(counters + C_NBIG, 3, 0, st))) return rc;  // big, chunk and final counts
-      T.begin();
-      k_level_hist<<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, nsg, B.keys0, B.keys1, B.hdl0, B.hdl1, B.text,
-                                             nb, B.tile_hist, B.seg_or, B.seg_and);
-      CX_LAUNCHED();
-      T.end(PH_HIST);
-      T.begin();
-      k_group_scan<<<ngroups, BLOCK, 0, st>>>(B.tile_prefix, B.group_prefix, nsg, B.tile_hist, B.gsum);
-      CX_LAUNCHED();
-      k_level_scan<<<nsg, BLOCK, 0, st>>>(B.segs, B.group_prefix, B.gsum, B.seg_or, B.seg_and, B.seg_split, Ls, 0);
-      CX_LAUNCHED();
-      T.end(PH_SCAN);
-      T.begin();
-      k_level_scatter<<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, B.group_prefix, nsg, B.seg_split, B.tile_hist,
-                                                B.gsum, B.keys0, B.keys1, B.hdl0, B.hdl1);
-      CX_LAUNCHED();
-      T.end(PH_SCATTER);
+      g_stats.levels++;
+      g_stats.big_segments += nsg_all;
+      if ((rc = fill_u32(counters + C_NBIG, 1, 0, st))) return rc;
+      for (size_t b0 = 0; b0 < big.size();) {
+        const size_t b1 = batch_end(big, b0, Lo);
+        const std::vector<Seg> part(big.begin() + b0, big.begin() + b1);
+        const uint32_t nsg = (uint32_t)part.size();
+        g_stats.level_batches++;
+        if ((rc = upload_segments(B, Lo, part, tprefix, gprefix, ntiles, ngroups, st))) return rc;
+        if ((rc = fill_u64((uint64_t *)B.seg_or, nsg, 0, st))) return rc;
+        if ((rc = fill_u64((uint64_t *)B.seg_and, nsg, ~0ull, st))) return rc;
+        if ((rc = fill_u32(counters + C_NCHUNK, 2, 0, st))) return rc;  // chunk and final counts
+        T.begin();
+        k_level_hist<<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, nsg, B.keys0, B.keys1, B.hdl0, B.hdl1, B.text,
+                                               nb, B.tile_hist, B.seg_or, B.seg_and);
+        CX_LAUNCHED();
+        T.end(PH_HIST);
+        T.begin();
+        k_group_scan<<<ngroups, BLOCK, 0, st>>>(B.tile_prefix, B.group_prefix, nsg, B.tile_hist, B.gsum);
+        CX_LAUNCHED();
+        k_level_scan<<<nsg, BLOCK, 0, st>>>(B.segs, B.group_prefix, B.gsum, B.seg_or, B.seg_and, B.seg_split, Ls, 0);
+        CX_LAUNCHED();
+        T.end(PH_SCAN);
+        T.begin();
+        k_level_scatter<<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, B.group_prefix, nsg, B.seg_split,
+                                                  B.tile_hist, B.gsum, B.keys0, B.keys1, B.hdl0, B.hdl1);
+        CX_LAUNCHED();
+        T.end(PH_SCATTER);
+        CX_CHECK(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, st));
+        CX_CHECK(hipStreamSynchronize(st));
+        T.collect();
+        if (hc[C_STATUS]) return CXBWT_EDEVICE;
+        if ((rc = finish_level(B, Lo, nb, rmax, bwt, hc[C_NCHUNK], hc[C_NFINAL], tprefix, T, st))) return rc;
+        b0 = b1;
+      }
       CX_CHECK(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, st));
       CX_CHECK(hipStreamSynchronize(st));
-      T.collect();
-      if (hc[C_STATUS]) return CXBWT_EDEVICE;
-      g_stats.levels++;
-      g_stats.big_segments += nsg;
       big.resize(hc[C_NBIG]);
       if (!big.empty()) {
         CX_CHECK(hipMemcpyAsync(big.data(), B.big_next, sizeof(Seg) * big.size(), hipMemcpyDeviceToHost, st));
         CX_CHECK(hipStreamSynchronize(st));
       }
-      if ((rc = finish_level(B, Lo, nb, rmax, bwt, hc[C_NCHUNK], hc[C_NFINAL], tprefix, T, st))) return rc;
     }
   }
   T.begin();

@@ -7,107 +7,104 @@
 
 namespace cxk {
 
-constexpr int W = 28;              // bases per key window
+constexpr int W = 27;              // bases per key window
 constexpr int BLOCK = 256;         // threads per workgroup
 constexpr int WAVES = BLOCK / 64;  // wave64
 constexpr uint32_t NODIGIT = 0xFFFFFFFFu;
 
 // ---------------------------------------------------------------------------
-// Suffix key of one 28-base window (see cxbwt.hip for why this order is the
+// Suffix key of one 27-base window (see cxbwt.hip for why this order is the
 // suffix order):
-//   bits 63..8  the 28 bases, 2 bits each, first base highest; zero past the
+//   bits 63..10 the 27 bases, 2 bits each, first base highest; zero past the
 //               end of the read
+//   bits  9..8  zero
 //   bits  7..3  clamped length: min(bases left in the read from the window
-//               start, 28)
+//               start, 27)
 //   bits  2..0  symbol preceding the suffix: 0..3 = A,C,G,T, 4 = '$'
 // Only bits [3, 64) take part in comparisons.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t order_bits(uint64_t k) { return k & ~7ull; }
-__device__ __forceinline__ uint32_t clamp_of(uint64_t k) { return (uint32_t)(k >> 3) & 31u; }
+__host__ __device__ __forceinline__ uint64_t order_bits(uint64_t k) { return k & ~7ull; }
+__host__ __device__ __forceinline__ uint32_t clamp_of(uint64_t k) { return (uint32_t)(k >> 3) & 31u; }
 // 8-bit digit j (0 = most significant) of the ordering bits; digit 7 is the
 // 5-bit clamped length
-__device__ __forceinline__ uint32_t digit_of(uint64_t k, int j) {
+__host__ __device__ __forceinline__ uint32_t digit_of(uint64_t k, int j) {
   return j < 7 ? (uint32_t)(k >> (56 - 8 * j)) & 0xFFu : (uint32_t)(k >> 3) & 0x1Fu;
 }
 __host__ __device__ __forceinline__ uint64_t digit_mask(int j) {
   return j < 7 ? (0xFFull << (56 - 8 * j)) : (0x1Full << 3);
 }
 // ---------------------------------------------------------------------------
-// Text records: the 2-bit bases interleaved with read-start bits, 16 bytes
-// per 32 bases, so that one window of any suffix is a single 32-byte read.
-//   bases   32 bases, first base in the top two bits (the packed input word)
-//   starts  bit t set when base 32*w + t is the first base of a non-empty
-//           read; one extra start bit marks position B (the end of the text)
-// A record array holds ceil(B/32) + 2 records; the last ones are padding.
+// Text records: one 16-byte record per 16 bases, each holding everything a
+// window starting in its 16 positions needs, so a window is one aligned
+// 16-byte load.  Record w covers positions 16w .. 16w+41:
+//   hi  bits 63..0   bases 16w .. 16w+31, first base in the top two bits
+//   lo  bits 63..44  bases 16w+32 .. 16w+41, same order
+//       bits 43..42  base 16w-1 (zero for w = 0)
+//       bits 41..0   start bits: bit k set when position 16w+k is the first
+//                    base of a non-empty read, or k = B - 16w (the end of the
+//                    text, B bases in all)
+// 3 bits per position: 42 positions fit 126 bits, enough for a window of
+// 27 bases starting at any of the 16 (15 + 27 = 42).  A record array holds
+// floor(B/16) + 2 records; positions past B read as zero.
 // ---------------------------------------------------------------------------
 struct alignas(16) TextRec {
-  uint64_t bases;
-  uint32_t starts;
-  uint32_t pad;
+  uint64_t hi;
+  uint64_t lo;
 };
 
-__device__ __forceinline__ uint32_t rec_base(const TextRec *__restrict__ text, uint64_t t) {
-  return (uint32_t)(text[t >> 5].bases >> (62 - 2 * (t & 31))) & 3u;
-}
-__device__ __forceinline__ bool rec_start(const TextRec *__restrict__ text, uint64_t t) {
-  return (text[t >> 5].starts >> (t & 31)) & 1u;
+constexpr int REC_SPAN = 42;                             // positions per record
+constexpr uint64_t REC_STARTS = (1ull << REC_SPAN) - 1;  // start-bit field of lo
+
+// base at offset k (0..41) of a record
+__host__ __device__ __forceinline__ uint32_t rec_base_at(const TextRec &t, uint32_t k) {
+  return k < 32 ? (uint32_t)(t.hi >> (62 - 2 * k)) & 3u : (uint32_t)(t.lo >> (62 - 2 * (k - 32))) & 3u;
 }
 
-// The two records a window key is built from, loaded before use so many
-// windows can be in flight per thread.  The record index is clamped into the
-// array (a clamped read is never used).
-struct WinWords {
-  TextRec a, b;
-};
-
-__device__ __forceinline__ WinWords window_load(const TextRec *__restrict__ text, uint64_t nb, uint64_t p,
-                                                uint32_t r) {
+// The record a window starting at q is built from, loaded before use so many
+// windows can be in flight per thread.  q is clamped to B (a clamped read is
+// never used).
+__host__ __device__ __forceinline__ TextRec window_load(const TextRec *__restrict__ text, uint64_t nb, uint64_t p, uint32_t r) {
   const uint64_t q = p + (uint64_t)W * r;
   const uint64_t qc = q <= nb ? q : nb;
-  WinWords w;
-  w.a = text[qc >> 5];
-  w.b = text[(qc >> 5) + 1];
-  return w;
+  return text[qc >> 4];
 }
 
 // Key of window r of the suffix starting at base p (the window starts at
-// q = p + 28 r).  The suffix's read ends just before the first read start s
-// after p; the window holds min(s - q, 28) bases.  For r >= 1 the suffix is
-// live: its read holds at least 28 r bases from p, so s >= q.
-__device__ __forceinline__ uint64_t window_combine(const WinWords &w, uint64_t nb, uint64_t p, uint32_t r,
+// q = p + 27 r).  The suffix's read ends just before the first read start s
+// after p; the window holds min(s - q, 27) bases.  For r >= 1 the suffix is
+// live: its read holds at least 27 r bases from p, so s >= q.
+__host__ __device__ __forceinline__ uint64_t window_combine(const TextRec &t, uint64_t nb, uint64_t p, uint32_t r,
                                                    uint32_t prev3) {
   const uint64_t q = p + (uint64_t)W * r;
   if (q > nb) return prev3;  // never taken for a live suffix
-  const uint64_t lo = r == 0 ? p + 1 : q;          // first position a start may sit at
-  const uint32_t o = (uint32_t)(lo - ((q >> 5) << 5));  // 0..32, offset of lo in the record pair
-  const uint64_t st = ((uint64_t)w.b.starts << 32) | w.a.starts;
-  const uint64_t from = o < 64 ? st >> o : 0ull;
-  const uint64_t s_rel = from ? (uint64_t)o + (uint64_t)__builtin_ctzll(from) : ~0ull;  // start - 32*(q>>5)
-  const uint64_t q_rel = q & 31;
-  const uint32_t clamp = (s_rel != ~0ull && s_rel < q_rel + W) ? (uint32_t)(s_rel - q_rel) : (uint32_t)W;
+  const uint32_t o = (uint32_t)(q & 15);      // window start inside the record
+  const uint32_t lo_off = r == 0 ? o + 1 : o;  // first position a start may sit at
+  const uint64_t from = (t.lo & REC_STARTS) >> lo_off;
+  const uint32_t s_rel = from ? lo_off + (uint32_t)__builtin_ctzll(from) : 64u;
+  const uint32_t clamp = s_rel < o + (uint32_t)W ? s_rel - o : (uint32_t)W;
   uint64_t chars = 0;
   if (clamp > 0) {
-    const uint32_t b = 2u * (uint32_t)q_rel;
-    uint64_t x = w.a.bases << b;
-    if (b) x |= w.b.bases >> (64 - b);
-    chars = x & ~0xFFull;
+    uint64_t x = t.hi << (2 * o);
+    if (o) x |= t.lo >> (64 - 2 * o);
+    chars = x & ~0x3FFull;
     if (clamp < (uint32_t)W) chars &= ~((1ull << (64 - 2 * clamp)) - 1);
   }
   return chars | ((uint64_t)clamp << 3) | prev3;
 }
 
-__device__ __forceinline__ uint64_t window_key(const TextRec *__restrict__ text, uint64_t nb, uint64_t p, uint32_t r,
+__host__ __device__ __forceinline__ uint64_t window_key(const TextRec *__restrict__ text, uint64_t nb, uint64_t p, uint32_t r,
                                                uint32_t prev3) {
   return window_combine(window_load(text, nb, p, r), nb, p, r, prev3);
 }
 
 // Window-0 key of the suffix starting at base p, with its preceding symbol:
 // '$' when p starts a read, else base p-1.
-__device__ __forceinline__ uint64_t first_key(const TextRec *__restrict__ text, uint64_t nb, uint64_t p) {
-  const WinWords w = window_load(text, nb, p, 0);
+__host__ __device__ __forceinline__ uint64_t first_key(const TextRec *__restrict__ text, uint64_t nb, uint64_t p) {
+  const TextRec t = window_load(text, nb, p, 0);
+  const uint32_t o = (uint32_t)(p & 15);
   uint32_t prev3 = 4;
-  if (!((w.a.starts >> (p & 31)) & 1u)) prev3 = rec_base(text, p - 1);
-  return window_combine(w, nb, p, 0, prev3);
+  if (!((t.lo >> o) & 1u)) prev3 = o ? rec_base_at(t, o - 1) : (uint32_t)(t.lo >> 42) & 3u;
+  return window_combine(t, nb, p, 0, prev3);
 }
 
 // ---------------------------------------------------------------------------

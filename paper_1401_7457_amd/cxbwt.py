@@ -44,7 +44,8 @@ class Stats(ctypes.Structure):
                 ("big_segments", ctypes.c_uint64), ("final_big", ctypes.c_uint64),
                 ("chunk_suffixes", ctypes.c_uint64), ("level_suffixes", ctypes.c_uint64),
                 ("scattered_suffixes", ctypes.c_uint64), ("regathered", ctypes.c_uint64),
-                ("window_fetches", ctypes.c_uint64), ("ms", ctypes.c_float * 8), ("launches", ctypes.c_uint32 * 8)]
+                ("window_fetches", ctypes.c_uint64), ("ms", ctypes.c_float * 8), ("launches", ctypes.c_uint32 * 8),
+                ("level_batches", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 def lib():
@@ -228,7 +229,7 @@ def build_batch_host(cols, device="cuda"):
 def last_stats() -> dict:
     s = Stats()
     lib().cxbwt_last_stats(ctypes.byref(s))
-    out = {f: int(getattr(s, f)) for f, _ in Stats._fields_ if f not in ("ms", "launches")}
+    out = {f: int(getattr(s, f)) for f, _ in Stats._fields_ if f not in ("ms", "launches", "reserved")}
     out["ms"] = {k: float(s.ms[i]) for i, k in enumerate(KERNEL_CLASSES) if s.launches[i]}
     out["launches"] = {k: int(s.launches[i]) for i, k in enumerate(KERNEL_CLASSES) if s.launches[i]}
     return out

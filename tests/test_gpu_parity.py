@@ -71,7 +71,7 @@ def test_pack_flags_bad_bytes():
     assert int(status.item()) != 0
 
 
-EDGE_LENS = [0, 1, 2, 27, 28, 29, 30, 55, 56, 57, 84, 85, 100, 112, 113]
+EDGE_LENS = [0, 1, 2, 15, 16, 17, 26, 27, 28, 29, 30, 53, 54, 55, 56, 57, 80, 81, 82, 84, 85, 100, 108, 112, 113]
 
 
 @pytest.mark.parametrize("alphabet", [b"A", b"AC", b"ACGT"])
@@ -127,6 +127,18 @@ def test_high_coverage_small_genome():
     g = datagen.random_genome(rng, 3000)
     col = datagen.sample_reads(rng, g, 20000, 100, 0.001)  # ~650x coverage: large tie groups
     _check(col, "650x coverage")
+
+
+def test_levels_in_several_batches():
+    """~2000x coverage of a 1.5 kb genome: thousands of level-2 segments of
+    more than one chunk each, more than the level scratch takes at once."""
+    rng = np.random.default_rng(21)
+    g = datagen.random_genome(rng, 1500)
+    col = datagen.sample_reads(rng, g, 30000, 100, 0.001)
+    _check(col, "2000x coverage, batched levels")
+    st = cxbwt.last_stats()
+    _say(f"levels={st['levels']} level_batches={st['level_batches']}")
+    assert st["level_batches"] > st["levels"] - 1, "no level ran in more than one batch"
 
 
 def test_variable_lengths_served_shape():
