@@ -93,12 +93,21 @@ struct CollMap {
   int64_t row_shift;   // n_c - (first base of c)
 };
 
+// Statistics counters are spread over STAT_SPREAD cache lines (indexed by
+// workgroup) so that thousands of workgroups never queue on one address.
+constexpr int STAT_SPREAD = 64;
+constexpr int STAT_STRIDE = 16;  // u64 counters per 128-byte line
+constexpr uint64_t STAT_WORDS = 2ull * STAT_SPREAD * STAT_STRIDE;  // fetches, then scattered
+__device__ __forceinline__ unsigned long long *stat_slot(unsigned long long *base) {
+  return base + (blockIdx.x % STAT_SPREAD) * STAT_STRIDE;
+}
+
 struct Lists {
   Seg *big_next;
-  uint32_t *n_big_next;
+  uint32_t *n_big_next;          // high half of *n_chunk_big
   uint32_t cap_big;
   Seg *chunks;
-  uint32_t *n_chunks;
+  unsigned long long *n_chunk_big;  // chunk count (low 32 bits), big count (high)
   uint32_t cap_chunks;
   Seg *finals;
   uint32_t *n_finals;
@@ -284,14 +293,15 @@ __global__ void k_coll_bases(const uint64_t *__restrict__ offsets, const uint64_
 constexpr int RANK_WPT = 16;                      // words per thread
 constexpr int RANK_BLOCK_WORDS = BLOCK * RANK_WPT;
 
-__global__ __launch_bounds__(BLOCK) void k_rank_count(const TextRec *__restrict__ text, uint64_t nw,
+// Counted on the read-start bitmap (32 positions a word, two records).
+__global__ __launch_bounds__(BLOCK) void k_rank_count(const uint32_t *__restrict__ sbits, uint64_t nw,
                                                       uint32_t *__restrict__ blocksum) {
   __shared__ uint32_t tmp[WAVES];
   const uint64_t w0 = (uint64_t)blockIdx.x * RANK_BLOCK_WORDS + (uint64_t)threadIdx.x * RANK_WPT;
   uint32_t c = 0;
 #pragma unroll
   for (int i = 0; i < RANK_WPT; ++i)
-    if (w0 + i < nw) c += (uint32_t)__popc((uint32_t)text[w0 + i].lo & 0xFFFFu);
+    if (w0 + i < nw) c += (uint32_t)__popc(sbits[w0 + i]);
   uint32_t total;
   block_excl_sum(c, tmp, &total);
   if (threadIdx.x == 0) blocksum[blockIdx.x] = total;
@@ -310,23 +320,26 @@ __global__ __launch_bounds__(BLOCK) void k_rank_top(uint32_t *__restrict__ block
   }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_rank_words(const TextRec *__restrict__ text, uint64_t nw,
+// srank of records 2k and 2k+1 from bitmap word k.
+__global__ __launch_bounds__(BLOCK) void k_rank_words(const uint32_t *__restrict__ sbits, uint64_t nw,
                                                       const uint32_t *__restrict__ blocksum,
-                                                      uint32_t *__restrict__ srank) {
+                                                      uint32_t *__restrict__ srank, uint64_t nrec) {
   __shared__ uint32_t tmp[WAVES];
   const uint64_t w0 = (uint64_t)blockIdx.x * RANK_BLOCK_WORDS + (uint64_t)threadIdx.x * RANK_WPT;
-  uint32_t cnt[RANK_WPT];
+  uint32_t word[RANK_WPT];
   uint32_t c = 0;
 #pragma unroll
   for (int i = 0; i < RANK_WPT; ++i) {
-    cnt[i] = w0 + i < nw ? (uint32_t)__popc((uint32_t)text[w0 + i].lo & 0xFFFFu) : 0u;
-    c += cnt[i];
+    word[i] = w0 + i < nw ? sbits[w0 + i] : 0u;
+    c += (uint32_t)__popc(word[i]);
   }
   uint32_t run = blocksum[blockIdx.x] + block_excl_sum(c, tmp, nullptr);
 #pragma unroll
   for (int i = 0; i < RANK_WPT; ++i) {
-    if (w0 + i < nw) srank[w0 + i] = run;
-    run += cnt[i];
+    const uint64_t r0 = 2 * (w0 + i);
+    if (r0 < nrec) srank[r0] = run;
+    if (r0 + 1 < nrec) srank[r0 + 1] = run + (uint32_t)__popc(word[i] & 0xFFFFu);
+    run += (uint32_t)__popc(word[i]);
   }
 }
 
@@ -594,56 +607,86 @@ __global__ __launch_bounds__(BLOCK) void k_level_scan(const Seg *__restrict__ se
     run += c;
   }
   __syncthreads();
-  // thread 0 classifies the buckets into LDS lists; one atomic per list
-  // reserves the global slots, then the workgroup copies the entries out
-  if (dg == 0) {
-    seg_split[s] = 1;
-    atomicAdd(L.scattered, (unsigned long long)sg.len);
+  // wave 0 classifies the buckets into LDS lists in one uniform (scalar)
+  // pass, reading the counts out of its lanes; lane 0 writes the entries.
+  // One atomic per list reserves the global slots, then the workgroup copies
+  // the entries out.
+  if (dg < 64) {
+    const uint32_t l = dg;
+    uint32_t cv[4], bv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      cv[i] = tot[i * 64 + l];
+      bv[i] = bstart[i * 64 + l];
+    }
+    if (l == 0) {
+      seg_split[s] = 1;
+      atomicAdd(stat_slot(L.scattered), (unsigned long long)sg.len);
+    }
+    const uint8_t nbuf = (uint8_t)(sg.buf ^ 1);
     uint32_t nc = 0, nbg = 0, nf = 0;
-    Seg cur{};
-    bool have = false;
-    for (int b = 0; b < 256; ++b) {
-      const uint32_t c = tot[b];
-      if (!c) continue;
-      const uint64_t st = sg.start + bstart[b];
-      if (c > (uint32_t)CHUNK) {
-        if (have) {
-          st_chunk[nc++] = cur;
-          have = false;
-        }
-        Seg nx{(uint32_t)st, c, sg.r, (uint8_t)(sg.d + 1), (uint8_t)(sg.buf ^ 1), 0, 0, sg.coll};
-        if (sg.d == 7) {
-          // bucket value b is the clamped length; all ordering bits agree
-          if (b < W) {
-            st_fin[nf++] = nx;
-          } else if (sg.r + 1 > L.rmax) {
-            atomicOr(L.status, ST_WINDOW_BOUND);
-          } else {
-            nx.r = sg.r + 1;
-            nx.d = 0;
-            nx.regather = 1;
-            st_big[nbg++] = nx;
+    uint32_t cur_start = 0, cur_len = 0;  // the open chunk (none while cur_len == 0)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      for (int ll = 0; ll < 64; ++ll) {
+        const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)cv[i], ll);
+        if (!c) continue;
+        const int b = i * 64 + ll;
+        const uint32_t st = sg.start + (uint32_t)__builtin_amdgcn_readlane((int)bv[i], ll);
+        if (c > (uint32_t)CHUNK) {
+          if (cur_len) {
+            if (l == 0) st_chunk[nc] = Seg{cur_start, cur_len, sg.r, sg.d, nbuf, 0, 0, sg.coll};
+            ++nc;
+            cur_len = 0;
           }
-        } else {
-          st_big[nbg++] = nx;
+          Seg nx{st, c, sg.r, (uint8_t)(sg.d + 1), nbuf, 0, 0, sg.coll};
+          if (sg.d == 7) {
+            // bucket value b is the clamped length; all ordering bits agree
+            if (b < W) {
+              if (l == 0) st_fin[nf] = nx;
+              ++nf;
+            } else if (sg.r + 1 > L.rmax) {
+              if (l == 0) atomicOr(L.status, ST_WINDOW_BOUND);
+            } else {
+              nx.r = sg.r + 1;
+              nx.d = 0;
+              nx.regather = 1;
+              if (l == 0) st_big[nbg] = nx;
+              ++nbg;
+            }
+          } else {
+            if (l == 0) st_big[nbg] = nx;
+            ++nbg;
+          }
+          continue;
         }
-        continue;
-      }
-      if (have && cur.len + c <= (uint64_t)CHUNK) {
-        cur.len += c;
-      } else {
-        if (have) st_chunk[nc++] = cur;
-        cur = Seg{(uint32_t)st, c, sg.r, sg.d, (uint8_t)(sg.buf ^ 1), 0, 0, sg.coll};
-        have = true;
+        if (cur_len && cur_len + c <= (uint32_t)CHUNK) {
+          cur_len += c;
+        } else {
+          if (cur_len) {
+            if (l == 0) st_chunk[nc] = Seg{cur_start, cur_len, sg.r, sg.d, nbuf, 0, 0, sg.coll};
+            ++nc;
+          }
+          cur_start = st;
+          cur_len = c;
+        }
       }
     }
-    if (have) st_chunk[nc++] = cur;
-    cnt3[0] = nc;
-    cnt3[1] = nbg;
-    cnt3[2] = nf;
-    base3[0] = nc ? atomicAdd(L.n_chunks, nc) : 0u;
-    base3[1] = nbg ? atomicAdd(L.n_big_next, nbg) : 0u;
-    base3[2] = nf ? atomicAdd(L.n_finals, nf) : 0u;
+    if (cur_len) {
+      if (l == 0) st_chunk[nc] = Seg{cur_start, cur_len, sg.r, sg.d, nbuf, 0, 0, sg.coll};
+      ++nc;
+    }
+    if (l == 0) {
+      cnt3[0] = nc;
+      cnt3[1] = nbg;
+      cnt3[2] = nf;
+      // one atomic reserves the chunk and big-segment slots together
+      unsigned long long old = 0;
+      if (nc || nbg) old = atomicAdd(L.n_chunk_big, (unsigned long long)nc | ((unsigned long long)nbg << 32));
+      base3[0] = (uint32_t)old;
+      base3[1] = (uint32_t)(old >> 32);
+      base3[2] = nf ? atomicAdd(L.n_finals, nf) : 0u;
+    }
   }
   __syncthreads();
   copy_out(L.chunks, L.cap_chunks, st_chunk, cnt3[0], base3[0], L.status);
@@ -938,7 +981,7 @@ __global__ __launch_bounds__(LOCAL_WG, LOCAL_OCCUPANCY) void k_local(
     if (j < m) emit_row(ch.start + j, cm, S.K[j], S.H[j], text, srank, bwt, start_row);
   }
   nfetch = wave_incl_sum(nfetch);
-  if (lane == 63 && nfetch) atomicAdd(fetches, (unsigned long long)nfetch);
+  if (lane == 63 && nfetch) atomicAdd(stat_slot(fetches), (unsigned long long)nfetch);
 }
 
 static_assert(CHUNK <= 65535, "group starts are 16-bit");
@@ -955,8 +998,8 @@ inline uint64_t align_up(uint64_t x) { return (x + 255) & ~255ull; }
 struct Layout {
   uint64_t keys0, keys1, hdl0, hdl1, text, srank, rank_blocks, start_row, tile_hist, gsum, segs, tile_prefix,
       group_prefix, seg_or, seg_and, seg_split, big_next, chunks, finals, coll_reads, coll_bases, cmap, counters,
-      total;
-  uint64_t cap_big, cap_chunks, cap_finals, seg_slots, max_tiles, max_groups, n_rec, n_rank_blocks;
+      stats, total;
+  uint64_t cap_big, cap_chunks, cap_finals, seg_slots, max_tiles, max_groups, n_rec, n_rank_words, n_rank_blocks;
 };
 
 bool sizes_ok(uint64_t n_reads, uint64_t n_bases, uint32_t max_read_len) {
@@ -982,7 +1025,8 @@ Layout make_layout(uint64_t n_reads, uint64_t nb, uint32_t n_coll) {
   L.max_tiles = ceil_div(nb, TILE) + L.seg_slots + 1;
   L.max_groups = ceil_div(nb, (uint64_t)TILE * GROUP_TILES) + L.seg_slots + 1;
   L.n_rec = nb / 16 + 2;
-  L.n_rank_blocks = ceil_div(L.n_rec, RANK_BLOCK_WORDS);
+  L.n_rank_words = ceil_div(L.n_rec, 2);  // bitmap words covering the records
+  L.n_rank_blocks = ceil_div(L.n_rank_words, RANK_BLOCK_WORDS);
   uint64_t off = 0;
   auto take = [&](uint64_t bytes) {
     uint64_t at = off;
@@ -1013,6 +1057,7 @@ Layout make_layout(uint64_t n_reads, uint64_t nb, uint32_t n_coll) {
   L.coll_bases = take(8 * ((uint64_t)n_coll + 1));
   L.cmap = take(sizeof(CollMap) * (uint64_t)n_coll);
   L.counters = take(64);
+  L.stats = take(8 * STAT_WORDS);
   L.total = off;
   return L;
 }
@@ -1113,7 +1158,8 @@ struct PhaseTimer {
 };
 
 // counters block layout (uint32 slots; 64-bit counters on even slots)
-enum { C_STATUS = 0, C_NBIG = 1, C_NCHUNK = 2, C_NFINAL = 3, C_FETCH = 8, C_SCATTERED = 10, C_COUNT = 16 };
+// (chunk and big counts share one 64-bit word)
+enum { C_STATUS = 0, C_NFINAL = 1, C_NCHUNK = 2, C_NBIG = 3, C_COUNT = 16 };
 
 struct Buffers {
   uint64_t *keys0, *keys1, *start_row, *coll_reads, *coll_bases;
@@ -1121,7 +1167,7 @@ struct Buffers {
   uint32_t *hdl0, *hdl1, *srank, *rank_blocks, *tile_hist, *gsum, *tile_prefix, *group_prefix, *counters;
   Seg *segs, *big_next, *chunks, *finals;
   CollMap *cmap;
-  unsigned long long *seg_or, *seg_and;
+  unsigned long long *seg_or, *seg_and, *stats;
   uint8_t *seg_split;
 };
 
@@ -1172,7 +1218,7 @@ int finish_level(const Buffers &B, const Layout &Lo, uint64_t nb, uint32_t rmax,
     T.begin();
     k_local<<<n_chunks, LOCAL_WG, 0, st>>>(B.chunks, B.keys0, B.keys1, B.hdl0, B.hdl1, B.text, B.srank, B.cmap,
                                         nb, rmax, bwt, B.start_row, B.counters + C_STATUS,
-                                        (unsigned long long *)(B.counters + C_FETCH));
+                                        B.stats);
     CX_LAUNCHED();
     T.end(PH_LOCAL);
     g_stats.chunks += n_chunks;
@@ -1231,6 +1277,7 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
   B.coll_bases = (uint64_t *)(ws + Lo.coll_bases);
   B.cmap = (CollMap *)(ws + Lo.cmap);
   B.counters = (uint32_t *)(ws + Lo.counters);
+  B.stats = (unsigned long long *)(ws + Lo.stats);
   const uint32_t rmax = maxlen / W + 1;
   uint32_t *counters = B.counters;
 
@@ -1241,6 +1288,7 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
   if (4 * n_sbits > 4 * 256 * Lo.max_tiles) return CXBWT_EDEVICE;
   int rc;
   if ((rc = fill_u32(counters, C_COUNT, 0, st))) return rc;
+  if ((rc = fill_u64((uint64_t *)B.stats, STAT_WORDS, 0, st))) return rc;
   if ((rc = fill_u32(sbits, n_sbits, 0, st))) return rc;
   CX_CHECK(hipMemcpyAsync(B.coll_reads, coll_reads, 8 * ((uint64_t)ncoll + 1), hipMemcpyHostToDevice, st));
   T.begin();
@@ -1278,17 +1326,19 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
   T.begin();
   k_text_records<<<grid_for(Lo.n_rec, 256), 256, 0, st>>>(packed, cxbwt_packed_words(nb), sbits, B.text, Lo.n_rec);
   CX_LAUNCHED();
-  k_rank_count<<<(unsigned)Lo.n_rank_blocks, BLOCK, 0, st>>>(B.text, Lo.n_rec, B.rank_blocks);
+  k_rank_count<<<(unsigned)Lo.n_rank_blocks, BLOCK, 0, st>>>(sbits, Lo.n_rank_words, B.rank_blocks);
   CX_LAUNCHED();
   k_rank_top<<<1, BLOCK, 0, st>>>(B.rank_blocks, (uint32_t)Lo.n_rank_blocks);
   CX_LAUNCHED();
-  k_rank_words<<<(unsigned)Lo.n_rank_blocks, BLOCK, 0, st>>>(B.text, Lo.n_rec, B.rank_blocks, B.srank);
+  k_rank_words<<<(unsigned)Lo.n_rank_blocks, BLOCK, 0, st>>>(sbits, Lo.n_rank_words, B.rank_blocks, B.srank,
+                                                              Lo.n_rec);
   CX_LAUNCHED();
   T.end(PH_PREP);
 
-  Lists Ls{B.big_next, counters + C_NBIG, (uint32_t)Lo.cap_big, B.chunks, counters + C_NCHUNK, (uint32_t)Lo.cap_chunks,
+  Lists Ls{B.big_next, counters + C_NBIG, (uint32_t)Lo.cap_big, B.chunks,
+           (unsigned long long *)(counters + C_NCHUNK), (uint32_t)Lo.cap_chunks,
            B.finals, counters + C_NFINAL, (uint32_t)Lo.cap_finals, counters + C_STATUS, rmax,
-           (unsigned long long *)(counters + C_SCATTERED)};
+           B.stats + STAT_SPREAD * STAT_STRIDE};
   std::vector<uint32_t> tprefix, gprefix;
   uint32_t ntiles = 0, ngroups = 0;
 
@@ -1363,7 +1413,7 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
         if ((rc = upload_segments(B, Lo, part, tprefix, gprefix, ntiles, ngroups, st))) return rc;
         if ((rc = fill_u64((uint64_t *)B.seg_or, nsg, 0, st))) return rc;
         if ((rc = fill_u64((uint64_t *)B.seg_and, nsg, ~0ull, st))) return rc;
-        if ((rc = fill_u32(counters + C_NCHUNK, 2, 0, st))) return rc;  // chunk and final counts
+        if ((rc = fill_u32(counters + C_NFINAL, 2, 0, st))) return rc;  // final and chunk counts
         T.begin();
         k_level_hist<<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, nsg, B.keys0, B.keys1, B.hdl0, B.hdl1, B.text,
                                                nb, B.tile_hist, B.seg_or, B.seg_and);
@@ -1400,11 +1450,15 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
   k_term<<<grid_for(n, 256), 256, 0, st>>>(offsets, n, B.text, B.srank, B.start_row, term_pos);
   CX_LAUNCHED();
   T.end(PH_FINAL);
+  std::vector<uint64_t> hs(STAT_WORDS);
   CX_CHECK(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, st));
+  CX_CHECK(hipMemcpyAsync(hs.data(), B.stats, 8 * STAT_WORDS, hipMemcpyDeviceToHost, st));
   CX_CHECK(hipStreamSynchronize(st));
   T.collect();
-  g_stats.window_fetches = (uint64_t)hc[C_FETCH] | ((uint64_t)hc[C_FETCH + 1] << 32);
-  g_stats.scattered_suffixes = (uint64_t)hc[C_SCATTERED] | ((uint64_t)hc[C_SCATTERED + 1] << 32);
+  for (int i = 0; i < STAT_SPREAD; ++i) {
+    g_stats.window_fetches += hs[i * STAT_STRIDE];
+    g_stats.scattered_suffixes += hs[(STAT_SPREAD + i) * STAT_STRIDE];
+  }
   if (hc[C_STATUS]) return CXBWT_EDEVICE;
   return CXBWT_OK;
 }
