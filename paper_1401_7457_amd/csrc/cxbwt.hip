@@ -764,13 +764,21 @@ __global__ __launch_bounds__(BLOCK) void k_emit_final(const Seg *__restrict__ se
 // groups cost little.
 // ---------------------------------------------------------------------------
 struct LocalSmem {
-  uint64_t K[CHUNK];       // key of each position
-  uint32_t H[CHUNK];       // handle of each position
-  uint16_t live[CHUNK];    // live positions, ascending
-  uint16_t gr[CHUNK];      // group of each live-list entry
-  uint16_t hp[CHUNK + 1];  // first live-list entry of each group
-  uint16_t dst[CHUNK];     // new position of each live-list entry
-  uint8_t head[CHUNK];     // position starts a group
+  uint64_t K[CHUNK];  // key of each position
+  uint32_t H[CHUNK];  // handle of each position
+  union {
+    struct {
+      uint16_t live[CHUNK];    // live positions, ascending
+      uint16_t gr[CHUNK];      // group of each live-list entry
+      uint16_t hp[CHUNK + 1];  // first live-list entry of each group
+      uint16_t dst[CHUNK];     // new position of each live-list entry
+    };
+    struct {                   // while the chunk is split by digits
+      uint32_t cnt[256];
+      uint32_t dstart[256];
+    };
+  };
+  uint8_t head[CHUNK];  // position starts a group
 };
 
 // waves per SIMD the chunk kernel is compiled for (bounds its registers)
@@ -783,6 +791,59 @@ constexpr int LOCAL_SLOTS = LOCAL_ITEMS;  // 64-entry slots of a full live list
 #define CXBWT_FETCH_BATCH 2
 #endif
 constexpr int FETCH_BATCH = CXBWT_FETCH_BATCH < LOCAL_SLOTS ? CXBWT_FETCH_BATCH : LOCAL_SLOTS;
+
+// Stable split of the m suffixes of a chunk by 8-bit digit sel, in place
+// (every suffix is held in registers before any moves).
+__device__ __forceinline__ void wave_split(LocalSmem &S, uint32_t m, int sel, uint32_t lane, uint64_t lt) {
+  for (uint32_t x = lane; x < 256; x += LOCAL_WG) S.cnt[x] = 0;
+  __syncthreads();
+  uint64_t kr[LOCAL_SLOTS];
+  uint32_t hr[LOCAL_SLOTS], dig[LOCAL_SLOTS], pos[LOCAL_SLOTS];
+#pragma unroll
+  for (int i = 0; i < LOCAL_SLOTS; ++i) {
+    const uint32_t j = i * LOCAL_WG + lane;
+    const bool valid = j < m;
+    dig[i] = NODIGIT;
+    if (valid) {
+      kr[i] = S.K[j];
+      hr[i] = S.H[j];
+      dig[i] = digit_of(kr[i], sel);
+    }
+    if (i * LOCAL_WG >= (int)m) continue;
+    // rank among the lanes of this slot with the same digit
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (dig[i] >> b) & 1u;
+      const uint64_t v = __ballot(bit);
+      peers &= bit ? v : ~v;
+    }
+    if (valid) {
+      const uint32_t before = S.cnt[dig[i]];
+      pos[i] = before + (uint32_t)__popcll(peers & lt);
+      if ((peers & lt) == 0) S.cnt[dig[i]] = before + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+  }
+  // digit starts: lane l sums digits 4l .. 4l+3
+  const uint32_t c0 = S.cnt[4 * lane], c1 = S.cnt[4 * lane + 1], c2 = S.cnt[4 * lane + 2], c3 = S.cnt[4 * lane + 3];
+  const uint32_t tot = c0 + c1 + c2 + c3;
+  const uint32_t ex = wave_incl_sum(tot) - tot;
+  S.dstart[4 * lane] = ex;
+  S.dstart[4 * lane + 1] = ex + c0;
+  S.dstart[4 * lane + 2] = ex + c0 + c1;
+  S.dstart[4 * lane + 3] = ex + c0 + c1 + c2;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < LOCAL_SLOTS; ++i) {
+    if (dig[i] != NODIGIT) {
+      const uint32_t q = S.dstart[dig[i]] + pos[i];
+      S.K[q] = kr[i];
+      S.H[q] = hr[i];
+    }
+  }
+  __syncthreads();
+}
 
 // Groups of the live list from the head flags of its positions: gr[x] and
 // hp[g] (hp[number of groups] = n).  One ballot per 64 entries.
@@ -830,15 +891,25 @@ __global__ __launch_bounds__(LOCAL_WG, LOCAL_OCCUPANCY) void k_local(
   }
   __syncthreads();
   // The chunk is a run of buckets that differ in digit d and agree before
-  // it (or, unsplit, one group to be sorted on its whole key).  Each group is
-  // sorted on its current key; after that, groups are runs of equal keys,
-  // refined window by window.
+  // it (or, unsplit, in read order, with d = 0).  Two stable splits, by digit
+  // d + 1 and then by digit d, leave it ordered by both digits; the groups of
+  // equal (d, d + 1) digits are then sorted on their current key, and after
+  // that groups are runs of equal keys, refined window by window.
   const int d0 = ch.d;
+  const bool two = d0 < 7;
+  if (two) {
+    wave_split(S, m, d0 + 1, lane, le & ~(1ull << lane));
+    wave_split(S, m, d0, lane, le & ~(1ull << lane));
+  }
 #pragma unroll
   for (int i = 0; i < LOCAL_SLOTS; ++i) {
     const uint32_t j = i * LOCAL_WG + lane;
     if (j < m) {
-      S.head[j] = (j == 0) || (!ch.unsplit && digit_of(S.K[j], d0) != digit_of(S.K[j - 1], d0));
+      bool h = j == 0;
+      if (!h && two) h = digit_of(S.K[j], d0) != digit_of(S.K[j - 1], d0) ||
+                         digit_of(S.K[j], d0 + 1) != digit_of(S.K[j - 1], d0 + 1);
+      else if (!h) h = !ch.unsplit && digit_of(S.K[j], d0) != digit_of(S.K[j - 1], d0);
+      S.head[j] = h;
       S.live[j] = (uint16_t)j;
     }
   }
