@@ -978,33 +978,30 @@ __global__ __launch_bounds__(LOCAL_WG, LOCAL_OCCUPANCY) void k_local(
     }
     // stable rank inside each live group by all-pairs comparison:
     // rank = #{t < j : key_t <= key_j} + #{t > j : key_t < key_j}; every
-    // rank is taken before any entry moves
+    // rank is taken before any entry moves.  The ordering bits oj are a
+    // multiple of 8, so (key_t & ~7) <= oj is key_t < oj + 8 and
+    // (key_t & ~7) < oj is key_t < oj: one 64-bit compare per key, on the
+    // raw keys (t = j adds nothing to the second count).
     for (uint32_t x = lane; x < n; x += LOCAL_WG) {
       const uint32_t j = S.live[x];
       const uint32_t g = S.gr[x];
       const uint32_t x0 = S.hp[g];
       const uint32_t a = S.live[x0];
       const uint32_t e = a + ((uint32_t)S.hp[g + 1] - x0);  // a group is a run of positions
-      const uint64_t kj = S.K[j];
-      const uint64_t oj = order_bits(kj);
-      // four independent LDS reads per step keep the loop off the
+      const uint64_t oj = order_bits(S.K[j]);
+      const uint64_t below = oj + 8;  // cannot wrap: key bits 9..8 are zero
+      // four independent LDS reads per step keep the loops off the
       // load-latency chain
       uint32_t c = 0;
       uint32_t t = a;
-      for (; t + 4 <= e; t += 4) {
-        const uint64_t o0 = order_bits(S.K[t]);
-        const uint64_t o1 = order_bits(S.K[t + 1]);
-        const uint64_t o2 = order_bits(S.K[t + 2]);
-        const uint64_t o3 = order_bits(S.K[t + 3]);
-        c += (t < j) ? (o0 <= oj) : (o0 < oj);
-        c += (t + 1 < j) ? (o1 <= oj) : (o1 < oj);
-        c += (t + 2 < j) ? (o2 <= oj) : (o2 < oj);
-        c += (t + 3 < j) ? (o3 <= oj) : (o3 < oj);
-      }
-      for (; t < e; ++t) {
-        const uint64_t ot = order_bits(S.K[t]);
-        c += (t < j) ? (ot <= oj) : (ot < oj);
-      }
+      for (; t + 4 <= j; t += 4)
+        c += (uint32_t)(S.K[t] < below) + (uint32_t)(S.K[t + 1] < below) + (uint32_t)(S.K[t + 2] < below) +
+             (uint32_t)(S.K[t + 3] < below);
+      for (; t < j; ++t) c += (uint32_t)(S.K[t] < below);
+      for (; t + 4 <= e; t += 4)
+        c += (uint32_t)(S.K[t] < oj) + (uint32_t)(S.K[t + 1] < oj) + (uint32_t)(S.K[t + 2] < oj) +
+             (uint32_t)(S.K[t + 3] < oj);
+      for (; t < e; ++t) c += (uint32_t)(S.K[t] < oj);
       S.dst[x] = (uint16_t)(a + c);
     }
     __syncthreads();
