@@ -152,6 +152,25 @@ def _batch_mode(args) -> dict:
             packed, _ = cxbwt.pack(dev[i][0])
             cxbwt.build(packed, dev[i][1], c.n_reads, c.n_bases, c.max_read_len)
 
+    tuning = None
+    if not args.no_tune:
+        # untimed: the instantiations are timed on the first wave, the fastest
+        # kept for both forms
+        from paper_1401_7457_amd import autotune
+        w = waves[0]
+        parts = [torch.zeros(1, dtype=torch.int64, device="cuda")]
+        base = 0
+        for i in w:
+            parts.append(dev[i][1][1:] + base)
+            base += cols[i].n_bases
+        cr = np.concatenate([[0], np.cumsum([cols[i].n_reads for i in w])]).astype(np.uint64)
+        packed, _ = cxbwt.pack(torch.cat([dev[i][0] for i in w]))
+        res = autotune.tune_build(packed, torch.cat(parts), int(cr[-1]), base, max(cols[i].max_read_len for i in w),
+                                  coll_reads=cr, repeats=1)
+        tuning = {"tile_items": res["choice"][0], "chunk_items": res["choice"][1],
+                  "ms_per_choice": {f"{a}x{b}": round(v, 3) for (a, b), v in res["ms"].items()}}
+        del packed
+
     out = {}
     for name, fn in (("batched", batched), ("one_at_a_time", sequential)):
         fn()  # warm-up (allocator, code objects)
@@ -175,6 +194,7 @@ def _batch_mode(args) -> dict:
                    "bases": total, "waves": len(waves)},
         "one_at_a_time_gbases_per_s": out["one_at_a_time"]["gbases_per_s"],
         "speedup_vs_one_at_a_time": out["batched"]["gbases_per_s"] / out["one_at_a_time"]["gbases_per_s"],
+        "tuning": tuning,
     }
 
 
@@ -237,6 +257,8 @@ def main() -> int:
     ap.add_argument("--workload", default="plain1", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-scale", type=float, default=0.1, help="oracle sample: plain1 recipe at this scale")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (it times every kernel instantiation on the workload before warm-up)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one device copy of this size (for counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -287,6 +309,15 @@ def main() -> int:
         torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
+
+    tuning = None
+    if not args.no_tune:
+        # untimed: every instantiation is timed on this workload, the fastest kept
+        from paper_1401_7457_amd import autotune
+        cxbwt.pack(text, out=packed, status=pstatus)
+        res = autotune.tune_build(packed, offsets, n, nb, maxlen, repeats=1, workspace=ws, out=(bwt, term))
+        tuning = {"tile_items": res["choice"][0], "chunk_items": res["choice"][1],
+                  "ms_per_choice": {f"{a}x{b}": round(v, 3) for (a, b), v in res["ms"].items()}}
 
     for _ in range(args.warmup):
         step()
@@ -348,6 +379,7 @@ def main() -> int:
                      "avg_launch_ms": dom_ms / max(1, per_launch[dom]), "launches_per_step": per_launch[dom],
                      "algorithmic_bytes_per_step": model[dom]},
         "kernel_ms": per_ms,
+        "tuning": tuning,
         "model_bytes_per_base": model_total / nb,
         "hbm_frac_model_whole_step": model_total / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS,
         "build_stats": {kk: v for kk, v in stats.items() if kk not in ("ms", "launches")},

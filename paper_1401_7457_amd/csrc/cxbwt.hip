@@ -49,17 +49,16 @@ namespace {
 
 using namespace cxk;
 
-#ifndef CXBWT_TILE_ITEMS
-#define CXBWT_TILE_ITEMS 12
-#endif
-constexpr int TILE_ITEMS = CXBWT_TILE_ITEMS;   // suffixes per thread in a level tile
-constexpr int TILE = BLOCK * TILE_ITEMS;       // suffixes per level tile
-#ifndef CXBWT_LOCAL_ITEMS
-#define CXBWT_LOCAL_ITEMS 8
-#endif
+// Tuning.  The level tile (suffixes per thread of a scatter) and the chunk
+// (suffixes per lane of the one-wave chunk kernel) are template parameters;
+// the library holds every listed instantiation and each build uses the one
+// its thread selected (cxbwt_set_tuning).  Capacities are sized for the
+// smallest tile and chunk, so a workspace fits every choice.
 constexpr int LOCAL_WG = 64;                   // one wave finishes a chunk
-constexpr int LOCAL_ITEMS = CXBWT_LOCAL_ITEMS; // suffixes per lane in a chunk
-constexpr int CHUNK = LOCAL_WG * LOCAL_ITEMS;  // largest run finished in LDS
+constexpr int MIN_TILE_ITEMS = 8;
+constexpr int MIN_CHUNK_ITEMS = 4;
+constexpr int MIN_TILE = BLOCK * MIN_TILE_ITEMS;
+constexpr int MIN_CHUNK = LOCAL_WG * MIN_CHUNK_ITEMS;
 constexpr int GROUP_TILES = 256;               // tiles per first-stage scan group
 constexpr uint64_t SEG_BATCH_MIN = 2048;       // segment size the level scratch is sized for
 
@@ -115,6 +114,7 @@ struct Lists {
   uint32_t *status;
   uint32_t rmax;
   unsigned long long *scattered;
+  uint32_t chunk;  // largest run finished by one wave (the selected chunk size)
 };
 
 // Number of read starts strictly before base p: for the first base of a
@@ -358,13 +358,13 @@ __global__ void k_term(const uint64_t *__restrict__ offsets, uint64_t n, const T
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(BLOCK) void k_gen(const Seg *__restrict__ segs, const uint32_t *__restrict__ tile_prefix,
-                                               uint32_t nsegs, const TextRec *__restrict__ text, uint64_t nb,
-                                               uint64_t *__restrict__ keys, uint32_t *__restrict__ hdl) {
+                                               uint32_t nsegs, uint32_t tile_len, const TextRec *__restrict__ text,
+                                               uint64_t nb, uint64_t *__restrict__ keys, uint32_t *__restrict__ hdl) {
   const uint32_t tile = blockIdx.x;
   const uint32_t s = find_upper(tile_prefix, nsegs, tile);
   const Seg sg = segs[s];
-  const uint64_t t0 = sg.start + (uint64_t)(tile - tile_prefix[s]) * TILE;
-  const uint64_t t1 = min(t0 + (uint64_t)TILE, sg.start + sg.len);
+  const uint64_t t0 = sg.start + (uint64_t)(tile - tile_prefix[s]) * tile_len;
+  const uint64_t t1 = min(t0 + (uint64_t)tile_len, sg.start + sg.len);
   for (uint64_t p = t0 + threadIdx.x; p < t1; p += BLOCK) {
     keys[p] = first_key(text, nb, p);
     hdl[p] = (uint32_t)p;
@@ -377,14 +377,14 @@ __global__ __launch_bounds__(BLOCK) void k_gen(const Seg *__restrict__ segs, con
 // and scattered; keys are never stored unsorted.  One segment per collection.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(BLOCK) void k_gen_hist(const Seg *__restrict__ segs, const uint32_t *__restrict__ tile_prefix,
-                                                    uint32_t nsegs, const TextRec *__restrict__ text, uint64_t nb,
-                                                    uint32_t *__restrict__ tile_hist) {
+                                                    uint32_t nsegs, uint32_t tile_len, const TextRec *__restrict__ text,
+                                                    uint64_t nb, uint32_t *__restrict__ tile_hist) {
   __shared__ uint32_t hist[256];
   const uint32_t tile = blockIdx.x;
   const uint32_t s = find_upper(tile_prefix, nsegs, tile);
   const Seg sg = segs[s];
-  const uint64_t t0 = sg.start + (uint64_t)(tile - tile_prefix[s]) * TILE;
-  const uint64_t t1 = min(t0 + (uint64_t)TILE, sg.start + sg.len);
+  const uint64_t t0 = sg.start + (uint64_t)(tile - tile_prefix[s]) * tile_len;
+  const uint64_t t1 = min(t0 + (uint64_t)tile_len, sg.start + sg.len);
   hist[threadIdx.x] = 0;
   __syncthreads();
   for (uint64_t p = t0 + threadIdx.x; p < t1; p += BLOCK) {
@@ -398,22 +398,24 @@ __global__ __launch_bounds__(BLOCK) void k_gen_hist(const Seg *__restrict__ segs
 // Stable scatter of `m` items held in registers to global positions
 // base[digit] + rank-within-tile, staged through LDS so that each digit's run
 // is written contiguously.
+template <int TI>
 struct ScatterSmem {
-  uint64_t sk[TILE];
-  uint32_t sh[TILE];
+  uint64_t sk[BLOCK * TI];
+  uint32_t sh[BLOCK * TI];
   uint32_t wcount[WAVES * 256];
   uint32_t dstart[256];
   uint64_t goff[256];
   uint32_t tmp[WAVES];
 };
 
-__device__ __forceinline__ void tile_scatter(ScatterSmem &S, const uint64_t (&kr)[TILE_ITEMS],
-                                             const uint32_t (&hr)[TILE_ITEMS], const uint32_t (&dig)[TILE_ITEMS],
-                                             uint32_t m, int d, uint64_t *__restrict__ Ko, uint32_t *__restrict__ Ho) {
-  uint32_t pos[TILE_ITEMS];
-  block_multisplit<TILE_ITEMS>(dig, pos, S.wcount, S.dstart, S.tmp);
+template <int TI>
+__device__ __forceinline__ void tile_scatter(ScatterSmem<TI> &S, const uint64_t (&kr)[TI], const uint32_t (&hr)[TI],
+                                             const uint32_t (&dig)[TI], uint32_t m, int d, uint64_t *__restrict__ Ko,
+                                             uint32_t *__restrict__ Ho) {
+  uint32_t pos[TI];
+  block_multisplit<TI>(dig, pos, S.wcount, S.dstart, S.tmp);
 #pragma unroll
-  for (int i = 0; i < TILE_ITEMS; ++i) {
+  for (int i = 0; i < TI; ++i) {
     if (dig[i] != NODIGIT) {
       S.sk[pos[i]] = kr[i];
       S.sh[pos[i]] = hr[i];
@@ -429,6 +431,7 @@ __device__ __forceinline__ void tile_scatter(ScatterSmem &S, const uint64_t (&kr
   }
 }
 
+template <int TI>
 __global__ __launch_bounds__(BLOCK) void k_gen_scatter(const Seg *__restrict__ segs,
                                                        const uint32_t *__restrict__ tile_prefix,
                                                        const uint32_t *__restrict__ group_prefix, uint32_t nsegs,
@@ -436,18 +439,19 @@ __global__ __launch_bounds__(BLOCK) void k_gen_scatter(const Seg *__restrict__ s
                                                        const uint32_t *__restrict__ tile_hist,
                                                        const uint32_t *__restrict__ gsum, uint64_t *__restrict__ Ko,
                                                        uint32_t *__restrict__ Ho) {
-  __shared__ ScatterSmem S;
+  constexpr uint32_t TL = BLOCK * TI;
+  __shared__ ScatterSmem<TI> S;
   const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
   const uint32_t s = find_upper(tile_prefix, nsegs, tile);
   const Seg sg = segs[s];
   const uint32_t tl = tile - tile_prefix[s];
-  const uint64_t t0 = sg.start + (uint64_t)tl * TILE;
-  const uint32_t m = (uint32_t)min((uint64_t)TILE, sg.start + sg.len - t0);
-  uint64_t kr[TILE_ITEMS];
-  uint32_t hr[TILE_ITEMS], dig[TILE_ITEMS];
+  const uint64_t t0 = sg.start + (uint64_t)tl * TL;
+  const uint32_t m = (uint32_t)min((uint64_t)TL, sg.start + sg.len - t0);
+  uint64_t kr[TI];
+  uint32_t hr[TI], dig[TI];
 #pragma unroll
-  for (int i = 0; i < TILE_ITEMS; ++i) {
-    const uint32_t li = item_index<TILE_ITEMS>(i);
+  for (int i = 0; i < TI; ++i) {
+    const uint32_t li = item_index<TI>(i);
     if (li < m) {
       kr[i] = first_key(text, nb, t0 + li);
       hr[i] = (uint32_t)(t0 + li);
@@ -470,8 +474,9 @@ __global__ __launch_bounds__(BLOCK) void k_gen_scatter(const Seg *__restrict__ s
 // Per-tile digit histogram and per-segment OR/AND of the ordering bits.  A
 // segment flagged `regather` first re-fetches its keys for window r.
 __global__ __launch_bounds__(BLOCK) void k_level_hist(const Seg *__restrict__ segs, const uint32_t *__restrict__ tile_prefix,
-                                                      uint32_t nsegs, uint64_t *keys0, uint64_t *keys1,
-                                                      const uint32_t *__restrict__ hdl0, const uint32_t *__restrict__ hdl1,
+                                                      uint32_t nsegs, uint32_t tile_len, uint64_t *keys0,
+                                                      uint64_t *keys1, const uint32_t *__restrict__ hdl0,
+                                                      const uint32_t *__restrict__ hdl1,
                                                       const TextRec *__restrict__ text, uint64_t nb,
                                                       uint32_t *__restrict__ tile_hist, unsigned long long *seg_or,
                                                       unsigned long long *seg_and) {
@@ -480,8 +485,8 @@ __global__ __launch_bounds__(BLOCK) void k_level_hist(const Seg *__restrict__ se
   const uint32_t tile = blockIdx.x;
   const uint32_t s = find_upper(tile_prefix, nsegs, tile);
   const Seg sg = segs[s];
-  const uint64_t t0 = sg.start + (uint64_t)(tile - tile_prefix[s]) * TILE;
-  const uint64_t t1 = min(t0 + (uint64_t)TILE, sg.start + sg.len);
+  const uint64_t t0 = sg.start + (uint64_t)(tile - tile_prefix[s]) * tile_len;
+  const uint64_t t1 = min(t0 + (uint64_t)tile_len, sg.start + sg.len);
   uint64_t *K = sg.buf ? keys1 : keys0;
   const uint32_t *H = sg.buf ? hdl1 : hdl0;
   hist[threadIdx.x] = 0;
@@ -543,7 +548,7 @@ __device__ void push_seg(Seg *list, uint32_t *count, uint32_t cap, const Seg &s,
 
 // Second scan stage, one workgroup per segment: digit totals from the group
 // totals, bucket starts, group bases.  The buckets are then sorted into runs
-// finished in LDS (chunks of at most CHUNK suffixes), segments for the next
+// finished in LDS (chunks of at most L.chunk suffixes), segments for the next
 // level and final groups of identical suffixes.  A segment whose current
 // digit is constant is not scattered: it moves to its first varying digit,
 // or, when all its ordering bits agree, to the next window (a full tie) or
@@ -633,7 +638,7 @@ __global__ __launch_bounds__(BLOCK) void k_level_scan(const Seg *__restrict__ se
         if (!c) continue;
         const int b = i * 64 + ll;
         const uint32_t st = sg.start + (uint32_t)__builtin_amdgcn_readlane((int)bv[i], ll);
-        if (c > (uint32_t)CHUNK) {
+        if (c > L.chunk) {
           if (cur_len) {
             if (l == 0) st_chunk[nc] = Seg{cur_start, cur_len, sg.r, sg.d, nbuf, 0, 0, sg.coll};
             ++nc;
@@ -660,7 +665,7 @@ __global__ __launch_bounds__(BLOCK) void k_level_scan(const Seg *__restrict__ se
           }
           continue;
         }
-        if (cur_len && cur_len + c <= (uint32_t)CHUNK) {
+        if (cur_len && cur_len + c <= L.chunk) {
           cur_len += c;
         } else {
           if (cur_len) {
@@ -695,6 +700,7 @@ __global__ __launch_bounds__(BLOCK) void k_level_scan(const Seg *__restrict__ se
 }
 
 // Stable scatter of one tile by its segment's digit into the other buffer.
+template <int TI>
 __global__ __launch_bounds__(BLOCK) void k_level_scatter(const Seg *__restrict__ segs,
                                                          const uint32_t *__restrict__ tile_prefix,
                                                          const uint32_t *__restrict__ group_prefix, uint32_t nsegs,
@@ -702,24 +708,25 @@ __global__ __launch_bounds__(BLOCK) void k_level_scatter(const Seg *__restrict__
                                                          const uint32_t *__restrict__ tile_hist,
                                                          const uint32_t *__restrict__ gsum, uint64_t *keys0,
                                                          uint64_t *keys1, uint32_t *hdl0, uint32_t *hdl1) {
-  __shared__ ScatterSmem S;
+  constexpr uint32_t TL = BLOCK * TI;
+  __shared__ ScatterSmem<TI> S;
   const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
   const uint32_t s = find_upper(tile_prefix, nsegs, tile);
   if (!seg_split[s]) return;
   const Seg sg = segs[s];
   const uint32_t tl = tile - tile_prefix[s];
-  const uint64_t t0 = sg.start + (uint64_t)tl * TILE;
-  const uint32_t m = (uint32_t)min((uint64_t)TILE, sg.start + sg.len - t0);
+  const uint64_t t0 = sg.start + (uint64_t)tl * TL;
+  const uint32_t m = (uint32_t)min((uint64_t)TL, sg.start + sg.len - t0);
   const uint64_t *Ki = sg.buf ? keys1 : keys0;
   const uint32_t *Hi = sg.buf ? hdl1 : hdl0;
   uint64_t *Ko = sg.buf ? keys0 : keys1;
   uint32_t *Ho = sg.buf ? hdl0 : hdl1;
   const int d = sg.d;
-  uint64_t kr[TILE_ITEMS];
-  uint32_t hr[TILE_ITEMS], dig[TILE_ITEMS];
+  uint64_t kr[TI];
+  uint32_t hr[TI], dig[TI];
 #pragma unroll
-  for (int i = 0; i < TILE_ITEMS; ++i) {
-    const uint32_t li = item_index<TILE_ITEMS>(i);
+  for (int i = 0; i < TI; ++i) {
+    const uint32_t li = item_index<TI>(i);
     if (li < m) {
       kr[i] = Ki[t0 + li];
       hr[i] = Hi[t0 + li];
@@ -737,7 +744,7 @@ __global__ __launch_bounds__(BLOCK) void k_level_scatter(const Seg *__restrict__
 
 // Groups of identical suffixes too large for one workgroup: emit in place.
 __global__ __launch_bounds__(BLOCK) void k_emit_final(const Seg *__restrict__ segs, const uint32_t *__restrict__ tile_prefix,
-                                                      uint32_t nsegs, const uint64_t *__restrict__ keys0,
+                                                      uint32_t nsegs, uint32_t tile_len, const uint64_t *__restrict__ keys0,
                                                       const uint64_t *__restrict__ keys1, const uint32_t *__restrict__ hdl0,
                                                       const uint32_t *__restrict__ hdl1, const TextRec *__restrict__ text,
                                                       const uint32_t *__restrict__ srank,
@@ -746,8 +753,8 @@ __global__ __launch_bounds__(BLOCK) void k_emit_final(const Seg *__restrict__ se
   const uint32_t tile = blockIdx.x;
   const uint32_t s = find_upper(tile_prefix, nsegs, tile);
   const Seg sg = segs[s];
-  const uint64_t t0 = sg.start + (uint64_t)(tile - tile_prefix[s]) * TILE;
-  const uint64_t t1 = min(t0 + (uint64_t)TILE, sg.start + sg.len);
+  const uint64_t t0 = sg.start + (uint64_t)(tile - tile_prefix[s]) * tile_len;
+  const uint64_t t1 = min(t0 + (uint64_t)tile_len, sg.start + sg.len);
   const uint64_t *K = sg.buf ? keys1 : keys0;
   const uint32_t *H = sg.buf ? hdl1 : hdl0;
   const CollMap cm = cmap[sg.coll];
@@ -755,7 +762,7 @@ __global__ __launch_bounds__(BLOCK) void k_emit_final(const Seg *__restrict__ se
 }
 
 // ---------------------------------------------------------------------------
-// a2/a3/a4 in one wave: finish a chunk of at most CHUNK suffixes in LDS.
+// a2/a3/a4 in one wave: finish a chunk of at most 64 LI suffixes in LDS.
 // A chunk is small enough that every group in it is ranked by all-pairs
 // comparison, so the kernel needs no multisplit and no cross-wave barrier;
 // many independent one-wave workgroups per CU hide each other's latency.
@@ -763,7 +770,9 @@ __global__ __launch_bounds__(BLOCK) void k_emit_final(const Seg *__restrict__ se
 // groups that are not finished), so the rounds that refine a few tied
 // groups cost little.
 // ---------------------------------------------------------------------------
+template <int LI>
 struct LocalSmem {
+  static constexpr int CHUNK = LOCAL_WG * LI;
   uint64_t K[CHUNK];  // key of each position
   uint32_t H[CHUNK];  // handle of each position
   union {
@@ -781,26 +790,18 @@ struct LocalSmem {
   uint8_t head[CHUNK];  // position starts a group
 };
 
-// waves per SIMD the chunk kernel is compiled for (bounds its registers)
-#ifndef CXBWT_LOCAL_OCCUPANCY
-#define CXBWT_LOCAL_OCCUPANCY 3
-#endif
-constexpr int LOCAL_OCCUPANCY = CXBWT_LOCAL_OCCUPANCY;
-constexpr int LOCAL_SLOTS = LOCAL_ITEMS;  // 64-entry slots of a full live list
-#ifndef CXBWT_FETCH_BATCH
-#define CXBWT_FETCH_BATCH 2
-#endif
-constexpr int FETCH_BATCH = CXBWT_FETCH_BATCH < LOCAL_SLOTS ? CXBWT_FETCH_BATCH : LOCAL_SLOTS;
+constexpr int FETCH_BATCH = 2;  // window loads in flight per lane
 
 // Stable split of the m suffixes of a chunk by 8-bit digit sel, in place
 // (every suffix is held in registers before any moves).
-__device__ __forceinline__ void wave_split(LocalSmem &S, uint32_t m, int sel, uint32_t lane, uint64_t lt) {
+template <int LI>
+__device__ __forceinline__ void wave_split(LocalSmem<LI> &S, uint32_t m, int sel, uint32_t lane, uint64_t lt) {
   for (uint32_t x = lane; x < 256; x += LOCAL_WG) S.cnt[x] = 0;
   __syncthreads();
-  uint64_t kr[LOCAL_SLOTS];
-  uint32_t hr[LOCAL_SLOTS], dig[LOCAL_SLOTS], pos[LOCAL_SLOTS];
+  uint64_t kr[LI];
+  uint32_t hr[LI], dig[LI], pos[LI];
 #pragma unroll
-  for (int i = 0; i < LOCAL_SLOTS; ++i) {
+  for (int i = 0; i < LI; ++i) {
     const uint32_t j = i * LOCAL_WG + lane;
     const bool valid = j < m;
     dig[i] = NODIGIT;
@@ -835,7 +836,7 @@ __device__ __forceinline__ void wave_split(LocalSmem &S, uint32_t m, int sel, ui
   S.dstart[4 * lane + 3] = ex + c0 + c1 + c2;
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < LOCAL_SLOTS; ++i) {
+  for (int i = 0; i < LI; ++i) {
     if (dig[i] != NODIGIT) {
       const uint32_t q = S.dstart[dig[i]] + pos[i];
       S.K[q] = kr[i];
@@ -847,10 +848,11 @@ __device__ __forceinline__ void wave_split(LocalSmem &S, uint32_t m, int sel, ui
 
 // Groups of the live list from the head flags of its positions: gr[x] and
 // hp[g] (hp[number of groups] = n).  One ballot per 64 entries.
-__device__ __forceinline__ void live_groups(LocalSmem &S, uint32_t n, uint32_t lane, uint64_t le) {
+template <int LI>
+__device__ __forceinline__ void live_groups(LocalSmem<LI> &S, uint32_t n, uint32_t lane, uint64_t le) {
   uint32_t run = 0;
 #pragma unroll
-  for (int i = 0; i < LOCAL_SLOTS; ++i) {
+  for (int i = 0; i < LI; ++i) {
     const uint32_t x = i * LOCAL_WG + lane;
     if (i * LOCAL_WG >= (int)n) break;
     const bool in = x < n;
@@ -867,12 +869,14 @@ __device__ __forceinline__ void live_groups(LocalSmem &S, uint32_t n, uint32_t l
   __syncthreads();
 }
 
-__global__ __launch_bounds__(LOCAL_WG, LOCAL_OCCUPANCY) void k_local(
+// LI suffixes per lane; OCC waves per SIMD the kernel is compiled for
+template <int LI, int OCC>
+__global__ __launch_bounds__(LOCAL_WG, OCC) void k_local(
     const Seg *__restrict__ chunks, const uint64_t *__restrict__ keys0, const uint64_t *__restrict__ keys1,
     const uint32_t *__restrict__ hdl0, const uint32_t *__restrict__ hdl1, const TextRec *__restrict__ text,
     const uint32_t *__restrict__ srank, const CollMap *__restrict__ cmap, uint64_t nb, uint32_t rmax,
     uint8_t *__restrict__ bwt, uint64_t *__restrict__ start_row, uint32_t *status, unsigned long long *fetches) {
-  __shared__ LocalSmem S;
+  __shared__ LocalSmem<LI> S;
   const Seg ch = chunks[blockIdx.x];
   const uint32_t m = (uint32_t)ch.len;
   const uint32_t lane = threadIdx.x;
@@ -882,7 +886,7 @@ __global__ __launch_bounds__(LOCAL_WG, LOCAL_OCCUPANCY) void k_local(
   // entry x of a list is handled by lane x % 64 in slot x / 64: neighbouring
   // lanes hold neighbouring positions, which mostly share a group
 #pragma unroll
-  for (int i = 0; i < LOCAL_SLOTS; ++i) {
+  for (int i = 0; i < LI; ++i) {
     const uint32_t j = i * LOCAL_WG + lane;
     if (j < m) {
       S.K[j] = Kg[ch.start + j];
@@ -902,7 +906,7 @@ __global__ __launch_bounds__(LOCAL_WG, LOCAL_OCCUPANCY) void k_local(
     wave_split(S, m, d0, lane, le & ~(1ull << lane));
   }
 #pragma unroll
-  for (int i = 0; i < LOCAL_SLOTS; ++i) {
+  for (int i = 0; i < LI; ++i) {
     const uint32_t j = i * LOCAL_WG + lane;
     if (j < m) {
       bool h = j == 0;
@@ -924,7 +928,7 @@ __global__ __launch_bounds__(LOCAL_WG, LOCAL_OCCUPANCY) void k_local(
     live_groups(S, n, lane, le);
     uint32_t kept = 0;
 #pragma unroll
-    for (int i = 0; i < LOCAL_SLOTS; ++i) {
+    for (int i = 0; i < LI; ++i) {
       if (i * LOCAL_WG >= (int)n) break;
       const uint32_t x = i * LOCAL_WG + lane;
       bool keep = false;
@@ -1006,10 +1010,10 @@ __global__ __launch_bounds__(LOCAL_WG, LOCAL_OCCUPANCY) void k_local(
     }
     __syncthreads();
     {
-      uint64_t sk[LOCAL_SLOTS];
-      uint32_t sh[LOCAL_SLOTS], sd[LOCAL_SLOTS];
+      uint64_t sk[LI];
+      uint32_t sh[LI], sd[LI];
 #pragma unroll
-      for (int i = 0; i < LOCAL_SLOTS; ++i) {
+      for (int i = 0; i < LI; ++i) {
         const uint32_t x = i * LOCAL_WG + lane;
         if (x < n) {
           const uint32_t j = S.live[x];
@@ -1020,7 +1024,7 @@ __global__ __launch_bounds__(LOCAL_WG, LOCAL_OCCUPANCY) void k_local(
       }
       __syncthreads();
 #pragma unroll
-      for (int i = 0; i < LOCAL_SLOTS; ++i) {
+      for (int i = 0; i < LI; ++i) {
         const uint32_t x = i * LOCAL_WG + lane;
         if (x < n) {
           S.K[sd[i]] = sk[i];
@@ -1031,7 +1035,7 @@ __global__ __launch_bounds__(LOCAL_WG, LOCAL_OCCUPANCY) void k_local(
     __syncthreads();
     // new group heads inside live groups: changes of the full key
 #pragma unroll
-    for (int i = 0; i < LOCAL_SLOTS; ++i) {
+    for (int i = 0; i < LI; ++i) {
       const uint32_t x = i * LOCAL_WG + lane;
       if (i * LOCAL_WG >= (int)n) break;
       if (x >= n) continue;
@@ -1044,7 +1048,7 @@ __global__ __launch_bounds__(LOCAL_WG, LOCAL_OCCUPANCY) void k_local(
   // a4: emit
   const CollMap cm = cmap[ch.coll];
 #pragma unroll
-  for (int i = 0; i < LOCAL_SLOTS; ++i) {
+  for (int i = 0; i < LI; ++i) {
     const uint32_t j = i * LOCAL_WG + lane;
     if (j < m) emit_row(ch.start + j, cm, S.K[j], S.H[j], text, srank, bwt, start_row);
   }
@@ -1052,13 +1056,25 @@ __global__ __launch_bounds__(LOCAL_WG, LOCAL_OCCUPANCY) void k_local(
   if (lane == 63 && nfetch) atomicAdd(stat_slot(fetches), (unsigned long long)nfetch);
 }
 
-static_assert(CHUNK <= 65535, "group starts are 16-bit");
 
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 thread_local cxbwt_stats g_stats;
 thread_local int g_timing = 0;
+
+// The instantiation a build uses (see the tuning constants).
+struct Tuning {
+  uint32_t tile_items;   // 8 or 12 suffixes per thread in a level tile
+  uint32_t chunk_items;  // 4 or 8 suffixes per lane in a chunk
+  uint32_t tile_len() const { return BLOCK * tile_items; }
+  uint32_t chunk() const { return LOCAL_WG * chunk_items; }
+};
+thread_local Tuning g_tuning{12, 8};
+
+bool tuning_ok(uint32_t tile_items, uint32_t chunk_items) {
+  return (tile_items == 8 || tile_items == 12) && (chunk_items == 4 || chunk_items == 8);
+}
 
 inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 inline uint64_t align_up(uint64_t x) { return (x + 255) & ~255ull; }
@@ -1076,22 +1092,23 @@ bool sizes_ok(uint64_t n_reads, uint64_t n_bases, uint32_t max_read_len) {
 
 Layout make_layout(uint64_t n_reads, uint64_t nb, uint32_t n_coll) {
   Layout L{};
-  // segments of one level are disjoint and each holds more than CHUNK
-  // suffixes; level 1 starts with one segment per collection
-  L.cap_big = nb / (CHUNK + 1) + 2;
+  // segments of one level are disjoint and each holds more than a chunk
+  // (at least MIN_CHUNK) suffixes; level 1 starts with one segment per
+  // collection
+  L.cap_big = nb / (MIN_CHUNK + 1) + 2;
   L.cap_finals = L.cap_big;
   // chunks of one level: two neighbouring chunks of a run hold more than
-  // CHUNK suffixes together, and a run ends at an oversized bucket or at the
+  // a chunk's suffixes together, and a run ends at an oversized bucket or at the
   // end of its parent (both at most cap_big per level); level 1 adds one
   // chunk per collection that fits a chunk
-  L.cap_chunks = 2 * ceil_div(nb, CHUNK) + 2 * L.cap_big + n_coll + 2;
+  L.cap_chunks = 2 * ceil_div(nb, MIN_CHUNK) + 2 * L.cap_big + n_coll + 2;
   // segments split in one batch of a level: the per-segment and per-tile
   // scratch is sized for segments of more than SEG_BATCH_MIN suffixes; a
   // level with more segments runs in several batches.  Level 1 (one segment
   // per collection) always fits one batch.
   L.seg_slots = std::max<uint64_t>(nb / (SEG_BATCH_MIN + 1) + 2, (uint64_t)n_coll + 1);
-  L.max_tiles = ceil_div(nb, TILE) + L.seg_slots + 1;
-  L.max_groups = ceil_div(nb, (uint64_t)TILE * GROUP_TILES) + L.seg_slots + 1;
+  L.max_tiles = ceil_div(nb, MIN_TILE) + L.seg_slots + 1;
+  L.max_groups = ceil_div(nb, (uint64_t)MIN_TILE * GROUP_TILES) + L.seg_slots + 1;
   L.n_rec = nb / 16 + 2;
   L.n_rank_words = ceil_div(L.n_rec, 2);  // bitmap words covering the records
   L.n_rank_blocks = ceil_div(L.n_rank_words, RANK_BLOCK_WORDS);
@@ -1241,11 +1258,11 @@ struct Buffers {
 
 // End of the batch of segments starting at b0 that fits the per-segment and
 // per-tile scratch (at least one segment: a single segment always fits).
-size_t batch_end(const std::vector<Seg> &segs, size_t b0, const Layout &Lo) {
+size_t batch_end(const std::vector<Seg> &segs, size_t b0, const Layout &Lo, uint32_t tile_len) {
   uint64_t tiles = 0, groups = 0;
   size_t b1 = b0;
   while (b1 < segs.size() && b1 - b0 < Lo.seg_slots) {
-    const uint64_t nt = ceil_div(segs[b1].len, TILE);
+    const uint64_t nt = ceil_div(segs[b1].len, tile_len);
     const uint64_t ng = ceil_div(nt, GROUP_TILES);
     if (b1 > b0 && (tiles + nt > Lo.max_tiles || groups + ng > Lo.max_groups)) break;
     tiles += nt;
@@ -1257,14 +1274,15 @@ size_t batch_end(const std::vector<Seg> &segs, size_t b0, const Layout &Lo) {
 
 // Upload a segment list with its tile and group prefixes; returns the tile
 // and group totals.
-int upload_segments(const Buffers &B, const Layout &Lo, const std::vector<Seg> &segs, std::vector<uint32_t> &tprefix,
-                    std::vector<uint32_t> &gprefix, uint32_t &ntiles, uint32_t &ngroups, hipStream_t st) {
+int upload_segments(const Buffers &B, const Layout &Lo, const std::vector<Seg> &segs, uint32_t tile_len,
+                    std::vector<uint32_t> &tprefix, std::vector<uint32_t> &gprefix, uint32_t &ntiles,
+                    uint32_t &ngroups, hipStream_t st) {
   const uint32_t ns = (uint32_t)segs.size();
   if (ns > Lo.seg_slots) return CXBWT_EDEVICE;
   tprefix.assign(ns + 1, 0);
   gprefix.assign(ns + 1, 0);
   for (uint32_t i = 0; i < ns; ++i) {
-    const uint32_t nt = (uint32_t)ceil_div(segs[i].len, TILE);
+    const uint32_t nt = (uint32_t)ceil_div(segs[i].len, tile_len);
     tprefix[i + 1] = tprefix[i] + nt;
     gprefix[i + 1] = gprefix[i] + (uint32_t)ceil_div(nt, GROUP_TILES);
   }
@@ -1278,15 +1296,19 @@ int upload_segments(const Buffers &B, const Layout &Lo, const std::vector<Seg> &
 }
 
 // Finish the chunks and final groups a level produced.
-int finish_level(const Buffers &B, const Layout &Lo, uint64_t nb, uint32_t rmax, uint8_t *bwt,
+int finish_level(const Buffers &B, const Layout &Lo, const Tuning &tu, uint64_t nb, uint32_t rmax, uint8_t *bwt,
                  uint32_t n_chunks, uint32_t n_finals, std::vector<uint32_t> &tprefix, PhaseTimer &T,
                  hipStream_t st) {
   if (n_chunks > Lo.cap_chunks || n_finals > Lo.cap_finals) return CXBWT_EDEVICE;
   if (n_chunks) {
     T.begin();
-    k_local<<<n_chunks, LOCAL_WG, 0, st>>>(B.chunks, B.keys0, B.keys1, B.hdl0, B.hdl1, B.text, B.srank, B.cmap,
-                                        nb, rmax, bwt, B.start_row, B.counters + C_STATUS,
-                                        B.stats);
+#define CX_LOCAL(LI, OCC)                                                                                         \
+  k_local<LI, OCC><<<n_chunks, LOCAL_WG, 0, st>>>(B.chunks, B.keys0, B.keys1, B.hdl0, B.hdl1, B.text, B.srank, \
+                                                  B.cmap, nb, rmax, bwt, B.start_row, B.counters + C_STATUS,  \
+                                                  B.stats)
+    if (tu.chunk_items == 8) CX_LOCAL(8, 3);
+    else CX_LOCAL(4, 5);
+#undef CX_LOCAL
     CX_LAUNCHED();
     T.end(PH_LOCAL);
     g_stats.chunks += n_chunks;
@@ -1298,13 +1320,14 @@ int finish_level(const Buffers &B, const Layout &Lo, uint64_t nb, uint32_t rmax,
     tprefix.assign(n_finals + 1, 0);
     uint64_t suffixes = 0;
     for (uint32_t i = 0; i < n_finals; ++i) {
-      tprefix[i + 1] = tprefix[i] + (uint32_t)ceil_div(fin[i].len, TILE);
+      tprefix[i + 1] = tprefix[i] + (uint32_t)ceil_div(fin[i].len, tu.tile_len());
       suffixes += fin[i].len;
     }
     CX_CHECK(hipMemcpyAsync(B.tile_prefix, tprefix.data(), 4 * (n_finals + 1), hipMemcpyHostToDevice, st));
     T.begin();
-    k_emit_final<<<tprefix[n_finals], BLOCK, 0, st>>>(B.finals, B.tile_prefix, n_finals, B.keys0, B.keys1, B.hdl0,
-                                                      B.hdl1, B.text, B.srank, B.cmap, bwt, B.start_row);
+    k_emit_final<<<tprefix[n_finals], BLOCK, 0, st>>>(B.finals, B.tile_prefix, n_finals, tu.tile_len(), B.keys0,
+                                                      B.keys1, B.hdl0, B.hdl1, B.text, B.srank, B.cmap, bwt,
+                                                      B.start_row);
     CX_LAUNCHED();
     T.end(PH_FINAL);
     g_stats.final_big += n_finals;
@@ -1348,9 +1371,11 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
   B.stats = (unsigned long long *)(ws + Lo.stats);
   const uint32_t rmax = maxlen / W + 1;
   uint32_t *counters = B.counters;
+  const Tuning tu = g_tuning;
+  const uint32_t tile_len = tu.tile_len();
 
   // the read-start bitmap lives in the tile histogram area, which is not
-  // used before level 1 (4 bytes per 32 bases against 1 KiB per 3072)
+  // used before level 1 (4 bytes per 32 bases against 1 KiB per 2048)
   uint32_t *sbits = B.tile_hist;
   const uint64_t n_sbits = nb / 32 + 4;
   if (4 * n_sbits > 4 * 256 * Lo.max_tiles) return CXBWT_EDEVICE;
@@ -1381,7 +1406,7 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
     const uint64_t bc = cbase[c + 1] - cbase[c];
     cm[c].out_shift = coll_reads[c + 1];
     cm[c].row_shift = (int64_t)nc - (int64_t)cbase[c];
-    if (bc > (uint64_t)CHUNK) big.push_back(Seg{(uint32_t)cbase[c], (uint32_t)bc, 0, 0, 0, 0, 0, c});
+    if (bc > (uint64_t)tu.chunk()) big.push_back(Seg{(uint32_t)cbase[c], (uint32_t)bc, 0, 0, 0, 0, 0, c});
     else if (bc > 0) small.push_back(Seg{(uint32_t)cbase[c], (uint32_t)bc, 0, 0, 0, 0, 1, c});
   }
   if (ncoll) CX_CHECK(hipMemcpyAsync(B.cmap, cm.data(), sizeof(CollMap) * ncoll, hipMemcpyHostToDevice, st));
@@ -1406,21 +1431,21 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
   Lists Ls{B.big_next, counters + C_NBIG, (uint32_t)Lo.cap_big, B.chunks,
            (unsigned long long *)(counters + C_NCHUNK), (uint32_t)Lo.cap_chunks,
            B.finals, counters + C_NFINAL, (uint32_t)Lo.cap_finals, counters + C_STATUS, rmax,
-           B.stats + STAT_SPREAD * STAT_STRIDE};
+           B.stats + STAT_SPREAD * STAT_STRIDE, tu.chunk()};
   std::vector<uint32_t> tprefix, gprefix;
   uint32_t ntiles = 0, ngroups = 0;
 
   // collections that fit one chunk: keys in read order, one unsplit chunk each
   if (!small.empty()) {
-    if ((rc = upload_segments(B, Lo, small, tprefix, gprefix, ntiles, ngroups, st))) return rc;
+    if ((rc = upload_segments(B, Lo, small, tile_len, tprefix, gprefix, ntiles, ngroups, st))) return rc;
     T.begin();
-    k_gen<<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, (uint32_t)small.size(), B.text, nb, B.keys0,
+    k_gen<<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, (uint32_t)small.size(), tile_len, B.text, nb, B.keys0,
                                     B.hdl0);
     CX_LAUNCHED();
     T.end(PH_GEN);
     CX_CHECK(hipMemcpyAsync(B.chunks, small.data(), sizeof(Seg) * small.size(), hipMemcpyHostToDevice, st));
     if (big.empty()) {
-      if ((rc = finish_level(B, Lo, nb, rmax, bwt, (uint32_t)small.size(), 0, tprefix, T, st))) return rc;
+      if ((rc = finish_level(B, Lo, tu, nb, rmax, bwt, (uint32_t)small.size(), 0, tprefix, T, st))) return rc;
     } else {
       // level 1 appends its chunks after these
       const uint32_t nsmall = (uint32_t)small.size();
@@ -1431,9 +1456,9 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
   if (!big.empty()) {
     // level 1: keys computed from the 2-bit reads, counted, recomputed, scattered
     const uint32_t ns = (uint32_t)big.size();
-    if ((rc = upload_segments(B, Lo, big, tprefix, gprefix, ntiles, ngroups, st))) return rc;
+    if ((rc = upload_segments(B, Lo, big, tile_len, tprefix, gprefix, ntiles, ngroups, st))) return rc;
     T.begin();
-    k_gen_hist<<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, ns, B.text, nb, B.tile_hist);
+    k_gen_hist<<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, ns, tile_len, B.text, nb, B.tile_hist);
     CX_LAUNCHED();
     T.end(PH_GEN);
     T.begin();
@@ -1443,8 +1468,12 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
     CX_LAUNCHED();
     T.end(PH_SCAN);
     T.begin();
-    k_gen_scatter<<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, B.group_prefix, ns, B.text, nb,
-                                            B.tile_hist, B.gsum, B.keys1, B.hdl1);
+    if (tu.tile_items == 8)
+      k_gen_scatter<8><<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, B.group_prefix, ns, B.text, nb, B.tile_hist,
+                                                 B.gsum, B.keys1, B.hdl1);
+    else
+      k_gen_scatter<12><<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, B.group_prefix, ns, B.text, nb, B.tile_hist,
+                                                  B.gsum, B.keys1, B.hdl1);
     CX_LAUNCHED();
     T.end(PH_SCATTER);
     for (const Seg &g : big) g_stats.level_suffixes += g.len;
@@ -1459,7 +1488,7 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
       CX_CHECK(hipMemcpyAsync(big.data(), B.big_next, sizeof(Seg) * big.size(), hipMemcpyDeviceToHost, st));
       CX_CHECK(hipStreamSynchronize(st));
     }
-    if ((rc = finish_level(B, Lo, nb, rmax, bwt, hc[C_NCHUNK], hc[C_NFINAL], tprefix, T, st))) return rc;
+    if ((rc = finish_level(B, Lo, tu, nb, rmax, bwt, hc[C_NCHUNK], hc[C_NFINAL], tprefix, T, st))) return rc;
     // levels 2..: every segment of a level is split by one digit, in batches
     // that fit the per-segment and per-tile scratch
     while (!big.empty()) {
@@ -1474,17 +1503,17 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
       g_stats.big_segments += nsg_all;
       if ((rc = fill_u32(counters + C_NBIG, 1, 0, st))) return rc;
       for (size_t b0 = 0; b0 < big.size();) {
-        const size_t b1 = batch_end(big, b0, Lo);
+        const size_t b1 = batch_end(big, b0, Lo, tile_len);
         const std::vector<Seg> part(big.begin() + b0, big.begin() + b1);
         const uint32_t nsg = (uint32_t)part.size();
         g_stats.level_batches++;
-        if ((rc = upload_segments(B, Lo, part, tprefix, gprefix, ntiles, ngroups, st))) return rc;
+        if ((rc = upload_segments(B, Lo, part, tile_len, tprefix, gprefix, ntiles, ngroups, st))) return rc;
         if ((rc = fill_u64((uint64_t *)B.seg_or, nsg, 0, st))) return rc;
         if ((rc = fill_u64((uint64_t *)B.seg_and, nsg, ~0ull, st))) return rc;
         if ((rc = fill_u32(counters + C_NFINAL, 2, 0, st))) return rc;  // final and chunk counts
         T.begin();
-        k_level_hist<<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, nsg, B.keys0, B.keys1, B.hdl0, B.hdl1, B.text,
-                                               nb, B.tile_hist, B.seg_or, B.seg_and);
+        k_level_hist<<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, nsg, tile_len, B.keys0, B.keys1, B.hdl0,
+                                               B.hdl1, B.text, nb, B.tile_hist, B.seg_or, B.seg_and);
         CX_LAUNCHED();
         T.end(PH_HIST);
         T.begin();
@@ -1494,15 +1523,19 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
         CX_LAUNCHED();
         T.end(PH_SCAN);
         T.begin();
-        k_level_scatter<<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, B.group_prefix, nsg, B.seg_split,
-                                                  B.tile_hist, B.gsum, B.keys0, B.keys1, B.hdl0, B.hdl1);
+        if (tu.tile_items == 8)
+          k_level_scatter<8><<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, B.group_prefix, nsg, B.seg_split,
+                                                       B.tile_hist, B.gsum, B.keys0, B.keys1, B.hdl0, B.hdl1);
+        else
+          k_level_scatter<12><<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, B.group_prefix, nsg, B.seg_split,
+                                                        B.tile_hist, B.gsum, B.keys0, B.keys1, B.hdl0, B.hdl1);
         CX_LAUNCHED();
         T.end(PH_SCATTER);
         CX_CHECK(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, st));
         CX_CHECK(hipStreamSynchronize(st));
         T.collect();
         if (hc[C_STATUS]) return CXBWT_EDEVICE;
-        if ((rc = finish_level(B, Lo, nb, rmax, bwt, hc[C_NCHUNK], hc[C_NFINAL], tprefix, T, st))) return rc;
+        if ((rc = finish_level(B, Lo, tu, nb, rmax, bwt, hc[C_NCHUNK], hc[C_NFINAL], tprefix, T, st))) return rc;
         b0 = b1;
       }
       CX_CHECK(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, st));
@@ -1595,6 +1628,19 @@ int cxbwt_build_batch(const uint64_t *packed, const uint64_t *offsets, uint64_t 
 int cxbwt_last_stats(cxbwt_stats *out) {
   if (!out) return CXBWT_EINVAL;
   *out = g_stats;
+  return CXBWT_OK;
+}
+
+int cxbwt_set_tuning(uint32_t tile_items, uint32_t chunk_items) {
+  if (!tuning_ok(tile_items, chunk_items)) return CXBWT_EINVAL;
+  g_tuning = Tuning{tile_items, chunk_items};
+  return CXBWT_OK;
+}
+
+int cxbwt_get_tuning(uint32_t *tile_items, uint32_t *chunk_items) {
+  if (!tile_items || !chunk_items) return CXBWT_EINVAL;
+  *tile_items = g_tuning.tile_items;
+  *chunk_items = g_tuning.chunk_items;
   return CXBWT_OK;
 }
 

@@ -23,7 +23,11 @@ STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ERANGE: "ERANGE", ENOMEM: "ENOMEM", 
 # Names the C ABI exports (include/cxbwt.h).
 ABI_FUNCTIONS = ("cxbwt_packed_words", "cxbwt_pack", "cxbwt_workspace_bytes", "cxbwt_build",
                  "cxbwt_batch_workspace_bytes", "cxbwt_build_batch", "cxbwt_last_stats", "cxbwt_set_timing",
-                 "cxbwt_status_str")
+                 "cxbwt_set_tuning", "cxbwt_get_tuning", "cxbwt_status_str")
+
+# kernel instantiations the library holds: (suffixes per thread in a level
+# tile, suffixes per lane in a chunk); the first is the default
+TUNING_CHOICES = ((12, 8), (8, 8), (12, 4), (8, 4))
 
 # kernel classes of cxbwt_stats.ms / launches
 KERNEL_CLASSES = ("prep", "gen", "level_hist", "level_scan", "level_scatter", "local", "final_emit", "unused")
@@ -74,6 +78,10 @@ def lib():
             L.cxbwt_last_stats.restype = ctypes.c_int
             L.cxbwt_set_timing.argtypes = [ctypes.c_int]
             L.cxbwt_set_timing.restype = ctypes.c_int
+            L.cxbwt_set_tuning.argtypes = [u32, u32]
+            L.cxbwt_set_tuning.restype = ctypes.c_int
+            L.cxbwt_get_tuning.argtypes = [ctypes.POINTER(u32), ctypes.POINTER(u32)]
+            L.cxbwt_get_tuning.restype = ctypes.c_int
             L.cxbwt_status_str.argtypes = [ctypes.c_int]
             L.cxbwt_status_str.restype = ctypes.c_char_p
             _lib = L
@@ -233,6 +241,21 @@ def last_stats() -> dict:
     out["ms"] = {k: float(s.ms[i]) for i, k in enumerate(KERNEL_CLASSES) if s.launches[i]}
     out["launches"] = {k: int(s.launches[i]) for i, k in enumerate(KERNEL_CLASSES) if s.launches[i]}
     return out
+
+
+def set_tuning(tile_items: int, chunk_items: int) -> None:
+    """Kernel instantiation used by later builds on this host thread."""
+    st = lib().cxbwt_set_tuning(int(tile_items), int(chunk_items))
+    if st != 0:
+        raise CxbwtError(st, f"cxbwt_set_tuning({tile_items}, {chunk_items})")
+
+
+def get_tuning() -> tuple:
+    t, c = ctypes.c_uint32(), ctypes.c_uint32()
+    st = lib().cxbwt_get_tuning(ctypes.byref(t), ctypes.byref(c))
+    if st != 0:
+        raise CxbwtError(st, "cxbwt_get_tuning")
+    return int(t.value), int(c.value)
 
 
 def set_timing(enable: bool) -> bool:

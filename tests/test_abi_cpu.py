@@ -103,3 +103,26 @@ def test_batch_argument_validation_needs_no_gpu():
     assert cxbwt.batch_workspace_bytes(4, 40, 10, 2) >= cxbwt.workspace_bytes(4, 40, 10)
     assert cxbwt.batch_workspace_bytes(4, 40, 10, 0) == 0
     assert cxbwt.batch_workspace_bytes(4, 40, 10, 5) == 0
+
+
+def test_tuning_choices_set_and_get_without_gpu():
+    before = cxbwt.get_tuning()
+    assert before == cxbwt.TUNING_CHOICES[0]
+    try:
+        for ch in cxbwt.TUNING_CHOICES:
+            cxbwt.set_tuning(*ch)
+            assert cxbwt.get_tuning() == ch
+        for bad in ((0, 8), (16, 8), (12, 2), (12, 16), (7, 4)):
+            with pytest.raises(cxbwt.CxbwtError):
+                cxbwt.set_tuning(*bad)
+        assert cxbwt.get_tuning() == cxbwt.TUNING_CHOICES[-1]
+    finally:
+        cxbwt.set_tuning(*before)
+
+
+def test_autotune_shape_key_classes():
+    from paper_1401_7457_amd import autotune
+    a = autotune.shape_key(4_000_000, 400_000_000, 100)
+    assert a == autotune.shape_key(4_100_000, 410_000_000, 100)
+    assert a != autotune.shape_key(40_000_000, 4_000_000_000, 100)
+    assert a != autotune.shape_key(2_000_000, 400_000_000, 250)
