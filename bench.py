@@ -83,18 +83,18 @@ def kernel_sources_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, kclass: str, launches_per_build: int):
+def measured_traffic(workload: str, kclass: str, launches_per_build: int, tuning: str):
     """HBM bytes per launch of a kernel class from the committed counter runs.
 
     None when no counter run exists for this workload, or when the kernel
-    sources changed since it was taken.
+    sources or the kernel instantiation (tuning, "AxB") differ from the run's.
     """
     import json as _json
     path = os.path.join(ROOT, "profiles", f"{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     rec = _json.load(open(path))
-    if rec.get("kernel_sources_sha256_16") != kernel_sources_hash():
+    if rec.get("kernel_sources_sha256_16") != kernel_sources_hash() or rec.get("tuning") != tuning:
         return None
     tot = 0.0
     for k in KERNELS_OF_CLASS.get(kclass, []):
@@ -259,6 +259,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (it times every kernel instantiation on the workload before warm-up)")
+    ap.add_argument("--tuning", default=None, help="force one instantiation, e.g. 8x6 (no autotuner)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one device copy of this size (for counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -311,7 +312,11 @@ def main() -> int:
         del src, dst
 
     tuning = None
-    if not args.no_tune:
+    if args.tuning:
+        a, b = (int(v) for v in args.tuning.split("x"))
+        cxbwt.set_tuning(a, b)
+        tuning = {"tile_items": a, "chunk_items": b, "forced": True}
+    elif not args.no_tune:
         # untimed: every instantiation is timed on this workload, the fastest kept
         from paper_1401_7457_amd import autotune
         cxbwt.pack(text, out=packed, status=pstatus)
@@ -375,7 +380,8 @@ def main() -> int:
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(args.workload, dom, per_launch[dom]),
+                     "traffic": measured_traffic(args.workload, dom, per_launch[dom],
+                                                 "%dx%d" % cxbwt.get_tuning()),
                      "avg_launch_ms": dom_ms / max(1, per_launch[dom]), "launches_per_step": per_launch[dom],
                      "algorithmic_bytes_per_step": model[dom]},
         "kernel_ms": per_ms,

@@ -187,12 +187,12 @@ typedef struct cxbwt_stats {
 /*
  * cxbwt_set_tuning -- pick, for later builds on the calling host thread, the
  * kernel instantiation the build uses (the library holds all of them):
- *   tile_items   suffixes per thread in a level tile (8 or 12; a tile is 256
+ *   tile_items   suffixes per thread in a level tile (6 or 8; a tile is 256
  *                threads): longer tiles write longer runs per bucket
- *   chunk_items  suffixes per lane of the one-wave chunk kernel (4 or 8): the
- *                largest run of small buckets finished in LDS is 64 x this
+ *   chunk_items  suffixes per lane of the one-wave chunk kernel (3, 6 or 8):
+ *                the largest run of small buckets finished in LDS is 64 x this
  * The output is the same for every choice; only speed differs.  Default
- * (12, 8).  CXBWT_EINVAL for other values.  cxbwt_get_tuning reads the
+ * (8, 6).  CXBWT_EINVAL for other values.  cxbwt_get_tuning reads the
  * current choice (CXBWT_EINVAL on NULL).  The workspace size does not depend
  * on the choice.  The autotuner in the Python package times the choices on a
  * sample of a workload and sets the fastest.

@@ -55,8 +55,8 @@ using namespace cxk;
 // its thread selected (cxbwt_set_tuning).  Capacities are sized for the
 // smallest tile and chunk, so a workspace fits every choice.
 constexpr int LOCAL_WG = 64;                   // one wave finishes a chunk
-constexpr int MIN_TILE_ITEMS = 8;
-constexpr int MIN_CHUNK_ITEMS = 4;
+constexpr int MIN_TILE_ITEMS = 6;
+constexpr int MIN_CHUNK_ITEMS = 3;
 constexpr int MIN_TILE = BLOCK * MIN_TILE_ITEMS;
 constexpr int MIN_CHUNK = LOCAL_WG * MIN_CHUNK_ITEMS;
 constexpr int GROUP_TILES = 256;               // tiles per first-stage scan group
@@ -1065,15 +1065,15 @@ thread_local int g_timing = 0;
 
 // The instantiation a build uses (see the tuning constants).
 struct Tuning {
-  uint32_t tile_items;   // 8 or 12 suffixes per thread in a level tile
-  uint32_t chunk_items;  // 4 or 8 suffixes per lane in a chunk
+  uint32_t tile_items;   // 6 or 8 suffixes per thread in a level tile
+  uint32_t chunk_items;  // 3, 6 or 8 suffixes per lane in a chunk
   uint32_t tile_len() const { return BLOCK * tile_items; }
   uint32_t chunk() const { return LOCAL_WG * chunk_items; }
 };
-thread_local Tuning g_tuning{12, 8};
+thread_local Tuning g_tuning{8, 6};
 
 bool tuning_ok(uint32_t tile_items, uint32_t chunk_items) {
-  return (tile_items == 8 || tile_items == 12) && (chunk_items == 4 || chunk_items == 8);
+  return (tile_items == 6 || tile_items == 8) && (chunk_items == 3 || chunk_items == 6 || chunk_items == 8);
 }
 
 inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
@@ -1307,7 +1307,8 @@ int finish_level(const Buffers &B, const Layout &Lo, const Tuning &tu, uint64_t 
                                                   B.cmap, nb, rmax, bwt, B.start_row, B.counters + C_STATUS,  \
                                                   B.stats)
     if (tu.chunk_items == 8) CX_LOCAL(8, 3);
-    else CX_LOCAL(4, 5);
+    else if (tu.chunk_items == 6) CX_LOCAL(6, 4);
+    else CX_LOCAL(3, 6);
 #undef CX_LOCAL
     CX_LAUNCHED();
     T.end(PH_LOCAL);
@@ -1375,7 +1376,7 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
   const uint32_t tile_len = tu.tile_len();
 
   // the read-start bitmap lives in the tile histogram area, which is not
-  // used before level 1 (4 bytes per 32 bases against 1 KiB per 2048)
+  // used before level 1 (4 bytes per 32 bases against 1 KiB per 1536)
   uint32_t *sbits = B.tile_hist;
   const uint64_t n_sbits = nb / 32 + 4;
   if (4 * n_sbits > 4 * 256 * Lo.max_tiles) return CXBWT_EDEVICE;
@@ -1472,8 +1473,8 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
       k_gen_scatter<8><<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, B.group_prefix, ns, B.text, nb, B.tile_hist,
                                                  B.gsum, B.keys1, B.hdl1);
     else
-      k_gen_scatter<12><<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, B.group_prefix, ns, B.text, nb, B.tile_hist,
-                                                  B.gsum, B.keys1, B.hdl1);
+      k_gen_scatter<6><<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, B.group_prefix, ns, B.text, nb, B.tile_hist,
+                                                 B.gsum, B.keys1, B.hdl1);
     CX_LAUNCHED();
     T.end(PH_SCATTER);
     for (const Seg &g : big) g_stats.level_suffixes += g.len;
@@ -1527,8 +1528,8 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
           k_level_scatter<8><<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, B.group_prefix, nsg, B.seg_split,
                                                        B.tile_hist, B.gsum, B.keys0, B.keys1, B.hdl0, B.hdl1);
         else
-          k_level_scatter<12><<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, B.group_prefix, nsg, B.seg_split,
-                                                        B.tile_hist, B.gsum, B.keys0, B.keys1, B.hdl0, B.hdl1);
+          k_level_scatter<6><<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, B.group_prefix, nsg, B.seg_split,
+                                                       B.tile_hist, B.gsum, B.keys0, B.keys1, B.hdl0, B.hdl1);
         CX_LAUNCHED();
         T.end(PH_SCATTER);
         CX_CHECK(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, st));
