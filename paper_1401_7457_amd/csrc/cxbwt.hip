@@ -533,170 +533,194 @@ __global__ __launch_bounds__(BLOCK) void k_group_scan(const uint32_t *__restrict
   gsum[(uint64_t)g * 256 + d] = run;
 }
 
-__device__ void copy_out(Seg *list, uint32_t cap, const Seg *staged, uint32_t count, uint32_t base, uint32_t *status) {
-  for (uint32_t i = threadIdx.x; i < count; i += BLOCK) {
-    if (base + i < cap) list[base + i] = staged[i];
-    else atomicOr(status, ST_LIST_OVERFLOW);
-  }
-}
-
 __device__ void push_seg(Seg *list, uint32_t *count, uint32_t cap, const Seg &s, uint32_t *status) {
   const uint32_t at = atomicAdd(count, 1u);
   if (at < cap) list[at] = s;
   else atomicOr(status, ST_LIST_OVERFLOW);
 }
 
-// Second scan stage, one workgroup per segment: digit totals from the group
-// totals, bucket starts, group bases.  The buckets are then sorted into runs
-// finished in LDS (chunks of at most L.chunk suffixes), segments for the next
-// level and final groups of identical suffixes.  A segment whose current
-// digit is constant is not scattered: it moves to its first varying digit,
-// or, when all its ordering bits agree, to the next window (a full tie) or
-// to the final list (an ended tie).
+// Sorts the buckets of one split segment (digit counts cv and starts bv,
+// digit i*64 + lane in slot i of each lane) into chunks (runs of small
+// buckets of at most L.chunk suffixes), next-level segments and final groups,
+// in one uniform (scalar) pass of the wave.  WRITE = false only counts the
+// entries; WRITE = true has lane 0 store them from the given list positions.
+template <bool WRITE>
+__device__ __forceinline__ void classify_buckets(const Seg &sg, const uint32_t (&cv)[4], const uint32_t (&bv)[4],
+                                                 const Lists &L, uint32_t &nc, uint32_t &nbg, uint32_t &nf,
+                                                 uint32_t base_c, uint32_t base_b, uint32_t base_f) {
+  const uint32_t l = lane_id();
+  const uint8_t nbuf = (uint8_t)(sg.buf ^ 1);
+  auto put = [&](Seg *list, uint32_t cap, uint32_t at, const Seg &e) {
+    if (WRITE && l == 0) {
+      if (at < cap) list[at] = e;
+      else atomicOr(L.status, ST_LIST_OVERFLOW);
+    }
+  };
+  nc = nbg = nf = 0;
+  uint32_t cur_start = 0, cur_len = 0;  // the open chunk (none while cur_len == 0)
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    for (int ll = 0; ll < 64; ++ll) {
+      const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)cv[i], ll);
+      if (!c) continue;
+      const int b = i * 64 + ll;
+      const uint32_t st = sg.start + (uint32_t)__builtin_amdgcn_readlane((int)bv[i], ll);
+      if (c > L.chunk) {
+        if (cur_len) {
+          put(L.chunks, L.cap_chunks, base_c + nc, Seg{cur_start, cur_len, sg.r, sg.d, nbuf, 0, 0, sg.coll});
+          ++nc;
+          cur_len = 0;
+        }
+        Seg nx{st, c, sg.r, (uint8_t)(sg.d + 1), nbuf, 0, 0, sg.coll};
+        if (sg.d == 7) {
+          // bucket value b is the clamped length; all ordering bits agree
+          if (b < W) {
+            put(L.finals, L.cap_finals, base_f + nf, nx);
+            ++nf;
+          } else if (sg.r + 1 > L.rmax) {
+            if (WRITE && l == 0) atomicOr(L.status, ST_WINDOW_BOUND);
+          } else {
+            nx.r = sg.r + 1;
+            nx.d = 0;
+            nx.regather = 1;
+            put(L.big_next, L.cap_big, base_b + nbg, nx);
+            ++nbg;
+          }
+        } else {
+          put(L.big_next, L.cap_big, base_b + nbg, nx);
+          ++nbg;
+        }
+        continue;
+      }
+      if (cur_len && cur_len + c <= L.chunk) {
+        cur_len += c;
+      } else {
+        if (cur_len) {
+          put(L.chunks, L.cap_chunks, base_c + nc, Seg{cur_start, cur_len, sg.r, sg.d, nbuf, 0, 0, sg.coll});
+          ++nc;
+        }
+        cur_start = st;
+        cur_len = c;
+      }
+    }
+  }
+  if (cur_len) {
+    put(L.chunks, L.cap_chunks, base_c + nc, Seg{cur_start, cur_len, sg.r, sg.d, nbuf, 0, 0, sg.coll});
+    ++nc;
+  }
+}
+
+// Second scan stage, one wave per segment (WAVES segments per workgroup):
+// digit totals from the group totals, bucket starts, group bases, then the
+// buckets sorted into chunks, segments for the next level and final groups
+// of identical suffixes.  A segment whose current digit is constant is not
+// scattered: it moves to its first varying digit, or, when all its ordering
+// bits agree, to the next window (a full tie) or to the final list (an ended
+// tie).  The workgroup reserves its list slots with one atomic per list.
 __global__ __launch_bounds__(BLOCK) void k_level_scan(const Seg *__restrict__ segs, const uint32_t *__restrict__ group_prefix,
-                                                      uint32_t *__restrict__ gsum,
+                                                      uint32_t nsegs, uint32_t *__restrict__ gsum,
                                                       const unsigned long long *__restrict__ seg_or,
                                                       const unsigned long long *__restrict__ seg_and,
                                                       uint8_t *__restrict__ seg_split, Lists L, int force_split) {
-  __shared__ uint32_t tot[256];
-  __shared__ uint32_t bstart[256];
-  __shared__ uint32_t tmp[WAVES];
-  __shared__ int single;
-  __shared__ Seg st_chunk[256], st_big[256], st_fin[256];
-  __shared__ uint32_t cnt3[3], base3[3];
-  const uint32_t s = blockIdx.x;
-  const Seg sg = segs[s];
-  const uint32_t gp0 = group_prefix[s], gp1 = group_prefix[s + 1];
-  const uint32_t dg = threadIdx.x;
-  uint32_t total = 0;
-#pragma unroll 8
-  for (uint32_t g = gp0; g < gp1; ++g) total += gsum[(uint64_t)g * 256 + dg];
-  tot[dg] = total;
-  if (dg == 0) single = 0;
-  __syncthreads();
-  if ((uint64_t)total == sg.len && !force_split) single = 1;
-  __syncthreads();
-  if (single) {
-    if (dg == 0) {
-      seg_split[s] = 0;
-      const uint64_t diff = (seg_or[s] ^ seg_and[s]) & ~7ull;
-      Seg nx = sg;
-      nx.regather = 0;
-      if (diff == 0) {
-        if (clamp_of(seg_and[s]) < (uint32_t)W) {
-          push_seg(L.finals, L.n_finals, L.cap_finals, sg, L.status);
-        } else if (sg.r + 1 > L.rmax) {
-          atomicOr(L.status, ST_WINDOW_BOUND);
+  __shared__ uint32_t wcnt[WAVES][3];
+  __shared__ uint32_t wbase[WAVES][3];
+  const uint32_t w = threadIdx.x >> 6;
+  const uint32_t l = lane_id();
+  const uint32_t s = blockIdx.x * WAVES + w;
+  uint32_t cv[4] = {0, 0, 0, 0}, bv[4] = {0, 0, 0, 0};
+  bool split = false;
+  Seg sg{};
+  if (s < nsegs) {
+    sg = segs[s];
+    const uint32_t gp0 = group_prefix[s], gp1 = group_prefix[s + 1];
+    for (uint32_t g = gp0; g < gp1; ++g) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) cv[i] += gsum[(uint64_t)g * 256 + i * 64 + l];
+    }
+    bool one = false;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) one |= cv[i] == sg.len;
+    if (__ballot(one) && !force_split) {
+      if (l == 0) {
+        seg_split[s] = 0;
+        const uint64_t diff = (seg_or[s] ^ seg_and[s]) & ~7ull;
+        Seg nx = sg;
+        nx.regather = 0;
+        if (diff == 0) {
+          if (clamp_of(seg_and[s]) < (uint32_t)W) {
+            push_seg(L.finals, L.n_finals, L.cap_finals, sg, L.status);
+          } else if (sg.r + 1 > L.rmax) {
+            atomicOr(L.status, ST_WINDOW_BOUND);
+          } else {
+            nx.r = sg.r + 1;
+            nx.d = 0;
+            nx.regather = 1;
+            push_seg(L.big_next, L.n_big_next, L.cap_big, nx, L.status);
+          }
         } else {
-          nx.r = sg.r + 1;
-          nx.d = 0;
-          nx.regather = 1;
+          const int top = 63 - __builtin_clzll(diff);
+          nx.d = (uint8_t)(top >= 8 ? (63 - top) >> 3 : 7);
           push_seg(L.big_next, L.n_big_next, L.cap_big, nx, L.status);
         }
-      } else {
-        const int top = 63 - __builtin_clzll(diff);
-        nx.d = (uint8_t)(top >= 8 ? (63 - top) >> 3 : 7);
-        push_seg(L.big_next, L.n_big_next, L.cap_big, nx, L.status);
+      }
+    } else {
+      split = true;
+      // bucket starts: exclusive scan over the digits in order
+      uint32_t carry = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t inc = wave_incl_sum(cv[i]);
+        bv[i] = carry + inc - cv[i];
+        carry += (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
+      }
+      uint32_t run[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) run[i] = sg.start + bv[i];
+      for (uint32_t g = gp0; g < gp1; ++g) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const uint64_t at = (uint64_t)g * 256 + i * 64 + l;
+          const uint32_t c = gsum[at];
+          gsum[at] = run[i];
+          run[i] += c;
+        }
+      }
+      if (l == 0) {
+        seg_split[s] = 1;
+        atomicAdd(stat_slot(L.scattered), (unsigned long long)sg.len);
       }
     }
-    return;
   }
-  const uint32_t ex = block_excl_sum(total, tmp, nullptr);
-  bstart[dg] = ex;
-  uint32_t run = (uint32_t)sg.start + ex;
-#pragma unroll 8
-  for (uint32_t g = gp0; g < gp1; ++g) {
-    const uint64_t at = (uint64_t)g * 256 + dg;
-    const uint32_t c = gsum[at];
-    gsum[at] = run;
-    run += c;
+  uint32_t nc = 0, nbg = 0, nf = 0;
+  if (split) classify_buckets<false>(sg, cv, bv, L, nc, nbg, nf, 0, 0, 0);
+  if (l == 0) {
+    wcnt[w][0] = nc;
+    wcnt[w][1] = nbg;
+    wcnt[w][2] = nf;
   }
   __syncthreads();
-  // wave 0 classifies the buckets into LDS lists in one uniform (scalar)
-  // pass, reading the counts out of its lanes; lane 0 writes the entries.
-  // One atomic per list reserves the global slots, then the workgroup copies
-  // the entries out.
-  if (dg < 64) {
-    const uint32_t l = dg;
-    uint32_t cv[4], bv[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      cv[i] = tot[i * 64 + l];
-      bv[i] = bstart[i * 64 + l];
+  if (threadIdx.x == 0) {
+    uint32_t tc = 0, tb = 0, tf = 0;
+    for (int ww = 0; ww < WAVES; ++ww) {
+      wbase[ww][0] = tc;
+      wbase[ww][1] = tb;
+      wbase[ww][2] = tf;
+      tc += wcnt[ww][0];
+      tb += wcnt[ww][1];
+      tf += wcnt[ww][2];
     }
-    if (l == 0) {
-      seg_split[s] = 1;
-      atomicAdd(stat_slot(L.scattered), (unsigned long long)sg.len);
-    }
-    const uint8_t nbuf = (uint8_t)(sg.buf ^ 1);
-    uint32_t nc = 0, nbg = 0, nf = 0;
-    uint32_t cur_start = 0, cur_len = 0;  // the open chunk (none while cur_len == 0)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      for (int ll = 0; ll < 64; ++ll) {
-        const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)cv[i], ll);
-        if (!c) continue;
-        const int b = i * 64 + ll;
-        const uint32_t st = sg.start + (uint32_t)__builtin_amdgcn_readlane((int)bv[i], ll);
-        if (c > L.chunk) {
-          if (cur_len) {
-            if (l == 0) st_chunk[nc] = Seg{cur_start, cur_len, sg.r, sg.d, nbuf, 0, 0, sg.coll};
-            ++nc;
-            cur_len = 0;
-          }
-          Seg nx{st, c, sg.r, (uint8_t)(sg.d + 1), nbuf, 0, 0, sg.coll};
-          if (sg.d == 7) {
-            // bucket value b is the clamped length; all ordering bits agree
-            if (b < W) {
-              if (l == 0) st_fin[nf] = nx;
-              ++nf;
-            } else if (sg.r + 1 > L.rmax) {
-              if (l == 0) atomicOr(L.status, ST_WINDOW_BOUND);
-            } else {
-              nx.r = sg.r + 1;
-              nx.d = 0;
-              nx.regather = 1;
-              if (l == 0) st_big[nbg] = nx;
-              ++nbg;
-            }
-          } else {
-            if (l == 0) st_big[nbg] = nx;
-            ++nbg;
-          }
-          continue;
-        }
-        if (cur_len && cur_len + c <= L.chunk) {
-          cur_len += c;
-        } else {
-          if (cur_len) {
-            if (l == 0) st_chunk[nc] = Seg{cur_start, cur_len, sg.r, sg.d, nbuf, 0, 0, sg.coll};
-            ++nc;
-          }
-          cur_start = st;
-          cur_len = c;
-        }
-      }
-    }
-    if (cur_len) {
-      if (l == 0) st_chunk[nc] = Seg{cur_start, cur_len, sg.r, sg.d, nbuf, 0, 0, sg.coll};
-      ++nc;
-    }
-    if (l == 0) {
-      cnt3[0] = nc;
-      cnt3[1] = nbg;
-      cnt3[2] = nf;
-      // one atomic reserves the chunk and big-segment slots together
-      unsigned long long old = 0;
-      if (nc || nbg) old = atomicAdd(L.n_chunk_big, (unsigned long long)nc | ((unsigned long long)nbg << 32));
-      base3[0] = (uint32_t)old;
-      base3[1] = (uint32_t)(old >> 32);
-      base3[2] = nf ? atomicAdd(L.n_finals, nf) : 0u;
+    // one atomic reserves the chunk and big-segment slots together
+    unsigned long long old = 0;
+    if (tc || tb) old = atomicAdd(L.n_chunk_big, (unsigned long long)tc | ((unsigned long long)tb << 32));
+    const uint32_t bf = tf ? atomicAdd(L.n_finals, tf) : 0u;
+    for (int ww = 0; ww < WAVES; ++ww) {
+      wbase[ww][0] += (uint32_t)old;
+      wbase[ww][1] += (uint32_t)(old >> 32);
+      wbase[ww][2] += bf;
     }
   }
   __syncthreads();
-  copy_out(L.chunks, L.cap_chunks, st_chunk, cnt3[0], base3[0], L.status);
-  copy_out(L.big_next, L.cap_big, st_big, cnt3[1], base3[1], L.status);
-  copy_out(L.finals, L.cap_finals, st_fin, cnt3[2], base3[2], L.status);
+  if (split) classify_buckets<true>(sg, cv, bv, L, nc, nbg, nf, wbase[w][0], wbase[w][1], wbase[w][2]);
 }
 
 // Stable scatter of one tile by its segment's digit into the other buffer.
@@ -1465,7 +1489,8 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
     T.begin();
     k_group_scan<<<ngroups, BLOCK, 0, st>>>(B.tile_prefix, B.group_prefix, ns, B.tile_hist, B.gsum);
     CX_LAUNCHED();
-    k_level_scan<<<ns, BLOCK, 0, st>>>(B.segs, B.group_prefix, B.gsum, B.seg_or, B.seg_and, B.seg_split, Ls, 1);
+    k_level_scan<<<(unsigned)ceil_div(ns, WAVES), BLOCK, 0, st>>>(B.segs, B.group_prefix, ns, B.gsum, B.seg_or,
+                                                                 B.seg_and, B.seg_split, Ls, 1);
     CX_LAUNCHED();
     T.end(PH_SCAN);
     T.begin();
@@ -1520,7 +1545,8 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
         T.begin();
         k_group_scan<<<ngroups, BLOCK, 0, st>>>(B.tile_prefix, B.group_prefix, nsg, B.tile_hist, B.gsum);
         CX_LAUNCHED();
-        k_level_scan<<<nsg, BLOCK, 0, st>>>(B.segs, B.group_prefix, B.gsum, B.seg_or, B.seg_and, B.seg_split, Ls, 0);
+        k_level_scan<<<(unsigned)ceil_div(nsg, WAVES), BLOCK, 0, st>>>(B.segs, B.group_prefix, nsg, B.gsum, B.seg_or,
+                                                                       B.seg_and, B.seg_split, Ls, 0);
         CX_LAUNCHED();
         T.end(PH_SCAN);
         T.begin();
