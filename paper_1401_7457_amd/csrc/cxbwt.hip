@@ -183,6 +183,15 @@ __global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
 // ---------------------------------------------------------------------------
 // a0: read packing (ASCII -> 2-bit, first base in the top bits)
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t base_code(uint32_t c, bool &bad) {
+  // A C G T = 0x41 0x43 0x47 0x54 -> 0 1 2 3 by bits 2..1 of c ^ (c >> 1)
+  bad |= !(c == 'A' || c == 'C' || c == 'G' || c == 'T');
+  return ((c >> 2) ^ (c >> 1)) & 3u;
+}
+
+// One thread per 32-base word.  Full words with a 16-byte aligned source
+// are read as two 16-byte loads (a wave covers 2 KB contiguously); the tail
+// word and unaligned sources go byte by byte.
 __global__ void k_pack(const uint8_t *__restrict__ ascii, uint64_t nb, uint64_t *__restrict__ packed, uint64_t nwords,
                        uint32_t *status) {
   const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -190,19 +199,24 @@ __global__ void k_pack(const uint8_t *__restrict__ ascii, uint64_t nb, uint64_t 
   const uint64_t t0 = w * 32;
   uint64_t x = 0;
   bool bad = false;
-  for (int j = 0; j < 32; ++j) {
-    const uint64_t t = t0 + j;
-    if (t >= nb) break;
-    const uint8_t c = ascii[t];
-    uint64_t code;
-    switch (c) {
-      case 'A': code = 0; break;
-      case 'C': code = 1; break;
-      case 'G': code = 2; break;
-      case 'T': code = 3; break;
-      default: code = 0; bad = true; break;
+  if (t0 + 32 <= nb && ((uintptr_t)ascii & 15) == 0) {
+    const uint4 *src = reinterpret_cast<const uint4 *>(ascii + t0);
+    const uint4 a = src[0], b = src[1];
+    const uint32_t v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int j = q * 4 + k;  // little-endian: byte k of word q is base j
+        x |= (uint64_t)base_code((v[q] >> (8 * k)) & 0xFFu, bad) << (62 - 2 * j);
+      }
     }
-    x |= code << (62 - 2 * j);
+  } else {
+    for (int j = 0; j < 32; ++j) {
+      const uint64_t t = t0 + j;
+      if (t >= nb) break;
+      x |= (uint64_t)base_code(ascii[t], bad) << (62 - 2 * j);
+    }
   }
   packed[w] = x;
   if (bad && status) atomicOr(status, ST_BAD_CHAR);
@@ -513,18 +527,30 @@ __global__ __launch_bounds__(BLOCK) void k_level_hist(const Seg *__restrict__ se
 
 // First scan stage: inside each group of at most GROUP_TILES consecutive
 // tiles of one segment, turn tile counts into exclusive prefixes per digit
-// and record the group totals.
+// and record the group totals.  Sixteen tile counts are loaded before any
+// is rewritten, so the loop waits for memory once per sixteen tiles.
 __global__ __launch_bounds__(BLOCK) void k_group_scan(const uint32_t *__restrict__ tile_prefix,
                                                       const uint32_t *__restrict__ group_prefix, uint32_t nsegs,
                                                       uint32_t *__restrict__ tile_hist, uint32_t *__restrict__ gsum) {
+  constexpr uint32_t NB = 16;
   const uint32_t g = blockIdx.x;
   const uint32_t s = find_upper(group_prefix, nsegs, g);
   const uint32_t tb = tile_prefix[s] + (g - group_prefix[s]) * GROUP_TILES;
   const uint32_t te = min(tb + (uint32_t)GROUP_TILES, tile_prefix[s + 1]);
   const uint32_t d = threadIdx.x;
   uint32_t run = 0;
-#pragma unroll 8
-  for (uint32_t t = tb; t < te; ++t) {
+  uint32_t t = tb;
+  for (; t + NB <= te; t += NB) {
+    uint32_t x[NB];
+#pragma unroll
+    for (uint32_t j = 0; j < NB; ++j) x[j] = tile_hist[(uint64_t)(t + j) * 256 + d];
+#pragma unroll
+    for (uint32_t j = 0; j < NB; ++j) {
+      tile_hist[(uint64_t)(t + j) * 256 + d] = run;
+      run += x[j];
+    }
+  }
+  for (; t < te; ++t) {
     const uint64_t at = (uint64_t)t * 256 + d;
     const uint32_t c = tile_hist[at];
     tile_hist[at] = run;
@@ -533,138 +559,178 @@ __global__ __launch_bounds__(BLOCK) void k_group_scan(const uint32_t *__restrict
   gsum[(uint64_t)g * 256 + d] = run;
 }
 
-__device__ void push_seg(Seg *list, uint32_t *count, uint32_t cap, const Seg &s, uint32_t *status) {
-  const uint32_t at = atomicAdd(count, 1u);
-  if (at < cap) list[at] = s;
-  else atomicOr(status, ST_LIST_OVERFLOW);
-}
-
-// Sorts the buckets of one split segment (digit counts cv and starts bv,
-// digit i*64 + lane in slot i of each lane) into chunks (runs of small
-// buckets of at most L.chunk suffixes), next-level segments and final groups,
-// in one uniform (scalar) pass of the wave.  WRITE = false only counts the
-// entries; WRITE = true has lane 0 store them from the given list positions.
-template <bool WRITE>
-__device__ __forceinline__ void classify_buckets(const Seg &sg, const uint32_t (&cv)[4], const uint32_t (&bv)[4],
-                                                 const Lists &L, uint32_t &nc, uint32_t &nbg, uint32_t &nf,
-                                                 uint32_t base_c, uint32_t base_b, uint32_t base_f) {
+// Digit totals of groups [g0, g1) added into cv (digit i*64 + lane in slot
+// i), eight groups in flight.
+__device__ __forceinline__ void group_totals(const uint32_t *__restrict__ gsum, uint32_t g0, uint32_t g1,
+                                             uint32_t (&cv)[4]) {
   const uint32_t l = lane_id();
-  const uint8_t nbuf = (uint8_t)(sg.buf ^ 1);
-  auto put = [&](Seg *list, uint32_t cap, uint32_t at, const Seg &e) {
-    if (WRITE && l == 0) {
-      if (at < cap) list[at] = e;
-      else atomicOr(L.status, ST_LIST_OVERFLOW);
-    }
-  };
-  nc = nbg = nf = 0;
-  uint32_t cur_start = 0, cur_len = 0;  // the open chunk (none while cur_len == 0)
+  uint32_t g = g0;
+  for (; g + 8 <= g1; g += 8) {
+    uint32_t x[8][4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    for (int ll = 0; ll < 64; ++ll) {
-      const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)cv[i], ll);
-      if (!c) continue;
-      const int b = i * 64 + ll;
-      const uint32_t st = sg.start + (uint32_t)__builtin_amdgcn_readlane((int)bv[i], ll);
-      if (c > L.chunk) {
-        if (cur_len) {
-          put(L.chunks, L.cap_chunks, base_c + nc, Seg{cur_start, cur_len, sg.r, sg.d, nbuf, 0, 0, sg.coll});
-          ++nc;
-          cur_len = 0;
-        }
-        Seg nx{st, c, sg.r, (uint8_t)(sg.d + 1), nbuf, 0, 0, sg.coll};
-        if (sg.d == 7) {
-          // bucket value b is the clamped length; all ordering bits agree
-          if (b < W) {
-            put(L.finals, L.cap_finals, base_f + nf, nx);
-            ++nf;
-          } else if (sg.r + 1 > L.rmax) {
-            if (WRITE && l == 0) atomicOr(L.status, ST_WINDOW_BOUND);
-          } else {
-            nx.r = sg.r + 1;
-            nx.d = 0;
-            nx.regather = 1;
-            put(L.big_next, L.cap_big, base_b + nbg, nx);
-            ++nbg;
-          }
-        } else {
-          put(L.big_next, L.cap_big, base_b + nbg, nx);
-          ++nbg;
-        }
-        continue;
-      }
-      if (cur_len && cur_len + c <= L.chunk) {
-        cur_len += c;
-      } else {
-        if (cur_len) {
-          put(L.chunks, L.cap_chunks, base_c + nc, Seg{cur_start, cur_len, sg.r, sg.d, nbuf, 0, 0, sg.coll});
-          ++nc;
-        }
-        cur_start = st;
-        cur_len = c;
-      }
-    }
+    for (int j = 0; j < 8; ++j)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) x[j][i] = gsum[(uint64_t)(g + j) * 256 + i * 64 + l];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) cv[i] += x[j][i];
   }
-  if (cur_len) {
-    put(L.chunks, L.cap_chunks, base_c + nc, Seg{cur_start, cur_len, sg.r, sg.d, nbuf, 0, 0, sg.coll});
-    ++nc;
-  }
+  for (; g < g1; ++g)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) cv[i] += gsum[(uint64_t)g * 256 + i * 64 + l];
 }
 
-// Second scan stage, one wave per segment (WAVES segments per workgroup):
-// digit totals from the group totals, bucket starts, group bases, then the
-// buckets sorted into chunks, segments for the next level and final groups
-// of identical suffixes.  A segment whose current digit is constant is not
-// scattered: it moves to its first varying digit, or, when all its ordering
-// bits agree, to the next window (a full tie) or to the final list (an ended
-// tie).  The workgroup reserves its list slots with one atomic per list.
-__global__ __launch_bounds__(BLOCK) void k_level_scan(const Seg *__restrict__ segs, const uint32_t *__restrict__ group_prefix,
-                                                      uint32_t nsegs, uint32_t *__restrict__ gsum,
+// Group totals of groups [g0, g1) replaced by the running bucket positions
+// (starting at run), eight groups in flight.
+__device__ __forceinline__ void group_starts(uint32_t *__restrict__ gsum, uint32_t g0, uint32_t g1,
+                                             uint32_t (&run)[4]) {
+  const uint32_t l = lane_id();
+  uint32_t g = g0;
+  for (; g + 8 <= g1; g += 8) {
+    uint32_t x[8][4];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) x[j][i] = gsum[(uint64_t)(g + j) * 256 + i * 64 + l];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        gsum[(uint64_t)(g + j) * 256 + i * 64 + l] = run[i];
+        run[i] += x[j][i];
+      }
+  }
+  for (; g < g1; ++g)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint64_t at = (uint64_t)g * 256 + i * 64 + l;
+      const uint32_t c = gsum[at];
+      gsum[at] = run[i];
+      run[i] += c;
+    }
+}
+
+// First set bit at or above `from` of a 256-bit mask held as four words;
+// 256 when there is none.
+__device__ __forceinline__ uint32_t first_set_from(const uint64_t (&m)[4], uint32_t from) {
+  uint32_t res = 256;
+#pragma unroll
+  for (int i = 3; i >= 0; --i) {
+    uint64_t x = m[i];
+    if (from >= (uint32_t)(i + 1) * 64) x = 0;
+    else if (from > (uint32_t)i * 64) x &= ~0ull << (from - (uint32_t)i * 64);
+    if (x) res = (uint32_t)i * 64 + (uint32_t)__builtin_ctzll(x);
+  }
+  return res;
+}
+
+// Value of bucket b (< 256) of a wave-distributed 256-entry array (bucket
+// i*64 + lane in slot i), the same in every lane.
+__device__ __forceinline__ uint32_t bucket_at(const uint32_t (&v)[4], uint32_t b) {
+  const int ln = (int)(b & 63);
+  const uint32_t x0 = (uint32_t)__builtin_amdgcn_readlane((int)v[0], ln);
+  const uint32_t x1 = (uint32_t)__builtin_amdgcn_readlane((int)v[1], ln);
+  const uint32_t x2 = (uint32_t)__builtin_amdgcn_readlane((int)v[2], ln);
+  const uint32_t x3 = (uint32_t)__builtin_amdgcn_readlane((int)v[3], ln);
+  const uint32_t i = b >> 6;
+  return i == 0 ? x0 : i == 1 ? x1 : i == 2 ? x2 : x3;
+}
+
+// Number of set bits of m below this lane.
+__device__ __forceinline__ uint32_t bits_below_lane(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Second scan stage.  Each segment gets its digit totals from the group
+// totals, its bucket starts and the start of every (group, digit) run, and
+// its buckets are sorted into chunks (runs of consecutive small buckets of
+// at most L.chunk suffixes), segments for the next level (buckets above
+// L.chunk) and final groups of identical suffixes (an ended tie at the last
+// digit).  A segment whose current digit is constant is not scattered: it
+// moves to its first varying digit, or, when all its ordering bits agree, to
+// the next window (a full tie) or to the final list (an ended tie).
+//
+// COOP = false: one wave per segment, WAVES segments per workgroup.
+// COOP = true: one segment per workgroup, its groups shared by the waves
+// (for segments spanning many groups).  All control below is uniform per
+// wave: chunk boundaries come from a walk of one step per chunk over bucket
+// masks, and the list entries are written by all lanes at once from
+// positions reserved with one atomic per list per workgroup.
+template <bool COOP>
+__global__ __launch_bounds__(BLOCK) void k_level_scan(const Seg *__restrict__ segs,
+                                                      const uint32_t *__restrict__ group_prefix, uint32_t nsegs,
+                                                      uint32_t *__restrict__ gsum,
                                                       const unsigned long long *__restrict__ seg_or,
                                                       const unsigned long long *__restrict__ seg_and,
                                                       uint8_t *__restrict__ seg_split, Lists L, int force_split) {
+  constexpr int CW = COOP ? 1 : WAVES;  // waves that classify a segment
+  __shared__ uint32_t part[COOP ? WAVES : 1][256];
+  __shared__ uint32_t cstart[CW][256];
+  __shared__ uint32_t clen[CW][256];
   __shared__ uint32_t wcnt[WAVES][3];
   __shared__ uint32_t wbase[WAVES][3];
-  const uint32_t w = threadIdx.x >> 6;
+  const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const uint32_t l = lane_id();
-  const uint32_t s = blockIdx.x * WAVES + w;
+  const uint32_t s = COOP ? blockIdx.x : blockIdx.x * WAVES + w;
+  const uint32_t cw = COOP ? 0 : w;  // this wave's chunk-list slot
   uint32_t cv[4] = {0, 0, 0, 0}, bv[4] = {0, 0, 0, 0};
-  bool split = false;
+  int mode = 0;  // 0: no segment, 1: passes through unsplit, 2: split by digit d
   Seg sg{};
+  Seg nx{};
+  int nx_list = 0;  // mode 1: 0 none, 1 next level, 2 final
   if (s < nsegs) {
     sg = segs[s];
     const uint32_t gp0 = group_prefix[s], gp1 = group_prefix[s + 1];
-    for (uint32_t g = gp0; g < gp1; ++g) {
+    uint32_t pre[4] = {0, 0, 0, 0};
+    uint32_t ga = gp0, gb = gp1;
+    if (COOP) {
+      const uint32_t per = (gp1 - gp0 + WAVES - 1) / WAVES;
+      ga = min(gp0 + w * per, gp1);
+      gb = min(ga + per, gp1);
+      uint32_t pc[4] = {0, 0, 0, 0};
+      group_totals(gsum, ga, gb, pc);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) cv[i] += gsum[(uint64_t)g * 256 + i * 64 + l];
+      for (int i = 0; i < 4; ++i) part[w][i * 64 + l] = pc[i];
+      __syncthreads();
+      for (uint32_t ww = 0; ww < (uint32_t)WAVES; ++ww)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const uint32_t x = part[ww][i * 64 + l];
+          cv[i] += x;
+          if (ww < w) pre[i] += x;
+        }
+    } else {
+      group_totals(gsum, gp0, gp1, cv);
     }
     bool one = false;
 #pragma unroll
     for (int i = 0; i < 4; ++i) one |= cv[i] == sg.len;
     if (__ballot(one) && !force_split) {
-      if (l == 0) {
-        seg_split[s] = 0;
-        const uint64_t diff = (seg_or[s] ^ seg_and[s]) & ~7ull;
-        Seg nx = sg;
-        nx.regather = 0;
-        if (diff == 0) {
-          if (clamp_of(seg_and[s]) < (uint32_t)W) {
-            push_seg(L.finals, L.n_finals, L.cap_finals, sg, L.status);
-          } else if (sg.r + 1 > L.rmax) {
-            atomicOr(L.status, ST_WINDOW_BOUND);
-          } else {
-            nx.r = sg.r + 1;
-            nx.d = 0;
-            nx.regather = 1;
-            push_seg(L.big_next, L.n_big_next, L.cap_big, nx, L.status);
-          }
+      mode = 1;
+      const unsigned long long o = seg_or[s], a = seg_and[s];
+      const uint64_t diff = (o ^ a) & ~7ull;
+      nx = sg;
+      nx.regather = 0;
+      if (diff == 0) {
+        if (clamp_of(a) < (uint32_t)W) {
+          nx = sg;
+          nx_list = 2;
+        } else if (sg.r + 1 > L.rmax) {
+          if (l == 0 && (!COOP || w == 0)) atomicOr(L.status, ST_WINDOW_BOUND);
         } else {
-          const int top = 63 - __builtin_clzll(diff);
-          nx.d = (uint8_t)(top >= 8 ? (63 - top) >> 3 : 7);
-          push_seg(L.big_next, L.n_big_next, L.cap_big, nx, L.status);
+          nx.r = sg.r + 1;
+          nx.d = 0;
+          nx.regather = 1;
+          nx_list = 1;
         }
+      } else {
+        const int top = 63 - __builtin_clzll(diff);
+        nx.d = (uint8_t)(top >= 8 ? (63 - top) >> 3 : 7);
+        nx_list = 1;
       }
     } else {
-      split = true;
+      mode = 2;
       // bucket starts: exclusive scan over the digits in order
       uint32_t carry = 0;
 #pragma unroll
@@ -675,24 +741,70 @@ __global__ __launch_bounds__(BLOCK) void k_level_scan(const Seg *__restrict__ se
       }
       uint32_t run[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) run[i] = sg.start + bv[i];
-      for (uint32_t g = gp0; g < gp1; ++g) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const uint64_t at = (uint64_t)g * 256 + i * 64 + l;
-          const uint32_t c = gsum[at];
-          gsum[at] = run[i];
-          run[i] += c;
-        }
-      }
-      if (l == 0) {
-        seg_split[s] = 1;
-        atomicAdd(stat_slot(L.scattered), (unsigned long long)sg.len);
-      }
+      for (int i = 0; i < 4; ++i) run[i] = sg.start + bv[i] + pre[i];
+      group_starts(gsum, ga, gb, run);
     }
   }
+  if (COOP && w != 0) mode = 0;  // wave 0 classifies the workgroup's segment
+
   uint32_t nc = 0, nbg = 0, nf = 0;
-  if (split) classify_buckets<false>(sg, cv, bv, L, nc, nbg, nf, 0, 0, 0);
+  uint64_t NB[4] = {0, 0, 0, 0}, FIN[4] = {0, 0, 0, 0};
+  if (mode == 1) {
+    nbg = nx_list == 1;
+    nf = nx_list == 2;
+  } else if (mode == 2) {
+    const uint32_t C = L.chunk;
+    uint64_t NZS[4], BIG[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      NZS[i] = __ballot(cv[i] != 0 && cv[i] <= C);
+      BIG[i] = __ballot(cv[i] > C);
+    }
+    // chunk walk: a chunk starts at a non-empty small bucket and takes the
+    // following buckets while its size stays within C and no big bucket
+    // intervenes
+    uint32_t b = first_set_from(NZS, 0);
+    while (b < 256) {
+      const uint32_t sb = bucket_at(bv, b);
+      // buckets below b wrap to large differences; the search starts at b + 1
+      uint64_t E[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) E[i] = __ballot(bv[i] + cv[i] - sb > C) | BIG[i];
+      const uint32_t e = first_set_from(E, b + 1);
+      const uint32_t se = e < 256 ? bucket_at(bv, e) : sg.len;
+      if (l == 0) {
+        cstart[cw][nc] = sb;
+        clen[cw][nc] = se - sb;
+      }
+      ++nc;
+      b = e < 256 ? first_set_from(NZS, e) : 256u;
+    }
+    if (sg.d == 7) {
+      // bucket value b is the clamped length; all ordering bits agree
+      FIN[0] = BIG[0] & ((1ull << W) - 1);
+      NB[0] = BIG[0] & ~FIN[0];
+      NB[1] = BIG[1];
+      NB[2] = BIG[2];
+      NB[3] = BIG[3];
+      if ((NB[0] | NB[1] | NB[2] | NB[3]) && sg.r + 1 > L.rmax) {
+        if (l == 0) atomicOr(L.status, ST_WINDOW_BOUND);
+        NB[0] = NB[1] = NB[2] = NB[3] = 0;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) NB[i] = BIG[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      nbg += (uint32_t)__popcll(NB[i]);
+      nf += (uint32_t)__popcll(FIN[i]);
+    }
+    if (l == 0) {
+      seg_split[s] = 1;
+      atomicAdd(stat_slot(L.scattered), (unsigned long long)sg.len);
+    }
+  }
+  if (mode == 1 && l == 0) seg_split[s] = 0;
   if (l == 0) {
     wcnt[w][0] = nc;
     wcnt[w][1] = nbg;
@@ -720,7 +832,46 @@ __global__ __launch_bounds__(BLOCK) void k_level_scan(const Seg *__restrict__ se
     }
   }
   __syncthreads();
-  if (split) classify_buckets<true>(sg, cv, bv, L, nc, nbg, nf, wbase[w][0], wbase[w][1], wbase[w][2]);
+  const uint32_t base_c = wbase[w][0], base_b = wbase[w][1], base_f = wbase[w][2];
+  bool overflow = false;
+  if (mode == 1) {
+    if (l == 0 && nx_list == 1) {
+      if (base_b < L.cap_big) L.big_next[base_b] = nx;
+      else overflow = true;
+    }
+    if (l == 0 && nx_list == 2) {
+      if (base_f < L.cap_finals) L.finals[base_f] = nx;
+      else overflow = true;
+    }
+  } else if (mode == 2) {
+    const uint8_t nbuf = (uint8_t)(sg.buf ^ 1);
+    for (uint32_t j = l; j < nc; j += 64) {
+      const uint32_t at = base_c + j;
+      if (at < L.cap_chunks) L.chunks[at] = Seg{sg.start + cstart[cw][j], clen[cw][j], sg.r, sg.d, nbuf, 0, 0, sg.coll};
+      else overflow = true;
+    }
+    const bool last = sg.d == 7;
+    uint32_t pb = 0, pf = 0;  // entries of the lower slots
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t st = sg.start + bv[i];
+      if ((NB[i] >> l) & 1) {
+        const uint32_t at = base_b + pb + bits_below_lane(NB[i]);
+        const Seg e = last ? Seg{st, cv[i], (uint16_t)(sg.r + 1), 0, nbuf, 1, 0, sg.coll}
+                           : Seg{st, cv[i], sg.r, (uint8_t)(sg.d + 1), nbuf, 0, 0, sg.coll};
+        if (at < L.cap_big) L.big_next[at] = e;
+        else overflow = true;
+      }
+      if ((FIN[i] >> l) & 1) {
+        const uint32_t at = base_f + pf + bits_below_lane(FIN[i]);
+        if (at < L.cap_finals) L.finals[at] = Seg{st, cv[i], sg.r, (uint8_t)(sg.d + 1), nbuf, 0, 0, sg.coll};
+        else overflow = true;
+      }
+      pb += (uint32_t)__popcll(NB[i]);
+      pf += (uint32_t)__popcll(FIN[i]);
+    }
+  }
+  if (overflow) atomicOr(L.status, ST_LIST_OVERFLOW);
 }
 
 // Stable scatter of one tile by its segment's digit into the other buffer.
@@ -1319,6 +1470,19 @@ int upload_segments(const Buffers &B, const Layout &Lo, const std::vector<Seg> &
   return CXBWT_OK;
 }
 
+// Second scan stage launch: a workgroup per segment when the segments span
+// many groups each (the first levels), else a wave per segment.
+void launch_level_scan(const Buffers &B, uint32_t ns, uint32_t ngroups, const Lists &Ls, int force_split,
+                       hipStream_t st) {
+  if (ngroups > 8u * ns)
+    k_level_scan<true><<<ns, BLOCK, 0, st>>>(B.segs, B.group_prefix, ns, B.gsum, B.seg_or, B.seg_and, B.seg_split,
+                                             Ls, force_split);
+  else
+    k_level_scan<false><<<(unsigned)ceil_div(ns, WAVES), BLOCK, 0, st>>>(B.segs, B.group_prefix, ns, B.gsum,
+                                                                          B.seg_or, B.seg_and, B.seg_split, Ls,
+                                                                          force_split);
+}
+
 // Finish the chunks and final groups a level produced.
 int finish_level(const Buffers &B, const Layout &Lo, const Tuning &tu, uint64_t nb, uint32_t rmax, uint8_t *bwt,
                  uint32_t n_chunks, uint32_t n_finals, std::vector<uint32_t> &tprefix, PhaseTimer &T,
@@ -1489,8 +1653,7 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
     T.begin();
     k_group_scan<<<ngroups, BLOCK, 0, st>>>(B.tile_prefix, B.group_prefix, ns, B.tile_hist, B.gsum);
     CX_LAUNCHED();
-    k_level_scan<<<(unsigned)ceil_div(ns, WAVES), BLOCK, 0, st>>>(B.segs, B.group_prefix, ns, B.gsum, B.seg_or,
-                                                                 B.seg_and, B.seg_split, Ls, 1);
+    launch_level_scan(B, ns, ngroups, Ls, 1, st);
     CX_LAUNCHED();
     T.end(PH_SCAN);
     T.begin();
@@ -1545,8 +1708,7 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
         T.begin();
         k_group_scan<<<ngroups, BLOCK, 0, st>>>(B.tile_prefix, B.group_prefix, nsg, B.tile_hist, B.gsum);
         CX_LAUNCHED();
-        k_level_scan<<<(unsigned)ceil_div(nsg, WAVES), BLOCK, 0, st>>>(B.segs, B.group_prefix, nsg, B.gsum, B.seg_or,
-                                                                       B.seg_and, B.seg_split, Ls, 0);
+        launch_level_scan(B, nsg, ngroups, Ls, 0, st);
         CX_LAUNCHED();
         T.end(PH_SCAN);
         T.begin();

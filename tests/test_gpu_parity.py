@@ -69,6 +69,29 @@ def test_pack_flags_bad_bytes():
     _, status = cxbwt.pack(dev)
     torch.cuda.synchronize()
     assert int(status.item()) != 0
+    # whole 32-byte words take the vector-load path: one bad byte anywhere in them
+    rng = np.random.default_rng(5)
+    for bad in (b"N", b"a", b"\x00", b"U", b"\xc1"):
+        for at in (0, 31, 32, 500, 4095):
+            text = datagen.ASCII[rng.integers(0, 4, size=4096)].copy()
+            text[at] = bad[0]
+            _say(f"pack bad byte {bad!r} at {at}")
+            _, status = cxbwt.pack(torch.from_numpy(text).cuda())
+            torch.cuda.synchronize()
+            assert int(status.item()) != 0, (bad, at)
+
+
+def test_pack_unaligned_source():
+    import torch
+    rng = np.random.default_rng(6)
+    text = datagen.ASCII[rng.integers(0, 4, size=5000)]
+    dev = torch.from_numpy(text).cuda()
+    for off in (1, 3, 8, 16, 17):
+        _say(f"pack unaligned offset {off}")
+        packed, status = cxbwt.pack(dev[off:])
+        torch.cuda.synchronize()
+        assert int(status.item()) == 0
+        assert np.array_equal(packed.cpu().numpy().view(np.uint64), oracle.pack(text[off:]))
 
 
 EDGE_LENS = [0, 1, 2, 15, 16, 17, 26, 27, 28, 29, 30, 53, 54, 55, 56, 57, 80, 81, 82, 84, 85, 100, 108, 112, 113]
