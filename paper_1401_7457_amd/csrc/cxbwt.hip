@@ -96,7 +96,26 @@ struct CollMap {
 // workgroup) so that thousands of workgroups never queue on one address.
 constexpr int STAT_SPREAD = 64;
 constexpr int STAT_STRIDE = 16;  // u64 counters per 128-byte line
-constexpr uint64_t STAT_WORDS = 2ull * STAT_SPREAD * STAT_STRIDE;  // fetches, then scattered
+// Kinds: window fetches, scattered suffixes, then what a level's scan
+// produced (folded and cleared after every scan): suffixes, re-keyed
+// suffixes, largest window, tiles and scan groups of the next level's
+// segments, and suffixes and tiles of the final groups.
+enum {
+  K_FETCHES = 0,
+  K_SCATTERED,
+  K_NEXT_LEN,
+  K_NEXT_REGATHER,
+  K_NEXT_MAXR,
+  K_NEXT_TILES,
+  K_NEXT_GROUPS,
+  K_FINAL_LEN,
+  K_FINAL_TILES,
+  K_KINDS
+};
+constexpr int K_LEVEL_FIRST = K_NEXT_LEN;
+constexpr int K_LEVEL_KINDS = K_KINDS - K_NEXT_LEN;
+constexpr uint64_t STAT_KIND = (uint64_t)STAT_SPREAD * STAT_STRIDE;
+constexpr uint64_t STAT_WORDS = K_KINDS * STAT_KIND;
 __device__ __forceinline__ unsigned long long *stat_slot(unsigned long long *base) {
   return base + (blockIdx.x % STAT_SPREAD) * STAT_STRIDE;
 }
@@ -113,8 +132,9 @@ struct Lists {
   uint32_t cap_finals;
   uint32_t *status;
   uint32_t rmax;
-  unsigned long long *scattered;
+  unsigned long long *stats;  // the statistics block (K_* kinds)
   uint32_t chunk;  // largest run finished by one wave (the selected chunk size)
+  uint32_t tile_len;  // suffixes per level tile
 };
 
 // Number of read starts strictly before base p: for the first base of a
@@ -637,6 +657,13 @@ __device__ __forceinline__ uint32_t bucket_at(const uint32_t (&v)[4], uint32_t b
   return i == 0 ? x0 : i == 1 ? x1 : i == 2 ? x2 : x3;
 }
 
+// Sum over the wave, in every lane.
+__device__ __forceinline__ uint32_t wave_total(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 // Number of set bits of m below this lane.
 __device__ __forceinline__ uint32_t bits_below_lane(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -670,6 +697,7 @@ __global__ __launch_bounds__(BLOCK) void k_level_scan(const Seg *__restrict__ se
   __shared__ uint32_t clen[CW][256];
   __shared__ uint32_t wcnt[WAVES][3];
   __shared__ uint32_t wbase[WAVES][3];
+  __shared__ uint32_t wstat[WAVES][K_LEVEL_KINDS];
   const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const uint32_t l = lane_id();
   const uint32_t s = COOP ? blockIdx.x : blockIdx.x * WAVES + w;
@@ -749,9 +777,23 @@ __global__ __launch_bounds__(BLOCK) void k_level_scan(const Seg *__restrict__ se
 
   uint32_t nc = 0, nbg = 0, nf = 0;
   uint64_t NB[4] = {0, 0, 0, 0}, FIN[4] = {0, 0, 0, 0};
+  // what this wave hands on: K_NEXT_LEN .. K_FINAL_TILES
+  uint32_t ls[K_LEVEL_KINDS] = {0, 0, 0, 0, 0, 0, 0};
+  const uint32_t T = L.tile_len;
   if (mode == 1) {
     nbg = nx_list == 1;
     nf = nx_list == 2;
+    const uint32_t nt = (nx.len + T - 1) / T;
+    if (nx_list == 1) {
+      ls[K_NEXT_LEN - K_LEVEL_FIRST] = nx.len;
+      ls[K_NEXT_REGATHER - K_LEVEL_FIRST] = nx.regather ? nx.len : 0u;
+      ls[K_NEXT_MAXR - K_LEVEL_FIRST] = nx.r;
+      ls[K_NEXT_TILES - K_LEVEL_FIRST] = nt;
+      ls[K_NEXT_GROUPS - K_LEVEL_FIRST] = (nt + GROUP_TILES - 1) / GROUP_TILES;
+    } else if (nx_list == 2) {
+      ls[K_FINAL_LEN - K_LEVEL_FIRST] = nx.len;
+      ls[K_FINAL_TILES - K_LEVEL_FIRST] = nt;
+    }
   } else if (mode == 2) {
     const uint32_t C = L.chunk;
     uint64_t NZS[4], BIG[4];
@@ -799,9 +841,31 @@ __global__ __launch_bounds__(BLOCK) void k_level_scan(const Seg *__restrict__ se
       nbg += (uint32_t)__popcll(NB[i]);
       nf += (uint32_t)__popcll(FIN[i]);
     }
+    uint32_t blen = 0, btiles = 0, bgroups = 0, flen = 0, ftiles = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t nt = (cv[i] + T - 1) / T;
+      if ((NB[i] >> l) & 1) {
+        blen += cv[i];
+        btiles += nt;
+        bgroups += (nt + GROUP_TILES - 1) / GROUP_TILES;
+      }
+      if ((FIN[i] >> l) & 1) {
+        flen += cv[i];
+        ftiles += nt;
+      }
+    }
+    blen = wave_total(blen);
+    ls[K_NEXT_LEN - K_LEVEL_FIRST] = blen;
+    ls[K_NEXT_REGATHER - K_LEVEL_FIRST] = sg.d == 7 ? blen : 0u;
+    ls[K_NEXT_MAXR - K_LEVEL_FIRST] = nbg ? sg.r + (sg.d == 7 ? 1u : 0u) : 0u;
+    ls[K_NEXT_TILES - K_LEVEL_FIRST] = wave_total(btiles);
+    ls[K_NEXT_GROUPS - K_LEVEL_FIRST] = wave_total(bgroups);
+    ls[K_FINAL_LEN - K_LEVEL_FIRST] = wave_total(flen);
+    ls[K_FINAL_TILES - K_LEVEL_FIRST] = wave_total(ftiles);
     if (l == 0) {
       seg_split[s] = 1;
-      atomicAdd(stat_slot(L.scattered), (unsigned long long)sg.len);
+      atomicAdd(stat_slot(L.stats + K_SCATTERED * STAT_KIND), (unsigned long long)sg.len);
     }
   }
   if (mode == 1 && l == 0) seg_split[s] = 0;
@@ -809,9 +873,22 @@ __global__ __launch_bounds__(BLOCK) void k_level_scan(const Seg *__restrict__ se
     wcnt[w][0] = nc;
     wcnt[w][1] = nbg;
     wcnt[w][2] = nf;
+#pragma unroll
+    for (int k = 0; k < K_LEVEL_KINDS; ++k) wstat[w][k] = ls[k];
   }
   __syncthreads();
   if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K_LEVEL_KINDS; ++k) {
+      unsigned long long v = 0;
+      for (int ww = 0; ww < WAVES; ++ww)
+        v = (k + K_LEVEL_FIRST == K_NEXT_MAXR) ? max(v, (unsigned long long)wstat[ww][k]) : v + wstat[ww][k];
+      unsigned long long *slot = stat_slot(L.stats + (k + K_LEVEL_FIRST) * STAT_KIND);
+      if (v) {
+        if (k + K_LEVEL_FIRST == K_NEXT_MAXR) atomicMax(slot, v);
+        else atomicAdd(slot, v);
+      }
+    }
     uint32_t tc = 0, tb = 0, tf = 0;
     for (int ww = 0; ww < WAVES; ++ww) {
       wbase[ww][0] = tc;
@@ -872,6 +949,118 @@ __global__ __launch_bounds__(BLOCK) void k_level_scan(const Seg *__restrict__ se
     }
   }
   if (overflow) atomicOr(L.status, ST_LIST_OVERFLOW);
+}
+
+// Folds the level kinds of the statistics block into out[0..K_LEVEL_KINDS)
+// (sums, a maximum for the window) and clears them for the next scan.  One
+// wave.
+__global__ __launch_bounds__(64) void k_level_fold(unsigned long long *__restrict__ stats,
+                                                   unsigned long long *__restrict__ out) {
+  const uint32_t l = lane_id();
+  for (int k = K_LEVEL_FIRST; k < K_KINDS; ++k) {
+    unsigned long long *slot = stats + k * STAT_KIND + (uint64_t)l * STAT_STRIDE;
+    unsigned long long v = *slot;
+    *slot = 0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const unsigned long long t = __shfl_xor(v, o, 64);
+      v = k == K_NEXT_MAXR ? max(v, t) : v + t;
+    }
+    if (l == 0) out[k - K_LEVEL_FIRST] = v;
+  }
+}
+
+// Tile and group prefixes of a segment list on the device.  Entries sit
+// item_index<SEGP_ITEMS> in each workgroup of BLOCK threads; k_seg_count
+// writes per-workgroup totals (tiles, groups), k_seg_scan adds the totals
+// of the workgroups before it, writes tile_prefix[i] and group_prefix[i]
+// (and entry n: the totals) and, when copy is given, the list itself.
+constexpr int SEGP_ITEMS = 16;
+constexpr uint32_t SEGP_WG = BLOCK * SEGP_ITEMS;
+
+__device__ __forceinline__ void seg_tiles(const Seg *__restrict__ list, uint32_t n, uint32_t tile_len,
+                                          uint32_t (&t)[SEGP_ITEMS], uint32_t (&g)[SEGP_ITEMS]) {
+#pragma unroll
+  for (int i = 0; i < SEGP_ITEMS; ++i) {
+    const uint64_t at = (uint64_t)blockIdx.x * SEGP_WG + item_index<SEGP_ITEMS>(i);
+    const uint32_t len = at < n ? list[at].len : 0u;
+    t[i] = (len + tile_len - 1) / tile_len;
+    g[i] = (t[i] + GROUP_TILES - 1) / GROUP_TILES;
+  }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_seg_count(const Seg *__restrict__ list, uint32_t n, uint32_t tile_len,
+                                                     uint32_t *__restrict__ wg_tot) {
+  __shared__ uint32_t tmp[WAVES];
+  uint32_t t[SEGP_ITEMS], g[SEGP_ITEMS];
+  seg_tiles(list, n, tile_len, t, g);
+  uint32_t st = 0, sgr = 0;
+#pragma unroll
+  for (int i = 0; i < SEGP_ITEMS; ++i) {
+    st += t[i];
+    sgr += g[i];
+  }
+  uint32_t tt = 0, tg = 0;
+  (void)block_excl_sum(st, tmp, &tt);
+  (void)block_excl_sum(sgr, tmp, &tg);
+  if (threadIdx.x == 0) {
+    wg_tot[2 * blockIdx.x] = tt;
+    wg_tot[2 * blockIdx.x + 1] = tg;
+  }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_seg_scan(const Seg *__restrict__ list, uint32_t n, uint32_t tile_len,
+                                                    const uint32_t *__restrict__ wg_tot, Seg *__restrict__ copy,
+                                                    uint32_t *__restrict__ tile_prefix,
+                                                    uint32_t *__restrict__ group_prefix) {
+  __shared__ uint32_t tmp[WAVES];
+  __shared__ uint32_t wt[WAVES][2];
+  // base of this workgroup: the totals of the workgroups before it
+  uint32_t bt = 0, bg = 0;
+  for (uint32_t k = threadIdx.x; k < blockIdx.x; k += BLOCK) {
+    bt += wg_tot[2 * k];
+    bg += wg_tot[2 * k + 1];
+  }
+  uint32_t sum_t = 0, sum_g = 0;
+  (void)block_excl_sum(bt, tmp, &sum_t);
+  (void)block_excl_sum(bg, tmp, &sum_g);
+  uint32_t t[SEGP_ITEMS], g[SEGP_ITEMS];
+  seg_tiles(list, n, tile_len, t, g);
+  // exclusive prefixes inside the wave, items in item_index order
+  const uint32_t w = threadIdx.x >> 6;
+  uint32_t pt[SEGP_ITEMS], pg[SEGP_ITEMS];
+  uint32_t ct = 0, cg = 0;
+#pragma unroll
+  for (int i = 0; i < SEGP_ITEMS; ++i) {
+    const uint32_t it = wave_incl_sum(t[i]), ig = wave_incl_sum(g[i]);
+    pt[i] = ct + it - t[i];
+    pg[i] = cg + ig - g[i];
+    ct += (uint32_t)__builtin_amdgcn_readlane((int)it, 63);
+    cg += (uint32_t)__builtin_amdgcn_readlane((int)ig, 63);
+  }
+  if (lane_id() == 0) {
+    wt[w][0] = ct;
+    wt[w][1] = cg;
+  }
+  __syncthreads();
+  uint32_t wbt = sum_t, wbg = sum_g;
+  for (uint32_t ww = 0; ww < w; ++ww) {
+    wbt += wt[ww][0];
+    wbg += wt[ww][1];
+  }
+#pragma unroll
+  for (int i = 0; i < SEGP_ITEMS; ++i) {
+    const uint64_t at = (uint64_t)blockIdx.x * SEGP_WG + item_index<SEGP_ITEMS>(i);
+    if (at < n) {
+      tile_prefix[at] = wbt + pt[i];
+      if (group_prefix) group_prefix[at] = wbg + pg[i];
+      if (copy) copy[at] = list[at];
+      if (at == n - 1) {
+        tile_prefix[n] = wbt + pt[i] + t[i];
+        if (group_prefix) group_prefix[n] = wbg + pg[i] + g[i];
+      }
+    }
+  }
 }
 
 // Stable scatter of one tile by its segment's digit into the other buffer.
@@ -1254,6 +1443,12 @@ bool tuning_ok(uint32_t tile_items, uint32_t chunk_items) {
 inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 inline uint64_t align_up(uint64_t x) { return (x + 255) & ~255ull; }
 
+// counters block layout (uint32 slots; 64-bit counters on even slots)
+// (chunk and big counts share one 64-bit word)
+// (chunk and big counts share one 64-bit word; the level kinds of the
+// statistics block are folded into the 64-bit words from C_FOLD on)
+enum { C_STATUS = 0, C_NFINAL = 1, C_NCHUNK = 2, C_NBIG = 3, C_FOLD = 16, C_COUNT = 32 };
+
 struct Layout {
   uint64_t keys0, keys1, hdl0, hdl1, text, srank, rank_blocks, start_row, tile_hist, gsum, segs, tile_prefix,
       group_prefix, seg_or, seg_and, seg_split, big_next, chunks, finals, coll_reads, coll_bases, cmap, counters,
@@ -1305,7 +1500,9 @@ Layout make_layout(uint64_t n_reads, uint64_t nb, uint32_t n_coll) {
   L.tile_hist = take(4 * 256 * L.max_tiles);
   L.gsum = take(4 * 256 * L.max_groups);
   L.segs = take(sizeof(Seg) * seg_slots);
-  L.tile_prefix = take(4 * (seg_slots + 1));
+  // tile prefixes serve a batch of segments and, after it, the final groups
+  // of the batch (each more than a chunk's suffixes: at most cap_finals)
+  L.tile_prefix = take(4 * (std::max(seg_slots, L.cap_finals) + 1));
   L.group_prefix = take(4 * (seg_slots + 1));
   L.seg_or = take(8 * seg_slots);
   L.seg_and = take(8 * seg_slots);
@@ -1316,7 +1513,7 @@ Layout make_layout(uint64_t n_reads, uint64_t nb, uint32_t n_coll) {
   L.coll_reads = take(8 * ((uint64_t)n_coll + 1));
   L.coll_bases = take(8 * ((uint64_t)n_coll + 1));
   L.cmap = take(sizeof(CollMap) * (uint64_t)n_coll);
-  L.counters = take(64);
+  L.counters = take(4 * C_COUNT);
   L.stats = take(8 * STAT_WORDS);
   L.total = off;
   return L;
@@ -1417,9 +1614,6 @@ struct PhaseTimer {
   }
 };
 
-// counters block layout (uint32 slots; 64-bit counters on even slots)
-// (chunk and big counts share one 64-bit word)
-enum { C_STATUS = 0, C_NFINAL = 1, C_NCHUNK = 2, C_NBIG = 3, C_COUNT = 16 };
 
 struct Buffers {
   uint64_t *keys0, *keys1, *start_row, *coll_reads, *coll_bases;
@@ -1483,11 +1677,58 @@ void launch_level_scan(const Buffers &B, uint32_t ns, uint32_t ngroups, const Li
                                                                           force_split);
 }
 
+// Tile prefixes (and group prefixes, and a copy of the list, when given) of
+// the first n entries of a segment list, computed on the device.  Uses the
+// scan-group totals area as scratch.
+int prefix_list(const Buffers &B, const Seg *list, uint32_t n, uint32_t tile_len, Seg *copy, uint32_t *tprefix,
+                uint32_t *gprefix, hipStream_t st) {
+  if (!n) return CXBWT_OK;
+  const unsigned nwg = (unsigned)ceil_div(n, SEGP_WG);
+  k_seg_count<<<nwg, BLOCK, 0, st>>>(list, n, tile_len, B.gsum);
+  CX_LAUNCHED();
+  k_seg_scan<<<nwg, BLOCK, 0, st>>>(list, n, tile_len, B.gsum, copy, tprefix, gprefix);
+  CX_LAUNCHED();
+  return CXBWT_OK;
+}
+
+// What one scan of a level handed on, from the counters block after the
+// fold.
+struct LevelOut {
+  uint32_t status, n_chunks, n_finals, n_big;  // n_big: all batches of the level so far
+  uint64_t next_len, next_regather, next_maxr, next_tiles, next_groups, final_len, final_tiles;
+};
+
+// Fold the level statistics, read the counters back (the one wait of a
+// level batch).
+int read_level(const Buffers &B, LevelOut &o, PhaseTimer &T, hipStream_t st) {
+  uint32_t hc[C_COUNT];
+  k_level_fold<<<1, 64, 0, st>>>(B.stats, (unsigned long long *)(B.counters + C_FOLD));
+  CX_LAUNCHED();
+  CX_CHECK(hipMemcpyAsync(hc, B.counters, sizeof(hc), hipMemcpyDeviceToHost, st));
+  CX_CHECK(hipStreamSynchronize(st));
+  T.collect();
+  uint64_t f[K_LEVEL_KINDS];
+  memcpy(f, hc + C_FOLD, sizeof(f));
+  o.status = hc[C_STATUS];
+  o.n_chunks = hc[C_NCHUNK];
+  o.n_finals = hc[C_NFINAL];
+  o.n_big = hc[C_NBIG];
+  o.next_len = f[K_NEXT_LEN - K_LEVEL_FIRST];
+  o.next_regather = f[K_NEXT_REGATHER - K_LEVEL_FIRST];
+  o.next_maxr = f[K_NEXT_MAXR - K_LEVEL_FIRST];
+  o.next_tiles = f[K_NEXT_TILES - K_LEVEL_FIRST];
+  o.next_groups = f[K_NEXT_GROUPS - K_LEVEL_FIRST];
+  o.final_len = f[K_FINAL_LEN - K_LEVEL_FIRST];
+  o.final_tiles = f[K_FINAL_TILES - K_LEVEL_FIRST];
+  return o.status ? CXBWT_EDEVICE : CXBWT_OK;
+}
+
 // Finish the chunks and final groups a level produced.
 int finish_level(const Buffers &B, const Layout &Lo, const Tuning &tu, uint64_t nb, uint32_t rmax, uint8_t *bwt,
-                 uint32_t n_chunks, uint32_t n_finals, std::vector<uint32_t> &tprefix, PhaseTimer &T,
+                 uint32_t n_chunks, uint32_t n_finals, uint64_t final_tiles, uint64_t final_len, PhaseTimer &T,
                  hipStream_t st) {
   if (n_chunks > Lo.cap_chunks || n_finals > Lo.cap_finals) return CXBWT_EDEVICE;
+  int rc;
   if (n_chunks) {
     T.begin();
 #define CX_LOCAL(LI, OCC)                                                                                         \
@@ -1503,26 +1744,53 @@ int finish_level(const Buffers &B, const Layout &Lo, const Tuning &tu, uint64_t 
     g_stats.chunks += n_chunks;
   }
   if (n_finals) {
-    std::vector<Seg> fin(n_finals);
-    CX_CHECK(hipMemcpyAsync(fin.data(), B.finals, sizeof(Seg) * n_finals, hipMemcpyDeviceToHost, st));
-    CX_CHECK(hipStreamSynchronize(st));
-    tprefix.assign(n_finals + 1, 0);
-    uint64_t suffixes = 0;
-    for (uint32_t i = 0; i < n_finals; ++i) {
-      tprefix[i + 1] = tprefix[i] + (uint32_t)ceil_div(fin[i].len, tu.tile_len());
-      suffixes += fin[i].len;
-    }
-    CX_CHECK(hipMemcpyAsync(B.tile_prefix, tprefix.data(), 4 * (n_finals + 1), hipMemcpyHostToDevice, st));
+    if (final_tiles == 0 || final_tiles > 0xFFFFFFFFull) return CXBWT_EDEVICE;
+    if ((rc = prefix_list(B, B.finals, n_finals, tu.tile_len(), nullptr, B.tile_prefix, nullptr, st))) return rc;
     T.begin();
-    k_emit_final<<<tprefix[n_finals], BLOCK, 0, st>>>(B.finals, B.tile_prefix, n_finals, tu.tile_len(), B.keys0,
-                                                      B.keys1, B.hdl0, B.hdl1, B.text, B.srank, B.cmap, bwt,
-                                                      B.start_row);
+    k_emit_final<<<(unsigned)final_tiles, BLOCK, 0, st>>>(B.finals, B.tile_prefix, n_finals, tu.tile_len(), B.keys0,
+                                                          B.keys1, B.hdl0, B.hdl1, B.text, B.srank, B.cmap, bwt,
+                                                          B.start_row);
     CX_LAUNCHED();
     T.end(PH_FINAL);
     g_stats.final_big += n_finals;
-    g_stats.chunk_suffixes -= suffixes;
+    g_stats.chunk_suffixes -= final_len;
   }
   return CXBWT_OK;
+}
+
+// One batch of a level 2..: nsg segments in B.segs with their tile and group
+// prefixes in place.  Counts, splits, scatters, then finishes the chunks and
+// final groups the batch produced.
+int run_level_batch(const Buffers &B, const Layout &Lo, const Tuning &tu, const Lists &Ls, uint64_t nb,
+                    uint32_t rmax, uint8_t *bwt, uint32_t nsg, uint32_t ntiles, uint32_t ngroups, LevelOut &o,
+                    PhaseTimer &T, hipStream_t st) {
+  int rc;
+  if ((rc = fill_u64((uint64_t *)B.seg_or, nsg, 0, st))) return rc;
+  if ((rc = fill_u64((uint64_t *)B.seg_and, nsg, ~0ull, st))) return rc;
+  if ((rc = fill_u32(B.counters + C_NFINAL, 2, 0, st))) return rc;  // final and chunk counts
+  T.begin();
+  k_level_hist<<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, nsg, tu.tile_len(), B.keys0, B.keys1, B.hdl0,
+                                         B.hdl1, B.text, nb, B.tile_hist, B.seg_or, B.seg_and);
+  CX_LAUNCHED();
+  T.end(PH_HIST);
+  T.begin();
+  k_group_scan<<<ngroups, BLOCK, 0, st>>>(B.tile_prefix, B.group_prefix, nsg, B.tile_hist, B.gsum);
+  CX_LAUNCHED();
+  launch_level_scan(B, nsg, ngroups, Ls, 0, st);
+  CX_LAUNCHED();
+  T.end(PH_SCAN);
+  T.begin();
+  if (tu.tile_items == 8)
+    k_level_scatter<8><<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, B.group_prefix, nsg, B.seg_split,
+                                                 B.tile_hist, B.gsum, B.keys0, B.keys1, B.hdl0, B.hdl1);
+  else
+    k_level_scatter<6><<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, B.group_prefix, nsg, B.seg_split,
+                                                 B.tile_hist, B.gsum, B.keys0, B.keys1, B.hdl0, B.hdl1);
+  CX_LAUNCHED();
+  T.end(PH_SCATTER);
+  g_stats.level_batches++;
+  if ((rc = read_level(B, o, T, st))) return rc;
+  return finish_level(B, Lo, tu, nb, rmax, bwt, o.n_chunks, o.n_finals, o.final_tiles, o.final_len, T, st);
 }
 
 // The whole build for ncoll collections laid end to end (a single build is
@@ -1620,7 +1888,7 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
   Lists Ls{B.big_next, counters + C_NBIG, (uint32_t)Lo.cap_big, B.chunks,
            (unsigned long long *)(counters + C_NCHUNK), (uint32_t)Lo.cap_chunks,
            B.finals, counters + C_NFINAL, (uint32_t)Lo.cap_finals, counters + C_STATUS, rmax,
-           B.stats + STAT_SPREAD * STAT_STRIDE, tu.chunk()};
+           B.stats, tu.chunk(), tile_len};
   std::vector<uint32_t> tprefix, gprefix;
   uint32_t ntiles = 0, ngroups = 0;
 
@@ -1634,7 +1902,7 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
     T.end(PH_GEN);
     CX_CHECK(hipMemcpyAsync(B.chunks, small.data(), sizeof(Seg) * small.size(), hipMemcpyHostToDevice, st));
     if (big.empty()) {
-      if ((rc = finish_level(B, Lo, tu, nb, rmax, bwt, (uint32_t)small.size(), 0, tprefix, T, st))) return rc;
+      if ((rc = finish_level(B, Lo, tu, nb, rmax, bwt, (uint32_t)small.size(), 0, 0, 0, T, st))) return rc;
     } else {
       // level 1 appends its chunks after these
       const uint32_t nsmall = (uint32_t)small.size();
@@ -1668,72 +1936,51 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
     for (const Seg &g : big) g_stats.level_suffixes += g.len;
     g_stats.levels = 1;
     g_stats.big_segments = ns;
-    CX_CHECK(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, st));
-    CX_CHECK(hipStreamSynchronize(st));
-    T.collect();
-    if (hc[C_STATUS]) return CXBWT_EDEVICE;
-    big.resize(hc[C_NBIG]);
-    if (!big.empty()) {
-      CX_CHECK(hipMemcpyAsync(big.data(), B.big_next, sizeof(Seg) * big.size(), hipMemcpyDeviceToHost, st));
-      CX_CHECK(hipStreamSynchronize(st));
-    }
-    if ((rc = finish_level(B, Lo, tu, nb, rmax, bwt, hc[C_NCHUNK], hc[C_NFINAL], tprefix, T, st))) return rc;
-    // levels 2..: every segment of a level is split by one digit, in batches
-    // that fit the per-segment and per-tile scratch
-    while (!big.empty()) {
-      const uint32_t nsg_all = (uint32_t)big.size();
-      if (nsg_all > Lo.cap_big) return CXBWT_EDEVICE;
-      for (uint32_t i = 0; i < nsg_all; ++i) {
-        g_stats.level_suffixes += big[i].len;
-        if (big[i].regather) g_stats.regathered += big[i].len;
-        g_stats.max_window = std::max<uint32_t>(g_stats.max_window, big[i].r);
-      }
+    LevelOut o{};
+    if ((rc = read_level(B, o, T, st))) return rc;
+    if ((rc = finish_level(B, Lo, tu, nb, rmax, bwt, o.n_chunks, o.n_finals, o.final_tiles, o.final_len, T, st)))
+      return rc;
+    // levels 2..: every segment of a level is split by one digit.  A level
+    // that fits the per-segment and per-tile scratch runs as one batch whose
+    // segment list is prepared on the device; a larger one is cut into
+    // batches on the host.
+    LevelOut acc = o;  // what the previous level handed on
+    uint32_t nbig = o.n_big;
+    while (nbig) {
+      if (nbig > Lo.cap_big) return CXBWT_EDEVICE;
       g_stats.levels++;
-      g_stats.big_segments += nsg_all;
+      g_stats.big_segments += nbig;
+      g_stats.level_suffixes += acc.next_len;
+      g_stats.regathered += acc.next_regather;
+      g_stats.max_window = std::max<uint32_t>(g_stats.max_window, (uint32_t)acc.next_maxr);
+      const uint64_t lt = acc.next_tiles, lg = acc.next_groups;
+      acc = LevelOut{};
       if ((rc = fill_u32(counters + C_NBIG, 1, 0, st))) return rc;
-      for (size_t b0 = 0; b0 < big.size();) {
-        const size_t b1 = batch_end(big, b0, Lo, tile_len);
-        const std::vector<Seg> part(big.begin() + b0, big.begin() + b1);
-        const uint32_t nsg = (uint32_t)part.size();
-        g_stats.level_batches++;
-        if ((rc = upload_segments(B, Lo, part, tile_len, tprefix, gprefix, ntiles, ngroups, st))) return rc;
-        if ((rc = fill_u64((uint64_t *)B.seg_or, nsg, 0, st))) return rc;
-        if ((rc = fill_u64((uint64_t *)B.seg_and, nsg, ~0ull, st))) return rc;
-        if ((rc = fill_u32(counters + C_NFINAL, 2, 0, st))) return rc;  // final and chunk counts
-        T.begin();
-        k_level_hist<<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, nsg, tile_len, B.keys0, B.keys1, B.hdl0,
-                                               B.hdl1, B.text, nb, B.tile_hist, B.seg_or, B.seg_and);
-        CX_LAUNCHED();
-        T.end(PH_HIST);
-        T.begin();
-        k_group_scan<<<ngroups, BLOCK, 0, st>>>(B.tile_prefix, B.group_prefix, nsg, B.tile_hist, B.gsum);
-        CX_LAUNCHED();
-        launch_level_scan(B, nsg, ngroups, Ls, 0, st);
-        CX_LAUNCHED();
-        T.end(PH_SCAN);
-        T.begin();
-        if (tu.tile_items == 8)
-          k_level_scatter<8><<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, B.group_prefix, nsg, B.seg_split,
-                                                       B.tile_hist, B.gsum, B.keys0, B.keys1, B.hdl0, B.hdl1);
-        else
-          k_level_scatter<6><<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, B.group_prefix, nsg, B.seg_split,
-                                                       B.tile_hist, B.gsum, B.keys0, B.keys1, B.hdl0, B.hdl1);
-        CX_LAUNCHED();
-        T.end(PH_SCATTER);
-        CX_CHECK(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, st));
+      if (nbig <= Lo.seg_slots && lt <= Lo.max_tiles && lg <= Lo.max_groups) {
+        if ((rc = prefix_list(B, B.big_next, nbig, tile_len, B.segs, B.tile_prefix, B.group_prefix, st))) return rc;
+        if ((rc = run_level_batch(B, Lo, tu, Ls, nb, rmax, bwt, nbig, (uint32_t)lt, (uint32_t)lg, o, T, st)))
+          return rc;
+        acc = o;
+      } else {
+        big.resize(nbig);
+        CX_CHECK(hipMemcpyAsync(big.data(), B.big_next, sizeof(Seg) * nbig, hipMemcpyDeviceToHost, st));
         CX_CHECK(hipStreamSynchronize(st));
-        T.collect();
-        if (hc[C_STATUS]) return CXBWT_EDEVICE;
-        if ((rc = finish_level(B, Lo, tu, nb, rmax, bwt, hc[C_NCHUNK], hc[C_NFINAL], tprefix, T, st))) return rc;
-        b0 = b1;
+        for (size_t b0 = 0; b0 < big.size();) {
+          const size_t b1 = batch_end(big, b0, Lo, tile_len);
+          const std::vector<Seg> part(big.begin() + b0, big.begin() + b1);
+          if ((rc = upload_segments(B, Lo, part, tile_len, tprefix, gprefix, ntiles, ngroups, st))) return rc;
+          if ((rc = run_level_batch(B, Lo, tu, Ls, nb, rmax, bwt, (uint32_t)part.size(), ntiles, ngroups, o, T,
+                                    st)))
+            return rc;
+          acc.next_len += o.next_len;
+          acc.next_regather += o.next_regather;
+          acc.next_maxr = std::max(acc.next_maxr, o.next_maxr);
+          acc.next_tiles += o.next_tiles;
+          acc.next_groups += o.next_groups;
+          b0 = b1;
+        }
       }
-      CX_CHECK(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, st));
-      CX_CHECK(hipStreamSynchronize(st));
-      big.resize(hc[C_NBIG]);
-      if (!big.empty()) {
-        CX_CHECK(hipMemcpyAsync(big.data(), B.big_next, sizeof(Seg) * big.size(), hipMemcpyDeviceToHost, st));
-        CX_CHECK(hipStreamSynchronize(st));
-      }
+      nbig = o.n_big;
     }
   }
   T.begin();

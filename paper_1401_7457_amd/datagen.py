@@ -188,7 +188,7 @@ def sample_reads(rng: np.random.Generator, genome: np.ndarray, n: int, read_len,
 # --- the five workloads (plain, plain, repeat-heavy, batched, served) -------
 
 def plain_config(k: int, scale: float = 1.0) -> Collection:
-    """Plain single-collection workloads 0, 1 and 2 (see the design doc recipe).
+    """Plain single-collection workloads 0, 1 and 2.
 
     scale < 1 shrinks the read count and genome together (same coverage and
     shape) for tests that must finish quickly.
