@@ -56,6 +56,7 @@ using namespace cxk;
 // smallest tile and chunk, so a workspace fits every choice.
 constexpr int LOCAL_WG = 64;                   // one wave finishes a chunk
 constexpr int MIN_TILE_ITEMS = 6;
+constexpr int MAX_TILE_ITEMS = 8;  // a level tile is at most BLOCK * MAX_TILE_ITEMS suffixes
 constexpr int MIN_CHUNK_ITEMS = 3;
 constexpr int MIN_TILE = BLOCK * MIN_TILE_ITEMS;
 constexpr int MIN_CHUNK = LOCAL_WG * MIN_CHUNK_ITEMS;
@@ -421,10 +422,16 @@ __global__ __launch_bounds__(BLOCK) void k_gen_hist(const Seg *__restrict__ segs
   const uint64_t t1 = min(t0 + (uint64_t)tile_len, sg.start + sg.len);
   hist[threadIdx.x] = 0;
   __syncthreads();
-  for (uint64_t p = t0 + threadIdx.x; p < t1; p += BLOCK) {
-    const uint64_t k = first_key(text, nb, p);
-    atomicAdd(&hist[digit_of(k, 0)], 1u);
+  // every record load of the thread is issued before the first count
+  uint64_t kk[MAX_TILE_ITEMS];
+#pragma unroll
+  for (int i = 0; i < MAX_TILE_ITEMS; ++i) {
+    const uint64_t p = t0 + (uint64_t)i * BLOCK + threadIdx.x;
+    if (p < t1) kk[i] = first_key(text, nb, p);
   }
+#pragma unroll
+  for (int i = 0; i < MAX_TILE_ITEMS; ++i)
+    if (t0 + (uint64_t)i * BLOCK + threadIdx.x < t1) atomicAdd(&hist[digit_of(kk[i], 0)], 1u);
   __syncthreads();
   tile_hist[(uint64_t)tile * 256 + threadIdx.x] = hist[threadIdx.x];
 }
@@ -525,17 +532,40 @@ __global__ __launch_bounds__(BLOCK) void k_level_hist(const Seg *__restrict__ se
   const uint32_t *H = sg.buf ? hdl1 : hdl0;
   hist[threadIdx.x] = 0;
   __syncthreads();
-  uint64_t o = 0, a = ~0ull;
-  for (uint64_t j = t0 + threadIdx.x; j < t1; j += BLOCK) {
-    uint64_t k = K[j];
-    if (sg.regather) {
-      k = window_key(text, nb, H[j], sg.r, (uint32_t)k & 7u);
-      K[j] = k;
-    }
-    atomicAdd(&hist[digit_of(k, sg.d)], 1u);
-    o |= k;
-    a &= k;
+  // all loads of the thread (keys, and for a re-keyed segment handles and
+  // then records) are issued before any result is used
+  uint64_t kk[MAX_TILE_ITEMS];
+  bool in[MAX_TILE_ITEMS];
+#pragma unroll
+  for (int i = 0; i < MAX_TILE_ITEMS; ++i) {
+    const uint64_t j = t0 + (uint64_t)i * BLOCK + threadIdx.x;
+    in[i] = j < t1;
+    if (in[i]) kk[i] = K[j];
   }
+  if (sg.regather) {
+    uint32_t hh[MAX_TILE_ITEMS];
+    TextRec tr[MAX_TILE_ITEMS];
+#pragma unroll
+    for (int i = 0; i < MAX_TILE_ITEMS; ++i)
+      if (in[i]) hh[i] = H[t0 + (uint64_t)i * BLOCK + threadIdx.x];
+#pragma unroll
+    for (int i = 0; i < MAX_TILE_ITEMS; ++i)
+      if (in[i]) tr[i] = window_load(text, nb, hh[i], sg.r);
+#pragma unroll
+    for (int i = 0; i < MAX_TILE_ITEMS; ++i)
+      if (in[i]) {
+        kk[i] = window_combine(tr[i], nb, hh[i], sg.r, (uint32_t)kk[i] & 7u);
+        K[t0 + (uint64_t)i * BLOCK + threadIdx.x] = kk[i];
+      }
+  }
+  uint64_t o = 0, a = ~0ull;
+#pragma unroll
+  for (int i = 0; i < MAX_TILE_ITEMS; ++i)
+    if (in[i]) {
+      atomicAdd(&hist[digit_of(kk[i], sg.d)], 1u);
+      o |= kk[i];
+      a &= kk[i];
+    }
   o = block_or(o, red);
   a = block_and(a, red);
   if (threadIdx.x == 0) {
@@ -1436,6 +1466,8 @@ struct Tuning {
 };
 thread_local Tuning g_tuning{8, 6};
 
+// the histogram kernels hold at most MAX_TILE_ITEMS items per thread
+static_assert(MAX_TILE_ITEMS == 8, "tile choices are 6 and 8 items per thread");
 bool tuning_ok(uint32_t tile_items, uint32_t chunk_items) {
   return (tile_items == 6 || tile_items == 8) && (chunk_items == 3 || chunk_items == 6 || chunk_items == 8);
 }
