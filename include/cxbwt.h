@@ -163,6 +163,51 @@ int cxbwt_build_batch(const uint64_t *packed, const uint64_t *offsets, uint64_t 
                       uint32_t max_read_len, const uint64_t *coll_reads, uint32_t n_coll, uint8_t *bwt,
                       uint64_t *term_pos, void *workspace, size_t workspace_bytes, void *stream);
 
+/*
+ * A build captured once in a hipGraph and replayed (the batched row of the
+ * design: every level's launches cover all collections, and the launches of
+ * the levels after the first are sized on the device, so the whole build is
+ * one graph with no host wait inside).  For callers that repeat builds of
+ * one shape in fixed buffers: a serving loop, a pipeline stage.
+ *
+ * cxbwt_graph_create -- capture a build.  Arguments as cxbwt_build_batch
+ *   (coll_reads may be NULL with n_coll == 1 for a single collection), plus
+ *   levels        sort levels scheduled inside the graph, level 1 included;
+ *                 0 = enough for any input of max_read_len (8 per 27-base
+ *                 window, plus 2).  Each scheduled level that finds no work
+ *                 costs a few empty launches.
+ *   stream        the caller's stream: creation first runs a short eager
+ *                 pass on it (offset validation, collection bases) and waits;
+ *                 the capture itself uses a stream of its own.
+ *   out           (host, out) the plan, or NULL on error.
+ * The graph binds every pointer given here.  A replay is valid while the
+ * buffers keep these sizes and every collection keeps its number of bases;
+ * the read contents and the read lengths inside a collection may change.
+ * Returns CXBWT_OK, CXBWT_EINVAL, CXBWT_ERANGE, CXBWT_ENOMEM, CXBWT_EDATA
+ * (invalid offsets found by the eager pass) or CXBWT_EDEVICE.
+ *
+ * cxbwt_graph_launch -- enqueue one replay on `stream` and return at once.
+ *
+ * cxbwt_graph_finish -- wait for the replay on `stream`, check it and read
+ *   its statistics (cxbwt_last_stats).  If the input needed more levels than
+ *   were captured, or a level did not fit the per-segment scratch in one
+ *   batch, the remaining levels run here on the host's schedule, with the
+ *   same result.  Returns CXBWT_OK, CXBWT_EDATA (offsets or read lengths),
+ *   CXBWT_EINVAL (the collection bases differ from the captured ones; the
+ *   outputs are then unspecified) or CXBWT_EDEVICE.
+ *
+ * cxbwt_graph_destroy -- free the plan (NULL is ignored).  Calls that
+ * overlap on one plan race; different plans need different workspaces.
+ */
+typedef struct cxbwt_graph cxbwt_graph;
+int cxbwt_graph_create(const uint64_t *packed, const uint64_t *offsets, uint64_t n_reads, uint64_t n_bases,
+                       uint32_t max_read_len, const uint64_t *coll_reads, uint32_t n_coll, uint8_t *bwt,
+                       uint64_t *term_pos, void *workspace, size_t workspace_bytes, uint32_t levels, void *stream,
+                       cxbwt_graph **out);
+int cxbwt_graph_launch(cxbwt_graph *g, void *stream);
+int cxbwt_graph_finish(cxbwt_graph *g, void *stream);
+void cxbwt_graph_destroy(cxbwt_graph *g);
+
 /* Counters describing the last cxbwt_build on the calling host thread. */
 typedef struct cxbwt_stats {
   uint32_t levels;             /* global sort levels run                               */

@@ -40,6 +40,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <new>
 #include <vector>
 
 #include "cxbwt.h"
@@ -68,6 +69,18 @@ constexpr uint32_t ST_TOO_LONG = 2u;
 constexpr uint32_t ST_BAD_CHAR = 4u;
 constexpr uint32_t ST_LIST_OVERFLOW = 8u;
 constexpr uint32_t ST_WINDOW_BOUND = 16u;
+constexpr uint32_t ST_PLAN_MISMATCH = 32u;  // inputs no longer match a captured build
+
+// counters block layout (uint32 slots; 64-bit values on even slots).  Chunk
+// and big counts share one 64-bit word; the level kinds of the statistics
+// block are folded into the 64-bit words from C_FOLD on; a build whose
+// levels are scheduled on the device keeps its running totals (G_*) from
+// C_CUM on.
+enum { C_STATUS = 0, C_NFINAL = 1, C_NCHUNK = 2, C_NBIG = 3, C_NCUR = 4, C_FLAGS = 5, C_FOLD = 16, C_CUM = 32,
+       C_COUNT = 64 };
+enum { G_LEVELS, G_BIGSEG, G_LEVSUF, G_REGATH, G_MAXWIN, G_CHUNKS, G_FINALS, G_FINLEN, G_BATCHES, G_COUNT };
+constexpr uint32_t FL_STALLED = 1u;     // a level did not fit the scratch: the host finishes the build
+constexpr uint32_t FL_INCOMPLETE = 2u;  // segments remain after the last scheduled level
 
 // A run of suffixes [start, start+len) in key/handle buffer `buf`, whose keys
 // are for window r and agree on every digit before d.
@@ -514,8 +527,15 @@ __global__ __launch_bounds__(BLOCK) void k_gen_scatter(const Seg *__restrict__ s
 
 // Per-tile digit histogram and per-segment OR/AND of the ordering bits.  A
 // segment flagged `regather` first re-fetches its keys for window r.
+//
+// Kernels of levels 2.. take their segment count from dev_nsegs when it is
+// given (a launch whose size was fixed before the count was known) and loop
+// over their work with the grid's stride; with the count passed by value
+// the grid covers the work and each workgroup takes one item.
+template <bool PERSIST>
 __global__ __launch_bounds__(BLOCK) void k_level_hist(const Seg *__restrict__ segs, const uint32_t *__restrict__ tile_prefix,
-                                                      uint32_t nsegs, uint32_t tile_len, uint64_t *keys0,
+                                                      uint32_t nsegs, const uint32_t *__restrict__ dev_nsegs,
+                                                      uint32_t tile_len, uint64_t *keys0,
                                                       uint64_t *keys1, const uint32_t *__restrict__ hdl0,
                                                       const uint32_t *__restrict__ hdl1,
                                                       const TextRec *__restrict__ text, uint64_t nb,
@@ -523,7 +543,10 @@ __global__ __launch_bounds__(BLOCK) void k_level_hist(const Seg *__restrict__ se
                                                       unsigned long long *seg_and) {
   __shared__ uint32_t hist[256];
   __shared__ uint64_t red[WAVES];
-  const uint32_t tile = blockIdx.x;
+  if (dev_nsegs) nsegs = *dev_nsegs;
+  if (nsegs == 0) return;
+  const uint32_t ntiles = PERSIST ? tile_prefix[nsegs] : blockIdx.x + 1;
+  for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
   const uint32_t s = find_upper(tile_prefix, nsegs, tile);
   const Seg sg = segs[s];
   const uint64_t t0 = sg.start + (uint64_t)(tile - tile_prefix[s]) * tile_len;
@@ -573,17 +596,24 @@ __global__ __launch_bounds__(BLOCK) void k_level_hist(const Seg *__restrict__ se
     atomicAnd(&seg_and[s], (unsigned long long)(a | 7ull));
   }
   tile_hist[(uint64_t)tile * 256 + threadIdx.x] = hist[threadIdx.x];
+  if (!PERSIST) break;
+  }
 }
 
 // First scan stage: inside each group of at most GROUP_TILES consecutive
 // tiles of one segment, turn tile counts into exclusive prefixes per digit
 // and record the group totals.  Sixteen tile counts are loaded before any
 // is rewritten, so the loop waits for memory once per sixteen tiles.
+template <bool PERSIST>
 __global__ __launch_bounds__(BLOCK) void k_group_scan(const uint32_t *__restrict__ tile_prefix,
                                                       const uint32_t *__restrict__ group_prefix, uint32_t nsegs,
+                                                      const uint32_t *__restrict__ dev_nsegs,
                                                       uint32_t *__restrict__ tile_hist, uint32_t *__restrict__ gsum) {
   constexpr uint32_t NB = 16;
-  const uint32_t g = blockIdx.x;
+  if (dev_nsegs) nsegs = *dev_nsegs;
+  if (nsegs == 0) return;
+  const uint32_t ngroups = PERSIST ? group_prefix[nsegs] : blockIdx.x + 1;
+  for (uint32_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
   const uint32_t s = find_upper(group_prefix, nsegs, g);
   const uint32_t tb = tile_prefix[s] + (g - group_prefix[s]) * GROUP_TILES;
   const uint32_t te = min(tb + (uint32_t)GROUP_TILES, tile_prefix[s + 1]);
@@ -607,6 +637,8 @@ __global__ __launch_bounds__(BLOCK) void k_group_scan(const uint32_t *__restrict
     run += c;
   }
   gsum[(uint64_t)g * 256 + d] = run;
+  if (!PERSIST) break;
+  }
 }
 
 // Digit totals of groups [g0, g1) added into cv (digit i*64 + lane in slot
@@ -714,13 +746,14 @@ __device__ __forceinline__ uint32_t bits_below_lane(uint64_t m) {
 // wave: chunk boundaries come from a walk of one step per chunk over bucket
 // masks, and the list entries are written by all lanes at once from
 // positions reserved with one atomic per list per workgroup.
-template <bool COOP>
+template <bool COOP, bool PERSIST>
 __global__ __launch_bounds__(BLOCK) void k_level_scan(const Seg *__restrict__ segs,
                                                       const uint32_t *__restrict__ group_prefix, uint32_t nsegs,
                                                       uint32_t *__restrict__ gsum,
                                                       const unsigned long long *__restrict__ seg_or,
                                                       const unsigned long long *__restrict__ seg_and,
-                                                      uint8_t *__restrict__ seg_split, Lists L, int force_split) {
+                                                      uint8_t *__restrict__ seg_split, Lists L, int force_split,
+                                                      const uint32_t *__restrict__ dev_nsegs) {
   constexpr int CW = COOP ? 1 : WAVES;  // waves that classify a segment
   __shared__ uint32_t part[COOP ? WAVES : 1][256];
   __shared__ uint32_t cstart[CW][256];
@@ -730,7 +763,11 @@ __global__ __launch_bounds__(BLOCK) void k_level_scan(const Seg *__restrict__ se
   __shared__ uint32_t wstat[WAVES][K_LEVEL_KINDS];
   const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const uint32_t l = lane_id();
-  const uint32_t s = COOP ? blockIdx.x : blockIdx.x * WAVES + w;
+  if (dev_nsegs) nsegs = *dev_nsegs;
+  constexpr uint32_t SPB = COOP ? 1u : (uint32_t)WAVES;  // segments per workgroup step
+  for (uint32_t blk = blockIdx.x; blk * SPB < nsegs; blk += gridDim.x) {
+  if (PERSIST) __syncthreads();  // the previous step's LDS reads are done
+  const uint32_t s = COOP ? blk : blk * WAVES + w;
   const uint32_t cw = COOP ? 0 : w;  // this wave's chunk-list slot
   uint32_t cv[4] = {0, 0, 0, 0}, bv[4] = {0, 0, 0, 0};
   int mode = 0;  // 0: no segment, 1: passes through unsplit, 2: split by digit d
@@ -979,14 +1016,18 @@ __global__ __launch_bounds__(BLOCK) void k_level_scan(const Seg *__restrict__ se
     }
   }
   if (overflow) atomicOr(L.status, ST_LIST_OVERFLOW);
+  if (!PERSIST) break;
+  }
 }
 
 // Folds the level kinds of the statistics block into out[0..K_LEVEL_KINDS)
 // (sums, a maximum for the window) and clears them for the next scan.  One
 // wave.
 __global__ __launch_bounds__(64) void k_level_fold(unsigned long long *__restrict__ stats,
-                                                   unsigned long long *__restrict__ out) {
+                                                   unsigned long long *__restrict__ out,
+                                                   const uint32_t *__restrict__ flags) {
   const uint32_t l = lane_id();
+  if (flags && (*flags & (FL_STALLED | FL_INCOMPLETE))) return;  // keep what the host resumes from
   for (int k = K_LEVEL_FIRST; k < K_KINDS; ++k) {
     unsigned long long *slot = stats + k * STAT_KIND + (uint64_t)l * STAT_STRIDE;
     unsigned long long v = *slot;
@@ -998,6 +1039,63 @@ __global__ __launch_bounds__(64) void k_level_fold(unsigned long long *__restric
     }
     if (l == 0) out[k - K_LEVEL_FIRST] = v;
   }
+}
+
+// Clears the per-segment OR/AND words of the segments counted at *dev_n.
+__global__ void k_fill_seg(unsigned long long *__restrict__ seg_or, unsigned long long *__restrict__ seg_and,
+                           const uint32_t *__restrict__ dev_n) {
+  const uint32_t n = *dev_n;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    seg_or[i] = 0;
+    seg_and[i] = ~0ull;
+  }
+}
+
+// Between two levels of a build scheduled on the device (one thread): adds
+// the finished level's chunks and final groups to the running totals, then
+// makes the segments the level handed on the current ones (C_NCUR), or
+// flags the build for the host when they would not fit the scratch or when
+// no level is left.
+__global__ void k_level_step(uint32_t *__restrict__ c, uint64_t seg_slots, uint64_t max_tiles, uint64_t max_groups,
+                             int last) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const uint32_t fl = c[C_FLAGS];
+  if (fl & (FL_STALLED | FL_INCOMPLETE)) return;
+  const unsigned long long *f = reinterpret_cast<const unsigned long long *>(c + C_FOLD);
+  unsigned long long *g = reinterpret_cast<unsigned long long *>(c + C_CUM);
+  g[G_CHUNKS] += c[C_NCHUNK];
+  g[G_FINALS] += c[C_NFINAL];
+  g[G_FINLEN] += f[K_FINAL_LEN - K_LEVEL_FIRST];
+  c[C_NCHUNK] = 0;
+  c[C_NFINAL] = 0;
+  c[C_NCUR] = 0;
+  const uint32_t nbig = c[C_NBIG];
+  if (nbig == 0) return;
+  if (last) {
+    c[C_FLAGS] = fl | FL_INCOMPLETE;
+    return;
+  }
+  if (nbig > seg_slots || f[K_NEXT_TILES - K_LEVEL_FIRST] > max_tiles ||
+      f[K_NEXT_GROUPS - K_LEVEL_FIRST] > max_groups) {
+    c[C_FLAGS] = fl | FL_STALLED;
+    return;
+  }
+  c[C_NCUR] = nbig;
+  c[C_NBIG] = 0;
+  g[G_LEVELS] += 1;
+  g[G_BIGSEG] += nbig;
+  g[G_LEVSUF] += f[K_NEXT_LEN - K_LEVEL_FIRST];
+  g[G_REGATH] += f[K_NEXT_REGATHER - K_LEVEL_FIRST];
+  g[G_MAXWIN] = max(g[G_MAXWIN], f[K_NEXT_MAXR - K_LEVEL_FIRST]);
+  g[G_BATCHES] += 1;
+}
+
+// A replayed build checks that the collection bases are those it was
+// captured for.
+__global__ void k_check_bases(const uint64_t *__restrict__ got, const uint64_t *__restrict__ want, uint32_t count,
+                              uint32_t *status) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count && got[i] != want[i]) atomicOr(status, ST_PLAN_MISMATCH);
 }
 
 // Tile and group prefixes of a segment list on the device.  Entries sit
@@ -1019,9 +1117,12 @@ __device__ __forceinline__ void seg_tiles(const Seg *__restrict__ list, uint32_t
   }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_seg_count(const Seg *__restrict__ list, uint32_t n, uint32_t tile_len,
+__global__ __launch_bounds__(BLOCK) void k_seg_count(const Seg *__restrict__ list, uint32_t n,
+                                                     const uint32_t *__restrict__ dev_n, uint32_t tile_len,
                                                      uint32_t *__restrict__ wg_tot) {
   __shared__ uint32_t tmp[WAVES];
+  if (dev_n) n = *dev_n;
+  if ((uint64_t)blockIdx.x * SEGP_WG >= n) return;
   uint32_t t[SEGP_ITEMS], g[SEGP_ITEMS];
   seg_tiles(list, n, tile_len, t, g);
   uint32_t st = 0, sgr = 0;
@@ -1039,12 +1140,15 @@ __global__ __launch_bounds__(BLOCK) void k_seg_count(const Seg *__restrict__ lis
   }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_seg_scan(const Seg *__restrict__ list, uint32_t n, uint32_t tile_len,
+__global__ __launch_bounds__(BLOCK) void k_seg_scan(const Seg *__restrict__ list, uint32_t n,
+                                                    const uint32_t *__restrict__ dev_n, uint32_t tile_len,
                                                     const uint32_t *__restrict__ wg_tot, Seg *__restrict__ copy,
                                                     uint32_t *__restrict__ tile_prefix,
                                                     uint32_t *__restrict__ group_prefix) {
   __shared__ uint32_t tmp[WAVES];
   __shared__ uint32_t wt[WAVES][2];
+  if (dev_n) n = *dev_n;
+  if ((uint64_t)blockIdx.x * SEGP_WG >= n) return;
   // base of this workgroup: the totals of the workgroups before it
   uint32_t bt = 0, bg = 0;
   for (uint32_t k = threadIdx.x; k < blockIdx.x; k += BLOCK) {
@@ -1094,19 +1198,31 @@ __global__ __launch_bounds__(BLOCK) void k_seg_scan(const Seg *__restrict__ list
 }
 
 // Stable scatter of one tile by its segment's digit into the other buffer.
-template <int TI>
+template <int TI, bool PERSIST>
 __global__ __launch_bounds__(BLOCK) void k_level_scatter(const Seg *__restrict__ segs,
                                                          const uint32_t *__restrict__ tile_prefix,
                                                          const uint32_t *__restrict__ group_prefix, uint32_t nsegs,
+                                                         const uint32_t *__restrict__ dev_nsegs,
                                                          const uint8_t *__restrict__ seg_split,
                                                          const uint32_t *__restrict__ tile_hist,
                                                          const uint32_t *__restrict__ gsum, uint64_t *keys0,
                                                          uint64_t *keys1, uint32_t *hdl0, uint32_t *hdl1) {
   constexpr uint32_t TL = BLOCK * TI;
   __shared__ ScatterSmem<TI> S;
-  const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  if (dev_nsegs) nsegs = *dev_nsegs;
+  if (nsegs == 0) return;
+  // virtual block v maps to a tile as a grid of ntiles would (neighbouring
+  // tiles on one XCD); a persistent grid is a multiple of the XCD count, so
+  // every workgroup stays on the XCD of its tiles
+  const uint32_t ntiles = PERSIST ? tile_prefix[nsegs] : gridDim.x;
+  for (uint32_t v = blockIdx.x; v < ntiles; v += gridDim.x) {
+  const uint32_t tile = xcd_tile(v, ntiles);
   const uint32_t s = find_upper(tile_prefix, nsegs, tile);
-  if (!seg_split[s]) return;
+  if (!seg_split[s]) {
+    if (!PERSIST) break;
+    continue;
+  }
+  if (PERSIST) __syncthreads();  // the previous tile's LDS reads are done
   const Seg sg = segs[s];
   const uint32_t tl = tile - tile_prefix[s];
   const uint64_t t0 = sg.start + (uint64_t)tl * TL;
@@ -1134,25 +1250,34 @@ __global__ __launch_bounds__(BLOCK) void k_level_scatter(const Seg *__restrict__
   const uint32_t g = group_prefix[s] + tl / GROUP_TILES;
   S.goff[threadIdx.x] = (uint64_t)gsum[(uint64_t)g * 256 + threadIdx.x] + tile_hist[(uint64_t)tile * 256 + threadIdx.x];
   tile_scatter(S, kr, hr, dig, m, d, Ko, Ho);
+  if (!PERSIST) break;
+  }
 }
 
 // Groups of identical suffixes too large for one workgroup: emit in place.
+template <bool PERSIST>
 __global__ __launch_bounds__(BLOCK) void k_emit_final(const Seg *__restrict__ segs, const uint32_t *__restrict__ tile_prefix,
-                                                      uint32_t nsegs, uint32_t tile_len, const uint64_t *__restrict__ keys0,
+                                                      uint32_t nsegs, const uint32_t *__restrict__ dev_nsegs,
+                                                      uint32_t tile_len, const uint64_t *__restrict__ keys0,
                                                       const uint64_t *__restrict__ keys1, const uint32_t *__restrict__ hdl0,
                                                       const uint32_t *__restrict__ hdl1, const TextRec *__restrict__ text,
                                                       const uint32_t *__restrict__ srank,
                                                       const CollMap *__restrict__ cmap, uint8_t *__restrict__ bwt,
                                                       uint64_t *__restrict__ start_row) {
-  const uint32_t tile = blockIdx.x;
-  const uint32_t s = find_upper(tile_prefix, nsegs, tile);
-  const Seg sg = segs[s];
-  const uint64_t t0 = sg.start + (uint64_t)(tile - tile_prefix[s]) * tile_len;
-  const uint64_t t1 = min(t0 + (uint64_t)tile_len, sg.start + sg.len);
-  const uint64_t *K = sg.buf ? keys1 : keys0;
-  const uint32_t *H = sg.buf ? hdl1 : hdl0;
-  const CollMap cm = cmap[sg.coll];
-  for (uint64_t j = t0 + threadIdx.x; j < t1; j += BLOCK) emit_row(j, cm, K[j], H[j], text, srank, bwt, start_row);
+  if (dev_nsegs) nsegs = *dev_nsegs;
+  if (nsegs == 0) return;
+  const uint32_t ntiles = PERSIST ? tile_prefix[nsegs] : blockIdx.x + 1;
+  for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const uint32_t s = find_upper(tile_prefix, nsegs, tile);
+    const Seg sg = segs[s];
+    const uint64_t t0 = sg.start + (uint64_t)(tile - tile_prefix[s]) * tile_len;
+    const uint64_t t1 = min(t0 + (uint64_t)tile_len, sg.start + sg.len);
+    const uint64_t *K = sg.buf ? keys1 : keys0;
+    const uint32_t *H = sg.buf ? hdl1 : hdl0;
+    const CollMap cm = cmap[sg.coll];
+    for (uint64_t j = t0 + threadIdx.x; j < t1; j += BLOCK) emit_row(j, cm, K[j], H[j], text, srank, bwt, start_row);
+    if (!PERSIST) break;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1263,18 +1388,24 @@ __device__ __forceinline__ void live_groups(LocalSmem<LI> &S, uint32_t n, uint32
   __syncthreads();
 }
 
-// LI suffixes per lane; OCC waves per SIMD the kernel is compiled for
-template <int LI, int OCC>
+// LI suffixes per lane; OCC waves per SIMD the kernel is compiled for;
+// PERSIST: a fixed grid loops over a chunk count on the device
+template <int LI, int OCC, bool PERSIST>
 __global__ __launch_bounds__(LOCAL_WG, OCC) void k_local(
     const Seg *__restrict__ chunks, const uint64_t *__restrict__ keys0, const uint64_t *__restrict__ keys1,
     const uint32_t *__restrict__ hdl0, const uint32_t *__restrict__ hdl1, const TextRec *__restrict__ text,
     const uint32_t *__restrict__ srank, const CollMap *__restrict__ cmap, uint64_t nb, uint32_t rmax,
-    uint8_t *__restrict__ bwt, uint64_t *__restrict__ start_row, uint32_t *status, unsigned long long *fetches) {
+    uint8_t *__restrict__ bwt, uint64_t *__restrict__ start_row, uint32_t *status, unsigned long long *fetches,
+    uint32_t n_chunks, const uint32_t *__restrict__ dev_nchunks) {
   __shared__ LocalSmem<LI> S;
-  const Seg ch = chunks[blockIdx.x];
-  const uint32_t m = (uint32_t)ch.len;
   const uint32_t lane = threadIdx.x;
   const uint64_t le = lanemask_lt() | (1ull << lane);
+  n_chunks = PERSIST ? *dev_nchunks : blockIdx.x + 1;
+  uint32_t nfetch = 0;
+  for (uint32_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
+  if (PERSIST) __syncthreads();  // the previous chunk's LDS reads are done
+  const Seg ch = chunks[c];
+  const uint32_t m = (uint32_t)ch.len;
   const uint64_t *Kg = ch.buf ? keys1 : keys0;
   const uint32_t *Hg = ch.buf ? hdl1 : hdl0;
   // entry x of a list is handled by lane x % 64 in slot x / 64: neighbouring
@@ -1314,7 +1445,6 @@ __global__ __launch_bounds__(LOCAL_WG, OCC) void k_local(
   __syncthreads();
   uint32_t n = m;  // live-list length
   uint32_t r = ch.r;
-  uint32_t nfetch = 0;
   bool fetch_round = false;
   for (;;) {
     // drop the finished groups: single suffixes, and (after the first sort)
@@ -1446,6 +1576,8 @@ __global__ __launch_bounds__(LOCAL_WG, OCC) void k_local(
     const uint32_t j = i * LOCAL_WG + lane;
     if (j < m) emit_row(ch.start + j, cm, S.K[j], S.H[j], text, srank, bwt, start_row);
   }
+  if (!PERSIST) break;
+  }
   nfetch = wave_incl_sum(nfetch);
   if (lane == 63 && nfetch) atomicAdd(stat_slot(fetches), (unsigned long long)nfetch);
 }
@@ -1475,11 +1607,6 @@ bool tuning_ok(uint32_t tile_items, uint32_t chunk_items) {
 inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 inline uint64_t align_up(uint64_t x) { return (x + 255) & ~255ull; }
 
-// counters block layout (uint32 slots; 64-bit counters on even slots)
-// (chunk and big counts share one 64-bit word)
-// (chunk and big counts share one 64-bit word; the level kinds of the
-// statistics block are folded into the 64-bit words from C_FOLD on)
-enum { C_STATUS = 0, C_NFINAL = 1, C_NCHUNK = 2, C_NBIG = 3, C_FOLD = 16, C_COUNT = 32 };
 
 struct Layout {
   uint64_t keys0, keys1, hdl0, hdl1, text, srank, rank_blocks, start_row, tile_hist, gsum, segs, tile_prefix,
@@ -1696,29 +1823,45 @@ int upload_segments(const Buffers &B, const Layout &Lo, const std::vector<Seg> &
   return CXBWT_OK;
 }
 
+// Workgroups of the launches whose size is fixed before their work count is
+// known (the work count is read on the device; see the kernels): a few per
+// CU, multiples of the XCD count.
+constexpr unsigned PG_HIST = 256 * 8;
+constexpr unsigned PG_GROUP = 256 * 4;
+constexpr unsigned PG_SCAN = 256 * 4;
+constexpr unsigned PG_SCATTER = 256 * 5;
+constexpr unsigned PG_EMIT = 256 * 4;
+constexpr unsigned PG_FILL = 256 * 2;
+
 // Second scan stage launch: a workgroup per segment when the segments span
-// many groups each (the first levels), else a wave per segment.
+// many groups each (the first levels), else a wave per segment.  With
+// dev_ns the count is on the device and the launch is the fixed one of a
+// wave per segment.
 void launch_level_scan(const Buffers &B, uint32_t ns, uint32_t ngroups, const Lists &Ls, int force_split,
-                       hipStream_t st) {
-  if (ngroups > 8u * ns)
-    k_level_scan<true><<<ns, BLOCK, 0, st>>>(B.segs, B.group_prefix, ns, B.gsum, B.seg_or, B.seg_and, B.seg_split,
-                                             Ls, force_split);
+                       hipStream_t st, const uint32_t *dev_ns = nullptr) {
+  if (dev_ns)
+    k_level_scan<false, true><<<PG_SCAN, BLOCK, 0, st>>>(B.segs, B.group_prefix, 0, B.gsum, B.seg_or, B.seg_and,
+                                                   B.seg_split, Ls, force_split, dev_ns);
+  else if (ngroups > 8u * ns)
+    k_level_scan<true, false><<<ns, BLOCK, 0, st>>>(B.segs, B.group_prefix, ns, B.gsum, B.seg_or, B.seg_and, B.seg_split,
+                                             Ls, force_split, nullptr);
   else
-    k_level_scan<false><<<(unsigned)ceil_div(ns, WAVES), BLOCK, 0, st>>>(B.segs, B.group_prefix, ns, B.gsum,
+    k_level_scan<false, false><<<(unsigned)ceil_div(ns, WAVES), BLOCK, 0, st>>>(B.segs, B.group_prefix, ns, B.gsum,
                                                                           B.seg_or, B.seg_and, B.seg_split, Ls,
-                                                                          force_split);
+                                                                          force_split, nullptr);
 }
 
 // Tile prefixes (and group prefixes, and a copy of the list, when given) of
 // the first n entries of a segment list, computed on the device.  Uses the
-// scan-group totals area as scratch.
+// scan-group totals area as scratch.  With dev_n the count is on the device
+// and n is only its bound.
 int prefix_list(const Buffers &B, const Seg *list, uint32_t n, uint32_t tile_len, Seg *copy, uint32_t *tprefix,
-                uint32_t *gprefix, hipStream_t st) {
+                uint32_t *gprefix, hipStream_t st, const uint32_t *dev_n = nullptr) {
   if (!n) return CXBWT_OK;
   const unsigned nwg = (unsigned)ceil_div(n, SEGP_WG);
-  k_seg_count<<<nwg, BLOCK, 0, st>>>(list, n, tile_len, B.gsum);
+  k_seg_count<<<nwg, BLOCK, 0, st>>>(list, n, dev_n, tile_len, B.gsum);
   CX_LAUNCHED();
-  k_seg_scan<<<nwg, BLOCK, 0, st>>>(list, n, tile_len, B.gsum, copy, tprefix, gprefix);
+  k_seg_scan<<<nwg, BLOCK, 0, st>>>(list, n, dev_n, tile_len, B.gsum, copy, tprefix, gprefix);
   CX_LAUNCHED();
   return CXBWT_OK;
 }
@@ -1734,7 +1877,7 @@ struct LevelOut {
 // level batch).
 int read_level(const Buffers &B, LevelOut &o, PhaseTimer &T, hipStream_t st) {
   uint32_t hc[C_COUNT];
-  k_level_fold<<<1, 64, 0, st>>>(B.stats, (unsigned long long *)(B.counters + C_FOLD));
+  k_level_fold<<<1, 64, 0, st>>>(B.stats, (unsigned long long *)(B.counters + C_FOLD), nullptr);
   CX_LAUNCHED();
   CX_CHECK(hipMemcpyAsync(hc, B.counters, sizeof(hc), hipMemcpyDeviceToHost, st));
   CX_CHECK(hipStreamSynchronize(st));
@@ -1755,6 +1898,32 @@ int read_level(const Buffers &B, LevelOut &o, PhaseTimer &T, hipStream_t st) {
   return o.status ? CXBWT_EDEVICE : CXBWT_OK;
 }
 
+// The chunk kernel for the selected chunk size: one workgroup per chunk, or
+// with dev_nchunks a fixed launch of a few waves per SIMD over a count on
+// the device.
+int launch_local(const Buffers &B, const Tuning &tu, uint64_t nb, uint32_t rmax, uint8_t *bwt, uint32_t n_chunks,
+                 const uint32_t *dev_nchunks, hipStream_t st) {
+  // the looping form holds a few more registers: one wave per SIMD fewer
+  // for the smallest chunk keeps it from spilling
+#define CX_LOCAL(LI, OCC, OCCP)                                                                                  \
+  do {                                                                                                           \
+    if (dev_nchunks)                                                                                             \
+      k_local<LI, OCCP, true><<<256u * 4u * OCCP, LOCAL_WG, 0, st>>>(                                            \
+          B.chunks, B.keys0, B.keys1, B.hdl0, B.hdl1, B.text, B.srank, B.cmap, nb, rmax, bwt, B.start_row,      \
+          B.counters + C_STATUS, B.stats, 0, dev_nchunks);                                                       \
+    else                                                                                                         \
+      k_local<LI, OCC, false><<<n_chunks, LOCAL_WG, 0, st>>>(B.chunks, B.keys0, B.keys1, B.hdl0, B.hdl1, B.text, \
+                                                            B.srank, B.cmap, nb, rmax, bwt, B.start_row,         \
+                                                            B.counters + C_STATUS, B.stats, n_chunks, nullptr);  \
+  } while (0)
+  if (tu.chunk_items == 8) CX_LOCAL(8, 3, 3);
+  else if (tu.chunk_items == 6) CX_LOCAL(6, 4, 4);
+  else CX_LOCAL(3, 6, 5);
+#undef CX_LOCAL
+  CX_LAUNCHED();
+  return CXBWT_OK;
+}
+
 // Finish the chunks and final groups a level produced.
 int finish_level(const Buffers &B, const Layout &Lo, const Tuning &tu, uint64_t nb, uint32_t rmax, uint8_t *bwt,
                  uint32_t n_chunks, uint32_t n_finals, uint64_t final_tiles, uint64_t final_len, PhaseTimer &T,
@@ -1763,15 +1932,7 @@ int finish_level(const Buffers &B, const Layout &Lo, const Tuning &tu, uint64_t 
   int rc;
   if (n_chunks) {
     T.begin();
-#define CX_LOCAL(LI, OCC)                                                                                         \
-  k_local<LI, OCC><<<n_chunks, LOCAL_WG, 0, st>>>(B.chunks, B.keys0, B.keys1, B.hdl0, B.hdl1, B.text, B.srank, \
-                                                  B.cmap, nb, rmax, bwt, B.start_row, B.counters + C_STATUS,  \
-                                                  B.stats)
-    if (tu.chunk_items == 8) CX_LOCAL(8, 3);
-    else if (tu.chunk_items == 6) CX_LOCAL(6, 4);
-    else CX_LOCAL(3, 6);
-#undef CX_LOCAL
-    CX_LAUNCHED();
+    if ((rc = launch_local(B, tu, nb, rmax, bwt, n_chunks, nullptr, st))) return rc;
     T.end(PH_LOCAL);
     g_stats.chunks += n_chunks;
   }
@@ -1779,14 +1940,58 @@ int finish_level(const Buffers &B, const Layout &Lo, const Tuning &tu, uint64_t 
     if (final_tiles == 0 || final_tiles > 0xFFFFFFFFull) return CXBWT_EDEVICE;
     if ((rc = prefix_list(B, B.finals, n_finals, tu.tile_len(), nullptr, B.tile_prefix, nullptr, st))) return rc;
     T.begin();
-    k_emit_final<<<(unsigned)final_tiles, BLOCK, 0, st>>>(B.finals, B.tile_prefix, n_finals, tu.tile_len(), B.keys0,
-                                                          B.keys1, B.hdl0, B.hdl1, B.text, B.srank, B.cmap, bwt,
-                                                          B.start_row);
+    k_emit_final<false><<<(unsigned)final_tiles, BLOCK, 0, st>>>(B.finals, B.tile_prefix, n_finals, nullptr, tu.tile_len(),
+                                                          B.keys0, B.keys1, B.hdl0, B.hdl1, B.text, B.srank, B.cmap,
+                                                          bwt, B.start_row);
     CX_LAUNCHED();
     T.end(PH_FINAL);
     g_stats.final_big += n_finals;
     g_stats.chunk_suffixes -= final_len;
   }
+  return CXBWT_OK;
+}
+
+// Histogram, two scan stages and scatter of a level 2.. over nsg segments
+// (ntiles tiles, ngroups groups), or with dev_nsg over a segment count on
+// the device in launches of fixed size.
+int launch_level_kernels(const Buffers &B, const Tuning &tu, const Lists &Ls, uint64_t nb, uint32_t nsg,
+                         uint32_t ntiles, uint32_t ngroups, const uint32_t *dev_nsg, PhaseTimer &T, hipStream_t st) {
+  const bool dev = dev_nsg != nullptr;
+  T.begin();
+  if (dev)
+    k_level_hist<true><<<PG_HIST, BLOCK, 0, st>>>(B.segs, B.tile_prefix, nsg, dev_nsg, tu.tile_len(), B.keys0,
+                                                  B.keys1, B.hdl0, B.hdl1, B.text, nb, B.tile_hist, B.seg_or,
+                                                  B.seg_and);
+  else
+    k_level_hist<false><<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, nsg, nullptr, tu.tile_len(), B.keys0,
+                                                  B.keys1, B.hdl0, B.hdl1, B.text, nb, B.tile_hist, B.seg_or,
+                                                  B.seg_and);
+  CX_LAUNCHED();
+  T.end(PH_HIST);
+  T.begin();
+  if (dev)
+    k_group_scan<true><<<PG_GROUP, BLOCK, 0, st>>>(B.tile_prefix, B.group_prefix, nsg, dev_nsg, B.tile_hist, B.gsum);
+  else
+    k_group_scan<false><<<ngroups, BLOCK, 0, st>>>(B.tile_prefix, B.group_prefix, nsg, nullptr, B.tile_hist, B.gsum);
+  CX_LAUNCHED();
+  launch_level_scan(B, nsg, ngroups, Ls, 0, st, dev_nsg);
+  CX_LAUNCHED();
+  T.end(PH_SCAN);
+  T.begin();
+#define CX_SCATTER(TI, P)                                                                                       \
+  k_level_scatter<TI, P><<<P ? PG_SCATTER : ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, B.group_prefix, nsg,  \
+                                                                    dev_nsg, B.seg_split, B.tile_hist, B.gsum,   \
+                                                                    B.keys0, B.keys1, B.hdl0, B.hdl1)
+  if (tu.tile_items == 8) {
+    if (dev) CX_SCATTER(8, true);
+    else CX_SCATTER(8, false);
+  } else {
+    if (dev) CX_SCATTER(6, true);
+    else CX_SCATTER(6, false);
+  }
+#undef CX_SCATTER
+  CX_LAUNCHED();
+  T.end(PH_SCATTER);
   return CXBWT_OK;
 }
 
@@ -1801,38 +2006,31 @@ int run_level_batch(const Buffers &B, const Layout &Lo, const Tuning &tu, const 
   if ((rc = fill_u64((uint64_t *)B.seg_and, nsg, ~0ull, st))) return rc;
   if ((rc = fill_u32(B.counters + C_NFINAL, 2, 0, st))) return rc;  // final and chunk counts
   T.begin();
-  k_level_hist<<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, nsg, tu.tile_len(), B.keys0, B.keys1, B.hdl0,
-                                         B.hdl1, B.text, nb, B.tile_hist, B.seg_or, B.seg_and);
-  CX_LAUNCHED();
-  T.end(PH_HIST);
-  T.begin();
-  k_group_scan<<<ngroups, BLOCK, 0, st>>>(B.tile_prefix, B.group_prefix, nsg, B.tile_hist, B.gsum);
-  CX_LAUNCHED();
-  launch_level_scan(B, nsg, ngroups, Ls, 0, st);
-  CX_LAUNCHED();
-  T.end(PH_SCAN);
-  T.begin();
-  if (tu.tile_items == 8)
-    k_level_scatter<8><<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, B.group_prefix, nsg, B.seg_split,
-                                                 B.tile_hist, B.gsum, B.keys0, B.keys1, B.hdl0, B.hdl1);
-  else
-    k_level_scatter<6><<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, B.group_prefix, nsg, B.seg_split,
-                                                 B.tile_hist, B.gsum, B.keys0, B.keys1, B.hdl0, B.hdl1);
-  CX_LAUNCHED();
-  T.end(PH_SCATTER);
+  if ((rc = launch_level_kernels(B, tu, Ls, nb, nsg, ntiles, ngroups, nullptr, T, st))) return rc;
   g_stats.level_batches++;
   if ((rc = read_level(B, o, T, st))) return rc;
   return finish_level(B, Lo, tu, nb, rmax, bwt, o.n_chunks, o.n_finals, o.final_tiles, o.final_len, T, st);
 }
 
-// The whole build for ncoll collections laid end to end (a single build is
-// one collection).  coll_reads (host) holds ncoll + 1 read boundaries.
-int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint64_t nb, uint32_t maxlen,
-              const uint64_t *coll_reads, uint32_t ncoll, uint8_t *bwt, uint64_t *term_pos, unsigned char *ws,
-              hipStream_t st) {
-  g_stats = cxbwt_stats{};
-  PhaseTimer T{st, g_timing != 0, {}};
-  const Layout Lo = make_layout(n, nb, ncoll);
+// Everything one build needs: its sizes, the caller's buffers, the workspace
+// layout and the level-1 plan made from the collection bases.
+struct Build {
+  const uint64_t *packed, *offsets;
+  uint64_t n, nb;
+  uint32_t maxlen, ncoll;
+  uint8_t *bwt;
+  uint64_t *term_pos;
+  Layout Lo;
+  Buffers B;
+  Tuning tu;
+  uint32_t rmax, tile_len;
+  Lists Ls;
+  std::vector<uint64_t> coll_reads, cbase;
+  std::vector<CollMap> cm;
+  std::vector<Seg> big, small;  // level-1 segments; collections that fit one chunk
+};
+
+Buffers buffers_of(unsigned char *ws, const Layout &Lo) {
   Buffers B;
   B.keys0 = (uint64_t *)(ws + Lo.keys0);
   B.keys1 = (uint64_t *)(ws + Lo.keys1);
@@ -1858,55 +2056,207 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
   B.cmap = (CollMap *)(ws + Lo.cmap);
   B.counters = (uint32_t *)(ws + Lo.counters);
   B.stats = (unsigned long long *)(ws + Lo.stats);
-  const uint32_t rmax = maxlen / W + 1;
-  uint32_t *counters = B.counters;
-  const Tuning tu = g_tuning;
-  const uint32_t tile_len = tu.tile_len();
+  return B;
+}
 
-  // the read-start bitmap lives in the tile histogram area, which is not
-  // used before level 1 (4 bytes per 32 bases against 1 KiB per 1536)
-  uint32_t *sbits = B.tile_hist;
-  const uint64_t n_sbits = nb / 32 + 4;
-  if (4 * n_sbits > 4 * 256 * Lo.max_tiles) return CXBWT_EDEVICE;
+void build_init(Build &b, const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint64_t nb, uint32_t maxlen,
+                const uint64_t *coll_reads, uint32_t ncoll, uint8_t *bwt, uint64_t *term_pos, unsigned char *ws) {
+  b.packed = packed;
+  b.offsets = offsets;
+  b.n = n;
+  b.nb = nb;
+  b.maxlen = maxlen;
+  b.ncoll = ncoll;
+  b.bwt = bwt;
+  b.term_pos = term_pos;
+  b.Lo = make_layout(n, nb, ncoll);
+  b.B = buffers_of(ws, b.Lo);
+  b.tu = g_tuning;
+  b.rmax = maxlen / W + 1;
+  b.tile_len = b.tu.tile_len();
+  uint32_t *c = b.B.counters;
+  b.Ls = Lists{b.B.big_next, c + C_NBIG, (uint32_t)b.Lo.cap_big, b.B.chunks, (unsigned long long *)(c + C_NCHUNK),
+               (uint32_t)b.Lo.cap_chunks, b.B.finals, c + C_NFINAL, (uint32_t)b.Lo.cap_finals, c + C_STATUS, b.rmax,
+               b.B.stats, b.tu.chunk(), b.tile_len};
+  b.coll_reads.assign(coll_reads, coll_reads + ncoll + 1);
+}
+
+// Clears the counters, statistics and read-start bitmap, validates the
+// offsets and marks the read starts.  With check_bases the collection bases
+// are compared with the planned ones (staged in the scan-group area).
+int enqueue_prep(const Build &b, const uint64_t *coll_reads_src, const uint64_t *bases_src, PhaseTimer &T,
+                 hipStream_t st) {
+  const Buffers &B = b.B;
+  uint32_t *sbits = B.tile_hist;  // the tile histograms are not used before level 1
+  const uint64_t n_sbits = b.nb / 32 + 4;
+  if (4 * n_sbits > 4 * 256 * b.Lo.max_tiles) return CXBWT_EDEVICE;
   int rc;
-  if ((rc = fill_u32(counters, C_COUNT, 0, st))) return rc;
+  if ((rc = fill_u32(B.counters, C_COUNT, 0, st))) return rc;
   if ((rc = fill_u64((uint64_t *)B.stats, STAT_WORDS, 0, st))) return rc;
   if ((rc = fill_u32(sbits, n_sbits, 0, st))) return rc;
-  CX_CHECK(hipMemcpyAsync(B.coll_reads, coll_reads, 8 * ((uint64_t)ncoll + 1), hipMemcpyHostToDevice, st));
+  CX_CHECK(hipMemcpyAsync(B.coll_reads, coll_reads_src, 8 * ((uint64_t)b.ncoll + 1), hipMemcpyHostToDevice, st));
   T.begin();
-  k_prep<<<grid_for(n, 256), 256, 0, st>>>(packed, offsets, n, nb, maxlen, B.coll_reads, ncoll, sbits, bwt,
-                                          term_pos, counters + C_STATUS);
+  k_prep<<<grid_for(b.n, 256), 256, 0, st>>>(b.packed, b.offsets, b.n, b.nb, b.maxlen, B.coll_reads, b.ncoll, sbits,
+                                            b.bwt, b.term_pos, B.counters + C_STATUS);
   CX_LAUNCHED();
   T.end(PH_PREP);
-  k_coll_bases<<<grid_for((uint64_t)ncoll + 1, 256), 256, 0, st>>>(offsets, B.coll_reads, ncoll, B.coll_bases);
+  k_coll_bases<<<grid_for((uint64_t)b.ncoll + 1, 256), 256, 0, st>>>(b.offsets, B.coll_reads, b.ncoll,
+                                                                     B.coll_bases);
   CX_LAUNCHED();
+  if (bases_src) {
+    uint64_t *want = (uint64_t *)B.gsum;
+    CX_CHECK(hipMemcpyAsync(want, bases_src, 8 * ((uint64_t)b.ncoll + 1), hipMemcpyHostToDevice, st));
+    k_check_bases<<<grid_for((uint64_t)b.ncoll + 1, 256), 256, 0, st>>>(B.coll_bases, want, b.ncoll + 1,
+                                                                        B.counters + C_STATUS);
+    CX_LAUNCHED();
+  }
+  return CXBWT_OK;
+}
+
+// Reads the collection bases back and plans level 1: the collections above
+// one chunk are its segments, the others one unsplit chunk each.
+int plan_level1(Build &b, PhaseTimer &T, hipStream_t st) {
   uint32_t hc[C_COUNT];
-  std::vector<uint64_t> cbase(ncoll + 1);
-  CX_CHECK(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, st));
-  CX_CHECK(hipMemcpyAsync(cbase.data(), B.coll_bases, 8 * ((uint64_t)ncoll + 1), hipMemcpyDeviceToHost, st));
+  b.cbase.assign((size_t)b.ncoll + 1, 0);
+  CX_CHECK(hipMemcpyAsync(hc, b.B.counters, sizeof(hc), hipMemcpyDeviceToHost, st));
+  CX_CHECK(hipMemcpyAsync(b.cbase.data(), b.B.coll_bases, 8 * ((uint64_t)b.ncoll + 1), hipMemcpyDeviceToHost, st));
   CX_CHECK(hipStreamSynchronize(st));
   T.collect();
   if (hc[C_STATUS] & (ST_BAD_OFFSETS | ST_TOO_LONG)) return CXBWT_EDATA;
   // offsets are valid, so the collection bases are non-decreasing and end at nb
-  std::vector<CollMap> cm(ncoll);
-  std::vector<Seg> big, small;
-  for (uint32_t c = 0; c < ncoll; ++c) {
-    const uint64_t nc = coll_reads[c + 1] - coll_reads[c];
-    const uint64_t bc = cbase[c + 1] - cbase[c];
-    cm[c].out_shift = coll_reads[c + 1];
-    cm[c].row_shift = (int64_t)nc - (int64_t)cbase[c];
-    if (bc > (uint64_t)tu.chunk()) big.push_back(Seg{(uint32_t)cbase[c], (uint32_t)bc, 0, 0, 0, 0, 0, c});
-    else if (bc > 0) small.push_back(Seg{(uint32_t)cbase[c], (uint32_t)bc, 0, 0, 0, 0, 1, c});
+  b.cm.assign(b.ncoll, CollMap{});
+  b.big.clear();
+  b.small.clear();
+  for (uint32_t c = 0; c < b.ncoll; ++c) {
+    const uint64_t nc = b.coll_reads[c + 1] - b.coll_reads[c];
+    const uint64_t bc = b.cbase[c + 1] - b.cbase[c];
+    b.cm[c].out_shift = b.coll_reads[c + 1];
+    b.cm[c].row_shift = (int64_t)nc - (int64_t)b.cbase[c];
+    if (bc > (uint64_t)b.tu.chunk()) b.big.push_back(Seg{(uint32_t)b.cbase[c], (uint32_t)bc, 0, 0, 0, 0, 0, c});
+    else if (bc > 0) b.small.push_back(Seg{(uint32_t)b.cbase[c], (uint32_t)bc, 0, 0, 0, 0, 1, c});
   }
-  if (ncoll) CX_CHECK(hipMemcpyAsync(B.cmap, cm.data(), sizeof(CollMap) * ncoll, hipMemcpyHostToDevice, st));
-  if (nb == 0) {
-    CX_CHECK(hipStreamSynchronize(st));
-    return CXBWT_OK;
+  return CXBWT_OK;
+}
+
+// Host sources of the level-1 copies: the segment lists with their tile
+// and group prefixes.  An eager build points them at vectors; a captured
+// build at pinned memory that lives as long as its graph.
+struct SegSrc {
+  const Seg *segs = nullptr;
+  const uint32_t *tprefix = nullptr, *gprefix = nullptr;
+  uint32_t ns = 0, ntiles = 0, ngroups = 0;
+};
+struct Level1Src {
+  const CollMap *cm = nullptr;
+  SegSrc big, small;
+  const uint32_t *nsmall = nullptr;
+};
+
+void seg_prefixes(const std::vector<Seg> &segs, uint32_t tile_len, std::vector<uint32_t> &tp,
+                  std::vector<uint32_t> &gp) {
+  const size_t ns = segs.size();
+  tp.assign(ns + 1, 0);
+  gp.assign(ns + 1, 0);
+  for (size_t i = 0; i < ns; ++i) {
+    const uint32_t nt = (uint32_t)ceil_div(segs[i].len, tile_len);
+    tp[i + 1] = tp[i] + nt;
+    gp[i + 1] = gp[i] + (uint32_t)ceil_div(nt, GROUP_TILES);
   }
-  g_stats.chunk_suffixes = nb;
-  // ranks of the read ends, for term_pos
+}
+
+int upload_src(const Buffers &B, const Layout &Lo, const SegSrc &s, hipStream_t st) {
+  if (s.ns > Lo.seg_slots || s.ntiles > Lo.max_tiles || s.ngroups > Lo.max_groups) return CXBWT_EDEVICE;
+  CX_CHECK(hipMemcpyAsync(B.segs, s.segs, sizeof(Seg) * s.ns, hipMemcpyHostToDevice, st));
+  CX_CHECK(hipMemcpyAsync(B.tile_prefix, s.tprefix, 4 * ((uint64_t)s.ns + 1), hipMemcpyHostToDevice, st));
+  CX_CHECK(hipMemcpyAsync(B.group_prefix, s.gprefix, 4 * ((uint64_t)s.ns + 1), hipMemcpyHostToDevice, st));
+  return CXBWT_OK;
+}
+
+// The final groups of the current level, with their count on the device.
+int finish_finals_dev(const Build &b, hipStream_t st) {
+  const Buffers &B = b.B;
+  int rc;
+  if ((rc = prefix_list(B, B.finals, (uint32_t)b.Lo.cap_finals, b.tile_len, nullptr, B.tile_prefix, nullptr, st,
+                        B.counters + C_NFINAL)))
+    return rc;
+  k_emit_final<true><<<PG_EMIT, BLOCK, 0, st>>>(B.finals, B.tile_prefix, 0, B.counters + C_NFINAL, b.tile_len, B.keys0,
+                                          B.keys1, B.hdl0, B.hdl1, B.text, B.srank, B.cmap, b.bwt, B.start_row);
+  CX_LAUNCHED();
+  return CXBWT_OK;
+}
+
+// Levels 2.. on the host's schedule: every segment of a level is split by
+// one digit.  A level that fits the per-segment and per-tile scratch runs
+// as one batch whose segment list is prepared on the device; a larger one
+// is cut into batches on the host.  acc is what the previous level handed
+// on, nbig its segment count.
+int run_levels(const Build &b, LevelOut acc, uint32_t nbig, PhaseTimer &T, hipStream_t st) {
+  const Buffers &B = b.B;
+  const Layout &Lo = b.Lo;
+  uint32_t *counters = B.counters;
+  std::vector<Seg> big;
+  std::vector<uint32_t> tprefix, gprefix;
+  uint32_t ntiles = 0, ngroups = 0;
+  LevelOut o{};
+  int rc;
+  while (nbig) {
+    if (nbig > Lo.cap_big) return CXBWT_EDEVICE;
+    g_stats.levels++;
+    g_stats.big_segments += nbig;
+    g_stats.level_suffixes += acc.next_len;
+    g_stats.regathered += acc.next_regather;
+    g_stats.max_window = std::max<uint32_t>(g_stats.max_window, (uint32_t)acc.next_maxr);
+    const uint64_t lt = acc.next_tiles, lg = acc.next_groups;
+    acc = LevelOut{};
+    if ((rc = fill_u32(counters + C_NBIG, 1, 0, st))) return rc;
+    if (nbig <= Lo.seg_slots && lt <= Lo.max_tiles && lg <= Lo.max_groups) {
+      if ((rc = prefix_list(B, B.big_next, nbig, b.tile_len, B.segs, B.tile_prefix, B.group_prefix, st))) return rc;
+      if ((rc = run_level_batch(B, Lo, b.tu, b.Ls, b.nb, b.rmax, b.bwt, nbig, (uint32_t)lt, (uint32_t)lg, o, T,
+                                st)))
+        return rc;
+      acc = o;
+    } else {
+      big.resize(nbig);
+      CX_CHECK(hipMemcpyAsync(big.data(), B.big_next, sizeof(Seg) * nbig, hipMemcpyDeviceToHost, st));
+      CX_CHECK(hipStreamSynchronize(st));
+      for (size_t b0 = 0; b0 < big.size();) {
+        const size_t b1 = batch_end(big, b0, Lo, b.tile_len);
+        const std::vector<Seg> part(big.begin() + b0, big.begin() + b1);
+        if ((rc = upload_segments(B, Lo, part, b.tile_len, tprefix, gprefix, ntiles, ngroups, st))) return rc;
+        if ((rc = run_level_batch(B, Lo, b.tu, b.Ls, b.nb, b.rmax, b.bwt, (uint32_t)part.size(), ntiles, ngroups, o,
+                                  T, st)))
+          return rc;
+        acc.next_len += o.next_len;
+        acc.next_regather += o.next_regather;
+        acc.next_maxr = std::max(acc.next_maxr, o.next_maxr);
+        acc.next_tiles += o.next_tiles;
+        acc.next_groups += o.next_groups;
+        b0 = b1;
+      }
+    }
+    nbig = o.n_big;
+  }
+  return CXBWT_OK;
+}
+
+// Text records, read-end ranks, the collections that fit one chunk, and
+// level 1.  Then either (device_levels = 0) the host schedules levels 2..
+// with a counter readback per level, or the next device_levels levels are
+// enqueued with their sizes read on the device (no host wait: the whole
+// sequence can be captured), followed by a last step that flags segments
+// left over.  Ends with term_pos.
+int enqueue_body(const Build &b, const Level1Src &src, uint32_t device_levels, PhaseTimer &T, hipStream_t st) {
+  const Buffers &B = b.B;
+  const Layout &Lo = b.Lo;
+  uint32_t *counters = B.counters;
+  const uint64_t nb = b.nb;
+  int rc;
+  if (b.ncoll) CX_CHECK(hipMemcpyAsync(B.cmap, src.cm, sizeof(CollMap) * b.ncoll, hipMemcpyHostToDevice, st));
+  if (nb == 0) return CXBWT_OK;
+  uint32_t *sbits = B.tile_hist;
   T.begin();
-  k_text_records<<<grid_for(Lo.n_rec, 256), 256, 0, st>>>(packed, cxbwt_packed_words(nb), sbits, B.text, Lo.n_rec);
+  k_text_records<<<grid_for(Lo.n_rec, 256), 256, 0, st>>>(b.packed, cxbwt_packed_words(nb), sbits, B.text,
+                                                           Lo.n_rec);
   CX_LAUNCHED();
   k_rank_count<<<(unsigned)Lo.n_rank_blocks, BLOCK, 0, st>>>(sbits, Lo.n_rank_words, B.rank_blocks);
   CX_LAUNCHED();
@@ -1917,47 +2267,38 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
   CX_LAUNCHED();
   T.end(PH_PREP);
 
-  Lists Ls{B.big_next, counters + C_NBIG, (uint32_t)Lo.cap_big, B.chunks,
-           (unsigned long long *)(counters + C_NCHUNK), (uint32_t)Lo.cap_chunks,
-           B.finals, counters + C_NFINAL, (uint32_t)Lo.cap_finals, counters + C_STATUS, rmax,
-           B.stats, tu.chunk(), tile_len};
-  std::vector<uint32_t> tprefix, gprefix;
-  uint32_t ntiles = 0, ngroups = 0;
-
   // collections that fit one chunk: keys in read order, one unsplit chunk each
-  if (!small.empty()) {
-    if ((rc = upload_segments(B, Lo, small, tile_len, tprefix, gprefix, ntiles, ngroups, st))) return rc;
+  if (src.small.ns) {
+    if ((rc = upload_src(B, Lo, src.small, st))) return rc;
     T.begin();
-    k_gen<<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, (uint32_t)small.size(), tile_len, B.text, nb, B.keys0,
-                                    B.hdl0);
+    k_gen<<<src.small.ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, src.small.ns, b.tile_len, B.text, nb, B.keys0,
+                                              B.hdl0);
     CX_LAUNCHED();
     T.end(PH_GEN);
-    CX_CHECK(hipMemcpyAsync(B.chunks, small.data(), sizeof(Seg) * small.size(), hipMemcpyHostToDevice, st));
-    if (big.empty()) {
-      if ((rc = finish_level(B, Lo, tu, nb, rmax, bwt, (uint32_t)small.size(), 0, 0, 0, T, st))) return rc;
+    CX_CHECK(hipMemcpyAsync(B.chunks, src.small.segs, sizeof(Seg) * src.small.ns, hipMemcpyHostToDevice, st));
+    if (!src.big.ns) {
+      if ((rc = finish_level(B, Lo, b.tu, nb, b.rmax, b.bwt, src.small.ns, 0, 0, 0, T, st))) return rc;
     } else {
       // level 1 appends its chunks after these
-      const uint32_t nsmall = (uint32_t)small.size();
-      CX_CHECK(hipMemcpyAsync(counters + C_NCHUNK, &nsmall, 4, hipMemcpyHostToDevice, st));
-      CX_CHECK(hipStreamSynchronize(st));  // host values above must stay alive until copied
+      CX_CHECK(hipMemcpyAsync(counters + C_NCHUNK, src.nsmall, 4, hipMemcpyHostToDevice, st));
     }
   }
-  if (!big.empty()) {
+  if (src.big.ns) {
     // level 1: keys computed from the 2-bit reads, counted, recomputed, scattered
-    const uint32_t ns = (uint32_t)big.size();
-    if ((rc = upload_segments(B, Lo, big, tile_len, tprefix, gprefix, ntiles, ngroups, st))) return rc;
+    const uint32_t ns = src.big.ns, ntiles = src.big.ntiles, ngroups = src.big.ngroups;
+    if ((rc = upload_src(B, Lo, src.big, st))) return rc;
     T.begin();
-    k_gen_hist<<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, ns, tile_len, B.text, nb, B.tile_hist);
+    k_gen_hist<<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, ns, b.tile_len, B.text, nb, B.tile_hist);
     CX_LAUNCHED();
     T.end(PH_GEN);
     T.begin();
-    k_group_scan<<<ngroups, BLOCK, 0, st>>>(B.tile_prefix, B.group_prefix, ns, B.tile_hist, B.gsum);
+    k_group_scan<false><<<ngroups, BLOCK, 0, st>>>(B.tile_prefix, B.group_prefix, ns, nullptr, B.tile_hist, B.gsum);
     CX_LAUNCHED();
-    launch_level_scan(B, ns, ngroups, Ls, 1, st);
+    launch_level_scan(B, ns, ngroups, b.Ls, 1, st);
     CX_LAUNCHED();
     T.end(PH_SCAN);
     T.begin();
-    if (tu.tile_items == 8)
+    if (b.tu.tile_items == 8)
       k_gen_scatter<8><<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, B.group_prefix, ns, B.text, nb, B.tile_hist,
                                                  B.gsum, B.keys1, B.hdl1);
     else
@@ -1965,74 +2306,227 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
                                                  B.gsum, B.keys1, B.hdl1);
     CX_LAUNCHED();
     T.end(PH_SCATTER);
-    for (const Seg &g : big) g_stats.level_suffixes += g.len;
-    g_stats.levels = 1;
-    g_stats.big_segments = ns;
-    LevelOut o{};
-    if ((rc = read_level(B, o, T, st))) return rc;
-    if ((rc = finish_level(B, Lo, tu, nb, rmax, bwt, o.n_chunks, o.n_finals, o.final_tiles, o.final_len, T, st)))
-      return rc;
-    // levels 2..: every segment of a level is split by one digit.  A level
-    // that fits the per-segment and per-tile scratch runs as one batch whose
-    // segment list is prepared on the device; a larger one is cut into
-    // batches on the host.
-    LevelOut acc = o;  // what the previous level handed on
-    uint32_t nbig = o.n_big;
-    while (nbig) {
-      if (nbig > Lo.cap_big) return CXBWT_EDEVICE;
-      g_stats.levels++;
-      g_stats.big_segments += nbig;
-      g_stats.level_suffixes += acc.next_len;
-      g_stats.regathered += acc.next_regather;
-      g_stats.max_window = std::max<uint32_t>(g_stats.max_window, (uint32_t)acc.next_maxr);
-      const uint64_t lt = acc.next_tiles, lg = acc.next_groups;
-      acc = LevelOut{};
-      if ((rc = fill_u32(counters + C_NBIG, 1, 0, st))) return rc;
-      if (nbig <= Lo.seg_slots && lt <= Lo.max_tiles && lg <= Lo.max_groups) {
-        if ((rc = prefix_list(B, B.big_next, nbig, tile_len, B.segs, B.tile_prefix, B.group_prefix, st))) return rc;
-        if ((rc = run_level_batch(B, Lo, tu, Ls, nb, rmax, bwt, nbig, (uint32_t)lt, (uint32_t)lg, o, T, st)))
+    if (device_levels == 0) {
+      LevelOut o{};
+      if ((rc = read_level(B, o, T, st))) return rc;
+      if ((rc = finish_level(B, Lo, b.tu, nb, b.rmax, b.bwt, o.n_chunks, o.n_finals, o.final_tiles, o.final_len, T,
+                             st)))
+        return rc;
+      if ((rc = run_levels(b, o, o.n_big, T, st))) return rc;
+    } else {
+      const uint32_t *ncur = counters + C_NCUR;
+      for (uint32_t lv = 0;; ++lv) {
+        // the level just scanned: fold, finish its chunks and final groups
+        k_level_fold<<<1, 64, 0, st>>>(B.stats, (unsigned long long *)(counters + C_FOLD), counters + C_FLAGS);
+        CX_LAUNCHED();
+        if ((rc = launch_local(B, b.tu, nb, b.rmax, b.bwt, (uint32_t)Lo.cap_chunks, counters + C_NCHUNK, st)))
           return rc;
-        acc = o;
-      } else {
-        big.resize(nbig);
-        CX_CHECK(hipMemcpyAsync(big.data(), B.big_next, sizeof(Seg) * nbig, hipMemcpyDeviceToHost, st));
-        CX_CHECK(hipStreamSynchronize(st));
-        for (size_t b0 = 0; b0 < big.size();) {
-          const size_t b1 = batch_end(big, b0, Lo, tile_len);
-          const std::vector<Seg> part(big.begin() + b0, big.begin() + b1);
-          if ((rc = upload_segments(B, Lo, part, tile_len, tprefix, gprefix, ntiles, ngroups, st))) return rc;
-          if ((rc = run_level_batch(B, Lo, tu, Ls, nb, rmax, bwt, (uint32_t)part.size(), ntiles, ngroups, o, T,
-                                    st)))
-            return rc;
-          acc.next_len += o.next_len;
-          acc.next_regather += o.next_regather;
-          acc.next_maxr = std::max(acc.next_maxr, o.next_maxr);
-          acc.next_tiles += o.next_tiles;
-          acc.next_groups += o.next_groups;
-          b0 = b1;
-        }
+        if ((rc = finish_finals_dev(b, st))) return rc;
+        const int last = lv == device_levels - 1;
+        k_level_step<<<1, 64, 0, st>>>(counters, Lo.seg_slots, Lo.max_tiles, Lo.max_groups, last);
+        CX_LAUNCHED();
+        if (last) break;
+        // the next level, sized on the device
+        if ((rc = prefix_list(B, B.big_next, (uint32_t)Lo.seg_slots, b.tile_len, B.segs, B.tile_prefix,
+                              B.group_prefix, st, ncur)))
+          return rc;
+        k_fill_seg<<<PG_FILL, 256, 0, st>>>(B.seg_or, B.seg_and, ncur);
+        CX_LAUNCHED();
+        if ((rc = launch_level_kernels(B, b.tu, b.Ls, nb, 0, 0, 0, ncur, T, st))) return rc;
       }
-      nbig = o.n_big;
     }
   }
   T.begin();
-  k_term<<<grid_for(n, 256), 256, 0, st>>>(offsets, n, B.text, B.srank, B.start_row, term_pos);
+  k_term<<<grid_for(b.n, 256), 256, 0, st>>>(b.offsets, b.n, B.text, B.srank, B.start_row, b.term_pos);
   CX_LAUNCHED();
   T.end(PH_FINAL);
+  return CXBWT_OK;
+}
+
+// Statistics counters of the build, and the device status.
+int read_totals(const Build &b, PhaseTimer &T, hipStream_t st, uint32_t (&hc)[C_COUNT]) {
   std::vector<uint64_t> hs(STAT_WORDS);
-  CX_CHECK(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, st));
-  CX_CHECK(hipMemcpyAsync(hs.data(), B.stats, 8 * STAT_WORDS, hipMemcpyDeviceToHost, st));
+  CX_CHECK(hipMemcpyAsync(hc, b.B.counters, sizeof(hc), hipMemcpyDeviceToHost, st));
+  CX_CHECK(hipMemcpyAsync(hs.data(), b.B.stats, 8 * STAT_WORDS, hipMemcpyDeviceToHost, st));
   CX_CHECK(hipStreamSynchronize(st));
   T.collect();
   for (int i = 0; i < STAT_SPREAD; ++i) {
-    g_stats.window_fetches += hs[i * STAT_STRIDE];
-    g_stats.scattered_suffixes += hs[(STAT_SPREAD + i) * STAT_STRIDE];
+    g_stats.window_fetches += hs[K_FETCHES * STAT_KIND + i * STAT_STRIDE];
+    g_stats.scattered_suffixes += hs[K_SCATTERED * STAT_KIND + i * STAT_STRIDE];
   }
+  return CXBWT_OK;
+}
+
+// Level-1 sources taken from the plan's vectors (an eager build).
+struct Level1Vectors {
+  std::vector<uint32_t> btp, bgp, stp, sgp;
+  uint32_t nsmall = 0;
+  Level1Src src;
+  void make(const Build &b) {
+    seg_prefixes(b.big, b.tile_len, btp, bgp);
+    seg_prefixes(b.small, b.tile_len, stp, sgp);
+    nsmall = (uint32_t)b.small.size();
+    src.cm = b.cm.data();
+    src.big = SegSrc{b.big.data(), btp.data(), bgp.data(), (uint32_t)b.big.size(), btp.back(), bgp.back()};
+    src.small = SegSrc{b.small.data(), stp.data(), sgp.data(), nsmall, stp.back(), sgp.back()};
+    src.nsmall = &nsmall;
+  }
+};
+
+void level1_stats(const Build &b) {
+  g_stats.chunk_suffixes = b.nb;
+  if (!b.big.empty()) {
+    g_stats.levels = 1;
+    g_stats.big_segments = b.big.size();
+    for (const Seg &g : b.big) g_stats.level_suffixes += g.len;
+  }
+}
+
+// The whole build for ncoll collections laid end to end (a single build is
+// one collection).  coll_reads (host) holds ncoll + 1 read boundaries.
+int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint64_t nb, uint32_t maxlen,
+              const uint64_t *coll_reads, uint32_t ncoll, uint8_t *bwt, uint64_t *term_pos, unsigned char *ws,
+              hipStream_t st) {
+  g_stats = cxbwt_stats{};
+  PhaseTimer T{st, g_timing != 0, {}};
+  Build b;
+  build_init(b, packed, offsets, n, nb, maxlen, coll_reads, ncoll, bwt, term_pos, ws);
+  int rc;
+  if ((rc = enqueue_prep(b, b.coll_reads.data(), nullptr, T, st))) return rc;
+  if ((rc = plan_level1(b, T, st))) return rc;
+  Level1Vectors v;
+  v.make(b);
+  level1_stats(b);
+  if ((rc = enqueue_body(b, v.src, 0, T, st))) return rc;
+  uint32_t hc[C_COUNT];
+  if ((rc = read_totals(b, T, st, hc))) return rc;
+  if (hc[C_STATUS]) return CXBWT_EDEVICE;
+  return CXBWT_OK;
+}
+
+// A build captured once in a hipGraph for fixed sizes and buffers, replayed
+// on new contents of the same buffers.
+struct GraphPlan {
+  Build b;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  unsigned char *pinned = nullptr;  // host sources of the captured copies
+  uint32_t levels = 0;              // levels 2.. scheduled on the device
+  cxbwt_stats base{};               // statistics of level 1 (known on the host)
+  ~GraphPlan() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (pinned) (void)hipHostFree(pinned);
+  }
+};
+
+int graph_capture(GraphPlan &P, hipStream_t st) {
+  Build &b = P.b;
+  PhaseTimer T{st, false, {}};
+  // eager pass: validate the offsets and learn the collection bases
+  int rc;
+  if ((rc = enqueue_prep(b, b.coll_reads.data(), nullptr, T, st))) return rc;
+  if ((rc = plan_level1(b, T, st))) return rc;
+  g_stats = cxbwt_stats{};
+  level1_stats(b);
+  P.base = g_stats;
+  // pinned copies of everything the captured copies read
+  Level1Vectors v;
+  v.make(b);
+  const size_t nc1 = (size_t)b.ncoll + 1;
+  const size_t nbg = b.big.size(), nsm = b.small.size();
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = (off + bytes + 255) & ~(size_t)255;
+    return at;
+  };
+  const size_t o_cr = take(8 * nc1), o_cb = take(8 * nc1), o_cm = take(sizeof(CollMap) * b.ncoll),
+               o_bs = take(sizeof(Seg) * nbg), o_btp = take(4 * (nbg + 1)), o_bgp = take(4 * (nbg + 1)),
+               o_ss = take(sizeof(Seg) * nsm), o_stp = take(4 * (nsm + 1)), o_sgp = take(4 * (nsm + 1)),
+               o_ns = take(4);
+  CX_CHECK(hipHostMalloc((void **)&P.pinned, off, hipHostMallocDefault));
+  unsigned char *h = P.pinned;
+  memcpy(h + o_cr, b.coll_reads.data(), 8 * nc1);
+  memcpy(h + o_cb, b.cbase.data(), 8 * nc1);
+  if (b.ncoll) memcpy(h + o_cm, b.cm.data(), sizeof(CollMap) * b.ncoll);
+  if (nbg) memcpy(h + o_bs, b.big.data(), sizeof(Seg) * nbg);
+  memcpy(h + o_btp, v.btp.data(), 4 * (nbg + 1));
+  memcpy(h + o_bgp, v.bgp.data(), 4 * (nbg + 1));
+  if (nsm) memcpy(h + o_ss, b.small.data(), sizeof(Seg) * nsm);
+  memcpy(h + o_stp, v.stp.data(), 4 * (nsm + 1));
+  memcpy(h + o_sgp, v.sgp.data(), 4 * (nsm + 1));
+  memcpy(h + o_ns, &v.nsmall, 4);
+  Level1Src src;
+  src.cm = (const CollMap *)(h + o_cm);
+  src.big = SegSrc{(const Seg *)(h + o_bs), (const uint32_t *)(h + o_btp), (const uint32_t *)(h + o_bgp),
+                   (uint32_t)nbg, v.btp.back(), v.bgp.back()};
+  src.small = SegSrc{(const Seg *)(h + o_ss), (const uint32_t *)(h + o_stp), (const uint32_t *)(h + o_sgp),
+                     (uint32_t)nsm, v.stp.back(), v.sgp.back()};
+  src.nsmall = (const uint32_t *)(h + o_ns);
+  // capture: every size below is fixed now or read on the device
+  CX_CHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  rc = enqueue_prep(b, (const uint64_t *)(h + o_cr), (const uint64_t *)(h + o_cb), T, st);
+  if (!rc) rc = enqueue_body(b, src, P.levels ? P.levels : 1, T, st);
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(st, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (ec != hipSuccess || !g) return CXBWT_EDEVICE;
+  P.graph = g;
+  CX_CHECK(hipGraphInstantiate(&P.exec, P.graph, nullptr, nullptr, 0));
+  return CXBWT_OK;
+}
+
+// After a replay: status, statistics, and the levels left to the host.
+int graph_finish(GraphPlan &P, hipStream_t st) {
+  Build &b = P.b;
+  PhaseTimer T{st, false, {}};
+  g_stats = P.base;
+  uint32_t hc[C_COUNT];
+  int rc;
+  if ((rc = read_totals(b, T, st, hc))) return rc;
+  if (hc[C_STATUS] & (ST_BAD_OFFSETS | ST_TOO_LONG)) return CXBWT_EDATA;
+  if (hc[C_STATUS] & ST_PLAN_MISMATCH) return CXBWT_EINVAL;
+  if (hc[C_STATUS]) return CXBWT_EDEVICE;
+  uint64_t g[G_COUNT], f[K_LEVEL_KINDS];
+  memcpy(g, hc + C_CUM, sizeof(g));
+  memcpy(f, hc + C_FOLD, sizeof(f));
+  g_stats.levels += (uint32_t)g[G_LEVELS];
+  g_stats.big_segments += g[G_BIGSEG];
+  g_stats.level_suffixes += g[G_LEVSUF];
+  g_stats.regathered += g[G_REGATH];
+  g_stats.max_window = std::max<uint32_t>(g_stats.max_window, (uint32_t)g[G_MAXWIN]);
+  g_stats.chunks += g[G_CHUNKS];
+  g_stats.final_big += g[G_FINALS];
+  g_stats.chunk_suffixes -= g[G_FINLEN];
+  g_stats.level_batches += (uint32_t)g[G_BATCHES];
+  if (!(hc[C_FLAGS] & (FL_STALLED | FL_INCOMPLETE))) return CXBWT_OK;
+  // the device schedule did not cover the build: the host finishes it
+  LevelOut acc{};
+  acc.next_len = f[K_NEXT_LEN - K_LEVEL_FIRST];
+  acc.next_regather = f[K_NEXT_REGATHER - K_LEVEL_FIRST];
+  acc.next_maxr = f[K_NEXT_MAXR - K_LEVEL_FIRST];
+  acc.next_tiles = f[K_NEXT_TILES - K_LEVEL_FIRST];
+  acc.next_groups = f[K_NEXT_GROUPS - K_LEVEL_FIRST];
+  if ((rc = run_levels(b, acc, hc[C_NBIG], T, st))) return rc;
+  k_term<<<grid_for(b.n, 256), 256, 0, st>>>(b.offsets, b.n, b.B.text, b.B.srank, b.B.start_row, b.term_pos);
+  CX_LAUNCHED();
+  // the statistics block still holds the replay's counts: take the rest only
+  g_stats.window_fetches = 0;
+  g_stats.scattered_suffixes = 0;
+  if ((rc = read_totals(b, T, st, hc))) return rc;
   if (hc[C_STATUS]) return CXBWT_EDEVICE;
   return CXBWT_OK;
 }
 
 }  // namespace
+
+struct cxbwt_graph {
+  GraphPlan p;
+};
 
 // ---------------------------------------------------------------------------
 // C ABI
@@ -2092,6 +2586,57 @@ int cxbwt_build_batch(const uint64_t *packed, const uint64_t *offsets, uint64_t 
   return run_build(packed, offsets, n_reads, n_bases, max_read_len, coll_reads, n_coll, bwt, term_pos,
                    (unsigned char *)workspace, (hipStream_t)stream);
 }
+
+int cxbwt_graph_create(const uint64_t *packed, const uint64_t *offsets, uint64_t n_reads, uint64_t n_bases,
+                       uint32_t max_read_len, const uint64_t *coll_reads, uint32_t n_coll, uint8_t *bwt,
+                       uint64_t *term_pos, void *workspace, size_t workspace_bytes, uint32_t levels, void *stream,
+                       cxbwt_graph **out) {
+  if (!out) return CXBWT_EINVAL;
+  *out = nullptr;
+  if (!packed || !offsets || !bwt || !term_pos || !workspace || n_reads == 0 || n_coll == 0) return CXBWT_EINVAL;
+  if (!sizes_ok(n_reads, n_bases, max_read_len)) return CXBWT_ERANGE;
+  const uint64_t one[2] = {0, n_reads};
+  if (!coll_reads) {
+    if (n_coll != 1) return CXBWT_EINVAL;
+    coll_reads = one;
+  }
+  if (n_coll > n_reads || coll_reads[0] != 0 || coll_reads[n_coll] != n_reads) return CXBWT_EINVAL;
+  for (uint32_t c = 0; c < n_coll; ++c)
+    if (coll_reads[c + 1] <= coll_reads[c]) return CXBWT_EINVAL;
+  if (workspace_bytes < cxbwt_batch_workspace_bytes(n_reads, n_bases, max_read_len, n_coll)) return CXBWT_ENOMEM;
+  if (((uintptr_t)workspace & 255u) != 0) return CXBWT_EINVAL;
+  cxbwt_graph *g = new (std::nothrow) cxbwt_graph;
+  if (!g) return CXBWT_ENOMEM;
+  build_init(g->p.b, packed, offsets, n_reads, n_bases, max_read_len, coll_reads, n_coll, bwt, term_pos,
+             (unsigned char *)workspace);
+  g->p.levels = levels ? levels : 8 * g->p.b.rmax + 2;
+  // the eager pass runs on the caller's stream; the capture on a stream of
+  // its own (a capture needs a non-default stream)
+  hipStream_t cs = nullptr;
+  int rc = CXBWT_OK;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) rc = CXBWT_EDEVICE;
+  if (!rc && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) rc = CXBWT_EDEVICE;
+  if (!rc) rc = graph_capture(g->p, cs);
+  if (cs) (void)hipStreamDestroy(cs);
+  if (rc) {
+    delete g;
+    return rc;
+  }
+  *out = g;
+  return CXBWT_OK;
+}
+
+int cxbwt_graph_launch(cxbwt_graph *g, void *stream) {
+  if (!g || !g->p.exec) return CXBWT_EINVAL;
+  return hipGraphLaunch(g->p.exec, (hipStream_t)stream) == hipSuccess ? CXBWT_OK : CXBWT_EDEVICE;
+}
+
+int cxbwt_graph_finish(cxbwt_graph *g, void *stream) {
+  if (!g || !g->p.exec) return CXBWT_EINVAL;
+  return graph_finish(g->p, (hipStream_t)stream);
+}
+
+void cxbwt_graph_destroy(cxbwt_graph *g) { delete g; }
 
 int cxbwt_last_stats(cxbwt_stats *out) {
   if (!out) return CXBWT_EINVAL;

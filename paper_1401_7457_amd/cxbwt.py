@@ -23,7 +23,8 @@ STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ERANGE: "ERANGE", ENOMEM: "ENOMEM", 
 # Names the C ABI exports (include/cxbwt.h).
 ABI_FUNCTIONS = ("cxbwt_packed_words", "cxbwt_pack", "cxbwt_workspace_bytes", "cxbwt_build",
                  "cxbwt_batch_workspace_bytes", "cxbwt_build_batch", "cxbwt_last_stats", "cxbwt_set_timing",
-                 "cxbwt_set_tuning", "cxbwt_get_tuning", "cxbwt_status_str")
+                 "cxbwt_set_tuning", "cxbwt_get_tuning", "cxbwt_graph_create", "cxbwt_graph_launch",
+                 "cxbwt_graph_finish", "cxbwt_graph_destroy", "cxbwt_status_str")
 
 # kernel instantiations the library holds: (suffixes per thread in a level
 # tile, suffixes per lane in a chunk); the first is the default
@@ -82,6 +83,15 @@ def lib():
             L.cxbwt_set_tuning.restype = ctypes.c_int
             L.cxbwt_get_tuning.argtypes = [ctypes.POINTER(u32), ctypes.POINTER(u32)]
             L.cxbwt_get_tuning.restype = ctypes.c_int
+            L.cxbwt_graph_create.argtypes = [vp, vp, u64, u64, u32, vp, u32, vp, vp, vp, ctypes.c_size_t, u32, vp,
+                                             ctypes.POINTER(vp)]
+            L.cxbwt_graph_create.restype = ctypes.c_int
+            L.cxbwt_graph_launch.argtypes = [vp, vp]
+            L.cxbwt_graph_launch.restype = ctypes.c_int
+            L.cxbwt_graph_finish.argtypes = [vp, vp]
+            L.cxbwt_graph_finish.restype = ctypes.c_int
+            L.cxbwt_graph_destroy.argtypes = [vp]
+            L.cxbwt_graph_destroy.restype = None
             L.cxbwt_status_str.argtypes = [ctypes.c_int]
             L.cxbwt_status_str.restype = ctypes.c_char_p
             _lib = L
@@ -185,6 +195,71 @@ def build_batch(packed, offsets, n_reads: int, n_bases: int, max_read_len: int, 
     if st != OK:
         raise CxbwtError(st, "cxbwt_build_batch")
     return bwt, term
+
+
+class BuildGraph:
+    """A build captured once in a hipGraph and replayed (cxbwt_graph_*).
+
+    The graph binds the given tensors: refill `packed` / `offsets` (same
+    sizes, same bases per collection) and call run() (or launch() then
+    finish()) for each build; the result lands in `bwt` / `term`.
+    coll_reads: host read boundaries of the collections, or None for one.
+    levels: sort levels scheduled inside the graph (0: enough for any input).
+    """
+
+    def __init__(self, packed, offsets, n_reads: int, n_bases: int, max_read_len: int, coll_reads=None,
+                 levels: int = 0, workspace=None, out=None, stream=None):
+        import torch
+        dev = packed.device
+        if coll_reads is None:
+            cr = np.array([0, n_reads], dtype=np.uint64)
+        else:
+            cr = np.ascontiguousarray(np.asarray(coll_reads, dtype=np.uint64))
+        n_coll = cr.size - 1
+        if workspace is None:
+            nbytes = batch_workspace_bytes(n_reads, n_bases, max_read_len, n_coll)
+            if nbytes == 0:
+                raise CxbwtError(ERANGE, "cxbwt_batch_workspace_bytes")
+            workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        if out is None:
+            out = (torch.empty(n_bases + n_reads, dtype=torch.uint8, device=dev),
+                   torch.empty(n_reads, dtype=torch.int64, device=dev))
+        self.packed, self.offsets, self.workspace = packed, offsets, workspace
+        self.bwt, self.term = out
+        self._h = ctypes.c_void_p()
+        st = lib().cxbwt_graph_create(ctypes.c_void_p(packed.data_ptr()), ctypes.c_void_p(offsets.data_ptr()),
+                                      n_reads, n_bases, max_read_len, cr.ctypes.data_as(ctypes.c_void_p), n_coll,
+                                      ctypes.c_void_p(self.bwt.data_ptr()), ctypes.c_void_p(self.term.data_ptr()),
+                                      ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), int(levels),
+                                      _stream_ptr(stream), ctypes.byref(self._h))
+        if st != OK:
+            raise CxbwtError(st, "cxbwt_graph_create")
+
+    def launch(self, stream=None) -> None:
+        st = lib().cxbwt_graph_launch(self._h, _stream_ptr(stream))
+        if st != OK:
+            raise CxbwtError(st, "cxbwt_graph_launch")
+
+    def finish(self, stream=None) -> None:
+        st = lib().cxbwt_graph_finish(self._h, _stream_ptr(stream))
+        if st != OK:
+            raise CxbwtError(st, "cxbwt_graph_finish")
+
+    def run(self, stream=None):
+        self.launch(stream)
+        self.finish(stream)
+        return self.bwt, self.term
+
+    def close(self) -> None:
+        if self._h:
+            lib().cxbwt_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def concat_collections(cols):
