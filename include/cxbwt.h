@@ -232,8 +232,9 @@ typedef struct cxbwt_stats {
 /*
  * cxbwt_set_tuning -- pick, for later builds on the calling host thread, the
  * kernel instantiation the build uses (the library holds all of them):
- *   tile_items   suffixes per thread in a level tile (6 or 8; a tile is 256
- *                threads): longer tiles write longer runs per bucket
+ *   tile_items   suffixes per thread in a level tile of 256 threads (6 or 8),
+ *                or 16: the wide tile of 4096 suffixes (512 threads x 8).
+ *                Longer tiles write longer runs per bucket
  *   chunk_items  suffixes per lane of the one-wave chunk kernel (3, 6 or 8):
  *                the largest run of small buckets finished in LDS is 64 x this
  * The output is the same for every choice; only speed differs.  Default

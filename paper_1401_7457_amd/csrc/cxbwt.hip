@@ -57,7 +57,7 @@ using namespace cxk;
 // smallest tile and chunk, so a workspace fits every choice.
 constexpr int LOCAL_WG = 64;                   // one wave finishes a chunk
 constexpr int MIN_TILE_ITEMS = 6;
-constexpr int MAX_TILE_ITEMS = 8;  // a level tile is at most BLOCK * MAX_TILE_ITEMS suffixes
+constexpr int MAX_TILE_ITEMS = 8;  // items per thread a histogram kernel loads at once
 constexpr int MIN_CHUNK_ITEMS = 3;
 constexpr int MIN_TILE = BLOCK * MIN_TILE_ITEMS;
 constexpr int MIN_CHUNK = LOCAL_WG * MIN_CHUNK_ITEMS;
@@ -424,6 +424,7 @@ __global__ __launch_bounds__(BLOCK) void k_gen(const Seg *__restrict__ segs, con
 // order, from the 2-bit reads) counted by their top digit, then recomputed
 // and scattered; keys are never stored unsorted.  One segment per collection.
 // ---------------------------------------------------------------------------
+template <int SUBT>
 __global__ __launch_bounds__(BLOCK) void k_gen_hist(const Seg *__restrict__ segs, const uint32_t *__restrict__ tile_prefix,
                                                     uint32_t nsegs, uint32_t tile_len, const TextRec *__restrict__ text,
                                                     uint64_t nb, uint32_t *__restrict__ tile_hist) {
@@ -435,39 +436,51 @@ __global__ __launch_bounds__(BLOCK) void k_gen_hist(const Seg *__restrict__ segs
   const uint64_t t1 = min(t0 + (uint64_t)tile_len, sg.start + sg.len);
   hist[threadIdx.x] = 0;
   __syncthreads();
-  // every record load of the thread is issued before the first count
-  uint64_t kk[MAX_TILE_ITEMS];
+  // every record load of a sub-tile is issued before its first count
 #pragma unroll
-  for (int i = 0; i < MAX_TILE_ITEMS; ++i) {
-    const uint64_t p = t0 + (uint64_t)i * BLOCK + threadIdx.x;
-    if (p < t1) kk[i] = first_key(text, nb, p);
+  for (int sub = 0; sub < SUBT; ++sub) {
+    const uint64_t u0 = t0 + (uint64_t)sub * BLOCK * MAX_TILE_ITEMS;
+    uint64_t kk[MAX_TILE_ITEMS];
+#pragma unroll
+    for (int i = 0; i < MAX_TILE_ITEMS; ++i) {
+      const uint64_t p = u0 + (uint64_t)i * BLOCK + threadIdx.x;
+      if (p < t1) kk[i] = first_key(text, nb, p);
+    }
+#pragma unroll
+    for (int i = 0; i < MAX_TILE_ITEMS; ++i)
+      if (u0 + (uint64_t)i * BLOCK + threadIdx.x < t1) atomicAdd(&hist[digit_of(kk[i], 0)], 1u);
   }
-#pragma unroll
-  for (int i = 0; i < MAX_TILE_ITEMS; ++i)
-    if (t0 + (uint64_t)i * BLOCK + threadIdx.x < t1) atomicAdd(&hist[digit_of(kk[i], 0)], 1u);
   __syncthreads();
   tile_hist[(uint64_t)tile * 256 + threadIdx.x] = hist[threadIdx.x];
 }
 
 // Stable scatter of `m` items held in registers to global positions
 // base[digit] + rank-within-tile, staged through LDS so that each digit's run
-// is written contiguously.
-template <int TI>
+// is written contiguously.  A tile is NW waves x TI items: the wide tile
+// (8 waves, 4096 suffixes) writes runs twice as long per bucket, which the
+// memory system turns into fuller line writes.
+template <int TI, int NW>
 struct ScatterSmem {
-  uint64_t sk[BLOCK * TI];
-  uint32_t sh[BLOCK * TI];
-  uint32_t wcount[WAVES * 256];
+  // the per-wave digit counters are dead once every rank is known, before
+  // the first staged write: they share the key staging area
+  static_assert(NW * 256 * 4 <= 64 * NW * TI * 8, "counters fit the key stage");
+  union {
+    uint64_t sk[64 * NW * TI];
+    uint32_t wcount[NW * 256];
+  };
+  uint32_t sh[64 * NW * TI];
   uint32_t dstart[256];
   uint64_t goff[256];
-  uint32_t tmp[WAVES];
+  uint32_t tmp[NW];
 };
 
-template <int TI>
-__device__ __forceinline__ void tile_scatter(ScatterSmem<TI> &S, const uint64_t (&kr)[TI], const uint32_t (&hr)[TI],
-                                             const uint32_t (&dig)[TI], uint32_t m, int d, uint64_t *__restrict__ Ko,
-                                             uint32_t *__restrict__ Ho) {
+template <int TI, int NW>
+__device__ __forceinline__ void tile_scatter(ScatterSmem<TI, NW> &S, const uint64_t (&kr)[TI],
+                                             const uint32_t (&hr)[TI], const uint32_t (&dig)[TI], uint32_t m, int d,
+                                             uint64_t *__restrict__ Ko, uint32_t *__restrict__ Ho) {
   uint32_t pos[TI];
-  block_multisplit<TI>(dig, pos, S.wcount, S.dstart, S.tmp);
+  block_multisplit<TI, NW>(dig, pos, S.wcount, S.dstart, S.tmp);
+  __syncthreads();  // every wave has read its counters before the stage is written
 #pragma unroll
   for (int i = 0; i < TI; ++i) {
     if (dig[i] != NODIGIT) {
@@ -476,7 +489,7 @@ __device__ __forceinline__ void tile_scatter(ScatterSmem<TI> &S, const uint64_t 
     }
   }
   __syncthreads();
-  for (uint32_t q = threadIdx.x; q < m; q += BLOCK) {
+  for (uint32_t q = threadIdx.x; q < m; q += 64 * NW) {
     const uint64_t k = S.sk[q];
     const uint32_t dd = digit_of(k, d);
     const uint64_t g = S.goff[dd] + (q - S.dstart[dd]);
@@ -485,16 +498,16 @@ __device__ __forceinline__ void tile_scatter(ScatterSmem<TI> &S, const uint64_t 
   }
 }
 
-template <int TI>
-__global__ __launch_bounds__(BLOCK) void k_gen_scatter(const Seg *__restrict__ segs,
+template <int TI, int NW>
+__global__ __launch_bounds__(64 * NW) void k_gen_scatter(const Seg *__restrict__ segs,
                                                        const uint32_t *__restrict__ tile_prefix,
                                                        const uint32_t *__restrict__ group_prefix, uint32_t nsegs,
                                                        const TextRec *__restrict__ text, uint64_t nb,
                                                        const uint32_t *__restrict__ tile_hist,
                                                        const uint32_t *__restrict__ gsum, uint64_t *__restrict__ Ko,
                                                        uint32_t *__restrict__ Ho) {
-  constexpr uint32_t TL = BLOCK * TI;
-  __shared__ ScatterSmem<TI> S;
+  constexpr uint32_t TL = 64 * NW * TI;
+  __shared__ ScatterSmem<TI, NW> S;
   const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
   const uint32_t s = find_upper(tile_prefix, nsegs, tile);
   const Seg sg = segs[s];
@@ -517,7 +530,9 @@ __global__ __launch_bounds__(BLOCK) void k_gen_scatter(const Seg *__restrict__ s
     }
   }
   const uint32_t g = group_prefix[s] + tl / GROUP_TILES;
-  S.goff[threadIdx.x] = (uint64_t)gsum[(uint64_t)g * 256 + threadIdx.x] + tile_hist[(uint64_t)tile * 256 + threadIdx.x];
+  if (threadIdx.x < 256)
+    S.goff[threadIdx.x] =
+        (uint64_t)gsum[(uint64_t)g * 256 + threadIdx.x] + tile_hist[(uint64_t)tile * 256 + threadIdx.x];
   tile_scatter(S, kr, hr, dig, m, 0, Ko, Ho);
 }
 
@@ -532,7 +547,7 @@ __global__ __launch_bounds__(BLOCK) void k_gen_scatter(const Seg *__restrict__ s
 // given (a launch whose size was fixed before the count was known) and loop
 // over their work with the grid's stride; with the count passed by value
 // the grid covers the work and each workgroup takes one item.
-template <bool PERSIST>
+template <bool PERSIST, int SUBT>
 __global__ __launch_bounds__(BLOCK) void k_level_hist(const Seg *__restrict__ segs, const uint32_t *__restrict__ tile_prefix,
                                                       uint32_t nsegs, const uint32_t *__restrict__ dev_nsegs,
                                                       uint32_t tile_len, uint64_t *keys0,
@@ -555,40 +570,45 @@ __global__ __launch_bounds__(BLOCK) void k_level_hist(const Seg *__restrict__ se
   const uint32_t *H = sg.buf ? hdl1 : hdl0;
   hist[threadIdx.x] = 0;
   __syncthreads();
-  // all loads of the thread (keys, and for a re-keyed segment handles and
+  // all loads of a sub-tile (keys, and for a re-keyed segment handles and
   // then records) are issued before any result is used
-  uint64_t kk[MAX_TILE_ITEMS];
-  bool in[MAX_TILE_ITEMS];
+  uint64_t o = 0, a = ~0ull;
+  // SUBT sub-tiles of BLOCK * MAX_TILE_ITEMS (two for the wide tile)
 #pragma unroll
-  for (int i = 0; i < MAX_TILE_ITEMS; ++i) {
-    const uint64_t j = t0 + (uint64_t)i * BLOCK + threadIdx.x;
-    in[i] = j < t1;
-    if (in[i]) kk[i] = K[j];
-  }
-  if (sg.regather) {
-    uint32_t hh[MAX_TILE_ITEMS];
-    TextRec tr[MAX_TILE_ITEMS];
+  for (int sub = 0; sub < SUBT; ++sub) {
+    const uint64_t u0 = t0 + (uint64_t)sub * BLOCK * MAX_TILE_ITEMS;
+    uint64_t kk[MAX_TILE_ITEMS];
+    bool in[MAX_TILE_ITEMS];
 #pragma unroll
-    for (int i = 0; i < MAX_TILE_ITEMS; ++i)
-      if (in[i]) hh[i] = H[t0 + (uint64_t)i * BLOCK + threadIdx.x];
+    for (int i = 0; i < MAX_TILE_ITEMS; ++i) {
+      const uint64_t j = u0 + (uint64_t)i * BLOCK + threadIdx.x;
+      in[i] = j < t1;
+      if (in[i]) kk[i] = K[j];
+    }
+    if (sg.regather) {
+      uint32_t hh[MAX_TILE_ITEMS];
+      TextRec tr[MAX_TILE_ITEMS];
 #pragma unroll
-    for (int i = 0; i < MAX_TILE_ITEMS; ++i)
-      if (in[i]) tr[i] = window_load(text, nb, hh[i], sg.r);
+      for (int i = 0; i < MAX_TILE_ITEMS; ++i)
+        if (in[i]) hh[i] = H[u0 + (uint64_t)i * BLOCK + threadIdx.x];
+#pragma unroll
+      for (int i = 0; i < MAX_TILE_ITEMS; ++i)
+        if (in[i]) tr[i] = window_load(text, nb, hh[i], sg.r);
+#pragma unroll
+      for (int i = 0; i < MAX_TILE_ITEMS; ++i)
+        if (in[i]) {
+          kk[i] = window_combine(tr[i], nb, hh[i], sg.r, (uint32_t)kk[i] & 7u);
+          K[u0 + (uint64_t)i * BLOCK + threadIdx.x] = kk[i];
+        }
+    }
 #pragma unroll
     for (int i = 0; i < MAX_TILE_ITEMS; ++i)
       if (in[i]) {
-        kk[i] = window_combine(tr[i], nb, hh[i], sg.r, (uint32_t)kk[i] & 7u);
-        K[t0 + (uint64_t)i * BLOCK + threadIdx.x] = kk[i];
+        atomicAdd(&hist[digit_of(kk[i], sg.d)], 1u);
+        o |= kk[i];
+        a &= kk[i];
       }
   }
-  uint64_t o = 0, a = ~0ull;
-#pragma unroll
-  for (int i = 0; i < MAX_TILE_ITEMS; ++i)
-    if (in[i]) {
-      atomicAdd(&hist[digit_of(kk[i], sg.d)], 1u);
-      o |= kk[i];
-      a &= kk[i];
-    }
   o = block_or(o, red);
   a = block_and(a, red);
   if (threadIdx.x == 0) {
@@ -1198,8 +1218,8 @@ __global__ __launch_bounds__(BLOCK) void k_seg_scan(const Seg *__restrict__ list
 }
 
 // Stable scatter of one tile by its segment's digit into the other buffer.
-template <int TI, bool PERSIST>
-__global__ __launch_bounds__(BLOCK) void k_level_scatter(const Seg *__restrict__ segs,
+template <int TI, int NW, bool PERSIST>
+__global__ __launch_bounds__(64 * NW) void k_level_scatter(const Seg *__restrict__ segs,
                                                          const uint32_t *__restrict__ tile_prefix,
                                                          const uint32_t *__restrict__ group_prefix, uint32_t nsegs,
                                                          const uint32_t *__restrict__ dev_nsegs,
@@ -1207,8 +1227,8 @@ __global__ __launch_bounds__(BLOCK) void k_level_scatter(const Seg *__restrict__
                                                          const uint32_t *__restrict__ tile_hist,
                                                          const uint32_t *__restrict__ gsum, uint64_t *keys0,
                                                          uint64_t *keys1, uint32_t *hdl0, uint32_t *hdl1) {
-  constexpr uint32_t TL = BLOCK * TI;
-  __shared__ ScatterSmem<TI> S;
+  constexpr uint32_t TL = 64 * NW * TI;
+  __shared__ ScatterSmem<TI, NW> S;
   if (dev_nsegs) nsegs = *dev_nsegs;
   if (nsegs == 0) return;
   // virtual block v maps to a tile as a grid of ntiles would (neighbouring
@@ -1248,7 +1268,9 @@ __global__ __launch_bounds__(BLOCK) void k_level_scatter(const Seg *__restrict__
     }
   }
   const uint32_t g = group_prefix[s] + tl / GROUP_TILES;
-  S.goff[threadIdx.x] = (uint64_t)gsum[(uint64_t)g * 256 + threadIdx.x] + tile_hist[(uint64_t)tile * 256 + threadIdx.x];
+  if (threadIdx.x < 256)
+    S.goff[threadIdx.x] =
+        (uint64_t)gsum[(uint64_t)g * 256 + threadIdx.x] + tile_hist[(uint64_t)tile * 256 + threadIdx.x];
   tile_scatter(S, kr, hr, dig, m, d, Ko, Ho);
   if (!PERSIST) break;
   }
@@ -1591,17 +1613,19 @@ thread_local int g_timing = 0;
 
 // The instantiation a build uses (see the tuning constants).
 struct Tuning {
-  uint32_t tile_items;   // 6 or 8 suffixes per thread in a level tile
+  uint32_t tile_items;   // 6, 8 or 16 suffixes per 256 threads' thread in a level tile (16: 8 waves x 8)
   uint32_t chunk_items;  // 3, 6 or 8 suffixes per lane in a chunk
   uint32_t tile_len() const { return BLOCK * tile_items; }
   uint32_t chunk() const { return LOCAL_WG * chunk_items; }
 };
 thread_local Tuning g_tuning{8, 6};
 
-// the histogram kernels hold at most MAX_TILE_ITEMS items per thread
-static_assert(MAX_TILE_ITEMS == 8, "tile choices are 6 and 8 items per thread");
+// tile_items 16 is the wide tile: 8 waves x 8 items (4096 suffixes); the
+// histogram kernels take it as two sub-tiles of BLOCK * MAX_TILE_ITEMS
+static_assert(BLOCK * MAX_TILE_ITEMS * 2 == 4096, "a wide tile is two histogram sub-tiles");
 bool tuning_ok(uint32_t tile_items, uint32_t chunk_items) {
-  return (tile_items == 6 || tile_items == 8) && (chunk_items == 3 || chunk_items == 6 || chunk_items == 8);
+  return (tile_items == 6 || tile_items == 8 || tile_items == 16) &&
+         (chunk_items == 3 || chunk_items == 6 || chunk_items == 8);
 }
 
 inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
@@ -1830,6 +1854,7 @@ constexpr unsigned PG_HIST = 256 * 8;
 constexpr unsigned PG_GROUP = 256 * 4;
 constexpr unsigned PG_SCAN = 256 * 4;
 constexpr unsigned PG_SCATTER = 256 * 5;
+constexpr unsigned PG_SCATTER_WIDE = 256 * 2;
 constexpr unsigned PG_EMIT = 256 * 4;
 constexpr unsigned PG_FILL = 256 * 2;
 
@@ -1958,14 +1983,18 @@ int launch_level_kernels(const Buffers &B, const Tuning &tu, const Lists &Ls, ui
                          uint32_t ntiles, uint32_t ngroups, const uint32_t *dev_nsg, PhaseTimer &T, hipStream_t st) {
   const bool dev = dev_nsg != nullptr;
   T.begin();
-  if (dev)
-    k_level_hist<true><<<PG_HIST, BLOCK, 0, st>>>(B.segs, B.tile_prefix, nsg, dev_nsg, tu.tile_len(), B.keys0,
-                                                  B.keys1, B.hdl0, B.hdl1, B.text, nb, B.tile_hist, B.seg_or,
-                                                  B.seg_and);
-  else
-    k_level_hist<false><<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, nsg, nullptr, tu.tile_len(), B.keys0,
-                                                  B.keys1, B.hdl0, B.hdl1, B.text, nb, B.tile_hist, B.seg_or,
-                                                  B.seg_and);
+#define CX_HIST(P, SUBT)                                                                                         \
+  k_level_hist<P, SUBT><<<P ? PG_HIST : ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, nsg, dev_nsg, tu.tile_len(), \
+                                                                B.keys0, B.keys1, B.hdl0, B.hdl1, B.text, nb,        \
+                                                                B.tile_hist, B.seg_or, B.seg_and)
+  if (tu.tile_items == 16) {
+    if (dev) CX_HIST(true, 2);
+    else CX_HIST(false, 2);
+  } else {
+    if (dev) CX_HIST(true, 1);
+    else CX_HIST(false, 1);
+  }
+#undef CX_HIST
   CX_LAUNCHED();
   T.end(PH_HIST);
   T.begin();
@@ -1978,16 +2007,19 @@ int launch_level_kernels(const Buffers &B, const Tuning &tu, const Lists &Ls, ui
   CX_LAUNCHED();
   T.end(PH_SCAN);
   T.begin();
-#define CX_SCATTER(TI, P)                                                                                       \
-  k_level_scatter<TI, P><<<P ? PG_SCATTER : ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, B.group_prefix, nsg,  \
-                                                                    dev_nsg, B.seg_split, B.tile_hist, B.gsum,   \
-                                                                    B.keys0, B.keys1, B.hdl0, B.hdl1)
-  if (tu.tile_items == 8) {
-    if (dev) CX_SCATTER(8, true);
-    else CX_SCATTER(8, false);
+#define CX_SCATTER(TI, NW, P)                                                                                   \
+  k_level_scatter<TI, NW, P><<<P ? (NW == 8 ? PG_SCATTER_WIDE : PG_SCATTER) : ntiles, 64 * NW, 0, st>>>(         \
+      B.segs, B.tile_prefix, B.group_prefix, nsg, dev_nsg, B.seg_split, B.tile_hist, B.gsum, B.keys0, B.keys1,    \
+      B.hdl0, B.hdl1)
+  if (tu.tile_items == 16) {
+    if (dev) CX_SCATTER(8, 8, true);
+    else CX_SCATTER(8, 8, false);
+  } else if (tu.tile_items == 8) {
+    if (dev) CX_SCATTER(8, 4, true);
+    else CX_SCATTER(8, 4, false);
   } else {
-    if (dev) CX_SCATTER(6, true);
-    else CX_SCATTER(6, false);
+    if (dev) CX_SCATTER(6, 4, true);
+    else CX_SCATTER(6, 4, false);
   }
 #undef CX_SCATTER
   CX_LAUNCHED();
@@ -2288,7 +2320,10 @@ int enqueue_body(const Build &b, const Level1Src &src, uint32_t device_levels, P
     const uint32_t ns = src.big.ns, ntiles = src.big.ntiles, ngroups = src.big.ngroups;
     if ((rc = upload_src(B, Lo, src.big, st))) return rc;
     T.begin();
-    k_gen_hist<<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, ns, b.tile_len, B.text, nb, B.tile_hist);
+    if (b.tu.tile_items == 16)
+      k_gen_hist<2><<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, ns, b.tile_len, B.text, nb, B.tile_hist);
+    else
+      k_gen_hist<1><<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, ns, b.tile_len, B.text, nb, B.tile_hist);
     CX_LAUNCHED();
     T.end(PH_GEN);
     T.begin();
@@ -2298,12 +2333,13 @@ int enqueue_body(const Build &b, const Level1Src &src, uint32_t device_levels, P
     CX_LAUNCHED();
     T.end(PH_SCAN);
     T.begin();
-    if (b.tu.tile_items == 8)
-      k_gen_scatter<8><<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, B.group_prefix, ns, B.text, nb, B.tile_hist,
-                                                 B.gsum, B.keys1, B.hdl1);
-    else
-      k_gen_scatter<6><<<ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, B.group_prefix, ns, B.text, nb, B.tile_hist,
-                                                 B.gsum, B.keys1, B.hdl1);
+#define CX_GEN_SCATTER(TI, NW)                                                                                    \
+  k_gen_scatter<TI, NW><<<ntiles, 64 * NW, 0, st>>>(B.segs, B.tile_prefix, B.group_prefix, ns, B.text, nb,         \
+                                                    B.tile_hist, B.gsum, B.keys1, B.hdl1)
+    if (b.tu.tile_items == 16) CX_GEN_SCATTER(8, 8);
+    else if (b.tu.tile_items == 8) CX_GEN_SCATTER(8, 4);
+    else CX_GEN_SCATTER(6, 4);
+#undef CX_GEN_SCATTER
     CX_LAUNCHED();
     T.end(PH_SCATTER);
     if (device_levels == 0) {

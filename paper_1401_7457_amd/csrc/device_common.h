@@ -138,7 +138,8 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
   return v;
 }
 
-// Exclusive prefix sum of one value per thread over the workgroup.
+// Exclusive prefix sum of one value per thread over a workgroup of NW waves.
+template <int NW = WAVES>
 __device__ __forceinline__ uint32_t block_excl_sum(uint32_t v, uint32_t *tmp, uint32_t *total) {
   const uint32_t inc = wave_incl_sum(v);
   const int w = threadIdx.x >> 6;
@@ -146,7 +147,7 @@ __device__ __forceinline__ uint32_t block_excl_sum(uint32_t v, uint32_t *tmp, ui
   __syncthreads();
   uint32_t pre = 0, tot = 0;
 #pragma unroll
-  for (int i = 0; i < WAVES; ++i) {
+  for (int i = 0; i < NW; ++i) {
     const uint32_t x = tmp[i];
     if (i < w) pre += x;
     tot += x;
@@ -195,16 +196,18 @@ __device__ __forceinline__ uint32_t item_index(int i) {
   return (uint32_t)((threadIdx.x >> 6) * (64 * NI) + i * 64) + lane_id();
 }
 
-// Stable 256-way split of up to BLOCK*NI items held in registers (layout of
-// item_index<NI>).  On return pos[i] is the destination of item i in
-// [0, count) and dstart[d] the first destination of digit d.  dig[i] ==
-// NODIGIT marks an absent item.  Ranks inside a wave come from ballot-matched
-// peer masks; waves are ordered by a digit-major scan of per-wave counts.
-template <int NI>
+// Stable 256-way split of up to 64*NW*NI items held in registers by a
+// workgroup of NW waves (layout of item_index<NI>).  On return pos[i] is the
+// destination of item i in [0, count) and dstart[d] the first destination of
+// digit d.  dig[i] == NODIGIT marks an absent item.  Ranks inside a wave come
+// from ballot-matched peer masks; waves are ordered by a digit-major scan of
+// per-wave counts (wcount holds NW * 256 counters, tmp NW words).
+template <int NI, int NW = WAVES>
 __device__ __forceinline__ void block_multisplit(const uint32_t (&dig)[NI], uint32_t (&pos)[NI], uint32_t *wcount,
                                                  uint32_t *dstart, uint32_t *tmp) {
+  static_assert(NW >= 4, "one digit per thread of the first four waves");
   const int w = threadIdx.x >> 6;
-  for (int x = threadIdx.x; x < WAVES * 256; x += BLOCK) wcount[x] = 0;
+  for (int x = threadIdx.x; x < NW * 256; x += NW * 64) wcount[x] = 0;
   __syncthreads();
   uint32_t *wc = wcount + w * 256;
   const uint64_t lt = lanemask_lt();
@@ -226,22 +229,24 @@ __device__ __forceinline__ void block_multisplit(const uint32_t (&dig)[NI], uint
     }
   }
   __syncthreads();
-  const uint32_t d = threadIdx.x;  // one digit per thread (BLOCK == 256)
+  const uint32_t d = threadIdx.x;  // one digit per thread of the first 256
   uint32_t run = 0;
+  if (d < 256) {
 #pragma unroll
-  for (int ww = 0; ww < WAVES; ++ww) {
-    const uint32_t c = wcount[ww * 256 + d];
-    wcount[ww * 256 + d] = run;
-    run += c;
+    for (int ww = 0; ww < NW; ++ww) {
+      const uint32_t c = wcount[ww * 256 + d];
+      wcount[ww * 256 + d] = run;
+      run += c;
+    }
   }
-  const uint32_t ex = block_excl_sum(run, tmp, nullptr);
-  dstart[d] = ex;
+  const uint32_t ex = block_excl_sum<NW>(run, tmp, nullptr);
+  if (d < 256) dstart[d] = ex;
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < NI; ++i)
     if (dig[i] != NODIGIT) pos[i] += dstart[dig[i]] + wc[dig[i]];
 }
 
-static_assert(BLOCK == 256, "block_multisplit assigns one digit per thread");
+static_assert(BLOCK == 256, "a default workgroup holds one thread per digit");
 
 }  // namespace cxk

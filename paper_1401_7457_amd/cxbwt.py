@@ -28,7 +28,7 @@ ABI_FUNCTIONS = ("cxbwt_packed_words", "cxbwt_pack", "cxbwt_workspace_bytes", "c
 
 # kernel instantiations the library holds: (suffixes per thread in a level
 # tile, suffixes per lane in a chunk); the first is the default
-TUNING_CHOICES = ((8, 6), (8, 8), (8, 3), (6, 6), (6, 8), (6, 3))
+TUNING_CHOICES = ((8, 6), (8, 8), (8, 3), (6, 6), (6, 8), (6, 3), (16, 6), (16, 8), (16, 3))
 
 # kernel classes of cxbwt_stats.ms / launches
 KERNEL_CLASSES = ("prep", "gen", "level_hist", "level_scan", "level_scatter", "local", "final_emit", "unused")

@@ -112,7 +112,7 @@ def test_tuning_choices_set_and_get_without_gpu():
         for ch in cxbwt.TUNING_CHOICES:
             cxbwt.set_tuning(*ch)
             assert cxbwt.get_tuning() == ch
-        for bad in ((0, 8), (16, 8), (12, 8), (8, 2), (8, 4), (8, 16), (7, 6)):
+        for bad in ((0, 8), (32, 8), (12, 8), (8, 2), (8, 4), (8, 16), (7, 6), (16, 16)):
             with pytest.raises(cxbwt.CxbwtError):
                 cxbwt.set_tuning(*bad)
         assert cxbwt.get_tuning() == cxbwt.TUNING_CHOICES[-1]

@@ -191,3 +191,24 @@ def test_changed_collection_bases_are_refused():
         assert e.value.status == cxbwt.EINVAL
     finally:
         g.close()
+
+
+@pytest.mark.parametrize("choice", [(16, 6), (6, 3), (16, 8)])
+def test_replay_with_other_instantiations(choice):
+    """The wide tile and the smallest tile and chunk inside a graph (persistent
+    forms of their kernels), including the host's completion (levels=2)."""
+    old = cxbwt.get_tuning()
+    rng = np.random.default_rng(61)
+    c = datagen.sample_reads(rng, datagen.random_genome(rng, 30_000), 9000, rng.integers(40, 151, size=9000), 0.005)
+    try:
+        cxbwt.set_tuning(*choice)
+        for levels in (0, 2):
+            packed, o_dev = _device_inputs(c.text, c.offsets)
+            _say(f"instantiation {choice}, levels={levels}: capture")
+            g = cxbwt.BuildGraph(packed, o_dev, c.n_reads, c.n_bases, c.max_read_len, levels=levels)
+            try:
+                _replay(g, f"instantiation {choice}, levels={levels}", c.text, c.offsets)
+            finally:
+                g.close()
+    finally:
+        cxbwt.set_tuning(*old)
