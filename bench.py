@@ -296,6 +296,8 @@ def main() -> int:
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (it times every kernel instantiation on the workload before warm-up)")
     ap.add_argument("--tuning", default=None, help="force one instantiation, e.g. 8x6 (no autotuner)")
+    ap.add_argument("--graph", action="store_true",
+                    help="plain: also time replays of the build captured in a hipGraph (reported beside the line)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one device copy of this size (for counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -393,6 +395,33 @@ def main() -> int:
             per_launch[kname] = stats["launches"][kname]
     cxbwt.set_timing(False)
     torch.cuda.synchronize()
+    # the same build captured once in a hipGraph (levels sized and scheduled
+    # on the device, as many as the eager build ran) and replayed: untimed
+    # capture, then the same number of timed steps
+    graph = None
+    if args.graph:
+        g = cxbwt.BuildGraph(packed, offsets, n, nb, maxlen, levels=stats["levels"], workspace=ws)
+
+        def gstep():
+            cxbwt.pack(text, out=packed, status=pstatus)
+            g.run()
+
+        for _ in range(max(1, args.warmup)):
+            gstep()
+        torch.cuda.synchronize()
+        same = bool(torch.equal(g.bwt, bwt) and torch.equal(g.term, term))
+        e2 = torch.cuda.Event(enable_timing=True)
+        e3 = torch.cuda.Event(enable_timing=True)
+        e2.record(stream)
+        for _ in range(args.steps):
+            gstep()
+        e3.record(stream)
+        torch.cuda.synchronize()
+        gms = e2.elapsed_time(e3) / args.steps
+        graph = {"ms_per_step": gms, "gbases_per_s": nb / (gms / 1e3) / 1e9, "levels_scheduled": stats["levels"],
+                 "equals_eager_build": same}
+        g.close()
+
     model = algorithmic_bytes(stats, n, nb)
     dom = max(per_ms, key=per_ms.get)
     dom_ms = per_ms[dom]
@@ -427,6 +456,8 @@ def main() -> int:
         "build_stats": {kk: v for kk, v in stats.items() if kk not in ("ms", "launches")},
         "wall_s_timed": wall,
     }
+    if graph is not None:
+        result["graph_replay"] = graph
     if not args.no_cpu_baseline:
         threads = len(os.sched_getaffinity(0))
         print(f"[bench] cpu baseline: oracle on {threads} threads", file=sys.stderr, flush=True)

@@ -176,9 +176,11 @@ int cxbwt_build_batch(const uint64_t *packed, const uint64_t *offsets, uint64_t 
  *                 0 = enough for any input of max_read_len (8 per 27-base
  *                 window, plus 2).  Each scheduled level that finds no work
  *                 costs a few empty launches.
- *   stream        the caller's stream: creation first runs a short eager
- *                 pass on it (offset validation, collection bases) and waits;
- *                 the capture itself uses a stream of its own.
+ *   stream        the caller's stream: creation first runs one eager build
+ *                 on it (it writes bwt and term_pos) and waits; the counts
+ *                 each of its levels saw size the captured launches (larger
+ *                 counts on a replay still run, looping).  The capture itself
+ *                 uses a stream of its own.
  *   out           (host, out) the plan, or NULL on error.
  * The graph binds every pointer given here.  A replay is valid while the
  * buffers keep these sizes and every collection keeps its number of bases;

@@ -1418,13 +1418,14 @@ __global__ __launch_bounds__(LOCAL_WG, OCC) void k_local(
     const uint32_t *__restrict__ hdl0, const uint32_t *__restrict__ hdl1, const TextRec *__restrict__ text,
     const uint32_t *__restrict__ srank, const CollMap *__restrict__ cmap, uint64_t nb, uint32_t rmax,
     uint8_t *__restrict__ bwt, uint64_t *__restrict__ start_row, uint32_t *status, unsigned long long *fetches,
-    uint32_t n_chunks, const uint32_t *__restrict__ dev_nchunks) {
+    uint32_t n_chunks, const uint32_t *__restrict__ dev_nchunks, uint32_t first) {
   __shared__ LocalSmem<LI> S;
   const uint32_t lane = threadIdx.x;
   const uint64_t le = lanemask_lt() | (1ull << lane);
-  n_chunks = PERSIST ? *dev_nchunks : blockIdx.x + 1;
+  // chunks first + blockIdx.x (+ k * gridDim.x when PERSIST) below the count
+  if (dev_nchunks) n_chunks = *dev_nchunks;
   uint32_t nfetch = 0;
-  for (uint32_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
+  for (uint32_t c = first + blockIdx.x; c < n_chunks; c += gridDim.x) {
   if (PERSIST) __syncthreads();  // the previous chunk's LDS reads are done
   const Seg ch = chunks[c];
   const uint32_t m = (uint32_t)ch.len;
@@ -1863,9 +1864,9 @@ constexpr unsigned PG_FILL = 256 * 2;
 // dev_ns the count is on the device and the launch is the fixed one of a
 // wave per segment.
 void launch_level_scan(const Buffers &B, uint32_t ns, uint32_t ngroups, const Lists &Ls, int force_split,
-                       hipStream_t st, const uint32_t *dev_ns = nullptr) {
+                       hipStream_t st, const uint32_t *dev_ns = nullptr, unsigned dev_grid = PG_SCAN) {
   if (dev_ns)
-    k_level_scan<false, true><<<PG_SCAN, BLOCK, 0, st>>>(B.segs, B.group_prefix, 0, B.gsum, B.seg_or, B.seg_and,
+    k_level_scan<false, true><<<dev_grid, BLOCK, 0, st>>>(B.segs, B.group_prefix, 0, B.gsum, B.seg_or, B.seg_and,
                                                    B.seg_split, Ls, force_split, dev_ns);
   else if (ngroups > 8u * ns)
     k_level_scan<true, false><<<ns, BLOCK, 0, st>>>(B.segs, B.group_prefix, ns, B.gsum, B.seg_or, B.seg_and, B.seg_split,
@@ -1923,23 +1924,63 @@ int read_level(const Buffers &B, LevelOut &o, PhaseTimer &T, hipStream_t st) {
   return o.status ? CXBWT_EDEVICE : CXBWT_OK;
 }
 
+// Work counts of one level as an eager build saw them (level 1 at index 0).
+// A captured build sizes its launches from them, so that each workgroup
+// usually takes one item as in an eager launch (the looping kernels stay
+// correct for larger counts).
+struct LevelShape {
+  uint32_t nsegs = 0, ntiles = 0, ngroups = 0, nchunks = 0, nfinals = 0, ftiles = 0;
+};
+thread_local std::vector<LevelShape> *g_shapes = nullptr;  // recorder of an eager build, when set
+
+void record_shape(uint32_t level, const LevelShape &x) {
+  if (!g_shapes) return;
+  if (g_shapes->size() <= level) g_shapes->resize(level + 1);
+  LevelShape &y = (*g_shapes)[level];
+  y.nsegs = std::max(y.nsegs, x.nsegs);
+  y.ntiles = std::max(y.ntiles, x.ntiles);
+  y.ngroups = std::max(y.ngroups, x.ngroups);
+  y.nchunks = std::max(y.nchunks, x.nchunks);
+  y.nfinals = std::max(y.nfinals, x.nfinals);
+  y.ftiles = std::max(y.ftiles, x.ftiles);
+}
+
+// Launch size for an item count seen before: a quarter more, a multiple of
+// the XCD count, or the fixed size when nothing was seen.
+unsigned grid_from(uint32_t seen, unsigned fixed) {
+  if (!seen) return fixed;
+  const uint64_t g = ((uint64_t)seen + seen / 4 + 64 + 7) & ~7ull;
+  return (unsigned)std::min<uint64_t>(g, 0x7FFFFFF8ull);
+}
+
 // The chunk kernel for the selected chunk size: one workgroup per chunk, or
-// with dev_nchunks a fixed launch of a few waves per SIMD over a count on
-// the device.
+// with dev_nchunks a launch of `grid` workgroups (0: a few waves per SIMD)
+// looping over a count on the device.
 int launch_local(const Buffers &B, const Tuning &tu, uint64_t nb, uint32_t rmax, uint8_t *bwt, uint32_t n_chunks,
-                 const uint32_t *dev_nchunks, hipStream_t st) {
+                 const uint32_t *dev_nchunks, hipStream_t st, unsigned grid = 0) {
   // the looping form holds a few more registers: one wave per SIMD fewer
   // for the smallest chunk keeps it from spilling
+  // with a device count and a grid: the one-chunk form over the first
+  // `grid` chunks, then the looping form over any beyond them
 #define CX_LOCAL(LI, OCC, OCCP)                                                                                  \
   do {                                                                                                           \
-    if (dev_nchunks)                                                                                             \
+    if (dev_nchunks && grid) {                                                                                   \
+      k_local<LI, OCC, false><<<grid, LOCAL_WG, 0, st>>>(B.chunks, B.keys0, B.keys1, B.hdl0, B.hdl1, B.text,      \
+                                                        B.srank, B.cmap, nb, rmax, bwt, B.start_row,             \
+                                                        B.counters + C_STATUS, B.stats, 0, dev_nchunks, 0);      \
+      k_local<LI, OCCP, true><<<256u, LOCAL_WG, 0, st>>>(B.chunks, B.keys0, B.keys1, B.hdl0, B.hdl1, B.text,      \
+                                                        B.srank, B.cmap, nb, rmax, bwt, B.start_row,             \
+                                                        B.counters + C_STATUS, B.stats, 0, dev_nchunks, grid);   \
+    } else if (dev_nchunks) {                                                                                    \
       k_local<LI, OCCP, true><<<256u * 4u * OCCP, LOCAL_WG, 0, st>>>(                                            \
           B.chunks, B.keys0, B.keys1, B.hdl0, B.hdl1, B.text, B.srank, B.cmap, nb, rmax, bwt, B.start_row,      \
-          B.counters + C_STATUS, B.stats, 0, dev_nchunks);                                                       \
-    else                                                                                                         \
+          B.counters + C_STATUS, B.stats, 0, dev_nchunks, 0);                                                    \
+    } else {                                                                                                     \
       k_local<LI, OCC, false><<<n_chunks, LOCAL_WG, 0, st>>>(B.chunks, B.keys0, B.keys1, B.hdl0, B.hdl1, B.text, \
                                                             B.srank, B.cmap, nb, rmax, bwt, B.start_row,         \
-                                                            B.counters + C_STATUS, B.stats, n_chunks, nullptr);  \
+                                                            B.counters + C_STATUS, B.stats, n_chunks, nullptr,   \
+                                                            0);                                                  \
+    }                                                                                                            \
   } while (0)
   if (tu.chunk_items == 8) CX_LOCAL(8, 3, 3);
   else if (tu.chunk_items == 6) CX_LOCAL(6, 4, 4);
@@ -1980,11 +2021,18 @@ int finish_level(const Buffers &B, const Layout &Lo, const Tuning &tu, uint64_t 
 // (ntiles tiles, ngroups groups), or with dev_nsg over a segment count on
 // the device in launches of fixed size.
 int launch_level_kernels(const Buffers &B, const Tuning &tu, const Lists &Ls, uint64_t nb, uint32_t nsg,
-                         uint32_t ntiles, uint32_t ngroups, const uint32_t *dev_nsg, PhaseTimer &T, hipStream_t st) {
+                         uint32_t ntiles, uint32_t ngroups, const uint32_t *dev_nsg, PhaseTimer &T, hipStream_t st,
+                         const LevelShape *seen = nullptr) {
   const bool dev = dev_nsg != nullptr;
+  // device mode: launch sizes from the counts seen, else fixed
+  const LevelShape none;
+  const LevelShape &sh = seen ? *seen : none;
+  const unsigned g_hist = grid_from(sh.ntiles, PG_HIST), g_group = grid_from(sh.ngroups, PG_GROUP),
+                 g_scan = grid_from((sh.nsegs + WAVES - 1) / WAVES, PG_SCAN),
+                 g_scatter = grid_from(sh.ntiles, tu.tile_items == 16 ? PG_SCATTER_WIDE : PG_SCATTER);
   T.begin();
 #define CX_HIST(P, SUBT)                                                                                         \
-  k_level_hist<P, SUBT><<<P ? PG_HIST : ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, nsg, dev_nsg, tu.tile_len(), \
+  k_level_hist<P, SUBT><<<P ? g_hist : ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, nsg, dev_nsg, tu.tile_len(),  \
                                                                 B.keys0, B.keys1, B.hdl0, B.hdl1, B.text, nb,        \
                                                                 B.tile_hist, B.seg_or, B.seg_and)
   if (tu.tile_items == 16) {
@@ -1999,16 +2047,16 @@ int launch_level_kernels(const Buffers &B, const Tuning &tu, const Lists &Ls, ui
   T.end(PH_HIST);
   T.begin();
   if (dev)
-    k_group_scan<true><<<PG_GROUP, BLOCK, 0, st>>>(B.tile_prefix, B.group_prefix, nsg, dev_nsg, B.tile_hist, B.gsum);
+    k_group_scan<true><<<g_group, BLOCK, 0, st>>>(B.tile_prefix, B.group_prefix, nsg, dev_nsg, B.tile_hist, B.gsum);
   else
     k_group_scan<false><<<ngroups, BLOCK, 0, st>>>(B.tile_prefix, B.group_prefix, nsg, nullptr, B.tile_hist, B.gsum);
   CX_LAUNCHED();
-  launch_level_scan(B, nsg, ngroups, Ls, 0, st, dev_nsg);
+  launch_level_scan(B, nsg, ngroups, Ls, 0, st, dev_nsg, g_scan);
   CX_LAUNCHED();
   T.end(PH_SCAN);
   T.begin();
 #define CX_SCATTER(TI, NW, P)                                                                                   \
-  k_level_scatter<TI, NW, P><<<P ? (NW == 8 ? PG_SCATTER_WIDE : PG_SCATTER) : ntiles, 64 * NW, 0, st>>>(         \
+  k_level_scatter<TI, NW, P><<<P ? g_scatter : ntiles, 64 * NW, 0, st>>>(                                       \
       B.segs, B.tile_prefix, B.group_prefix, nsg, dev_nsg, B.seg_split, B.tile_hist, B.gsum, B.keys0, B.keys1,    \
       B.hdl0, B.hdl1)
   if (tu.tile_items == 16) {
@@ -2205,13 +2253,13 @@ int upload_src(const Buffers &B, const Layout &Lo, const SegSrc &s, hipStream_t 
 }
 
 // The final groups of the current level, with their count on the device.
-int finish_finals_dev(const Build &b, hipStream_t st) {
+int finish_finals_dev(const Build &b, hipStream_t st, unsigned emit_grid = PG_EMIT) {
   const Buffers &B = b.B;
   int rc;
   if ((rc = prefix_list(B, B.finals, (uint32_t)b.Lo.cap_finals, b.tile_len, nullptr, B.tile_prefix, nullptr, st,
                         B.counters + C_NFINAL)))
     return rc;
-  k_emit_final<true><<<PG_EMIT, BLOCK, 0, st>>>(B.finals, B.tile_prefix, 0, B.counters + C_NFINAL, b.tile_len, B.keys0,
+  k_emit_final<true><<<emit_grid, BLOCK, 0, st>>>(B.finals, B.tile_prefix, 0, B.counters + C_NFINAL, b.tile_len, B.keys0,
                                           B.keys1, B.hdl0, B.hdl1, B.text, B.srank, B.cmap, b.bwt, B.start_row);
   CX_LAUNCHED();
   return CXBWT_OK;
@@ -2246,6 +2294,8 @@ int run_levels(const Build &b, LevelOut acc, uint32_t nbig, PhaseTimer &T, hipSt
       if ((rc = run_level_batch(B, Lo, b.tu, b.Ls, b.nb, b.rmax, b.bwt, nbig, (uint32_t)lt, (uint32_t)lg, o, T,
                                 st)))
         return rc;
+      record_shape(g_stats.levels - 1, LevelShape{nbig, (uint32_t)lt, (uint32_t)lg, o.n_chunks, o.n_finals,
+                                                  (uint32_t)o.final_tiles});
       acc = o;
     } else {
       big.resize(nbig);
@@ -2258,6 +2308,8 @@ int run_levels(const Build &b, LevelOut acc, uint32_t nbig, PhaseTimer &T, hipSt
         if ((rc = run_level_batch(B, Lo, b.tu, b.Ls, b.nb, b.rmax, b.bwt, (uint32_t)part.size(), ntiles, ngroups, o,
                                   T, st)))
           return rc;
+        record_shape(g_stats.levels - 1, LevelShape{(uint32_t)part.size(), ntiles, ngroups, o.n_chunks, o.n_finals,
+                                                    (uint32_t)o.final_tiles});
         acc.next_len += o.next_len;
         acc.next_regather += o.next_regather;
         acc.next_maxr = std::max(acc.next_maxr, o.next_maxr);
@@ -2277,7 +2329,8 @@ int run_levels(const Build &b, LevelOut acc, uint32_t nbig, PhaseTimer &T, hipSt
 // enqueued with their sizes read on the device (no host wait: the whole
 // sequence can be captured), followed by a last step that flags segments
 // left over.  Ends with term_pos.
-int enqueue_body(const Build &b, const Level1Src &src, uint32_t device_levels, PhaseTimer &T, hipStream_t st) {
+int enqueue_body(const Build &b, const Level1Src &src, uint32_t device_levels, PhaseTimer &T, hipStream_t st,
+                 const std::vector<LevelShape> *shapes = nullptr) {
   const Buffers &B = b.B;
   const Layout &Lo = b.Lo;
   uint32_t *counters = B.counters;
@@ -2345,19 +2398,25 @@ int enqueue_body(const Build &b, const Level1Src &src, uint32_t device_levels, P
     if (device_levels == 0) {
       LevelOut o{};
       if ((rc = read_level(B, o, T, st))) return rc;
+      record_shape(0, LevelShape{ns, ntiles, ngroups, o.n_chunks, o.n_finals, (uint32_t)o.final_tiles});
       if ((rc = finish_level(B, Lo, b.tu, nb, b.rmax, b.bwt, o.n_chunks, o.n_finals, o.final_tiles, o.final_len, T,
                              st)))
         return rc;
       if ((rc = run_levels(b, o, o.n_big, T, st))) return rc;
     } else {
       const uint32_t *ncur = counters + C_NCUR;
+      const LevelShape none;
+      auto seen = [&](uint32_t lv) -> const LevelShape & {
+        return shapes && lv < shapes->size() ? (*shapes)[lv] : none;
+      };
       for (uint32_t lv = 0;; ++lv) {
         // the level just scanned: fold, finish its chunks and final groups
         k_level_fold<<<1, 64, 0, st>>>(B.stats, (unsigned long long *)(counters + C_FOLD), counters + C_FLAGS);
         CX_LAUNCHED();
-        if ((rc = launch_local(B, b.tu, nb, b.rmax, b.bwt, (uint32_t)Lo.cap_chunks, counters + C_NCHUNK, st)))
+        if ((rc = launch_local(B, b.tu, nb, b.rmax, b.bwt, (uint32_t)Lo.cap_chunks, counters + C_NCHUNK, st,
+                               grid_from(seen(lv).nchunks, 0))))
           return rc;
-        if ((rc = finish_finals_dev(b, st))) return rc;
+        if ((rc = finish_finals_dev(b, st, grid_from(seen(lv).ftiles, PG_EMIT)))) return rc;
         const int last = lv == device_levels - 1;
         k_level_step<<<1, 64, 0, st>>>(counters, Lo.seg_slots, Lo.max_tiles, Lo.max_groups, last);
         CX_LAUNCHED();
@@ -2368,7 +2427,7 @@ int enqueue_body(const Build &b, const Level1Src &src, uint32_t device_levels, P
           return rc;
         k_fill_seg<<<PG_FILL, 256, 0, st>>>(B.seg_or, B.seg_and, ncur);
         CX_LAUNCHED();
-        if ((rc = launch_level_kernels(B, b.tu, b.Ls, nb, 0, 0, 0, ncur, T, st))) return rc;
+        if ((rc = launch_level_kernels(B, b.tu, b.Ls, nb, 0, 0, 0, ncur, T, st, &seen(lv + 1)))) return rc;
       }
     }
   }
@@ -2447,8 +2506,9 @@ struct GraphPlan {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   unsigned char *pinned = nullptr;  // host sources of the captured copies
-  uint32_t levels = 0;              // levels 2.. scheduled on the device
+  uint32_t levels = 0;              // levels scheduled on the device, level 1 included
   cxbwt_stats base{};               // statistics of level 1 (known on the host)
+  std::vector<LevelShape> shapes;   // per-level counts of the eager build made at creation
   ~GraphPlan() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -2459,16 +2519,25 @@ struct GraphPlan {
 int graph_capture(GraphPlan &P, hipStream_t st) {
   Build &b = P.b;
   PhaseTimer T{st, false, {}};
-  // eager pass: validate the offsets and learn the collection bases
+  // eager build: validates the offsets, learns the collection bases and
+  // records every level's counts, which size the captured launches
   int rc;
   if ((rc = enqueue_prep(b, b.coll_reads.data(), nullptr, T, st))) return rc;
   if ((rc = plan_level1(b, T, st))) return rc;
+  Level1Vectors v;
+  v.make(b);
   g_stats = cxbwt_stats{};
   level1_stats(b);
   P.base = g_stats;
+  P.shapes.clear();
+  g_shapes = &P.shapes;
+  rc = enqueue_body(b, v.src, 0, T, st);
+  g_shapes = nullptr;
+  uint32_t hc[C_COUNT];
+  if (!rc) rc = read_totals(b, T, st, hc);
+  if (rc) return rc;
+  if (hc[C_STATUS]) return CXBWT_EDEVICE;
   // pinned copies of everything the captured copies read
-  Level1Vectors v;
-  v.make(b);
   const size_t nc1 = (size_t)b.ncoll + 1;
   const size_t nbg = b.big.size(), nsm = b.small.size();
   size_t off = 0;
@@ -2503,7 +2572,7 @@ int graph_capture(GraphPlan &P, hipStream_t st) {
   // capture: every size below is fixed now or read on the device
   CX_CHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
   rc = enqueue_prep(b, (const uint64_t *)(h + o_cr), (const uint64_t *)(h + o_cb), T, st);
-  if (!rc) rc = enqueue_body(b, src, P.levels ? P.levels : 1, T, st);
+  if (!rc) rc = enqueue_body(b, src, P.levels ? P.levels : 1, T, st, &P.shapes);
   hipGraph_t g = nullptr;
   const hipError_t ec = hipStreamEndCapture(st, &g);
   if (rc) {

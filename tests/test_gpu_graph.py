@@ -212,3 +212,25 @@ def test_replay_with_other_instantiations(choice):
                 g.close()
     finally:
         cxbwt.set_tuning(*old)
+
+
+def test_replay_needing_far_more_work_than_captured():
+    """Captured on 6000 copies of one read (few chunks, large final groups),
+    replayed on reads of a genome of the same shape (many chunks and tiles):
+    the launches sized at capture loop over the extra work."""
+    rng = np.random.default_rng(71)
+    one = datagen.ASCII[rng.integers(0, 4, size=100)]
+    text_a = np.tile(one, 6000)
+    offsets = np.arange(0, text_a.size + 1, 100, dtype=np.uint64)
+    b = datagen.sample_reads(rng, datagen.random_genome(rng, 60_000), 6000, 100, 0.005)
+    assert np.array_equal(b.offsets, offsets)
+    packed, o_dev = _device_inputs(text_a, offsets)
+    _say("capture on identical reads")
+    g = cxbwt.BuildGraph(packed, o_dev, 6000, text_a.size, 100)
+    try:
+        for k, text in enumerate((b.text, text_a, b.text)):
+            _refill(g, text, offsets)
+            st = _replay(g, f"more work than captured, content {k}", text, offsets)
+            _say(f"content {k}: chunks={st['chunks']} final groups={st['final_big']}")
+    finally:
+        g.close()
