@@ -1471,8 +1471,11 @@ __global__ __launch_bounds__(LOCAL_WG, OCC) void k_local(
   bool fetch_round = false;
   for (;;) {
     // drop the finished groups: single suffixes, and (after the first sort)
-    // runs of equal keys that end inside the window, i.e. identical suffixes
-    live_groups(S, n, lane, le);
+    // runs of equal keys that end inside the window, i.e. identical suffixes.
+    // A group is a run of live entries from a head to the next head, so an
+    // entry is alone in its group when it and the next live entry are both
+    // heads; the other test is the same for every member of a group of
+    // equal keys, so whole groups stay or go.
     uint32_t kept = 0;
 #pragma unroll
     for (int i = 0; i < LI; ++i) {
@@ -1482,9 +1485,9 @@ __global__ __launch_bounds__(LOCAL_WG, OCC) void k_local(
       uint16_t pos = 0;
       if (x < n) {
         pos = S.live[x];
-        const uint32_t g = S.gr[x];
-        const uint32_t size = (uint32_t)S.hp[g + 1] - S.hp[g];
-        keep = size >= 2 && (!fetch_round || clamp_of(S.K[pos]) == (uint32_t)W);
+        // entry x + 1 is read before any slot writes an index above x
+        const bool alone = S.head[pos] && (x + 1 >= n || S.head[S.live[x + 1]]);
+        keep = !alone && (!fetch_round || clamp_of(S.K[pos]) == (uint32_t)W);
       }
       const uint64_t kb = __ballot(keep);
       // compaction moves entries down only, so slot i never overwrites an
