@@ -88,13 +88,22 @@ def measured_traffic(workload: str, kclass: str, launches_per_build: int, tuning
 
     None when no counter run exists for this workload, or when the kernel
     sources or the kernel instantiation (tuning, "AxB") differ from the run's.
+    The chunk kernel's work depends only on the chunk size (B): the level
+    tile (A) cuts the levels' tiles, not the buckets that become chunks, so
+    for that class only B has to match.
     """
     import json as _json
     path = os.path.join(ROOT, "profiles", f"{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     rec = _json.load(open(path))
-    if rec.get("kernel_sources_sha256_16") != kernel_sources_hash() or rec.get("tuning") != tuning:
+    if rec.get("kernel_sources_sha256_16") != kernel_sources_hash():
+        return None
+    run_tuning = rec.get("tuning") or ""
+    if kclass == "local":
+        if run_tuning.split("x")[-1] != tuning.split("x")[-1]:
+            return None
+    elif run_tuning != tuning:
         return None
     tot = 0.0
     for k in KERNELS_OF_CLASS.get(kclass, []):
