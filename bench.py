@@ -32,13 +32,13 @@ WORKLOADS = {
 }
 
 
-def algorithmic_bytes(stats: dict, n_reads: int, n_bases: int) -> dict:
+def algorithmic_bytes(stats: dict, n_reads: int, n_bases: int, tile_len: int = 2048) -> dict:
     """Bytes each kernel class must move, by the per-suffix model of the design.
 
     gen           0.375 B per base: read the 2-bit bases and the end bits
                   (level 1 counts keys computed from the reads)
     level_hist    8 B per suffix visit (key read) + 12 B per later-window re-key
-    level_scan    4 B per tile counter read and written (1 KB per 3072-suffix tile)
+    level_scan    4 B per tile counter read and written (1 KB per tile of tile_len suffixes)
     level_scatter level 1: 12.375 B per base (bases + end bits read, key + handle
                   written); later levels: 24 B per moved suffix (key + handle
                   read and written)
@@ -56,7 +56,7 @@ def algorithmic_bytes(stats: dict, n_reads: int, n_bases: int) -> dict:
         "prep": 17.0 * n_reads + 0.1875 * n_bases,
         "gen": 0.375 * n_bases,
         "level_hist": 8.0 * stats.get("level_suffixes", 0) - 8.0 * level1 + 12.0 * stats.get("regathered", 0),
-        "level_scan": 2.0 * 1024 * stats.get("level_suffixes", 0) / 3072,
+        "level_scan": 2.0 * 1024 * stats.get("level_suffixes", 0) / tile_len,
         "level_scatter": 12.375 * level1 + 24.0 * (scattered - level1),
         "local": 13.0 * cs + 16.0 * stats.get("window_fetches", 0) + 8.0 * n_reads,
         "final_emit": 13.0 * fin,
@@ -431,7 +431,7 @@ def main() -> int:
                  "equals_eager_build": same}
         g.close()
 
-    model = algorithmic_bytes(stats, n, nb)
+    model = algorithmic_bytes(stats, n, nb, tile_len=256 * cxbwt.get_tuning()[0])
     dom = max(per_ms, key=per_ms.get)
     dom_ms = per_ms[dom]
     achieved = model[dom] / (dom_ms / 1e3) / 1e9
