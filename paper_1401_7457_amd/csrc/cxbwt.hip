@@ -286,8 +286,16 @@ __global__ void k_prep(const uint64_t *__restrict__ packed, const uint64_t *__re
     return;
   }
   // row (i - first_read) of the collection, whose output starts at byte
-  // (bases before it) + (reads before it): byte offsets[first_read] + i
-  const uint64_t out = offsets[first_read] + i;
+  // (bases before it) + (reads before it): byte offsets[first_read] + i.
+  // Valid offsets never decrease, so the collection's first offset is at
+  // most a; checking it keeps every write in bounds when another read's
+  // offsets are the invalid ones.
+  const uint64_t ob = offsets[first_read];
+  if (ob > a) {
+    atomicOr(status, ST_BAD_OFFSETS);
+    return;
+  }
+  const uint64_t out = ob + i;
   if (i == n - 1) atomicOr(&sbits[nb >> 5], 1u << (nb & 31));  // end of the text
   if (b > a) {
     const uint64_t e = b - 1;
@@ -2196,6 +2204,28 @@ int enqueue_prep(const Build &b, const uint64_t *coll_reads_src, const uint64_t 
   return CXBWT_OK;
 }
 
+// Text records and the read-start ranks: they need the read-start bitmap
+// only, so they are enqueued before the host waits for the level-1 plan.
+int enqueue_records(const Build &b, PhaseTimer &T, hipStream_t st) {
+  const Buffers &B = b.B;
+  const Layout &Lo = b.Lo;
+  if (b.nb == 0) return CXBWT_OK;
+  uint32_t *sbits = B.tile_hist;
+  T.begin();
+  k_text_records<<<grid_for(Lo.n_rec, 256), 256, 0, st>>>(b.packed, cxbwt_packed_words(b.nb), sbits, B.text,
+                                                           Lo.n_rec);
+  CX_LAUNCHED();
+  k_rank_count<<<(unsigned)Lo.n_rank_blocks, BLOCK, 0, st>>>(sbits, Lo.n_rank_words, B.rank_blocks);
+  CX_LAUNCHED();
+  k_rank_top<<<1, BLOCK, 0, st>>>(B.rank_blocks, (uint32_t)Lo.n_rank_blocks);
+  CX_LAUNCHED();
+  k_rank_words<<<(unsigned)Lo.n_rank_blocks, BLOCK, 0, st>>>(sbits, Lo.n_rank_words, B.rank_blocks, B.srank,
+                                                              Lo.n_rec);
+  CX_LAUNCHED();
+  T.end(PH_PREP);
+  return CXBWT_OK;
+}
+
 // Reads the collection bases back and plans level 1: the collections above
 // one chunk are its segments, the others one unsplit chunk each.
 int plan_level1(Build &b, PhaseTimer &T, hipStream_t st) {
@@ -2341,19 +2371,6 @@ int enqueue_body(const Build &b, const Level1Src &src, uint32_t device_levels, P
   int rc;
   if (b.ncoll) CX_CHECK(hipMemcpyAsync(B.cmap, src.cm, sizeof(CollMap) * b.ncoll, hipMemcpyHostToDevice, st));
   if (nb == 0) return CXBWT_OK;
-  uint32_t *sbits = B.tile_hist;
-  T.begin();
-  k_text_records<<<grid_for(Lo.n_rec, 256), 256, 0, st>>>(b.packed, cxbwt_packed_words(nb), sbits, B.text,
-                                                           Lo.n_rec);
-  CX_LAUNCHED();
-  k_rank_count<<<(unsigned)Lo.n_rank_blocks, BLOCK, 0, st>>>(sbits, Lo.n_rank_words, B.rank_blocks);
-  CX_LAUNCHED();
-  k_rank_top<<<1, BLOCK, 0, st>>>(B.rank_blocks, (uint32_t)Lo.n_rank_blocks);
-  CX_LAUNCHED();
-  k_rank_words<<<(unsigned)Lo.n_rank_blocks, BLOCK, 0, st>>>(sbits, Lo.n_rank_words, B.rank_blocks, B.srank,
-                                                              Lo.n_rec);
-  CX_LAUNCHED();
-  T.end(PH_PREP);
 
   // collections that fit one chunk: keys in read order, one unsplit chunk each
   if (src.small.ns) {
@@ -2491,6 +2508,7 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
   build_init(b, packed, offsets, n, nb, maxlen, coll_reads, ncoll, bwt, term_pos, ws);
   int rc;
   if ((rc = enqueue_prep(b, b.coll_reads.data(), nullptr, T, st))) return rc;
+  if ((rc = enqueue_records(b, T, st))) return rc;
   if ((rc = plan_level1(b, T, st))) return rc;
   Level1Vectors v;
   v.make(b);
@@ -2526,6 +2544,7 @@ int graph_capture(GraphPlan &P, hipStream_t st) {
   // records every level's counts, which size the captured launches
   int rc;
   if ((rc = enqueue_prep(b, b.coll_reads.data(), nullptr, T, st))) return rc;
+  if ((rc = enqueue_records(b, T, st))) return rc;
   if ((rc = plan_level1(b, T, st))) return rc;
   Level1Vectors v;
   v.make(b);
@@ -2575,6 +2594,7 @@ int graph_capture(GraphPlan &P, hipStream_t st) {
   // capture: every size below is fixed now or read on the device
   CX_CHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
   rc = enqueue_prep(b, (const uint64_t *)(h + o_cr), (const uint64_t *)(h + o_cb), T, st);
+  if (!rc) rc = enqueue_records(b, T, st);
   if (!rc) rc = enqueue_body(b, src, P.levels ? P.levels : 1, T, st, &P.shapes);
   hipGraph_t g = nullptr;
   const hipError_t ec = hipStreamEndCapture(st, &g);

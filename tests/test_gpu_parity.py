@@ -175,7 +175,8 @@ def test_device_rejects_bad_offsets():
     import torch
     _say("bad offsets")
     text = np.frombuffer(b"ACGTACGT", np.uint8).copy()
-    for offs in ([0, 5, 3, 8], [1, 4, 8], [0, 4, 7]):
+    # huge first offsets too: a valid read must not take its output row from them
+    for offs in ([0, 5, 3, 8], [1, 4, 8], [0, 4, 7], [10**12, 4, 8], [0, 2**40, 8], [2**40, 2**40 + 4, 8]):
         t = torch.from_numpy(text).cuda()
         o = torch.tensor(offs, dtype=torch.int64, device="cuda")
         packed, _ = cxbwt.pack(t)
