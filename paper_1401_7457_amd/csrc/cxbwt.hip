@@ -400,13 +400,16 @@ __global__ __launch_bounds__(BLOCK) void k_rank_words(const uint32_t *__restrict
 }
 
 // term_pos of every non-empty read from the row its offset-0 suffix recorded.
-__global__ void k_term(const uint64_t *__restrict__ offsets, uint64_t n, const TextRec *__restrict__ text,
-                       const uint32_t *__restrict__ srank, const uint64_t *__restrict__ start_row,
-                       uint64_t *__restrict__ term_pos) {
+// (A replayed graph runs this even when k_prep found the offsets invalid:
+// reads that leave the text are skipped, and the result is then reported
+// as an error.)
+__global__ void k_term(const uint64_t *__restrict__ offsets, uint64_t n, uint64_t nb,
+                       const TextRec *__restrict__ text, const uint32_t *__restrict__ srank,
+                       const uint64_t *__restrict__ start_row, uint64_t *__restrict__ term_pos) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const uint64_t a = offsets[i], b = offsets[i + 1];
-  if (b > a) term_pos[i] = start_row[start_rank(text, srank, a)];
+  if (b > a && b <= nb) term_pos[i] = start_row[start_rank(text, srank, a)];
 }
 
 // ---------------------------------------------------------------------------
@@ -2452,7 +2455,7 @@ int enqueue_body(const Build &b, const Level1Src &src, uint32_t device_levels, P
     }
   }
   T.begin();
-  k_term<<<grid_for(b.n, 256), 256, 0, st>>>(b.offsets, b.n, B.text, B.srank, B.start_row, b.term_pos);
+  k_term<<<grid_for(b.n, 256), 256, 0, st>>>(b.offsets, b.n, b.nb, B.text, B.srank, B.start_row, b.term_pos);
   CX_LAUNCHED();
   T.end(PH_FINAL);
   return CXBWT_OK;
@@ -2640,7 +2643,8 @@ int graph_finish(GraphPlan &P, hipStream_t st) {
   acc.next_tiles = f[K_NEXT_TILES - K_LEVEL_FIRST];
   acc.next_groups = f[K_NEXT_GROUPS - K_LEVEL_FIRST];
   if ((rc = run_levels(b, acc, hc[C_NBIG], T, st))) return rc;
-  k_term<<<grid_for(b.n, 256), 256, 0, st>>>(b.offsets, b.n, b.B.text, b.B.srank, b.B.start_row, b.term_pos);
+  k_term<<<grid_for(b.n, 256), 256, 0, st>>>(b.offsets, b.n, b.nb, b.B.text, b.B.srank, b.B.start_row,
+                                              b.term_pos);
   CX_LAUNCHED();
   // the statistics block still holds the replay's counts: take the rest only
   g_stats.window_fetches = 0;

@@ -234,3 +234,24 @@ def test_replay_needing_far_more_work_than_captured():
             _say(f"content {k}: chunks={st['chunks']} final groups={st['final_big']}")
     finally:
         g.close()
+
+
+def test_replay_with_invalid_offsets_reports_edata_then_recovers():
+    """A replay whose offsets are invalid (a read end past the text) reports
+    CXBWT_EDATA; the next replay of valid offsets is exact again."""
+    rng = np.random.default_rng(81)
+    c = datagen.sample_reads(rng, datagen.random_genome(rng, 20_000), 3000, 80, 0.005)
+    packed, o_dev = _device_inputs(c.text, c.offsets)
+    g = cxbwt.BuildGraph(packed, o_dev, c.n_reads, c.n_bases, c.max_read_len)
+    try:
+        bad = c.offsets.copy()
+        bad[5] = np.uint64(2 ** 40)
+        _refill(g, c.text, bad)
+        _say("replay with an invalid offset")
+        with pytest.raises(cxbwt.CxbwtError) as e:
+            g.run()
+        assert e.value.status == cxbwt.EDATA
+        _refill(g, c.text, c.offsets)
+        _replay(g, "replay after the invalid one", c.text, c.offsets)
+    finally:
+        g.close()
