@@ -24,12 +24,17 @@
 //   * sort    = most-significant digit first.  Level 1 computes window-0 keys
 //               from the 2-bit reads and scatters them by their top 8 bits
 //               (keys are never stored unsorted); further 8-bit levels split
-//               every bucket larger than one workgroup's share (1024
-//               suffixes).  Runs of small buckets are then sorted on their
-//               remaining digits, tie-refined window by window and emitted
-//               inside one workgroup, in LDS.  A tie on a full window
-//               (clamped length 27) fetches the next window of the tied
-//               suffixes only, one aligned 16-byte text record each.
+//               every bucket larger than one chunk (64 x 3, 6 or 8 suffixes,
+//               the tuning's choice).  Runs of small buckets are then sorted
+//               on their remaining digits, tie-refined window by window and
+//               emitted by one wave, in LDS.  A tie on a full window (clamped
+//               length 27) fetches the next window of the tied suffixes only,
+//               one aligned 16-byte text record each.
+//   * levels  = each level's scan hands on the next level's segment list and
+//               its tile totals; the lists and their prefixes are built on the
+//               device, so the host reads one small counter block per level,
+//               and a build whose level kernels read their sizes on the
+//               device can be captured whole in a hipGraph.
 //
 // Every pass is stable and the initial order is read-major, so suffixes that
 // are equal through their terminators stay in read-index order (the stability
