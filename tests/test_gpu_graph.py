@@ -255,3 +255,31 @@ def test_replay_with_invalid_offsets_reports_edata_then_recovers():
         _replay(g, "replay after the invalid one", c.text, c.offsets)
     finally:
         g.close()
+
+
+@pytest.mark.parametrize("kind", ["all_small", "all_empty"])
+def test_graph_without_levels(kind):
+    """Graphs with no sort level: every collection fits one chunk, or every
+    read is empty (no suffix but the terminators)."""
+    import torch
+    rng = np.random.default_rng(91)
+    if kind == "all_small":
+        cols = [datagen.random_collection(rng, int(rng.integers(1, 6)), [0, 1, 5, 16, 27, 28]) for _ in range(7)]
+    else:
+        cols = [datagen.from_reads([""] * 5), datagen.from_reads([""] * 3)]
+    text, offsets, coll_reads, maxlen = cxbwt.concat_collections(cols)
+    n, nb = offsets.size - 1, int(offsets[-1])
+    packed, o_dev = _device_inputs(text, offsets)
+    _say(f"graph without levels ({kind}): {len(cols)} collections, {nb} bases")
+    g = cxbwt.BuildGraph(packed, o_dev, n, nb, maxlen, coll_reads=coll_reads)
+    try:
+        for rep in range(2):
+            b, t = g.run()
+            torch.cuda.synchronize()
+            outs = cxbwt.split_batch_output(b.cpu().numpy(), t.cpu().numpy().view(np.uint64), cols)
+            for i, (c, (bb, tt)) in enumerate(zip(cols, outs)):
+                eb, et = oracle.bwt(c.text, c.offsets)
+                assert np.array_equal(bb, eb), f"{kind} replay {rep}: collection {i} BWT differs"
+                assert np.array_equal(tt, et), f"{kind} replay {rep}: collection {i} term_pos differs"
+    finally:
+        g.close()
