@@ -105,6 +105,34 @@ def test_batch_argument_validation_needs_no_gpu():
     assert cxbwt.batch_workspace_bytes(4, 40, 10, 5) == 0
 
 
+def test_graph_argument_validation_needs_no_gpu():
+    """cxbwt_graph_* reject bad arguments before any HIP call."""
+    L = cxbwt.lib()
+    fake = ctypes.c_void_p(0x1000)
+    null = ctypes.c_void_p(0)
+
+    def create(coll, n=4, nb=40, wsb=1 << 40, ws=fake, packed=fake, out=True):
+        h = ctypes.c_void_p(0x1234)
+        arr = (ctypes.c_uint64 * len(coll))(*coll) if coll is not None else None
+        ncoll = len(coll) - 1 if coll is not None else 1
+        rc = L.cxbwt_graph_create(packed, fake, n, nb, 10, arr, ncoll, fake, fake, ws, wsb, 0, null,
+                                  ctypes.byref(h) if out else None)
+        return rc, h.value
+
+    rc, h = create([0, 2, 4], packed=null)
+    assert rc == cxbwt.EINVAL and h is None       # null input; *out cleared
+    assert create([0, 2, 3])[0] == cxbwt.EINVAL   # does not end at n_reads
+    assert create([0, 2, 2, 4])[0] == cxbwt.EINVAL  # empty collection
+    assert create([0, 2, 4], wsb=10)[0] == cxbwt.ENOMEM
+    assert create([0, 2, 4], ws=ctypes.c_void_p(0x1001))[0] == cxbwt.EINVAL  # workspace not 256-aligned
+    assert create([0, 2, 4], nb=1 << 32)[0] == cxbwt.ERANGE
+    assert create(None, wsb=10)[0] == cxbwt.ENOMEM  # one collection when coll_reads is NULL
+    assert create([0, 2, 4], out=False)[0] == cxbwt.EINVAL
+    assert L.cxbwt_graph_launch(null, null) == cxbwt.EINVAL
+    assert L.cxbwt_graph_finish(null, null) == cxbwt.EINVAL
+    L.cxbwt_graph_destroy(null)  # ignored
+
+
 def test_tuning_choices_set_and_get_without_gpu():
     before = cxbwt.get_tuning()
     assert before == cxbwt.TUNING_CHOICES[0]
