@@ -794,6 +794,8 @@ __global__ __launch_bounds__(BLOCK) void k_level_scan(const Seg *__restrict__ se
   __shared__ uint32_t part[COOP ? WAVES : 1][256];
   __shared__ uint32_t cstart[CW][256];
   __shared__ uint32_t clen[CW][256];
+  __shared__ uint32_t wbv[CW][257];  // bucket starts of the classifying wave, then the segment length
+  __shared__ uint32_t wnx[CW][256];  // per bucket: end of a chunk starting there | next chunk start << 16
   __shared__ uint32_t wcnt[WAVES][3];
   __shared__ uint32_t wbase[WAVES][3];
   __shared__ uint32_t wstat[WAVES][K_LEVEL_KINDS];
@@ -905,24 +907,66 @@ __global__ __launch_bounds__(BLOCK) void k_level_scan(const Seg *__restrict__ se
       NZS[i] = __ballot(cv[i] != 0 && cv[i] <= C);
       BIG[i] = __ballot(cv[i] > C);
     }
-    // chunk walk: a chunk starts at a non-empty small bucket and takes the
+    // chunks: a chunk starts at a non-empty small bucket and takes the
     // following buckets while its size stays within C and no big bucket
-    // intervenes
+    // intervenes.  Every lane first finds, for its four buckets b, where a
+    // chunk starting at b would end (e: the first big bucket after b, or the
+    // first bucket that would take the size above C, by binary search on the
+    // bucket starts) and where the next chunk would start (the first
+    // non-empty small bucket at or after e); the walk over the chunk starts
+    // is then one LDS read per chunk.
+#pragma unroll
+    for (int i = 0; i < 4; ++i) wbv[cw][i * 64 + l] = bv[i];
+    if (l == 0) wbv[cw][256] = sg.len;
+    uint32_t big_after[4], nzs_after[4];  // first set bit in the words above word i
+    {
+      uint32_t fb = 256, fn = 256;
+#pragma unroll
+      for (int i = 3; i >= 0; --i) {
+        big_after[i] = fb;
+        nzs_after[i] = fn;
+        if (BIG[i]) fb = (uint32_t)i * 64 + (uint32_t)__builtin_ctzll(BIG[i]);
+        if (NZS[i]) fn = (uint32_t)i * 64 + (uint32_t)__builtin_ctzll(NZS[i]);
+      }
+    }
+    const uint64_t above = ~(lanemask_lt() | (1ull << l));  // lanes above this one
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t b = (uint32_t)i * 64 + l;
+      const uint32_t sb = bv[i];
+      // largest x >= b whose prefix bv[x] + cv[x] = wbv[x + 1] stays within
+      // sb + C (monotone in x); differences, so sb + C cannot wrap
+      uint32_t x = b;
+#pragma unroll
+      for (uint32_t step = 128; step > 0; step >>= 1) {
+        const uint32_t y = x + step;
+        if (y < 256 && wbv[cw][y + 1] - sb <= C) x = y;
+      }
+      const uint64_t mb = BIG[i] & above;
+      const uint32_t nbig = mb ? (uint32_t)i * 64 + (uint32_t)__builtin_ctzll(mb) : big_after[i];
+      const uint32_t e = min(x + 1, nbig);
+      uint32_t nxt = 256;
+      if (e < 256) {
+        const uint32_t w = e >> 6;
+        const uint64_t word = w == 0 ? NZS[0] : w == 1 ? NZS[1] : w == 2 ? NZS[2] : NZS[3];
+        const uint64_t m = word & (~0ull << (e & 63));
+        const uint32_t after = w == 0 ? nzs_after[0] : w == 1 ? nzs_after[1] : w == 2 ? nzs_after[2] : nzs_after[3];
+        nxt = m ? w * 64 + (uint32_t)__builtin_ctzll(m) : after;
+      }
+      wnx[cw][b] = e | (nxt << 16);
+    }
     uint32_t b = first_set_from(NZS, 0);
     while (b < 256) {
-      const uint32_t sb = bucket_at(bv, b);
-      // buckets below b wrap to large differences; the search starts at b + 1
-      uint64_t E[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) E[i] = __ballot(bv[i] + cv[i] - sb > C) | BIG[i];
-      const uint32_t e = first_set_from(E, b + 1);
-      const uint32_t se = e < 256 ? bucket_at(bv, e) : sg.len;
+      const uint32_t v = (uint32_t)__builtin_amdgcn_readfirstlane((int)wnx[cw][b]);
+      const uint32_t e = v & 0xFFFFu;
+      const uint32_t sb = (uint32_t)__builtin_amdgcn_readfirstlane((int)wbv[cw][b]);
+      const uint32_t se = (uint32_t)__builtin_amdgcn_readfirstlane((int)wbv[cw][e]);
       if (l == 0) {
         cstart[cw][nc] = sb;
         clen[cw][nc] = se - sb;
       }
       ++nc;
-      b = e < 256 ? first_set_from(NZS, e) : 256u;
+      b = v >> 16;
     }
     if (sg.d == 7) {
       // bucket value b is the clamped length; all ordering bits agree
