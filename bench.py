@@ -87,7 +87,8 @@ def measured_traffic(workload: str, kclass: str, launches_per_build: int, tuning
     """HBM bytes per launch of a kernel class from the committed counter runs.
 
     None when no counter run exists for this workload, or when the kernel
-    sources or the kernel instantiation (tuning, "AxB") differ from the run's.
+    sources differ from the runs' or no run used the kernel instantiation
+    (tuning, "AxB").
     The chunk kernel's work depends only on the chunk size (B): the level
     tile (A) cuts the levels' tiles, not the buckets that become chunks, so
     for that class only B has to match.
@@ -99,15 +100,21 @@ def measured_traffic(workload: str, kclass: str, launches_per_build: int, tuning
     rec = _json.load(open(path))
     if rec.get("kernel_sources_sha256_16") != kernel_sources_hash():
         return None
-    run_tuning = rec.get("tuning") or ""
-    if kclass == "local":
-        if run_tuning.split("x")[-1] != tuning.split("x")[-1]:
-            return None
-    elif run_tuning != tuning:
+    # the main run, then counter runs of other instantiations of the same sources
+    runs = [rec] + list(rec.get("other_tunings", []))
+
+    def matches(run_tuning: str) -> bool:
+        if kclass == "local":
+            return run_tuning.split("x")[-1] == tuning.split("x")[-1]
+        return run_tuning == tuning
+
+    run = next((r for r in runs if r.get("tuning") == tuning), None) \
+        or next((r for r in runs if matches(r.get("tuning") or "")), None)
+    if run is None:
         return None
     tot = 0.0
     for k in KERNELS_OF_CLASS.get(kclass, []):
-        e = rec["kernels"].get(k)
+        e = run["kernels"].get(k)
         if e:
             tot += (e["fetch_MB_per_dispatch"] + e["write_MB_per_dispatch"]) * 1e6 * e["dispatches_per_build"]
     return tot / max(1, launches_per_build) if tot else None

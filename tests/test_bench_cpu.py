@@ -51,6 +51,17 @@ def test_counter_runs_match_sources_and_instantiation(tmp_path, monkeypatch):
     # the scatters depend on both parts
     assert bench.measured_traffic("plain1", "level_scatter", 7, "8x3") == (6 * 40e6 + 54e6) / 7
     assert bench.measured_traffic("plain1", "level_scatter", 7, "16x3") is None
+    # counter runs of further instantiations of the same sources
+    rec["other_tunings"] = [{"tuning": "6x3", "kernels": {
+        "k_local": {"dispatches_per_build": 5, "fetch_MB_per_dispatch": 200.0, "write_MB_per_dispatch": 10.0},
+        "k_level_scatter": {"dispatches_per_build": 6, "fetch_MB_per_dispatch": 30.0,
+                            "write_MB_per_dispatch": 30.0}}}]
+    (tmp_path / "profiles" / "plain1_traffic.json").write_text(json.dumps(rec))
+    assert bench.measured_traffic("plain1", "level_scatter", 6, "6x3") == 360e6 / 6
+    assert bench.measured_traffic("plain1", "level_scatter", 7, "8x3") == (6 * 40e6 + 54e6) / 7
+    assert bench.measured_traffic("plain1", "local", 5, "6x3") == 210e6  # its own run first
+    assert bench.measured_traffic("plain1", "local", 5, "16x3") == 110e6
+    assert bench.measured_traffic("plain1", "level_scatter", 7, "16x3") is None
     # other sources, or no counter run: nothing
     monkeypatch.setattr(bench, "kernel_sources_hash", lambda: "other")
     assert bench.measured_traffic("plain1", "local", 5, "8x3") is None
