@@ -14,6 +14,7 @@ Functions:
   sorted_suffixes(text, offsets)-- the sorted (read, offset) pairs themselves
   bwt_bruteforce(reads)         -- pure Python, tiny inputs only
   pack(text)                    -- the 2-bit packed input layout, written out
+  adjacent_lcp / live_profile   -- ties left after each fixed-width window
 """
 from __future__ import annotations
 
@@ -191,3 +192,56 @@ def pack(text) -> np.ndarray:
         shifts = (62 - 2 * np.arange(chunk.size)).astype(np.uint64)
         words[t0 // 32] = np.bitwise_or.reduce(chunk << shifts) if chunk.size else 0
     return words
+
+
+def adjacent_lcp(text, offsets, order: np.ndarray) -> np.ndarray:
+    """Bases shared by each sorted suffix and the one before it (row 0: 0).
+
+    `order` is the (rows, 2) array of (read, offset) from sorted_suffixes.
+    Terminators are all distinct (Section 2), so a common prefix never
+    extends past either suffix's last base.
+    """
+    text, offsets = _as_inputs(text, offsets)
+    order = np.asarray(order, dtype=np.int64)
+    rows = order.shape[0]
+    lcp = np.zeros(rows, dtype=np.int64)
+    if rows < 2:
+        return lcp
+    start = offsets[order[:, 0]].astype(np.int64) + order[:, 1]
+    rem = (offsets[order[:, 0] + 1] - offsets[order[:, 0]]).astype(np.int64) - order[:, 1]
+    a, b = start[:-1], start[1:]
+    cand = np.nonzero(np.minimum(rem[:-1], rem[1:]) > 0)[0]
+    k = 0
+    while cand.size:
+        same = text[a[cand] + k] == text[b[cand] + k]
+        cand = cand[same]
+        lcp[cand + 1] += 1
+        k += 1
+        cand = cand[np.minimum(rem[cand], rem[cand + 1]) > k]
+    return lcp
+
+
+def live_profile(text, offsets, width: int, order: np.ndarray | None = None) -> list[int]:
+    """Suffixes still tied after each window of `width` bases (Section 3.2).
+
+    Sorting by successive fixed-width windows leaves a suffix undecided after
+    r windows exactly when some other suffix shares its first r*width bases,
+    which in sorted order means a neighbour with a common prefix of at least
+    r*width bases.  Entry r-1 of the result is that count for r = 1, 2, ...
+    up to the last nonzero one; its sum is the number of next-window loads a
+    schedule that refines only tied suffixes makes.
+    """
+    if order is None:
+        order = sorted_suffixes(text, offsets)
+    lcp = adjacent_lcp(text, offsets, order)
+    best = lcp.copy()
+    if best.size > 1:
+        best[:-1] = np.maximum(best[:-1], lcp[1:])
+    out = []
+    r = 1
+    while True:
+        c = int(np.count_nonzero(best >= r * width))
+        if c == 0:
+            return out
+        out.append(c)
+        r += 1

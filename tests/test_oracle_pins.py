@@ -306,3 +306,65 @@ def test_c_checker_on_edge_collections():
         c = datagen.from_reads(reads)
         b, t = oracle.bwt(c.text, c.offsets)
         assert oracle.check_bwt(b, t, c.text, c.offsets) == 0
+
+
+# ---- live-round profile (ties left after each window) -----------------------
+
+def _tied_bruteforce(reads, width):
+    """Per round r, suffixes that share their first r*width bases with another."""
+    sufs = [r[k:] for r in reads for k in range(len(r) + 1)]
+    out = []
+    r = 1
+    while True:
+        need = r * width
+        heads = [s[:need] for s in sufs if len(s) >= need]
+        seen = {}
+        for h in heads:
+            seen[h] = seen.get(h, 0) + 1
+        c = sum(v for v in seen.values() if v > 1)
+        if c == 0:
+            return out
+        out.append(c)
+        r += 1
+
+
+@pytest.mark.parametrize("alpha", ["A", "AC", "ACGT"])
+def test_live_profile_vs_pairwise_bruteforce(alpha):
+    rng = np.random.default_rng(31 + len(alpha))
+    for _ in range(200):
+        n = int(rng.integers(1, 8))
+        reads = ["".join(rng.choice(list(alpha), size=int(rng.integers(0, 14)))) for _ in range(n)]
+        text, off = _col(reads)
+        for width in (1, 2, 3, 5):
+            assert oracle.live_profile(text, off, width) == _tied_bruteforce(reads, width), (reads, width)
+
+
+def test_live_profile_closed_forms():
+    # n identical reads of length m: after r windows every suffix with at
+    # least r*w bases is tied with its copies, (n)(m - r*w + 1) of them
+    text, off = _col(["ACGTTGCA"] * 4)
+    assert oracle.live_profile(text, off, 3) == [4 * 6, 4 * 3]
+    # one homopolymer read A^m: after r windows the m - r*w + 1 suffixes with
+    # at least r*w bases all share them, while two or more are left
+    text, off = _col(["A" * 8])
+    assert oracle.live_profile(text, off, 2) == [7, 5, 3]
+    assert oracle.live_profile(text, off, 4) == [5]
+    # distinct reads with no shared 2-base prefix
+    text, off = _col(["AC", "GT", "CA"])
+    assert oracle.live_profile(text, off, 2) == []
+    # the adjacent common prefixes of Fig. 1's collection by hand
+    reads = ["ACG", "AC"]
+    text, off = _col(reads)
+    order = oracle.sorted_suffixes(text, off)
+    assert oracle.adjacent_lcp(text, off, order).tolist() == _lcp_by_hand(reads, order)
+
+
+def _lcp_by_hand(reads, order):
+    sufs = [reads[i][k:] for i, k in order.tolist()]
+    out = [0]
+    for x, y in zip(sufs, sufs[1:]):
+        c = 0
+        while c < min(len(x), len(y)) and x[c] == y[c]:
+            c += 1
+        out.append(c)
+    return out
