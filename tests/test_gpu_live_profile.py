@@ -67,3 +67,27 @@ def test_window_loads_equal_oracle_tie_profile(case):
     exp_b, exp_t = oracle.bwt(col.text, col.offsets)
     assert np.array_equal(b, exp_b) and np.array_equal(t, exp_t)
     assert st["window_fetches"] + st["regathered"] == sum(prof)
+
+
+def test_batch_window_loads_equal_sum_of_collection_profiles():
+    # a suffix ties only with suffixes of its own collection: the batch's
+    # loads are the sum of each collection's profile, not the profile of the
+    # collections pooled
+    rng = np.random.default_rng(7457)
+    cols = []
+    for k in range(12):
+        g = datagen.random_genome(rng, int(rng.integers(2000, 20000)))
+        cols.append(datagen.sample_reads(rng, g, int(rng.integers(200, 3000)), [75, 100, 150][k % 3], 0.01))
+    shared = "ACGTTGCAAC" * 10
+    cols.append(datagen.from_reads([shared] * 700))
+    cols.append(datagen.from_reads([shared] * 5 + ["ACGT" * 20] * 3))
+    _say(f"batch: {len(cols)} collections, {sum(c.n_bases for c in cols)} bases")
+    outs = cxbwt.build_batch_host(cols)
+    st = cxbwt.last_stats()
+    total = 0
+    for i, (c, (b, t)) in enumerate(zip(cols, outs)):
+        eb, et = oracle.bwt(c.text, c.offsets)
+        assert np.array_equal(b, eb) and np.array_equal(t, et), f"collection {i} differs from the oracle"
+        total += sum(oracle.live_profile(c.text, c.offsets, WINDOW_BASES))
+    _say(f"batch: fetches={st['window_fetches']} regathered={st['regathered']} oracle total={total}")
+    assert st["window_fetches"] + st["regathered"] == total
