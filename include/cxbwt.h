@@ -222,6 +222,10 @@ typedef struct cxbwt_stats {
   uint64_t scattered_suffixes; /* suffixes moved by global scatters                    */
   uint64_t regathered;         /* later-window keys fetched by the global levels        */
   uint64_t window_fetches;     /* later-window keys fetched inside waves                */
+  /* regathered + window_fetches is the number of (suffix, window r >= 1)
+   * pairs for which another suffix of the same collection shares the
+   * suffix's first 27 r bases: only tied suffixes load a later window
+   * (Section 3.2's stringword iterations, restricted to the ties).           */
   /* With timing on (cxbwt_set_timing): summed kernel time in ms and launch
    * count per kernel class: 0 prep, 1 key generation, 2 level histogram,
    * 3 level scan, 4 level scatter, 5 in-wave finish, 6 final emit.           */
