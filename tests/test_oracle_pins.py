@@ -368,3 +368,103 @@ def _lcp_by_hand(reads, order):
             c += 1
         out.append(c)
     return out
+
+
+# ---- the Python invariant checks reject damaged BWTs ------------------------
+# Each damage below keeps everything the other checks look at, so the check
+# named in the test is the one that must catch it; a check that accepted
+# everything would fail here.
+
+def _small_true_bwt():
+    col = datagen.plain_config(0, scale=0.05)
+    bwt, tp = oracle.bwt(col.text, col.offsets)
+    return col, bwt, tp
+
+
+def _swap_rows_with_different_symbols(bwt, lo, rng):
+    b = bwt.copy()
+    i = int(rng.integers(lo, b.size))
+    j = int(rng.integers(lo, b.size))
+    while b[i] == b[j]:
+        j = int(rng.integers(lo, b.size))
+    b[i], b[j] = b[j], b[i]
+    return b
+
+
+def test_check_counts_rejects_wrong_symbols_and_term_pos():
+    col, bwt, tp = _small_true_bwt()
+    invariants.check_counts(bwt, tp, col.text, col.offsets)
+    b = bwt.copy()
+    i = col.n_reads + 7
+    b[i] = ord("A") if b[i] != ord("A") else ord("C")
+    with pytest.raises(AssertionError):
+        invariants.check_counts(b, tp, col.text, col.offsets)
+    b = bwt.copy()
+    b[int(tp[3])] = ord("G")  # a '$' row loses its terminator
+    with pytest.raises(AssertionError):
+        invariants.check_counts(b, tp, col.text, col.offsets)
+    t = tp.copy()
+    t[0] = next(r for r in range(col.n_reads, bwt.size) if bwt[r] != ord("$"))
+    with pytest.raises(AssertionError):
+        invariants.check_counts(bwt, t, col.text, col.offsets)
+
+
+def test_check_dollar_rows_rejects_moved_terminator_rows():
+    col, bwt, tp = _small_true_bwt()
+    invariants.check_dollar_rows(bwt, col.text, col.offsets)
+    # rows 0 and 1 exchanged (their symbols differ): counts still hold
+    k = next(k for k in range(col.n_reads - 1) if bwt[k] != bwt[k + 1])
+    b = bwt.copy()
+    b[k], b[k + 1] = b[k + 1], b[k]
+    invariants.check_counts(b, tp, col.text, col.offsets)
+    with pytest.raises(AssertionError):
+        invariants.check_dollar_rows(b, col.text, col.offsets)
+    # a bare-terminator row exchanged with a later row of another symbol
+    j = next(j for j in range(col.n_reads, bwt.size) if bwt[j] != bwt[0] and bwt[j] != ord("$"))
+    b = bwt.copy()
+    b[0], b[j] = b[j], b[0]
+    with pytest.raises(AssertionError):
+        invariants.check_dollar_rows(b, col.text, col.offsets)
+
+
+def test_lf_reconstruct_rejects_swapped_symbols_and_term_pos():
+    col, bwt, tp = _small_true_bwt()
+    invariants.lf_reconstruct(bwt, tp, col.text, col.offsets)
+    rng = np.random.default_rng(5)
+    for _ in range(5):
+        b = _swap_rows_with_different_symbols(bwt, col.n_reads, rng)
+        invariants.check_counts(b, tp, col.text, col.offsets)
+        invariants.check_dollar_rows(b, col.text, col.offsets)
+        with pytest.raises(AssertionError):
+            invariants.lf_reconstruct(b, tp, col.text, col.offsets)
+    # term_pos entries of two reads exchanged: still the set of '$' rows
+    t = tp.copy()
+    t[0], t[1] = t[1], t[0]
+    invariants.check_counts(bwt, t, col.text, col.offsets)
+    with pytest.raises(AssertionError):
+        invariants.lf_reconstruct(bwt, t, col.text, col.offsets)
+    # the walk of one listed read only
+    with pytest.raises(AssertionError):
+        invariants.lf_reconstruct(bwt, t, col.text, col.offsets, reads=np.array([1]))
+    invariants.lf_reconstruct(bwt, t, col.text, col.offsets, reads=np.array([2, 3]))
+
+
+# ---- the C oracle under AddressSanitizer + UndefinedBehaviorSanitizer -------
+
+def test_oracle_c_under_address_and_undefined_sanitizers(tmp_path):
+    exe = str(tmp_path / "oracle_sanitize")
+    cmd = ["gcc", "-O1", "-g", "-std=c11", "-pthread", "-fno-omit-frame-pointer",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+           os.path.join(ROOT, "tests", "oracle_sanitize_main.c"), os.path.join(ROOT, "oracle", "cx_oracle.c"),
+           "-o", exe]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0 and "asan" in (res.stderr or "").lower():
+        pytest.skip("sanitizer runtime not available: " + res.stderr[-200:])
+    assert res.returncode == 0, res.stderr
+    # verify_asan_link_order=0: the process may start with other libraries preloaded
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1:verify_asan_link_order=0",
+               UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+    run = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=300)
+    assert run.returncode == 0, run.stdout[-2000:] + run.stderr[-4000:]
+    assert "runtime error" not in run.stderr
+    assert "oracle sanitizer run ok" in run.stdout
