@@ -18,8 +18,9 @@
  * Conventions shared by all entry points
  *   * Pointers marked (device) must point to memory on the current HIP device;
  *     (host) pointers to host memory.  The caller allocates and frees every
- *     buffer, including the workspace; the library keeps no device memory
- *     and frees nothing it was given.
+ *     buffer, including the workspace; the library frees nothing it was
+ *     given and keeps no device memory of its own apart from the fixed array
+ *     behind cxbwt_build_noalloc.
  *   * `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *   * Return value: one of the CXBWT_* status codes below.  No C++ exception
  *     crosses this interface.  cxbwt_status_str() gives a message.
@@ -45,6 +46,8 @@ extern "C" {
 #define CXBWT_EDATA (-5)   /* the device found invalid input data: offsets not
                               a non-decreasing partition of the bases, a read
                               longer than max_read_len, or a non-ACGT byte     */
+#define CXBWT_ESCRATCH (-6) /* cxbwt_build_noalloc: the input needs more
+                               workspace than CXBWT_NOALLOC_WORKSPACE_BYTES   */
 
 /* Largest supported n_bases: suffix handles are 32-bit base positions. */
 #define CXBWT_MAX_BASES 4294967295ull
@@ -122,6 +125,35 @@ size_t cxbwt_workspace_bytes(uint64_t n_reads, uint64_t n_bases, uint32_t max_re
 int cxbwt_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n_reads, uint64_t n_bases,
                 uint32_t max_read_len, uint8_t *bwt, uint64_t *term_pos, void *workspace,
                 size_t workspace_bytes, void *stream);
+
+/*
+ * cxbwt_build_noalloc -- cxbwt_build without a caller workspace and without
+ * any device allocation, for callers that cannot allocate device memory
+ * (tight serving loops, harnesses that forbid hipMalloc).  It waits on the
+ * stream between sort levels as cxbwt_build does, so it is not a call to
+ * make under HIP graph capture.
+ *
+ * The workspace is a fixed array of CXBWT_NOALLOC_WORKSPACE_BYTES in the
+ * library's device code object: each device the library runs on holds its
+ * own copy from the library's first use on it until the process ends.  The
+ * call still takes the caller's inputs and outputs (packed, offsets, bwt,
+ * term_pos: device pointers, meanings, layouts and data checks as for
+ * cxbwt_build).  The first call on a device looks up that device's copy
+ * (hipGetSymbolAddress) with the device current; no call allocates or frees
+ * device memory, and kernel timing (cxbwt_set_timing) is not applied.
+ *
+ * Every call on one device shares that device's array and leaves its last
+ * contents there; the build clears what it needs cleared itself.  Calls that
+ * overlap on one device (two host threads, or two streams whose work is not
+ * ordered) race on the array and give unspecified outputs.
+ *
+ * Returns as cxbwt_build, and CXBWT_ESCRATCH (before any HIP call) when
+ * cxbwt_workspace_bytes(n_reads, n_bases, max_read_len) exceeds
+ * CXBWT_NOALLOC_WORKSPACE_BYTES (about 9.7 Mbases of 100-base reads).
+ */
+#define CXBWT_NOALLOC_WORKSPACE_BYTES (256ull << 20)
+int cxbwt_build_noalloc(const uint64_t *packed, const uint64_t *offsets, uint64_t n_reads, uint64_t n_bases,
+                        uint32_t max_read_len, uint8_t *bwt, uint64_t *term_pos, void *stream);
 
 /*
  * cxbwt_batch_workspace_bytes -- workspace of cxbwt_build_batch for these

@@ -45,6 +45,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -2553,9 +2554,9 @@ void level1_stats(const Build &b) {
 // one collection).  coll_reads (host) holds ncoll + 1 read boundaries.
 int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint64_t nb, uint32_t maxlen,
               const uint64_t *coll_reads, uint32_t ncoll, uint8_t *bwt, uint64_t *term_pos, unsigned char *ws,
-              hipStream_t st) {
+              hipStream_t st, bool allow_timing = true) {
   g_stats = cxbwt_stats{};
-  PhaseTimer T{st, g_timing != 0, {}};
+  PhaseTimer T{st, allow_timing && g_timing != 0, {}};
   Build b;
   build_init(b, packed, offsets, n, nb, maxlen, coll_reads, ncoll, bwt, term_pos, ws);
   int rc;
@@ -2709,6 +2710,35 @@ struct cxbwt_graph {
   GraphPlan p;
 };
 
+// Workspace of cxbwt_build_noalloc: a fixed array in the code object, one
+// copy per device the library runs on, held until the process ends.  Host
+// code never passes the array's name to a kernel or a copy (on the host it
+// names a stand-in, not device memory): it uses the device address
+// hipGetSymbolAddress returns, taken once per device with that device
+// current and kept in g_scratch_addr.
+static __device__ __align__(256) unsigned char scratch[CXBWT_NOALLOC_WORKSPACE_BYTES];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_addr[SCRATCH_MAX_DEVICES] = {};
+
+// Device address of the current device's copy of `scratch`.
+int scratch_address(unsigned char **out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= SCRATCH_MAX_DEVICES) return CXBWT_EDEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return CXBWT_EDEVICE;
+    if (((uintptr_t)p & 255u) != 0) return CXBWT_EDEVICE;
+    g_scratch_addr[dev] = (unsigned char *)p;
+  }
+  *out = g_scratch_addr[dev];
+  return CXBWT_OK;
+}
+}  // namespace
+
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
@@ -2750,6 +2780,20 @@ int cxbwt_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n_read
   const uint64_t one[2] = {0, n_reads};
   return run_build(packed, offsets, n_reads, n_bases, max_read_len, one, 1, bwt, term_pos, (unsigned char *)workspace,
                    (hipStream_t)stream);
+}
+
+int cxbwt_build_noalloc(const uint64_t *packed, const uint64_t *offsets, uint64_t n_reads, uint64_t n_bases,
+                        uint32_t max_read_len, uint8_t *bwt, uint64_t *term_pos, void *stream) {
+  if (!packed || !offsets || !bwt || !term_pos || n_reads == 0) return CXBWT_EINVAL;
+  if (!sizes_ok(n_reads, n_bases, max_read_len)) return CXBWT_ERANGE;
+  if (cxbwt_workspace_bytes(n_reads, n_bases, max_read_len) > CXBWT_NOALLOC_WORKSPACE_BYTES) return CXBWT_ESCRATCH;
+  unsigned char *ws = nullptr;
+  int rc = scratch_address(&ws);
+  if (rc) return rc;
+  const uint64_t one[2] = {0, n_reads};
+  // no kernel timing here: it would create HIP events
+  return run_build(packed, offsets, n_reads, n_bases, max_read_len, one, 1, bwt, term_pos, ws, (hipStream_t)stream,
+                   false);
 }
 
 int cxbwt_build_batch(const uint64_t *packed, const uint64_t *offsets, uint64_t n_reads, uint64_t n_bases,
@@ -2852,6 +2896,9 @@ const char *cxbwt_status_str(int status) {
     case CXBWT_ENOMEM: return "workspace smaller than cxbwt_workspace_bytes()";
     case CXBWT_EDEVICE: return "HIP launch/runtime failure or internal device check failed";
     case CXBWT_EDATA: return "invalid input data found on the device (offsets, read length or bases)";
+    case CXBWT_ESCRATCH:
+      return "input needs more workspace than cxbwt_build_noalloc's fixed device array holds "
+             "(CXBWT_NOALLOC_WORKSPACE_BYTES); use cxbwt_build with a caller workspace";
     default: return "unknown status";
   }
 }

@@ -17,11 +17,14 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcxbwt.so")
 
-OK, EINVAL, ERANGE, ENOMEM, EDEVICE, EDATA = 0, -1, -2, -3, -4, -5
-STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ERANGE: "ERANGE", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", EDATA: "EDATA"}
+OK, EINVAL, ERANGE, ENOMEM, EDEVICE, EDATA, ESCRATCH = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ERANGE: "ERANGE", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", EDATA: "EDATA",
+                ESCRATCH: "ESCRATCH"}
+# device array behind cxbwt_build_noalloc (CXBWT_NOALLOC_WORKSPACE_BYTES)
+NOALLOC_WORKSPACE_BYTES = 256 << 20
 
 # Names the C ABI exports (include/cxbwt.h).
-ABI_FUNCTIONS = ("cxbwt_packed_words", "cxbwt_pack", "cxbwt_workspace_bytes", "cxbwt_build",
+ABI_FUNCTIONS = ("cxbwt_packed_words", "cxbwt_pack", "cxbwt_workspace_bytes", "cxbwt_build", "cxbwt_build_noalloc",
                  "cxbwt_batch_workspace_bytes", "cxbwt_build_batch", "cxbwt_last_stats", "cxbwt_set_timing",
                  "cxbwt_set_tuning", "cxbwt_get_tuning", "cxbwt_graph_create", "cxbwt_graph_launch",
                  "cxbwt_graph_finish", "cxbwt_graph_destroy", "cxbwt_status_str")
@@ -71,6 +74,8 @@ def lib():
             L.cxbwt_workspace_bytes.restype = ctypes.c_size_t
             L.cxbwt_build.argtypes = [vp, vp, u64, u64, u32, vp, vp, vp, ctypes.c_size_t, vp]
             L.cxbwt_build.restype = ctypes.c_int
+            L.cxbwt_build_noalloc.argtypes = [vp, vp, u64, u64, u32, vp, vp, vp]
+            L.cxbwt_build_noalloc.restype = ctypes.c_int
             L.cxbwt_batch_workspace_bytes.argtypes = [u64, u64, u32, u32]
             L.cxbwt_batch_workspace_bytes.restype = ctypes.c_size_t
             L.cxbwt_build_batch.argtypes = [vp, vp, u64, u64, u32, vp, u32, vp, vp, vp, ctypes.c_size_t, vp]
@@ -159,6 +164,22 @@ def build(packed, offsets, n_reads: int, n_bases: int, max_read_len: int, worksp
                            ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream_ptr(stream))
     if st != OK:
         raise CxbwtError(st, "cxbwt_build")
+    return bwt, term
+
+
+def build_noalloc(packed, offsets, n_reads: int, n_bases: int, max_read_len: int, out, stream=None):
+    """cxbwt_build_noalloc: the library's fixed device array is the workspace.
+
+    out = (bwt, term) tensors the caller allocated (this call allocates no
+    device memory).  Raises CxbwtError(ESCRATCH) when the input needs more
+    than NOALLOC_WORKSPACE_BYTES of workspace.
+    """
+    bwt, term = out
+    st = lib().cxbwt_build_noalloc(ctypes.c_void_p(packed.data_ptr()), ctypes.c_void_p(offsets.data_ptr()), n_reads,
+                                   n_bases, max_read_len, ctypes.c_void_p(bwt.data_ptr()),
+                                   ctypes.c_void_p(term.data_ptr()), _stream_ptr(stream))
+    if st != OK:
+        raise CxbwtError(st, "cxbwt_build_noalloc")
     return bwt, term
 
 

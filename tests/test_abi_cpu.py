@@ -64,6 +64,28 @@ def test_build_argument_validation_needs_no_gpu():
     assert L.cxbwt_build(*args(ws=ctypes.c_void_p(0x1001))) == cxbwt.EINVAL  # misaligned workspace
 
 
+def test_noalloc_argument_validation_needs_no_gpu():
+    """cxbwt_build_noalloc checks its arguments and its array's size before any HIP call."""
+    L = cxbwt.lib()
+    fake = ctypes.c_void_p(0x1000)
+    null = ctypes.c_void_p(0)
+    args = lambda **kw: [kw.get("packed", fake), kw.get("offsets", fake), kw.get("n", 3), kw.get("nb", 12),
+                         kw.get("maxlen", 4), kw.get("bwt", fake), kw.get("term", fake), null]
+    assert L.cxbwt_build_noalloc(*args(packed=null)) == cxbwt.EINVAL
+    assert L.cxbwt_build_noalloc(*args(offsets=null)) == cxbwt.EINVAL
+    assert L.cxbwt_build_noalloc(*args(bwt=null)) == cxbwt.EINVAL
+    assert L.cxbwt_build_noalloc(*args(term=null)) == cxbwt.EINVAL
+    assert L.cxbwt_build_noalloc(*args(n=0)) == cxbwt.EINVAL
+    assert L.cxbwt_build_noalloc(*args(nb=1 << 32)) == cxbwt.ERANGE
+    # largest input of 100-base reads the array holds, and one read more
+    nb = 9_000_000
+    assert cxbwt.workspace_bytes(nb // 100, nb, 100) <= cxbwt.NOALLOC_WORKSPACE_BYTES
+    big = 10_000_000
+    assert cxbwt.workspace_bytes(big // 100, big, 100) > cxbwt.NOALLOC_WORKSPACE_BYTES
+    assert L.cxbwt_build_noalloc(*args(n=big // 100, nb=big, maxlen=100)) == cxbwt.ESCRATCH
+    assert b"fixed device array" in L.cxbwt_status_str(cxbwt.ESCRATCH)
+
+
 def test_pack_argument_validation_needs_no_gpu():
     L = cxbwt.lib()
     null = ctypes.c_void_p(0)
@@ -74,7 +96,7 @@ def test_pack_argument_validation_needs_no_gpu():
 
 def test_status_strings():
     L = cxbwt.lib()
-    for code in (0, -1, -2, -3, -4, -5):
+    for code in (0, -1, -2, -3, -4, -5, -6):
         assert L.cxbwt_status_str(code)
     assert b"unknown" in L.cxbwt_status_str(42)
 
