@@ -3,12 +3,19 @@
 A step is one pass of the whole device path over one resident collection:
 pack the ASCII reads to 2-bit words, then cxbwt_build (suffix listing, the
 digit levels, the in-workgroup sort + tie refinement, and the BWT emit).
-The default workload is the plain single build of 4M reads x 100 bases from a
-seeded 20 Mb random genome (20x coverage, 0.5% substitutions, both strands).
+The default workload (the headline line) is the largest single-GPU
+configuration: the repeat-heavy plain build of 40M reads x 100 bases from a
+seeded 200 Mb genome with 10% diverged repeat families (4 Gbases).  The
+20x-coverage build of 4M reads x 100 bases (400 Mbases) follows as a
+secondary line inside the same JSON object.
 
 Prints one JSON line (rank 0): metric/value/unit, timing, the roofline of the
-dominant kernel class (algorithmic bytes / its HIP-event time) and the CPU
-oracle timed on a bounded sample of the same workload on the host cores.
+dominant kernel class (algorithmic bytes / its HIP-event time, with the HBM
+traffic of the committed counter runs per launch and per step) and the CPU
+oracle timed on a bounded sample of the same recipe on the host cores.
+
+Other modes: --mode batch / serve (the batched and served forms) and
+--mode sweep (100/200/400-base reads at equal total bases).
 """
 from __future__ import annotations
 
@@ -28,8 +35,12 @@ WORKLOADS = {
     "plain0": (0, "plain single build: 10k reads x 100 bp, 100 kb genome, 1% subst, both strands"),
     "plain1": (1, "plain single build: 4M reads x 100 bp, 20 Mb genome (20x), 0.5% subst, both strands"),
     "plain2": (2, "plain single build, repeat-heavy: 40M reads x 100 bp, 200 Mb genome with 10% 1-5 kb "
-                  "repeat units x50 at 1% divergence, 0.5% subst"),
+                  "repeat units x50 at 1% divergence, 0.5% subst, both strands"),
 }
+DEFAULT_WORKLOAD = "plain2"      # the largest configuration one GPU builds in one call
+SECONDARY_WORKLOAD = "plain1"    # reported inside the same line
+# oracle sample per headline workload: that recipe at this scale (10-30 s of CPU work)
+CPU_SAMPLE_SCALE = {"plain0": 1.0, "plain1": 0.1, "plain2": 0.02}
 
 
 def algorithmic_bytes(stats: dict, n_reads: int, n_bases: int, tile_len: int = 2048) -> dict:
@@ -48,6 +59,20 @@ def algorithmic_bytes(stats: dict, n_reads: int, n_bases: int, tile_len: int = 2
     prep          17 B per read (two offsets, one BWT byte) + 0.19 B per base
                   (end-bit ranks)
     """
+    if stats.get("schedule", 0) == 1:
+        # the stringword schedule: per window, keys computed in base order
+        # (text record and start ranks ~1.25 B, key written 8 B) and permuted
+        # by handle (handle 4 B, key 8 B gathered, key 8 B written); per digit
+        # pass a histogram read (8 B) and a scatter (24 B); one emit (13 B)
+        return {
+            "prep": 17.0 * n_reads + 0.1875 * n_bases,
+            "gen": 29.25 * stats.get("window_fetches", 0),
+            "level_hist": 8.0 * stats.get("level_suffixes", 0),
+            "level_scan": 2.0 * 1024 * stats.get("level_suffixes", 0) / 2048,
+            "level_scatter": 24.0 * stats.get("scattered_suffixes", 0),
+            "local": 0.0,
+            "final_emit": 13.0 * n_bases,
+        }
     cs = stats.get("chunk_suffixes", 0)
     fin = n_bases - cs
     scattered = stats.get("scattered_suffixes", 0)
@@ -73,65 +98,307 @@ KERNELS_OF_CLASS = {
     "final_emit": ["k_emit_final", "k_term"],
 }
 
+# the device code whose counter runs a traffic record holds (host code that
+# only sequences launches is not part of it)
+KERNEL_SOURCES = ("cxbwt_kernels.h", "device_common.h")
+
 
 def kernel_sources_hash() -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in ("cxbwt.hip", "device_common.h"):
+    for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_1401_7457_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, kclass: str, launches_per_build: int, tuning: str):
-    """HBM bytes per launch of a kernel class from the committed counter runs.
-
-    None when no counter run exists for this workload, or when the kernel
-    sources differ from the runs' or no run used the kernel instantiation
-    (tuning, "AxB").
-    The chunk kernel's work depends only on the chunk size (B): the level
-    tile (A) cuts the levels' tiles, not the buckets that become chunks, so
-    for that class only B has to match.
-    """
-    import json as _json
+def traffic_record(workload: str):
+    """The committed counter-run record of a workload (profiles/<workload>_traffic.json),
+    or None when there is none or it was taken with other kernel sources."""
     path = os.path.join(ROOT, "profiles", f"{workload}_traffic.json")
     if not os.path.exists(path):
         return None
-    rec = _json.load(open(path))
+    with open(path) as f:
+        rec = json.load(f)
     if rec.get("kernel_sources_sha256_16") != kernel_sources_hash():
         return None
-    # the main run, then counter runs of other instantiations of the same sources
-    runs = [rec] + list(rec.get("other_tunings", []))
+    return rec
+
+
+def measured_traffic(workload: str, kclass: str, tuning: str):
+    """HBM bytes per build (one step) of a kernel class from the committed counter runs.
+
+    Each counter run holds, per kernel, the FETCH_SIZE and WRITE_SIZE totals
+    (MB) over `builds` builds; they are scaled by the record's calibration
+    (the same counters read for a plain copy of known size).  None when no
+    record matches the kernel sources or no run used the kernel instantiation
+    (tuning, "AxB").  The chunk kernel's work depends only on the chunk size
+    (B): the level tile (A) cuts the levels' tiles, not the buckets that
+    become chunks, so for that class only B has to match.
+    """
+    rec = traffic_record(workload)
+    if rec is None:
+        return None
 
     def matches(run_tuning: str) -> bool:
         if kclass == "local":
             return run_tuning.split("x")[-1] == tuning.split("x")[-1]
         return run_tuning == tuning
 
+    runs = rec.get("runs", [])
     run = next((r for r in runs if r.get("tuning") == tuning), None) \
         or next((r for r in runs if matches(r.get("tuning") or "")), None)
     if run is None:
         return None
+    cal = rec["calibration"]
     tot = 0.0
     for k in KERNELS_OF_CLASS.get(kclass, []):
         e = run["kernels"].get(k)
         if e:
-            tot += (e["fetch_MB_per_dispatch"] + e["write_MB_per_dispatch"]) * 1e6 * e["dispatches_per_build"]
-    return tot / max(1, launches_per_build) if tot else None
+            tot += (e["fetch_MB"] * cal["fetch_factor"] + e["write_MB"] * cal["write_factor"]) * 1e6
+    return tot / rec["builds"] if tot else None
 
 
-def cpu_baseline(scale: float, threads: int) -> dict:
+def host_info() -> dict:
+    """CPU model, host RAM and the threads this process may use."""
+    model, ram_gb = "unknown", None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal:"):
+                    ram_gb = round(int(line.split()[1]) / 2 ** 20, 1)
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "host_ram_gib": ram_gb, "threads": len(os.sched_getaffinity(0))}
+
+
+def cpu_baseline(workload: str, threads: int) -> dict:
+    """The oracle (untuned) on the host cores: the headline recipe at a bounded
+    scale on every thread, plus the 1 Mbase recipe (plain0) on every thread
+    (median of 3) and on one thread."""
     from oracle import oracle  # the CPU baseline leg is the oracle itself
     from paper_1401_7457_amd import datagen
-    col = datagen.plain_config(1, scale=scale)
+    k, _ = WORKLOADS[workload]
+    scale = CPU_SAMPLE_SCALE[workload]
+    col = datagen.plain_config(k, scale=scale)
     oracle.load()
     t0 = time.perf_counter()
     oracle.bwt(col.text, col.offsets, threads=threads)
     dt = time.perf_counter() - t0
+    small = datagen.plain_config(0)
+    runs = []
+    for _ in range(3):
+        t1 = time.perf_counter()
+        oracle.bwt(small.text, small.offsets, threads=threads)
+        runs.append(time.perf_counter() - t1)
+    t1 = time.perf_counter()
+    oracle.bwt(small.text, small.offsets, threads=1)
+    one = time.perf_counter() - t1
+    info = host_info()
     return {"value": col.n_bases / dt / 1e9, "unit": "Gbases/s", "cores": threads, "kind": "oracle",
-            "sample": f"same recipe at scale {scale:g}: {col.n_reads} reads x 100 bp from a "
-                      f"{int(20_000_000 * scale)} b genome (same 20x coverage), {dt:.2f} s",
-            "seconds": dt}
+            "sample": f"{workload} recipe at scale {scale:g}: {col.n_reads} reads x 100 bp, {col.n_bases} bases "
+                      f"(genome and read count scaled together, same coverage), {dt:.2f} s",
+            "seconds": dt, "cpu_model": info["cpu_model"], "host_ram_gib": info["host_ram_gib"],
+            "plain0_seconds_median3": sorted(runs)[1], "plain0_seconds_1_thread": one,
+            "plain0_gbases_per_s_1_thread": small.n_bases / one / 1e9}
+
+
+SCHEDULE_NAMES = {0: "msd", 1: "stringword"}
+
+
+def choice_name(ch) -> str:
+    """"AxB" for an MSD choice, "AxB-stringword" for the stringword schedule."""
+    a, b, sched = ch
+    return f"{a}x{b}" + ("" if sched == 0 else "-" + SCHEDULE_NAMES[sched])
+
+
+def tuning_record(res: dict, repeats: int) -> dict:
+    a, b, sched = res["choice"]
+    return {"tile_items": a, "chunk_items": b, "schedule": SCHEDULE_NAMES[sched], "repeats": repeats,
+            "ms_per_choice": {choice_name(ch): round(v, 3) for ch, v in res["ms"].items()}}
+
+
+def _tune(args, packed, offsets, n, nb, maxlen, ws, bwt, term, pstatus, text):
+    """Autotuner (untimed): every instantiation timed on this workload, the fastest kept."""
+    from paper_1401_7457_amd import autotune, cxbwt
+    if args.tuning:
+        a, b = (int(v) for v in args.tuning.split("x")[:2])
+        sched = cxbwt.SCHEDULE_STRINGWORD if args.tuning.endswith("sw") else cxbwt.SCHEDULE_MSD
+        autotune.apply((a, b, sched))
+        return {"tile_items": a, "chunk_items": b, "schedule": SCHEDULE_NAMES[sched], "forced": True}
+    if args.no_tune:
+        return None
+    cxbwt.pack(text, out=packed, status=pstatus)
+    res = autotune.tune_build(packed, offsets, n, nb, maxlen, repeats=args.tune_repeats, workspace=ws,
+                              out=(bwt, term))
+    return tuning_record(res, args.tune_repeats)
+
+
+def _plain_line(args, workload: str, col=None, label: str | None = None) -> dict:
+    """One resident collection: timed steps, per-class kernel times, the roofline."""
+    import numpy as np
+    import torch
+
+    from paper_1401_7457_amd import cxbwt, datagen
+    if col is None:
+        k, label = WORKLOADS[workload]
+        col = datagen.plain_config(k)
+    n, nb, maxlen = col.n_reads, col.n_bases, col.max_read_len
+    print(f"[bench] workload {workload}: reads={n} bases={nb}", file=sys.stderr, flush=True)
+
+    text = torch.from_numpy(col.text).cuda()
+    offsets = torch.from_numpy(col.offsets.view(np.int64)).cuda()
+    packed = torch.empty(cxbwt.packed_words(nb), dtype=torch.int64, device="cuda")
+    pstatus = torch.empty(1, dtype=torch.int32, device="cuda")
+    ws = cxbwt.alloc_workspace(n, nb, maxlen)
+    bwt = torch.empty(nb + n, dtype=torch.uint8, device="cuda")
+    term = torch.empty(n, dtype=torch.int64, device="cuda")
+
+    def step():
+        cxbwt.pack(text, out=packed, status=pstatus)
+        cxbwt.build(packed, offsets, n, nb, maxlen, workspace=ws, out=(bwt, term))
+
+    tuning = _tune(args, packed, offsets, n, nb, maxlen, ws, bwt, term, pstatus, text)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    if int(pstatus.item()) != 0:
+        raise RuntimeError("input holds a non-ACGT byte")
+
+    # timed region: whole steps, bracketed by synchronisation
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms_step = e0.elapsed_time(e1) / args.steps
+
+    # per-kernel-class timing (HIP events the library records on the build's
+    # stream, which is torch's current stream here), separate steps
+    cxbwt.set_timing(True)
+    per_ms, per_launch = {}, {}
+    stats = None
+    tsteps = max(1, min(args.steps, 3))
+    for _ in range(tsteps):
+        step()
+        stats = cxbwt.last_stats()
+        for kname, v in stats["ms"].items():
+            per_ms[kname] = per_ms.get(kname, 0.0) + v / tsteps
+            per_launch[kname] = stats["launches"][kname]
+    cxbwt.set_timing(False)
+    torch.cuda.synchronize()
+
+    graph = None
+    if args.graph:
+        # the same build captured once in a hipGraph (levels sized and
+        # scheduled on the device, as many as the eager build ran) and
+        # replayed: untimed capture, then the same number of timed steps
+        g = cxbwt.BuildGraph(packed, offsets, n, nb, maxlen, levels=stats["levels"], workspace=ws)
+
+        def gstep():
+            cxbwt.pack(text, out=packed, status=pstatus)
+            g.run()
+
+        for _ in range(max(1, args.warmup)):
+            gstep()
+        torch.cuda.synchronize()
+        same = bool(torch.equal(g.bwt, bwt) and torch.equal(g.term, term))
+        e2 = torch.cuda.Event(enable_timing=True)
+        e3 = torch.cuda.Event(enable_timing=True)
+        e2.record(stream)
+        for _ in range(args.steps):
+            gstep()
+        e3.record(stream)
+        torch.cuda.synchronize()
+        gms = e2.elapsed_time(e3) / args.steps
+        graph = {"ms_per_step": gms, "gbases_per_s": nb / (gms / 1e3) / 1e9, "levels_scheduled": stats["levels"],
+                 "equals_eager_build": same}
+        g.close()
+
+    tuning_str = "%dx%d" % cxbwt.get_tuning()
+    model = algorithmic_bytes(stats, n, nb, tile_len=256 * cxbwt.get_tuning()[0])
+    dom = max(per_ms, key=per_ms.get)
+    dom_ms = per_ms[dom]
+    launches = max(1, per_launch[dom])
+    alg_step = model[dom]
+    achieved = alg_step / (dom_ms / 1e3) / 1e9  # = per-launch bytes / average launch time
+    traffic_step = measured_traffic(workload, dom, tuning_str)
+    rec = traffic_record(workload)
+    roofline = {
+        "bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS,
+        "traffic": None if traffic_step is None else traffic_step / launches,
+        "traffic_per_step": traffic_step,
+        "algorithmic_bytes_per_launch": alg_step / launches,
+        "algorithmic_bytes_per_step": alg_step,
+        "traffic_ratio": None if traffic_step is None else traffic_step / alg_step,
+        "kernel_ms_per_step": dom_ms, "launches_per_step": per_launch[dom], "avg_launch_ms": dom_ms / launches,
+        "traffic_calibration": None if rec is None else rec["calibration"].get("note"),
+    }
+    model_total = sum(model.values())
+    return {
+        "value": nb / (ms_step / 1e3) / 1e9,
+        "ms_per_step": ms_step,
+        "config": {"workload": label, "reads": n, "bases": nb, "read_len": maxlen, "seed": col.seed,
+                   "parallelism": "single GPU"},
+        "roofline": roofline,
+        "kernel_ms": per_ms,
+        "tuning": tuning,
+        "model_bytes_per_base": model_total / nb,
+        "hbm_frac_model_whole_step": model_total / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS,
+        "build_stats": {kk: v for kk, v in stats.items() if kk not in ("ms", "launches")},
+        "wall_s_timed": wall,
+        "graph_replay": graph,
+    }
+
+
+def _sweep_mode(args) -> dict:
+    """Read-length sweep at equal total bases (Section 4.3, Table 4: 100/200/400 bp)."""
+    import gc
+
+    import torch
+
+    from paper_1401_7457_amd import datagen
+    total = int(args.sweep_gbases * 1e9)
+    lines = []
+    for L in (100, 200, 400):
+        col = datagen.length_sweep_config(L, total)
+        label = f"read-length sweep: {col.n_reads} reads x {L} bp ({total / 1e9:g} Gbases), " \
+                f"{total // 20 / 1e6:g} Mb genome (20x), 0.5% subst, both strands"
+        line = _plain_line(args, f"sweep{L}", col=col, label=label)
+        line["read_len"] = L
+        lines.append(line)
+        print(f"[bench] sweep {L} bp: {line['ms_per_step']:.1f} ms/step", file=sys.stderr, flush=True)
+        del col
+        gc.collect()
+        torch.cuda.empty_cache()
+    base = lines[0]["value"]
+    return {
+        "metric": "BWT build Gbases/s at 1 GPU by read length (equal total bases)",
+        "value": base,
+        "unit": "Gbases/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "higher_is_better": True,
+        "data": "synthetic",
+        "config": {"workload": f"read-length sweep at {total / 1e9:g} Gbases: 100/200/400 bp"},
+        "lines": [{"read_len": x["read_len"], "gbases_per_s": x["value"], "ms_per_step": x["ms_per_step"],
+                   "relative_to_100bp": x["value"] / base, "hbm_frac_model_whole_step": x["hbm_frac_model_whole_step"],
+                   "model_bytes_per_base": x["model_bytes_per_base"], "kernel_ms": x["kernel_ms"],
+                   "tuning": x["tuning"], "build_stats": x["build_stats"], "config": x["config"]} for x in lines],
+    }
 
 
 def _batch_mode(args) -> dict:
@@ -180,9 +447,8 @@ def _batch_mode(args) -> dict:
         text, offs, cr, base, maxlen = wave_in[0]
         packed, _ = cxbwt.pack(text)
         res = autotune.tune_build(packed, offs, int(cr[-1]), base, maxlen,
-                                  coll_reads=cr, repeats=1)
-        tuning = {"tile_items": res["choice"][0], "chunk_items": res["choice"][1],
-                  "ms_per_choice": {f"{a}x{b}": round(v, 3) for (a, b), v in res["ms"].items()}}
+                                  coll_reads=cr, repeats=args.tune_repeats)
+        tuning = tuning_record(res, args.tune_repeats)
         del packed
 
     out = {}
@@ -248,22 +514,27 @@ def _serve_mode(args) -> dict:
     from paper_1401_7457_amd import cxbwt, datagen, serve
     jobs = datagen.job_stream(count=args.jobs, rate_per_s=1.0, scale=args.scale)
     mean_bases = float(np.mean([j.collection.n_bases for j in jobs]))
-    # capacity: throughput of one-at-a-time builds of these jobs
+    budget = int(args.budget_gb * 2 ** 30)
     ex = serve.DeviceExecutor(keep_on_device=True)
-    probe = jobs[: min(8, len(jobs))]
-    rep0, _ = serve.replay([(0.0, j.collection) for j in probe], ex, int(args.budget_gb * 2 ** 30),
-                           max_batch_jobs=1)
+    # capacity: one-at-a-time builds of the first jobs, measured warm (the
+    # probe runs twice; the second run is kept)
+    probe = [(0.0, j.collection) for j in jobs[: min(8, len(jobs))]]
+    for _ in range(2):
+        rep0, _ = serve.replay(probe, ex, budget, max_batch_jobs=1)
     capacity = rep0["gbases_per_s"] * 1e9  # bases per second
     rate = args.load * capacity / mean_bases
     arrivals = [(j.arrival_s / rate, j.collection) for j in jobs]
     total = sum(j.collection.n_bases for j in jobs)
-    print(f"[bench] serve: {len(jobs)} jobs, {total} bases, rate {rate:.1f}/s (load {args.load})",
-          file=sys.stderr, flush=True)
+    print(f"[bench] serve: {len(jobs)} jobs, {total} bases, capacity {capacity / 1e9:.2f} Gbases/s, "
+          f"rate {rate:.1f}/s (load {args.load})", file=sys.stderr, flush=True)
     res = {}
     for name, kw in (("continuous", {}), ("one_at_a_time", {"max_batch_jobs": 1})):
         torch.cuda.synchronize()
-        rep, _ = serve.replay(arrivals, ex, int(args.budget_gb * 2 ** 30), **kw)
+        rep, _ = serve.replay(arrivals, ex, budget, **kw)
         res[name] = rep
+        print(f"[bench] serve {name}: {rep['gbases_per_s']:.2f} Gbases/s, p50 {rep['latency_p50_s'] * 1e3:.1f} ms, "
+              f"p99 {rep['latency_p99_s'] * 1e3:.1f} ms, {rep['mean_jobs_per_batch']:.2f} jobs per batch",
+              file=sys.stderr, flush=True)
     c, b = res["continuous"], res["one_at_a_time"]
     return {
         "metric": "served BWT build aggregate Gbases/s and p50/p99 job latency at 1 GPU",
@@ -273,39 +544,115 @@ def _serve_mode(args) -> dict:
         "higher_is_better": True,
         "data": "synthetic",
         "config": {"workload": f"served: Poisson arrivals at {args.load:g} x measured capacity, {len(jobs)} jobs, "
-                               f"log-uniform 10k-5M reads x{args.scale:g}, L uniform 100-250, 1% subst",
-                   "bases": total, "budget_gb": args.budget_gb},
+                               f"log-uniform 10k-5M reads x{args.scale:g}, L uniform 100-250, 1-10 Mb genomes "
+                               f"x{args.scale:g}, 1% subst",
+                   "bases": total, "budget_gb": args.budget_gb, "mean_job_bases": mean_bases},
+        "capacity_one_at_a_time_gbases_per_s": capacity / 1e9,
+        "offered_rate_jobs_per_s": rate,
         "latency_note": "arrival to BWT complete on the device (device-to-host copy not included)",
         "latency_p50_s": c["latency_p50_s"],
         "latency_p99_s": c["latency_p99_s"],
         "mean_jobs_per_batch": c["mean_jobs_per_batch"],
+        "batches": c["batches"],
+        "makespan_s": c["makespan_s"],
         "one_at_a_time": {"gbases_per_s": b["gbases_per_s"], "latency_p50_s": b["latency_p50_s"],
-                          "latency_p99_s": b["latency_p99_s"]},
+                          "latency_p99_s": b["latency_p99_s"], "makespan_s": b["makespan_s"]},
+        "speedup_vs_one_at_a_time": c["gbases_per_s"] / b["gbases_per_s"],
     }
+
+
+def _ceilings_mode(args) -> dict:
+    """Memory-system ceilings the kernels are measured against, with torch's own
+    kernels: a streaming copy, random 16-byte gathers (the window fetches'
+    access pattern) and writes in runs of 8 and 16 consecutive records per
+    bucket per tile (the level scatters' write pattern; index_copy_ also
+    reads its 8-byte indices), each timed with events over several
+    repetitions."""
+    import torch
+    out = {}
+    reps = max(3, args.steps)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps / 1e3
+
+    n = 1 << 28  # 2 GiB of int64
+    src = torch.ones(n, dtype=torch.int64, device="cuda")
+    dst = torch.empty_like(src)
+    t = timed(lambda: dst.copy_(src))
+    out["copy_gb_per_s"] = 2 * 8 * n / t / 1e9
+    del src, dst
+    g = torch.Generator(device="cuda")
+    g.manual_seed(14017457)
+    for table_mib in (256, 4096):
+        rows = (table_mib << 20) // 16
+        table = torch.zeros((rows, 2), dtype=torch.int64, device="cuda")
+        idx = torch.randint(0, rows, (1 << 24,), device="cuda", generator=g)
+        t = timed(lambda: table.index_select(0, idx))
+        out[f"random_16B_loads_per_s_table_{table_mib}MiB"] = idx.numel() / t
+        del table, idx
+    # the write pattern of a level scatter: ~400M (key u64, handle u32)
+    # records in tiles of 256 r, each tile writing a run of r records to each
+    # of 256 evenly filled buckets at the bucket's running position
+    for r in (8, 16):
+        ntiles = 400_000_000 // (256 * r)
+        t_ = torch.arange(ntiles, device="cuda").view(-1, 1, 1)
+        b_ = torch.arange(256, device="cuda").view(1, -1, 1)
+        k_ = torch.arange(r, device="cuda").view(1, 1, -1)
+        pos = (b_ * (ntiles * r) + t_ * r + k_).reshape(-1)
+        m = pos.numel()
+        keys = torch.ones(m, dtype=torch.int64, device="cuda")
+        hdl = torch.ones(m, dtype=torch.int32, device="cuda")
+        ko = torch.empty_like(keys)
+        ho = torch.empty_like(hdl)
+
+        def scat():
+            ko.index_copy_(0, pos, keys)
+            ho.index_copy_(0, pos, hdl)
+        t = timed(scat)
+        out[f"scatter_runs_of_{r}_ms_per_400M"] = t * 1e3 * 400_000_000 / m
+        out[f"scatter_runs_of_{r}_gb_per_s"] = m * 24 / t / 1e9
+        del pos, keys, hdl, ko, ho, t_, b_, k_
+    return {"metric": "memory-system ceilings at 1 GPU (torch kernels)", "unit": "various", "n_gpus": 1,
+            "data": "synthetic", "reps": reps, "ceilings": out}
 
 
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve"],
-                    help="plain: one collection (the headline line); batch / serve: the batched and served forms")
+    ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve", "sweep", "ceilings"],
+                    help="plain: one collection (the headline line); batch / serve: the batched and served forms; "
+                         "sweep: 100/200/400-base reads at equal total bases")
     ap.add_argument("--scale", type=float, default=0.05, help="batch/serve: size scale of the collections")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--jobs", type=int, default=60)
-    ap.add_argument("--load", type=float, default=0.8, help="serve: offered load relative to measured capacity")
+    ap.add_argument("--load", type=float, default=1.5,
+                    help="serve: offered load relative to the measured one-at-a-time capacity")
     ap.add_argument("--budget-gb", type=float, default=250.0)
+    ap.add_argument("--sweep-gbases", type=float, default=2.0, help="sweep: total bases per read length")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="plain1", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-scale", type=float, default=0.1, help="oracle sample: plain1 recipe at this scale")
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
+    ap.add_argument("--no-secondary", action="store_true",
+                    help=f"plain: skip the {SECONDARY_WORKLOAD} line reported beside the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (it times every kernel instantiation on the workload before warm-up)")
-    ap.add_argument("--tuning", default=None, help="force one instantiation, e.g. 8x6 (no autotuner)")
+    ap.add_argument("--tune-repeats", type=int, default=3, help="timed builds per instantiation in the autotuner")
+    ap.add_argument("--tuning", default=None,
+                    help="force one choice, e.g. 8x6, or 8x6sw for the stringword schedule (no autotuner)")
     ap.add_argument("--graph", action="store_true",
                     help="plain: also time replays of the build captured in a hipGraph (reported beside the line)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
-                    help="also run one device copy of this size (for counter calibration under rocprofv3)")
+                    help="also run, before the builds, one device copy of this size and one random gather of "
+                         "16-byte rows from a table of this size (for counter calibration under rocprofv3)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -314,162 +661,85 @@ def main() -> int:
               "(one build runs on one device); run with --gpus 1", file=sys.stderr)
         return 2
 
-    import numpy as np
     import torch
 
-    from paper_1401_7457_amd import cxbwt, datagen
+    from paper_1401_7457_amd import cxbwt
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     torch.cuda.set_device(0)
     cxbwt.lib()
-    if args.mode != "plain":
-        res = _batch_mode(args) if args.mode == "batch" else _serve_mode(args)
+    if args.copy_calibration_mib:
+        calibration_kernels(args.copy_calibration_mib)
+    if args.mode in ("batch", "serve", "sweep", "ceilings"):
+        res = {"batch": _batch_mode, "serve": _serve_mode, "sweep": _sweep_mode,
+               "ceilings": _ceilings_mode}[args.mode](args)
         print(json.dumps(res), flush=True)
         return 0
-    k, label = WORKLOADS[args.workload]
-    col = datagen.plain_config(k)
-    n, nb, maxlen = col.n_reads, col.n_bases, col.max_read_len
-    print(f"[bench] workload {args.workload}: reads={n} bases={nb}", file=sys.stderr, flush=True)
 
-    text = torch.from_numpy(col.text).cuda()
-    offsets = torch.from_numpy(col.offsets.view(np.int64)).cuda()
-    packed = torch.empty(cxbwt.packed_words(nb), dtype=torch.int64, device="cuda")
-    pstatus = torch.empty(1, dtype=torch.int32, device="cuda")
-    ws = cxbwt.alloc_workspace(n, nb, maxlen)
-    bwt = torch.empty(nb + n, dtype=torch.uint8, device="cuda")
-    term = torch.empty(n, dtype=torch.int64, device="cuda")
-
-    def step():
-        cxbwt.pack(text, out=packed, status=pstatus)
-        cxbwt.build(packed, offsets, n, nb, maxlen, workspace=ws, out=(bwt, term))
-
-    if args.copy_calibration_mib:
-        # a plain streaming kernel of known traffic (reads and writes
-        # copy_calibration_mib MiB each) for scaling the HBM byte counters
-        src = torch.ones((args.copy_calibration_mib << 20) // 4, dtype=torch.int32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        torch.neg(src, out=dst)
-        torch.cuda.synchronize()
-        del src, dst
-
-    tuning = None
-    if args.tuning:
-        a, b = (int(v) for v in args.tuning.split("x"))
-        cxbwt.set_tuning(a, b)
-        tuning = {"tile_items": a, "chunk_items": b, "forced": True}
-    elif not args.no_tune:
-        # untimed: every instantiation is timed on this workload, the fastest kept
-        from paper_1401_7457_amd import autotune
-        cxbwt.pack(text, out=packed, status=pstatus)
-        res = autotune.tune_build(packed, offsets, n, nb, maxlen, repeats=1, workspace=ws, out=(bwt, term))
-        tuning = {"tile_items": res["choice"][0], "chunk_items": res["choice"][1],
-                  "ms_per_choice": {f"{a}x{b}": round(v, 3) for (a, b), v in res["ms"].items()}}
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    if int(pstatus.item()) != 0:
-        raise RuntimeError("input holds a non-ACGT byte")
-
-    # timed region: whole steps, bracketed by synchronisation
-    stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        step()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    ms_step = e0.elapsed_time(e1) / args.steps
-
-    # per-kernel-class timing (HIP events on the build's stream), separate steps
-    cxbwt.set_timing(True)
-    per_ms, per_launch, bytes_tot = {}, {}, {}
-    stats = None
-    tsteps = max(1, min(args.steps, 3))
-    for _ in range(tsteps):
-        step()
-        stats = cxbwt.last_stats()
-        for kname, v in stats["ms"].items():
-            per_ms[kname] = per_ms.get(kname, 0.0) + v / tsteps
-            per_launch[kname] = stats["launches"][kname]
-    cxbwt.set_timing(False)
-    torch.cuda.synchronize()
-    # the same build captured once in a hipGraph (levels sized and scheduled
-    # on the device, as many as the eager build ran) and replayed: untimed
-    # capture, then the same number of timed steps
-    graph = None
-    if args.graph:
-        g = cxbwt.BuildGraph(packed, offsets, n, nb, maxlen, levels=stats["levels"], workspace=ws)
-
-        def gstep():
-            cxbwt.pack(text, out=packed, status=pstatus)
-            g.run()
-
-        for _ in range(max(1, args.warmup)):
-            gstep()
-        torch.cuda.synchronize()
-        same = bool(torch.equal(g.bwt, bwt) and torch.equal(g.term, term))
-        e2 = torch.cuda.Event(enable_timing=True)
-        e3 = torch.cuda.Event(enable_timing=True)
-        e2.record(stream)
-        for _ in range(args.steps):
-            gstep()
-        e3.record(stream)
-        torch.cuda.synchronize()
-        gms = e2.elapsed_time(e3) / args.steps
-        graph = {"ms_per_step": gms, "gbases_per_s": nb / (gms / 1e3) / 1e9, "levels_scheduled": stats["levels"],
-                 "equals_eager_build": same}
-        g.close()
-
-    model = algorithmic_bytes(stats, n, nb, tile_len=256 * cxbwt.get_tuning()[0])
-    dom = max(per_ms, key=per_ms.get)
-    dom_ms = per_ms[dom]
-    achieved = model[dom] / (dom_ms / 1e3) / 1e9
-    model_total = sum(model.values())
-
+    head = _plain_line(args, args.workload)
     result = {
         "metric": "BWT build Gbases/s at 1 GPU",
-        "value": nb / (ms_step / 1e3) / 1e9,
+        "value": head["value"],
         "unit": "Gbases/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": label, "reads": n, "bases": nb, "read_len": maxlen, "seed": col.seed,
-                   "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(args.workload, dom, per_launch[dom],
-                                                 "%dx%d" % cxbwt.get_tuning()),
-                     "avg_launch_ms": dom_ms / max(1, per_launch[dom]), "launches_per_step": per_launch[dom],
-                     "algorithmic_bytes_per_step": model[dom]},
-        "kernel_ms": per_ms,
-        "tuning": tuning,
-        "model_bytes_per_base": model_total / nb,
-        "hbm_frac_model_whole_step": model_total / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS,
-        "build_stats": {kk: v for kk, v in stats.items() if kk not in ("ms", "launches")},
-        "wall_s_timed": wall,
     }
-    if graph is not None:
-        result["graph_replay"] = graph
+    result.update({k: v for k, v in head.items() if k not in ("value", "ms_per_step", "graph_replay")})
+    if head["graph_replay"] is not None:
+        result["graph_replay"] = head["graph_replay"]
+    if args.workload != SECONDARY_WORKLOAD and not args.no_secondary:
+        import gc
+        gc.collect()
+        torch.cuda.empty_cache()
+        sec = _plain_line(args, SECONDARY_WORKLOAD)
+        result["secondary"] = {"workload": sec["config"]["workload"], "gbases_per_s": sec["value"],
+                               "ms_per_step": sec["ms_per_step"], "config": sec["config"],
+                               "roofline": sec["roofline"], "kernel_ms": sec["kernel_ms"], "tuning": sec["tuning"],
+                               "model_bytes_per_base": sec["model_bytes_per_base"],
+                               "hbm_frac_model_whole_step": sec["hbm_frac_model_whole_step"],
+                               "build_stats": sec["build_stats"]}
+        if sec["graph_replay"] is not None:
+            result["secondary"]["graph_replay"] = sec["graph_replay"]
     if not args.no_cpu_baseline:
         threads = len(os.sched_getaffinity(0))
         print(f"[bench] cpu baseline: oracle on {threads} threads", file=sys.stderr, flush=True)
-        result["cpu_baseline"] = cpu_baseline(args.cpu_scale, threads)
+        result["cpu_baseline"] = cpu_baseline(args.workload, threads)
     print(json.dumps(result), flush=True)
     return 0
+
+
+def calibration_kernels(mib: int) -> None:
+    """Kernels of known traffic for scaling the HBM byte counters: torch's neg
+    over `mib` MiB (reads and writes `mib` MiB each), then an index_select of
+    16-byte rows at uniform random indices from a table of `mib` MiB (one
+    random 16-byte load per output row, rows = table rows / 4; the indices
+    are read and the rows written in order)."""
+    import torch
+    src = torch.ones((mib << 20) // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
+    table = torch.zeros(((mib << 20) // 16, 2), dtype=torch.int64, device="cuda")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(14017457)
+    idx = torch.randint(0, table.shape[0], (table.shape[0] // 4,), device="cuda", generator=g)
+    torch.cuda.synchronize()
+    out = table.index_select(0, idx)
+    torch.cuda.synchronize()
+    print(f"[bench] calibration: neg over {mib} MiB; index_select of {idx.numel()} random 16-byte rows "
+          f"from {table.shape[0]} rows", file=sys.stderr, flush=True)
+    del table, idx, out
 
 
 if __name__ == "__main__":

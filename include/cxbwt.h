@@ -51,6 +51,9 @@ extern "C" {
 
 /* Largest supported n_bases: suffix handles are 32-bit base positions. */
 #define CXBWT_MAX_BASES 4294967295ull
+/* Largest n_bases of cxbwt_build_ranges (and cxbwt_pack): positions kept in
+ * 64 bits per listed suffix, with 32-bit handles inside one range. */
+#define CXBWT_MAX_RANGE_BASES (1ull << 38)
 /* Largest supported max_read_len. */
 #define CXBWT_MAX_READ_LEN 65535u
 
@@ -67,6 +70,7 @@ uint64_t cxbwt_packed_words(uint64_t n_bases);
 /*
  * cxbwt_pack -- read packing (the 2-bit representation of Section 3, used
  * there to size the explicit-suffix alternative; here the device input form).
+ * Up to CXBWT_MAX_RANGE_BASES bases.
  *
  *   ascii     (device) n_bases bytes, each 'A', 'C', 'G' or 'T'.
  *   n_bases   number of bases.
@@ -77,7 +81,7 @@ uint64_t cxbwt_packed_words(uint64_t n_bases);
  *             A).  Read it after the stream completes.
  *   stream    hipStream_t as void*.
  * Asynchronous on `stream`.  Returns CXBWT_EINVAL for null ascii/packed with
- * n_bases > 0, CXBWT_ERANGE above CXBWT_MAX_BASES, CXBWT_EDEVICE on a launch
+ * n_bases > 0, CXBWT_ERANGE above CXBWT_MAX_RANGE_BASES, CXBWT_EDEVICE on a launch
  * failure.
  */
 int cxbwt_pack(const uint8_t *ascii, uint64_t n_bases, uint64_t *packed, uint32_t *d_status,
@@ -154,6 +158,50 @@ int cxbwt_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n_read
 #define CXBWT_NOALLOC_WORKSPACE_BYTES (256ull << 20)
 int cxbwt_build_noalloc(const uint64_t *packed, const uint64_t *offsets, uint64_t n_reads, uint64_t n_bases,
                         uint32_t max_read_len, uint8_t *bwt, uint64_t *term_pos, void *stream);
+
+/*
+ * The build in ranges -- Section 3.1's partitioning of the suffixes by their
+ * leading characters (Fig. 2 steps 1-3): the suffixes are counted by the
+ * top digits of their first 27-base window key, prefix classes larger than
+ * the budget are counted again one 8-bit digit deeper, and consecutive
+ * classes are packed in key order into ranges of at most
+ * max_range_suffixes suffixes.  Each range is listed from the text on its
+ * own (one scan of every position per range), sorted and refined like a
+ * whole collection, and written at the BWT rows after the ranges below it;
+ * the concatenation is the BWT.  The sort buffers hold one range at a time,
+ * so the workspace is about 1.3 bytes per base for the text plus 27.5 bytes
+ * per suffix of the largest range (cxbwt_range_workspace_bytes), against
+ * 27.5 bytes per base for cxbwt_build.
+ *
+ * Collections above CXBWT_MAX_BASES bases (up to CXBWT_MAX_RANGE_BASES) are
+ * built this way only: the suffixes of a range are then named by 32-bit
+ * indices into a table of their 64-bit base positions (8 more bytes per
+ * suffix of a range, one more load per later-window fetch), the indirection
+ * Section 3.2 describes for sorting by index.  CXBWT_RANGE_WIDE asks for
+ * that form below the limit too.
+ *
+ * cxbwt_range_workspace_bytes -- workspace for these sizes, budget and
+ *   flags; pure host arithmetic, 0 when out of range.
+ *
+ * cxbwt_build_ranges -- arguments and results as cxbwt_build (one
+ *   collection; the output is identical), plus
+ *     max_range_suffixes  the most suffixes one range may hold
+ *                         (1 .. CXBWT_MAX_BASES).
+ *     flags               0 or CXBWT_RANGE_WIDE.
+ *   n_bases may reach CXBWT_MAX_RANGE_BASES.  Returns as cxbwt_build,
+ *   CXBWT_EINVAL for unknown flags, CXBWT_ENOMEM below
+ *   cxbwt_range_workspace_bytes(), and CXBWT_ERANGE when more than
+ *   max_range_suffixes suffixes share one whole first-window key (the
+ *   partitioning cannot split them).  It waits on the stream between the
+ *   counting passes, ranges and levels; cxbwt_last_stats().ranges gives the
+ *   number of ranges.
+ */
+#define CXBWT_RANGE_WIDE 1u
+size_t cxbwt_range_workspace_bytes(uint64_t n_reads, uint64_t n_bases, uint32_t max_read_len,
+                                   uint64_t max_range_suffixes, uint32_t flags);
+int cxbwt_build_ranges(const uint64_t *packed, const uint64_t *offsets, uint64_t n_reads, uint64_t n_bases,
+                       uint32_t max_read_len, uint64_t max_range_suffixes, uint32_t flags, uint8_t *bwt,
+                       uint64_t *term_pos, void *workspace, size_t workspace_bytes, void *stream);
 
 /*
  * cxbwt_batch_workspace_bytes -- workspace of cxbwt_build_batch for these
@@ -264,6 +312,8 @@ typedef struct cxbwt_stats {
   float ms[8];
   uint32_t launches[8];
   uint32_t level_batches;      /* batches the levels after the first ran in            */
+  uint32_t ranges;             /* key ranges of a build in ranges (0 otherwise)        */
+  uint32_t schedule;           /* CXBWT_SCHEDULE_* the build ran                       */
   uint32_t reserved;
 } cxbwt_stats;
 
@@ -283,6 +333,30 @@ typedef struct cxbwt_stats {
  */
 int cxbwt_set_tuning(uint32_t tile_items, uint32_t chunk_items);
 int cxbwt_get_tuning(uint32_t *tile_items, uint32_t *chunk_items);
+
+/*
+ * cxbwt_set_schedule -- the sort schedule of later single-collection builds
+ * (cxbwt_build, cxbwt_build_noalloc) on the calling host thread:
+ *   CXBWT_SCHEDULE_MSD         (default) most significant digit first on the
+ *                              first 27-base window; later windows are
+ *                              fetched for tied suffixes only, and small
+ *                              buckets are finished in one wave.
+ *   CXBWT_SCHEDULE_STRINGWORD  Section 3.2's schedule as the paper runs it:
+ *                              a least-significant-digit radix sort of every
+ *                              window of every suffix, last window first
+ *                              (ceil((max_read_len + 1) / 27) windows, up to
+ *                              eight 8-bit passes each, passes over a digit
+ *                              no key varies in skipped), each window's keys
+ *                              computed in base order and permuted into the
+ *                              current order by handle (the paper's
+ *                              "stringwords" permuted by index).
+ * Both give the same output.  Batched builds and builds in ranges use the
+ * MSD schedule.  CXBWT_EINVAL for another value; cxbwt_get_schedule reads it.
+ */
+#define CXBWT_SCHEDULE_MSD 0u
+#define CXBWT_SCHEDULE_STRINGWORD 1u
+int cxbwt_set_schedule(uint32_t schedule);
+int cxbwt_get_schedule(uint32_t *schedule);
 
 /* Copies the last build's counters (host) into *out; CXBWT_EINVAL on NULL. */
 int cxbwt_last_stats(cxbwt_stats *out);

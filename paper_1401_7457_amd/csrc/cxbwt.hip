@@ -50,1625 +50,11 @@
 #include <vector>
 
 #include "cxbwt.h"
-#include "device_common.h"
+#include "cxbwt_kernels.h"
 
 namespace {
 
 using namespace cxk;
-
-// Tuning.  The level tile (suffixes per thread of a scatter) and the chunk
-// (suffixes per lane of the one-wave chunk kernel) are template parameters;
-// the library holds every listed instantiation and each build uses the one
-// its thread selected (cxbwt_set_tuning).  Capacities are sized for the
-// smallest tile and chunk, so a workspace fits every choice.
-constexpr int LOCAL_WG = 64;                   // one wave finishes a chunk
-constexpr int MIN_TILE_ITEMS = 6;
-constexpr int MAX_TILE_ITEMS = 8;  // items per thread a histogram kernel loads at once
-constexpr int MIN_CHUNK_ITEMS = 3;
-constexpr int MIN_TILE = BLOCK * MIN_TILE_ITEMS;
-constexpr int MIN_CHUNK = LOCAL_WG * MIN_CHUNK_ITEMS;
-constexpr int GROUP_TILES = 256;               // tiles per first-stage scan group
-constexpr uint64_t SEG_BATCH_MIN = 2048;       // segment size the level scratch is sized for
-
-constexpr uint32_t ST_BAD_OFFSETS = 1u;
-constexpr uint32_t ST_TOO_LONG = 2u;
-constexpr uint32_t ST_BAD_CHAR = 4u;
-constexpr uint32_t ST_LIST_OVERFLOW = 8u;
-constexpr uint32_t ST_WINDOW_BOUND = 16u;
-constexpr uint32_t ST_PLAN_MISMATCH = 32u;  // inputs no longer match a captured build
-
-// counters block layout (uint32 slots; 64-bit values on even slots).  Chunk
-// and big counts share one 64-bit word; the level kinds of the statistics
-// block are folded into the 64-bit words from C_FOLD on; a build whose
-// levels are scheduled on the device keeps its running totals (G_*) from
-// C_CUM on.
-enum { C_STATUS = 0, C_NFINAL = 1, C_NCHUNK = 2, C_NBIG = 3, C_NCUR = 4, C_FLAGS = 5, C_FOLD = 16, C_CUM = 32,
-       C_COUNT = 64 };
-enum { G_LEVELS, G_BIGSEG, G_LEVSUF, G_REGATH, G_MAXWIN, G_CHUNKS, G_FINALS, G_FINLEN, G_BATCHES, G_COUNT };
-constexpr uint32_t FL_STALLED = 1u;     // a level did not fit the scratch: the host finishes the build
-constexpr uint32_t FL_INCOMPLETE = 2u;  // segments remain after the last scheduled level
-
-// A run of suffixes [start, start+len) in key/handle buffer `buf`, whose keys
-// are for window r and agree on every digit before d.
-// Positions fit 32 bits (at most CXBWT_MAX_BASES bases).
-struct Seg {
-  uint32_t start;
-  uint32_t len;
-  uint16_t r;
-  uint8_t d;
-  uint8_t buf : 1;
-  uint8_t regather : 1;  // keys must be re-fetched for window r before use
-  uint8_t unsplit : 1;   // chunk only: suffixes are in read order, not yet split by digit d
-  uint32_t coll;         // collection the suffixes belong to
-};
-static_assert(sizeof(Seg) == 16, "segment records are 16 bytes");
-
-// Where collection c's rows go.  Suffix position j (a base position of the
-// whole batch) of collection c is BWT row j + row_shift of that collection,
-// stored at output byte j + out_shift (the outputs of the collections are
-// concatenated, each n_c + B_c bytes).
-struct CollMap {
-  uint64_t out_shift;  // reads in collections 0..c
-  int64_t row_shift;   // n_c - (first base of c)
-};
-
-// Statistics counters are spread over STAT_SPREAD cache lines (indexed by
-// workgroup) so that thousands of workgroups never queue on one address.
-constexpr int STAT_SPREAD = 64;
-constexpr int STAT_STRIDE = 16;  // u64 counters per 128-byte line
-// Kinds: window fetches, scattered suffixes, then what a level's scan
-// produced (folded and cleared after every scan): suffixes, re-keyed
-// suffixes, largest window, tiles and scan groups of the next level's
-// segments, and suffixes and tiles of the final groups.
-enum {
-  K_FETCHES = 0,
-  K_SCATTERED,
-  K_NEXT_LEN,
-  K_NEXT_REGATHER,
-  K_NEXT_MAXR,
-  K_NEXT_TILES,
-  K_NEXT_GROUPS,
-  K_FINAL_LEN,
-  K_FINAL_TILES,
-  K_KINDS
-};
-constexpr int K_LEVEL_FIRST = K_NEXT_LEN;
-constexpr int K_LEVEL_KINDS = K_KINDS - K_NEXT_LEN;
-constexpr uint64_t STAT_KIND = (uint64_t)STAT_SPREAD * STAT_STRIDE;
-constexpr uint64_t STAT_WORDS = K_KINDS * STAT_KIND;
-__device__ __forceinline__ unsigned long long *stat_slot(unsigned long long *base) {
-  return base + (blockIdx.x % STAT_SPREAD) * STAT_STRIDE;
-}
-
-struct Lists {
-  Seg *big_next;
-  uint32_t *n_big_next;          // high half of *n_chunk_big
-  uint32_t cap_big;
-  Seg *chunks;
-  unsigned long long *n_chunk_big;  // chunk count (low 32 bits), big count (high)
-  uint32_t cap_chunks;
-  Seg *finals;
-  uint32_t *n_finals;
-  uint32_t cap_finals;
-  uint32_t *status;
-  uint32_t rmax;
-  unsigned long long *stats;  // the statistics block (K_* kinds)
-  uint32_t chunk;  // largest run finished by one wave (the selected chunk size)
-  uint32_t tile_len;  // suffixes per level tile
-};
-
-// Number of read starts strictly before base p: for the first base of a
-// read, the index of that read among the non-empty reads.  srank[w] counts
-// the starts at positions below 16w.
-__device__ __forceinline__ uint32_t start_rank(const TextRec *__restrict__ text, const uint32_t *__restrict__ srank,
-                                               uint64_t p) {
-  const uint64_t below = text[p >> 4].lo & ((1ull << (p & 15)) - 1ull);
-  return srank[p >> 4] + (uint32_t)__popcll(below);
-}
-
-// Writes the BWT row of a sorted suffix; an offset-0 suffix also records its
-// row under its read's rank among the non-empty reads (k_term turns those
-// into term_pos).
-__device__ __forceinline__ void emit_row(uint64_t j, const CollMap &cm, uint64_t key, uint32_t p,
-                                         const TextRec *__restrict__ text, const uint32_t *__restrict__ srank,
-                                         uint8_t *__restrict__ bwt, uint64_t *__restrict__ start_row) {
-  const uint32_t pv = (uint32_t)key & 7u;
-  const uint32_t lut = 'A' | ('C' << 8) | ('G' << 16) | ('T' << 24);
-  bwt[j + cm.out_shift] = pv == 4 ? (uint8_t)'$' : (uint8_t)((lut >> (8 * pv)) & 0xFFu);
-  if (pv == 4) start_row[start_rank(text, srank, p)] = (uint64_t)((int64_t)j + cm.row_shift);
-}
-
-// Base t of the packed input (2 bits, first base of a word highest).
-__device__ __forceinline__ uint32_t base_at(const uint64_t *__restrict__ packed, uint64_t t) {
-  return (uint32_t)(packed[t >> 5] >> (62 - 2 * (t & 31))) & 3u;
-}
-
-// Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.  The
-// scatters give consecutive tiles to the same XCD (tile = xcd * (N/8) + k
-// for the k-th workgroup of an XCD), so that the partial cache lines that
-// neighbouring tiles write into one bucket meet in the same L2.
-#ifndef CXBWT_XCDS
-#define CXBWT_XCDS 8
-#endif
-__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t n) {
-  const uint32_t per = n / CXBWT_XCDS;
-  const uint32_t full = per * CXBWT_XCDS;
-  if (CXBWT_XCDS <= 1 || b >= full) return b;
-  return (b % CXBWT_XCDS) * per + b / CXBWT_XCDS;
-}
-
-__device__ __forceinline__ uint32_t find_upper(const uint32_t *prefix, uint32_t count, uint32_t x) {
-  // largest s < count with prefix[s] <= x (prefix[0] == 0, non-decreasing)
-  uint32_t lo = 0, hi = count;
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (prefix[mid] <= x) lo = mid;
-    else hi = mid;
-  }
-  return lo;
-}
-
-// ---------------------------------------------------------------------------
-// small utility kernels
-// ---------------------------------------------------------------------------
-__global__ void k_fill_u64(uint64_t *p, uint64_t n, uint64_t v) {
-  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (; i < n; i += (uint64_t)gridDim.x * blockDim.x) p[i] = v;
-}
-__global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
-  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (; i < n; i += (uint64_t)gridDim.x * blockDim.x) p[i] = v;
-}
-
-// ---------------------------------------------------------------------------
-// a0: read packing (ASCII -> 2-bit, first base in the top bits)
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t base_code(uint32_t c, bool &bad) {
-  // A C G T = 0x41 0x43 0x47 0x54 -> 0 1 2 3 by bits 2..1 of c ^ (c >> 1)
-  bad |= !(c == 'A' || c == 'C' || c == 'G' || c == 'T');
-  return ((c >> 2) ^ (c >> 1)) & 3u;
-}
-
-// One thread per 32-base word.  Full words with a 16-byte aligned source
-// are read as two 16-byte loads (a wave covers 2 KB contiguously); the tail
-// word and unaligned sources go byte by byte.
-__global__ void k_pack(const uint8_t *__restrict__ ascii, uint64_t nb, uint64_t *__restrict__ packed, uint64_t nwords,
-                       uint32_t *status) {
-  const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (w >= nwords) return;
-  const uint64_t t0 = w * 32;
-  uint64_t x = 0;
-  bool bad = false;
-  if (t0 + 32 <= nb && ((uintptr_t)ascii & 15) == 0) {
-    const uint4 *src = reinterpret_cast<const uint4 *>(ascii + t0);
-    const uint4 a = src[0], b = src[1];
-    const uint32_t v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int j = q * 4 + k;  // little-endian: byte k of word q is base j
-        x |= (uint64_t)base_code((v[q] >> (8 * k)) & 0xFFu, bad) << (62 - 2 * j);
-      }
-    }
-  } else {
-    for (int j = 0; j < 32; ++j) {
-      const uint64_t t = t0 + j;
-      if (t >= nb) break;
-      x |= (uint64_t)base_code(ascii[t], bad) << (62 - 2 * j);
-    }
-  }
-  packed[w] = x;
-  if (bad && status) atomicOr(status, ST_BAD_CHAR);
-}
-
-// ---------------------------------------------------------------------------
-// read preparation: validate offsets, mark read starts in a bitmap (bit t of
-// word t/32 for position t), emit the n rows of the bare terminators (row i =
-// $_i, preceded by the last base of read i)
-// ---------------------------------------------------------------------------
-__global__ void k_prep(const uint64_t *__restrict__ packed, const uint64_t *__restrict__ offsets, uint64_t n, uint64_t nb,
-                       uint32_t maxlen, const uint64_t *__restrict__ coll_reads, uint32_t ncoll,
-                       uint32_t *sbits, uint8_t *__restrict__ bwt, uint64_t *__restrict__ term_pos,
-                       uint32_t *status) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  // collection of read i: largest c with coll_reads[c] <= i
-  uint32_t clo = 0, chi = ncoll;
-  while (chi - clo > 1) {
-    const uint32_t mid = (clo + chi) >> 1;
-    if (coll_reads[mid] <= i) clo = mid;
-    else chi = mid;
-  }
-  const uint64_t first_read = coll_reads[clo];
-  const uint64_t a = offsets[i], b = offsets[i + 1];
-  const bool bad = b < a || b > nb || (i == 0 && a != 0) || (i == n - 1 && b != nb);
-  if (bad) {
-    atomicOr(status, ST_BAD_OFFSETS);
-    return;
-  }
-  if (b - a > (uint64_t)maxlen) {
-    atomicOr(status, ST_TOO_LONG);
-    return;
-  }
-  // row (i - first_read) of the collection, whose output starts at byte
-  // (bases before it) + (reads before it): byte offsets[first_read] + i.
-  // Valid offsets never decrease, so the collection's first offset is at
-  // most a; checking it keeps every write in bounds when another read's
-  // offsets are the invalid ones.
-  const uint64_t ob = offsets[first_read];
-  if (ob > a) {
-    atomicOr(status, ST_BAD_OFFSETS);
-    return;
-  }
-  const uint64_t out = ob + i;
-  if (i == n - 1) atomicOr(&sbits[nb >> 5], 1u << (nb & 31));  // end of the text
-  if (b > a) {
-    const uint64_t e = b - 1;
-    atomicOr(&sbits[a >> 5], 1u << (a & 31));
-    const uint32_t lut = 'A' | ('C' << 8) | ('G' << 16) | ('T' << 24);
-    bwt[out] = (uint8_t)((lut >> (8 * base_at(packed, e))) & 0xFFu);
-  } else {
-    bwt[out] = (uint8_t)'$';
-    term_pos[i] = i - first_read;
-  }
-}
-
-// 32 bases of the packed input starting at position t (a multiple of 16),
-// first base highest; words past the input read as zero.
-__device__ __forceinline__ uint64_t packed_at16(const uint64_t *__restrict__ packed, uint64_t nwords, uint64_t t) {
-  const uint64_t k = t >> 5;
-  const uint64_t w0 = k < nwords ? packed[k] : 0ull;
-  if (!(t & 31)) return w0;
-  const uint64_t w1 = k + 1 < nwords ? packed[k + 1] : 0ull;
-  return (w0 << 32) | (w1 >> 32);
-}
-
-// Text records from the packed bases and the read-start bitmap (k_prep);
-// the bitmap holds at least floor(B/32) + 4 zero-padded words.
-__global__ void k_text_records(const uint64_t *__restrict__ packed, uint64_t nwords, const uint32_t *__restrict__ sbits,
-                               TextRec *__restrict__ text, uint64_t nrec) {
-  const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (w >= nrec) return;
-  const uint64_t t = 16 * w;
-  TextRec r;
-  r.hi = packed_at16(packed, nwords, t);
-  const uint64_t tail = packed_at16(packed, nwords, t + 32) & ~((1ull << 44) - 1);  // bases t+32 .. t+41
-  const uint64_t prev = w ? (packed_at16(packed, nwords, t - 16) >> 32) & 3ull : 0ull;  // base t-1
-  const uint64_t k = t >> 5;
-  const uint64_t bits = (((uint64_t)sbits[k + 1] << 32) | sbits[k]) >> (t & 31);
-  r.lo = tail | (prev << 42) | (bits & REC_STARTS);
-  text[w] = r;
-}
-
-// First base of every collection (host needs them to lay out segments).
-__global__ void k_coll_bases(const uint64_t *__restrict__ offsets, const uint64_t *__restrict__ coll_reads,
-                             uint32_t ncoll, uint64_t *__restrict__ bases) {
-  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c <= ncoll) bases[c] = offsets[coll_reads[c]];
-}
-
-// ---------------------------------------------------------------------------
-// exclusive prefix counts of the read starts, per text record (each record
-// owns the start bits of its first 16 positions)
-// ---------------------------------------------------------------------------
-constexpr int RANK_WPT = 16;                      // words per thread
-constexpr int RANK_BLOCK_WORDS = BLOCK * RANK_WPT;
-
-// Counted on the read-start bitmap (32 positions a word, two records).
-__global__ __launch_bounds__(BLOCK) void k_rank_count(const uint32_t *__restrict__ sbits, uint64_t nw,
-                                                      uint32_t *__restrict__ blocksum) {
-  __shared__ uint32_t tmp[WAVES];
-  const uint64_t w0 = (uint64_t)blockIdx.x * RANK_BLOCK_WORDS + (uint64_t)threadIdx.x * RANK_WPT;
-  uint32_t c = 0;
-#pragma unroll
-  for (int i = 0; i < RANK_WPT; ++i)
-    if (w0 + i < nw) c += (uint32_t)__popc(sbits[w0 + i]);
-  uint32_t total;
-  block_excl_sum(c, tmp, &total);
-  if (threadIdx.x == 0) blocksum[blockIdx.x] = total;
-}
-
-__global__ __launch_bounds__(BLOCK) void k_rank_top(uint32_t *__restrict__ blocksum, uint32_t nblocks) {
-  __shared__ uint32_t tmp[WAVES];
-  uint32_t running = 0;
-  for (uint32_t base = 0; base < nblocks; base += BLOCK) {
-    const uint32_t i = base + threadIdx.x;
-    const uint32_t v = i < nblocks ? blocksum[i] : 0u;
-    uint32_t total;
-    const uint32_t ex = block_excl_sum(v, tmp, &total);
-    if (i < nblocks) blocksum[i] = running + ex;
-    running += total;
-  }
-}
-
-// srank of records 2k and 2k+1 from bitmap word k.
-__global__ __launch_bounds__(BLOCK) void k_rank_words(const uint32_t *__restrict__ sbits, uint64_t nw,
-                                                      const uint32_t *__restrict__ blocksum,
-                                                      uint32_t *__restrict__ srank, uint64_t nrec) {
-  __shared__ uint32_t tmp[WAVES];
-  const uint64_t w0 = (uint64_t)blockIdx.x * RANK_BLOCK_WORDS + (uint64_t)threadIdx.x * RANK_WPT;
-  uint32_t word[RANK_WPT];
-  uint32_t c = 0;
-#pragma unroll
-  for (int i = 0; i < RANK_WPT; ++i) {
-    word[i] = w0 + i < nw ? sbits[w0 + i] : 0u;
-    c += (uint32_t)__popc(word[i]);
-  }
-  uint32_t run = blocksum[blockIdx.x] + block_excl_sum(c, tmp, nullptr);
-#pragma unroll
-  for (int i = 0; i < RANK_WPT; ++i) {
-    const uint64_t r0 = 2 * (w0 + i);
-    if (r0 < nrec) srank[r0] = run;
-    if (r0 + 1 < nrec) srank[r0 + 1] = run + (uint32_t)__popc(word[i] & 0xFFFFu);
-    run += (uint32_t)__popc(word[i]);
-  }
-}
-
-// term_pos of every non-empty read from the row its offset-0 suffix recorded.
-// (A replayed graph runs this even when k_prep found the offsets invalid:
-// reads that leave the text are skipped, and the result is then reported
-// as an error.)
-__global__ void k_term(const uint64_t *__restrict__ offsets, uint64_t n, uint64_t nb,
-                       const TextRec *__restrict__ text, const uint32_t *__restrict__ srank,
-                       const uint64_t *__restrict__ start_row, uint64_t *__restrict__ term_pos) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint64_t a = offsets[i], b = offsets[i + 1];
-  if (b > a && b <= nb) term_pos[i] = start_row[start_rank(text, srank, a)];
-}
-
-// ---------------------------------------------------------------------------
-// a1 for collections that fit one chunk: window-0 keys in read order
-// ---------------------------------------------------------------------------
-
-__global__ __launch_bounds__(BLOCK) void k_gen(const Seg *__restrict__ segs, const uint32_t *__restrict__ tile_prefix,
-                                               uint32_t nsegs, uint32_t tile_len, const TextRec *__restrict__ text,
-                                               uint64_t nb, uint64_t *__restrict__ keys, uint32_t *__restrict__ hdl) {
-  const uint32_t tile = blockIdx.x;
-  const uint32_t s = find_upper(tile_prefix, nsegs, tile);
-  const Seg sg = segs[s];
-  const uint64_t t0 = sg.start + (uint64_t)(tile - tile_prefix[s]) * tile_len;
-  const uint64_t t1 = min(t0 + (uint64_t)tile_len, sg.start + sg.len);
-  for (uint64_t p = t0 + threadIdx.x; p < t1; p += BLOCK) {
-    keys[p] = first_key(text, nb, p);
-    hdl[p] = (uint32_t)p;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// a1 + a2, level 1: window-0 keys of every suffix of a collection (read
-// order, from the 2-bit reads) counted by their top digit, then recomputed
-// and scattered; keys are never stored unsorted.  One segment per collection.
-// ---------------------------------------------------------------------------
-template <int SUBT>
-__global__ __launch_bounds__(BLOCK) void k_gen_hist(const Seg *__restrict__ segs, const uint32_t *__restrict__ tile_prefix,
-                                                    uint32_t nsegs, uint32_t tile_len, const TextRec *__restrict__ text,
-                                                    uint64_t nb, uint32_t *__restrict__ tile_hist) {
-  __shared__ uint32_t hist[256];
-  const uint32_t tile = blockIdx.x;
-  const uint32_t s = find_upper(tile_prefix, nsegs, tile);
-  const Seg sg = segs[s];
-  const uint64_t t0 = sg.start + (uint64_t)(tile - tile_prefix[s]) * tile_len;
-  const uint64_t t1 = min(t0 + (uint64_t)tile_len, sg.start + sg.len);
-  hist[threadIdx.x] = 0;
-  __syncthreads();
-  // every record load of a sub-tile is issued before its first count
-#pragma unroll
-  for (int sub = 0; sub < SUBT; ++sub) {
-    const uint64_t u0 = t0 + (uint64_t)sub * BLOCK * MAX_TILE_ITEMS;
-    uint64_t kk[MAX_TILE_ITEMS];
-#pragma unroll
-    for (int i = 0; i < MAX_TILE_ITEMS; ++i) {
-      const uint64_t p = u0 + (uint64_t)i * BLOCK + threadIdx.x;
-      if (p < t1) kk[i] = first_key(text, nb, p);
-    }
-#pragma unroll
-    for (int i = 0; i < MAX_TILE_ITEMS; ++i)
-      if (u0 + (uint64_t)i * BLOCK + threadIdx.x < t1) atomicAdd(&hist[digit_of(kk[i], 0)], 1u);
-  }
-  __syncthreads();
-  tile_hist[(uint64_t)tile * 256 + threadIdx.x] = hist[threadIdx.x];
-}
-
-// Stable scatter of `m` items held in registers to global positions
-// base[digit] + rank-within-tile, staged through LDS so that each digit's run
-// is written contiguously.  A tile is NW waves x TI items: the wide tile
-// (8 waves, 4096 suffixes) writes runs twice as long per bucket, which the
-// memory system turns into fuller line writes.
-template <int TI, int NW>
-struct ScatterSmem {
-  // the per-wave digit counters are dead once every rank is known, before
-  // the first staged write: they share the key staging area
-  static_assert(NW * 256 * 4 <= 64 * NW * TI * 8, "counters fit the key stage");
-  union {
-    uint64_t sk[64 * NW * TI];
-    uint32_t wcount[NW * 256];
-  };
-  uint32_t sh[64 * NW * TI];
-  uint32_t dstart[256];
-  uint64_t goff[256];
-  uint32_t tmp[NW];
-};
-
-template <int TI, int NW>
-__device__ __forceinline__ void tile_scatter(ScatterSmem<TI, NW> &S, const uint64_t (&kr)[TI],
-                                             const uint32_t (&hr)[TI], const uint32_t (&dig)[TI], uint32_t m, int d,
-                                             uint64_t *__restrict__ Ko, uint32_t *__restrict__ Ho) {
-  uint32_t pos[TI];
-  block_multisplit<TI, NW>(dig, pos, S.wcount, S.dstart, S.tmp);
-  __syncthreads();  // every wave has read its counters before the stage is written
-#pragma unroll
-  for (int i = 0; i < TI; ++i) {
-    if (dig[i] != NODIGIT) {
-      S.sk[pos[i]] = kr[i];
-      S.sh[pos[i]] = hr[i];
-    }
-  }
-  __syncthreads();
-  for (uint32_t q = threadIdx.x; q < m; q += 64 * NW) {
-    const uint64_t k = S.sk[q];
-    const uint32_t dd = digit_of(k, d);
-    const uint64_t g = S.goff[dd] + (q - S.dstart[dd]);
-    Ko[g] = k;
-    Ho[g] = S.sh[q];
-  }
-}
-
-template <int TI, int NW>
-__global__ __launch_bounds__(64 * NW) void k_gen_scatter(const Seg *__restrict__ segs,
-                                                       const uint32_t *__restrict__ tile_prefix,
-                                                       const uint32_t *__restrict__ group_prefix, uint32_t nsegs,
-                                                       const TextRec *__restrict__ text, uint64_t nb,
-                                                       const uint32_t *__restrict__ tile_hist,
-                                                       const uint32_t *__restrict__ gsum, uint64_t *__restrict__ Ko,
-                                                       uint32_t *__restrict__ Ho) {
-  constexpr uint32_t TL = 64 * NW * TI;
-  __shared__ ScatterSmem<TI, NW> S;
-  const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-  const uint32_t s = find_upper(tile_prefix, nsegs, tile);
-  const Seg sg = segs[s];
-  const uint32_t tl = tile - tile_prefix[s];
-  const uint64_t t0 = sg.start + (uint64_t)tl * TL;
-  const uint32_t m = (uint32_t)min((uint64_t)TL, sg.start + sg.len - t0);
-  uint64_t kr[TI];
-  uint32_t hr[TI], dig[TI];
-#pragma unroll
-  for (int i = 0; i < TI; ++i) {
-    const uint32_t li = item_index<TI>(i);
-    if (li < m) {
-      kr[i] = first_key(text, nb, t0 + li);
-      hr[i] = (uint32_t)(t0 + li);
-      dig[i] = digit_of(kr[i], 0);
-    } else {
-      kr[i] = 0;
-      hr[i] = 0;
-      dig[i] = NODIGIT;
-    }
-  }
-  const uint32_t g = group_prefix[s] + tl / GROUP_TILES;
-  if (threadIdx.x < 256)
-    S.goff[threadIdx.x] =
-        (uint64_t)gsum[(uint64_t)g * 256 + threadIdx.x] + tile_hist[(uint64_t)tile * 256 + threadIdx.x];
-  tile_scatter(S, kr, hr, dig, m, 0, Ko, Ho);
-}
-
-// ---------------------------------------------------------------------------
-// a2/a3 levels 2..: split every oversized segment by one 8-bit digit
-// ---------------------------------------------------------------------------
-
-// Per-tile digit histogram and per-segment OR/AND of the ordering bits.  A
-// segment flagged `regather` first re-fetches its keys for window r.
-//
-// Kernels of levels 2.. take their segment count from dev_nsegs when it is
-// given (a launch whose size was fixed before the count was known) and loop
-// over their work with the grid's stride; with the count passed by value
-// the grid covers the work and each workgroup takes one item.
-template <bool PERSIST, int SUBT>
-__global__ __launch_bounds__(BLOCK) void k_level_hist(const Seg *__restrict__ segs, const uint32_t *__restrict__ tile_prefix,
-                                                      uint32_t nsegs, const uint32_t *__restrict__ dev_nsegs,
-                                                      uint32_t tile_len, uint64_t *keys0,
-                                                      uint64_t *keys1, const uint32_t *__restrict__ hdl0,
-                                                      const uint32_t *__restrict__ hdl1,
-                                                      const TextRec *__restrict__ text, uint64_t nb,
-                                                      uint32_t *__restrict__ tile_hist, unsigned long long *seg_or,
-                                                      unsigned long long *seg_and) {
-  __shared__ uint32_t hist[256];
-  __shared__ uint64_t red[WAVES];
-  if (dev_nsegs) nsegs = *dev_nsegs;
-  if (nsegs == 0) return;
-  const uint32_t ntiles = PERSIST ? tile_prefix[nsegs] : blockIdx.x + 1;
-  for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-  const uint32_t s = find_upper(tile_prefix, nsegs, tile);
-  const Seg sg = segs[s];
-  const uint64_t t0 = sg.start + (uint64_t)(tile - tile_prefix[s]) * tile_len;
-  const uint64_t t1 = min(t0 + (uint64_t)tile_len, sg.start + sg.len);
-  uint64_t *K = sg.buf ? keys1 : keys0;
-  const uint32_t *H = sg.buf ? hdl1 : hdl0;
-  hist[threadIdx.x] = 0;
-  __syncthreads();
-  // all loads of a sub-tile (keys, and for a re-keyed segment handles and
-  // then records) are issued before any result is used
-  uint64_t o = 0, a = ~0ull;
-  // SUBT sub-tiles of BLOCK * MAX_TILE_ITEMS (two for the wide tile)
-#pragma unroll
-  for (int sub = 0; sub < SUBT; ++sub) {
-    const uint64_t u0 = t0 + (uint64_t)sub * BLOCK * MAX_TILE_ITEMS;
-    uint64_t kk[MAX_TILE_ITEMS];
-    bool in[MAX_TILE_ITEMS];
-#pragma unroll
-    for (int i = 0; i < MAX_TILE_ITEMS; ++i) {
-      const uint64_t j = u0 + (uint64_t)i * BLOCK + threadIdx.x;
-      in[i] = j < t1;
-      if (in[i]) kk[i] = K[j];
-    }
-    if (sg.regather) {
-      uint32_t hh[MAX_TILE_ITEMS];
-      TextRec tr[MAX_TILE_ITEMS];
-#pragma unroll
-      for (int i = 0; i < MAX_TILE_ITEMS; ++i)
-        if (in[i]) hh[i] = H[u0 + (uint64_t)i * BLOCK + threadIdx.x];
-#pragma unroll
-      for (int i = 0; i < MAX_TILE_ITEMS; ++i)
-        if (in[i]) tr[i] = window_load(text, nb, hh[i], sg.r);
-#pragma unroll
-      for (int i = 0; i < MAX_TILE_ITEMS; ++i)
-        if (in[i]) {
-          kk[i] = window_combine(tr[i], nb, hh[i], sg.r, (uint32_t)kk[i] & 7u);
-          K[u0 + (uint64_t)i * BLOCK + threadIdx.x] = kk[i];
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < MAX_TILE_ITEMS; ++i)
-      if (in[i]) {
-        atomicAdd(&hist[digit_of(kk[i], sg.d)], 1u);
-        o |= kk[i];
-        a &= kk[i];
-      }
-  }
-  o = block_or(o, red);
-  a = block_and(a, red);
-  if (threadIdx.x == 0) {
-    atomicOr(&seg_or[s], (unsigned long long)order_bits(o));
-    atomicAnd(&seg_and[s], (unsigned long long)(a | 7ull));
-  }
-  tile_hist[(uint64_t)tile * 256 + threadIdx.x] = hist[threadIdx.x];
-  if (!PERSIST) break;
-  }
-}
-
-// First scan stage: inside each group of at most GROUP_TILES consecutive
-// tiles of one segment, turn tile counts into exclusive prefixes per digit
-// and record the group totals.  Sixteen tile counts are loaded before any
-// is rewritten, so the loop waits for memory once per sixteen tiles.
-template <bool PERSIST>
-__global__ __launch_bounds__(BLOCK) void k_group_scan(const uint32_t *__restrict__ tile_prefix,
-                                                      const uint32_t *__restrict__ group_prefix, uint32_t nsegs,
-                                                      const uint32_t *__restrict__ dev_nsegs,
-                                                      uint32_t *__restrict__ tile_hist, uint32_t *__restrict__ gsum) {
-  constexpr uint32_t NB = 16;
-  if (dev_nsegs) nsegs = *dev_nsegs;
-  if (nsegs == 0) return;
-  const uint32_t ngroups = PERSIST ? group_prefix[nsegs] : blockIdx.x + 1;
-  for (uint32_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
-  const uint32_t s = find_upper(group_prefix, nsegs, g);
-  const uint32_t tb = tile_prefix[s] + (g - group_prefix[s]) * GROUP_TILES;
-  const uint32_t te = min(tb + (uint32_t)GROUP_TILES, tile_prefix[s + 1]);
-  const uint32_t d = threadIdx.x;
-  uint32_t run = 0;
-  uint32_t t = tb;
-  for (; t + NB <= te; t += NB) {
-    uint32_t x[NB];
-#pragma unroll
-    for (uint32_t j = 0; j < NB; ++j) x[j] = tile_hist[(uint64_t)(t + j) * 256 + d];
-#pragma unroll
-    for (uint32_t j = 0; j < NB; ++j) {
-      tile_hist[(uint64_t)(t + j) * 256 + d] = run;
-      run += x[j];
-    }
-  }
-  for (; t < te; ++t) {
-    const uint64_t at = (uint64_t)t * 256 + d;
-    const uint32_t c = tile_hist[at];
-    tile_hist[at] = run;
-    run += c;
-  }
-  gsum[(uint64_t)g * 256 + d] = run;
-  if (!PERSIST) break;
-  }
-}
-
-// Digit totals of groups [g0, g1) added into cv (digit i*64 + lane in slot
-// i), eight groups in flight.
-__device__ __forceinline__ void group_totals(const uint32_t *__restrict__ gsum, uint32_t g0, uint32_t g1,
-                                             uint32_t (&cv)[4]) {
-  const uint32_t l = lane_id();
-  uint32_t g = g0;
-  for (; g + 8 <= g1; g += 8) {
-    uint32_t x[8][4];
-#pragma unroll
-    for (int j = 0; j < 8; ++j)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) x[j][i] = gsum[(uint64_t)(g + j) * 256 + i * 64 + l];
-#pragma unroll
-    for (int j = 0; j < 8; ++j)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) cv[i] += x[j][i];
-  }
-  for (; g < g1; ++g)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) cv[i] += gsum[(uint64_t)g * 256 + i * 64 + l];
-}
-
-// Group totals of groups [g0, g1) replaced by the running bucket positions
-// (starting at run), eight groups in flight.
-__device__ __forceinline__ void group_starts(uint32_t *__restrict__ gsum, uint32_t g0, uint32_t g1,
-                                             uint32_t (&run)[4]) {
-  const uint32_t l = lane_id();
-  uint32_t g = g0;
-  for (; g + 8 <= g1; g += 8) {
-    uint32_t x[8][4];
-#pragma unroll
-    for (int j = 0; j < 8; ++j)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) x[j][i] = gsum[(uint64_t)(g + j) * 256 + i * 64 + l];
-#pragma unroll
-    for (int j = 0; j < 8; ++j)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        gsum[(uint64_t)(g + j) * 256 + i * 64 + l] = run[i];
-        run[i] += x[j][i];
-      }
-  }
-  for (; g < g1; ++g)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const uint64_t at = (uint64_t)g * 256 + i * 64 + l;
-      const uint32_t c = gsum[at];
-      gsum[at] = run[i];
-      run[i] += c;
-    }
-}
-
-// First set bit at or above `from` of a 256-bit mask held as four words;
-// 256 when there is none.
-__device__ __forceinline__ uint32_t first_set_from(const uint64_t (&m)[4], uint32_t from) {
-  uint32_t res = 256;
-#pragma unroll
-  for (int i = 3; i >= 0; --i) {
-    uint64_t x = m[i];
-    if (from >= (uint32_t)(i + 1) * 64) x = 0;
-    else if (from > (uint32_t)i * 64) x &= ~0ull << (from - (uint32_t)i * 64);
-    if (x) res = (uint32_t)i * 64 + (uint32_t)__builtin_ctzll(x);
-  }
-  return res;
-}
-
-// Value of bucket b (< 256) of a wave-distributed 256-entry array (bucket
-// i*64 + lane in slot i), the same in every lane.
-__device__ __forceinline__ uint32_t bucket_at(const uint32_t (&v)[4], uint32_t b) {
-  const int ln = (int)(b & 63);
-  const uint32_t x0 = (uint32_t)__builtin_amdgcn_readlane((int)v[0], ln);
-  const uint32_t x1 = (uint32_t)__builtin_amdgcn_readlane((int)v[1], ln);
-  const uint32_t x2 = (uint32_t)__builtin_amdgcn_readlane((int)v[2], ln);
-  const uint32_t x3 = (uint32_t)__builtin_amdgcn_readlane((int)v[3], ln);
-  const uint32_t i = b >> 6;
-  return i == 0 ? x0 : i == 1 ? x1 : i == 2 ? x2 : x3;
-}
-
-// Sum over the wave, in every lane.
-__device__ __forceinline__ uint32_t wave_total(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-// Number of set bits of m below this lane.
-__device__ __forceinline__ uint32_t bits_below_lane(uint64_t m) {
-  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-}
-
-// Second scan stage.  Each segment gets its digit totals from the group
-// totals, its bucket starts and the start of every (group, digit) run, and
-// its buckets are sorted into chunks (runs of consecutive small buckets of
-// at most L.chunk suffixes), segments for the next level (buckets above
-// L.chunk) and final groups of identical suffixes (an ended tie at the last
-// digit).  A segment whose current digit is constant is not scattered: it
-// moves to its first varying digit, or, when all its ordering bits agree, to
-// the next window (a full tie) or to the final list (an ended tie).
-//
-// COOP = false: one wave per segment, WAVES segments per workgroup.
-// COOP = true: one segment per workgroup, its groups shared by the waves
-// (for segments spanning many groups).  All control below is uniform per
-// wave: chunk boundaries come from a walk of one step per chunk over bucket
-// masks, and the list entries are written by all lanes at once from
-// positions reserved with one atomic per list per workgroup.
-template <bool COOP, bool PERSIST>
-__global__ __launch_bounds__(BLOCK) void k_level_scan(const Seg *__restrict__ segs,
-                                                      const uint32_t *__restrict__ group_prefix, uint32_t nsegs,
-                                                      uint32_t *__restrict__ gsum,
-                                                      const unsigned long long *__restrict__ seg_or,
-                                                      const unsigned long long *__restrict__ seg_and,
-                                                      uint8_t *__restrict__ seg_split, Lists L, int force_split,
-                                                      const uint32_t *__restrict__ dev_nsegs) {
-  constexpr int CW = COOP ? 1 : WAVES;  // waves that classify a segment
-  __shared__ uint32_t part[COOP ? WAVES : 1][256];
-  __shared__ uint32_t cstart[CW][256];
-  __shared__ uint32_t clen[CW][256];
-  __shared__ uint32_t wbv[CW][257];  // bucket starts of the classifying wave, then the segment length
-  __shared__ uint32_t wnx[CW][256];  // per bucket: end of a chunk starting there | next chunk start << 16
-  __shared__ uint32_t wcnt[WAVES][3];
-  __shared__ uint32_t wbase[WAVES][3];
-  __shared__ uint32_t wstat[WAVES][K_LEVEL_KINDS];
-  const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const uint32_t l = lane_id();
-  if (dev_nsegs) nsegs = *dev_nsegs;
-  constexpr uint32_t SPB = COOP ? 1u : (uint32_t)WAVES;  // segments per workgroup step
-  for (uint32_t blk = blockIdx.x; blk * SPB < nsegs; blk += gridDim.x) {
-  if (PERSIST) __syncthreads();  // the previous step's LDS reads are done
-  const uint32_t s = COOP ? blk : blk * WAVES + w;
-  const uint32_t cw = COOP ? 0 : w;  // this wave's chunk-list slot
-  uint32_t cv[4] = {0, 0, 0, 0}, bv[4] = {0, 0, 0, 0};
-  int mode = 0;  // 0: no segment, 1: passes through unsplit, 2: split by digit d
-  Seg sg{};
-  Seg nx{};
-  int nx_list = 0;  // mode 1: 0 none, 1 next level, 2 final
-  if (s < nsegs) {
-    sg = segs[s];
-    const uint32_t gp0 = group_prefix[s], gp1 = group_prefix[s + 1];
-    uint32_t pre[4] = {0, 0, 0, 0};
-    uint32_t ga = gp0, gb = gp1;
-    if (COOP) {
-      const uint32_t per = (gp1 - gp0 + WAVES - 1) / WAVES;
-      ga = min(gp0 + w * per, gp1);
-      gb = min(ga + per, gp1);
-      uint32_t pc[4] = {0, 0, 0, 0};
-      group_totals(gsum, ga, gb, pc);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) part[w][i * 64 + l] = pc[i];
-      __syncthreads();
-      for (uint32_t ww = 0; ww < (uint32_t)WAVES; ++ww)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const uint32_t x = part[ww][i * 64 + l];
-          cv[i] += x;
-          if (ww < w) pre[i] += x;
-        }
-    } else {
-      group_totals(gsum, gp0, gp1, cv);
-    }
-    bool one = false;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) one |= cv[i] == sg.len;
-    if (__ballot(one) && !force_split) {
-      mode = 1;
-      const unsigned long long o = seg_or[s], a = seg_and[s];
-      const uint64_t diff = (o ^ a) & ~7ull;
-      nx = sg;
-      nx.regather = 0;
-      if (diff == 0) {
-        if (clamp_of(a) < (uint32_t)W) {
-          nx = sg;
-          nx_list = 2;
-        } else if (sg.r + 1 > L.rmax) {
-          if (l == 0 && (!COOP || w == 0)) atomicOr(L.status, ST_WINDOW_BOUND);
-        } else {
-          nx.r = sg.r + 1;
-          nx.d = 0;
-          nx.regather = 1;
-          nx_list = 1;
-        }
-      } else {
-        const int top = 63 - __builtin_clzll(diff);
-        nx.d = (uint8_t)(top >= 8 ? (63 - top) >> 3 : 7);
-        nx_list = 1;
-      }
-    } else {
-      mode = 2;
-      // bucket starts: exclusive scan over the digits in order
-      uint32_t carry = 0;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const uint32_t inc = wave_incl_sum(cv[i]);
-        bv[i] = carry + inc - cv[i];
-        carry += (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
-      }
-      uint32_t run[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) run[i] = sg.start + bv[i] + pre[i];
-      group_starts(gsum, ga, gb, run);
-    }
-  }
-  if (COOP && w != 0) mode = 0;  // wave 0 classifies the workgroup's segment
-
-  uint32_t nc = 0, nbg = 0, nf = 0;
-  uint64_t NB[4] = {0, 0, 0, 0}, FIN[4] = {0, 0, 0, 0};
-  // what this wave hands on: K_NEXT_LEN .. K_FINAL_TILES
-  uint32_t ls[K_LEVEL_KINDS] = {0, 0, 0, 0, 0, 0, 0};
-  const uint32_t T = L.tile_len;
-  if (mode == 1) {
-    nbg = nx_list == 1;
-    nf = nx_list == 2;
-    const uint32_t nt = (nx.len + T - 1) / T;
-    if (nx_list == 1) {
-      ls[K_NEXT_LEN - K_LEVEL_FIRST] = nx.len;
-      ls[K_NEXT_REGATHER - K_LEVEL_FIRST] = nx.regather ? nx.len : 0u;
-      ls[K_NEXT_MAXR - K_LEVEL_FIRST] = nx.r;
-      ls[K_NEXT_TILES - K_LEVEL_FIRST] = nt;
-      ls[K_NEXT_GROUPS - K_LEVEL_FIRST] = (nt + GROUP_TILES - 1) / GROUP_TILES;
-    } else if (nx_list == 2) {
-      ls[K_FINAL_LEN - K_LEVEL_FIRST] = nx.len;
-      ls[K_FINAL_TILES - K_LEVEL_FIRST] = nt;
-    }
-  } else if (mode == 2) {
-    const uint32_t C = L.chunk;
-    uint64_t NZS[4], BIG[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      NZS[i] = __ballot(cv[i] != 0 && cv[i] <= C);
-      BIG[i] = __ballot(cv[i] > C);
-    }
-    // chunks: a chunk starts at a non-empty small bucket and takes the
-    // following buckets while its size stays within C and no big bucket
-    // intervenes.  Every lane first finds, for its four buckets b, where a
-    // chunk starting at b would end (e: the first big bucket after b, or the
-    // first bucket that would take the size above C, by binary search on the
-    // bucket starts) and where the next chunk would start (the first
-    // non-empty small bucket at or after e); the walk over the chunk starts
-    // is then one LDS read per chunk.
-#pragma unroll
-    for (int i = 0; i < 4; ++i) wbv[cw][i * 64 + l] = bv[i];
-    if (l == 0) wbv[cw][256] = sg.len;
-    uint32_t big_after[4], nzs_after[4];  // first set bit in the words above word i
-    {
-      uint32_t fb = 256, fn = 256;
-#pragma unroll
-      for (int i = 3; i >= 0; --i) {
-        big_after[i] = fb;
-        nzs_after[i] = fn;
-        if (BIG[i]) fb = (uint32_t)i * 64 + (uint32_t)__builtin_ctzll(BIG[i]);
-        if (NZS[i]) fn = (uint32_t)i * 64 + (uint32_t)__builtin_ctzll(NZS[i]);
-      }
-    }
-    const uint64_t above = ~(lanemask_lt() | (1ull << l));  // lanes above this one
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const uint32_t b = (uint32_t)i * 64 + l;
-      const uint32_t sb = bv[i];
-      // largest x >= b whose prefix bv[x] + cv[x] = wbv[x + 1] stays within
-      // sb + C (monotone in x); differences, so sb + C cannot wrap
-      uint32_t x = b;
-#pragma unroll
-      for (uint32_t step = 128; step > 0; step >>= 1) {
-        const uint32_t y = x + step;
-        if (y < 256 && wbv[cw][y + 1] - sb <= C) x = y;
-      }
-      const uint64_t mb = BIG[i] & above;
-      const uint32_t nbig = mb ? (uint32_t)i * 64 + (uint32_t)__builtin_ctzll(mb) : big_after[i];
-      const uint32_t e = min(x + 1, nbig);
-      uint32_t nxt = 256;
-      if (e < 256) {
-        const uint32_t w = e >> 6;
-        const uint64_t word = w == 0 ? NZS[0] : w == 1 ? NZS[1] : w == 2 ? NZS[2] : NZS[3];
-        const uint64_t m = word & (~0ull << (e & 63));
-        const uint32_t after = w == 0 ? nzs_after[0] : w == 1 ? nzs_after[1] : w == 2 ? nzs_after[2] : nzs_after[3];
-        nxt = m ? w * 64 + (uint32_t)__builtin_ctzll(m) : after;
-      }
-      wnx[cw][b] = e | (nxt << 16);
-    }
-    uint32_t b = first_set_from(NZS, 0);
-    while (b < 256) {
-      const uint32_t v = (uint32_t)__builtin_amdgcn_readfirstlane((int)wnx[cw][b]);
-      const uint32_t e = v & 0xFFFFu;
-      const uint32_t sb = (uint32_t)__builtin_amdgcn_readfirstlane((int)wbv[cw][b]);
-      const uint32_t se = (uint32_t)__builtin_amdgcn_readfirstlane((int)wbv[cw][e]);
-      if (l == 0) {
-        cstart[cw][nc] = sb;
-        clen[cw][nc] = se - sb;
-      }
-      ++nc;
-      b = v >> 16;
-    }
-    if (sg.d == 7) {
-      // bucket value b is the clamped length; all ordering bits agree
-      FIN[0] = BIG[0] & ((1ull << W) - 1);
-      NB[0] = BIG[0] & ~FIN[0];
-      NB[1] = BIG[1];
-      NB[2] = BIG[2];
-      NB[3] = BIG[3];
-      if ((NB[0] | NB[1] | NB[2] | NB[3]) && sg.r + 1 > L.rmax) {
-        if (l == 0) atomicOr(L.status, ST_WINDOW_BOUND);
-        NB[0] = NB[1] = NB[2] = NB[3] = 0;
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) NB[i] = BIG[i];
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      nbg += (uint32_t)__popcll(NB[i]);
-      nf += (uint32_t)__popcll(FIN[i]);
-    }
-    uint32_t blen = 0, btiles = 0, bgroups = 0, flen = 0, ftiles = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const uint32_t nt = (cv[i] + T - 1) / T;
-      if ((NB[i] >> l) & 1) {
-        blen += cv[i];
-        btiles += nt;
-        bgroups += (nt + GROUP_TILES - 1) / GROUP_TILES;
-      }
-      if ((FIN[i] >> l) & 1) {
-        flen += cv[i];
-        ftiles += nt;
-      }
-    }
-    blen = wave_total(blen);
-    ls[K_NEXT_LEN - K_LEVEL_FIRST] = blen;
-    ls[K_NEXT_REGATHER - K_LEVEL_FIRST] = sg.d == 7 ? blen : 0u;
-    ls[K_NEXT_MAXR - K_LEVEL_FIRST] = nbg ? sg.r + (sg.d == 7 ? 1u : 0u) : 0u;
-    ls[K_NEXT_TILES - K_LEVEL_FIRST] = wave_total(btiles);
-    ls[K_NEXT_GROUPS - K_LEVEL_FIRST] = wave_total(bgroups);
-    ls[K_FINAL_LEN - K_LEVEL_FIRST] = wave_total(flen);
-    ls[K_FINAL_TILES - K_LEVEL_FIRST] = wave_total(ftiles);
-    if (l == 0) {
-      seg_split[s] = 1;
-      atomicAdd(stat_slot(L.stats + K_SCATTERED * STAT_KIND), (unsigned long long)sg.len);
-    }
-  }
-  if (mode == 1 && l == 0) seg_split[s] = 0;
-  if (l == 0) {
-    wcnt[w][0] = nc;
-    wcnt[w][1] = nbg;
-    wcnt[w][2] = nf;
-#pragma unroll
-    for (int k = 0; k < K_LEVEL_KINDS; ++k) wstat[w][k] = ls[k];
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < K_LEVEL_KINDS; ++k) {
-      unsigned long long v = 0;
-      for (int ww = 0; ww < WAVES; ++ww)
-        v = (k + K_LEVEL_FIRST == K_NEXT_MAXR) ? max(v, (unsigned long long)wstat[ww][k]) : v + wstat[ww][k];
-      unsigned long long *slot = stat_slot(L.stats + (k + K_LEVEL_FIRST) * STAT_KIND);
-      if (v) {
-        if (k + K_LEVEL_FIRST == K_NEXT_MAXR) atomicMax(slot, v);
-        else atomicAdd(slot, v);
-      }
-    }
-    uint32_t tc = 0, tb = 0, tf = 0;
-    for (int ww = 0; ww < WAVES; ++ww) {
-      wbase[ww][0] = tc;
-      wbase[ww][1] = tb;
-      wbase[ww][2] = tf;
-      tc += wcnt[ww][0];
-      tb += wcnt[ww][1];
-      tf += wcnt[ww][2];
-    }
-    // one atomic reserves the chunk and big-segment slots together
-    unsigned long long old = 0;
-    if (tc || tb) old = atomicAdd(L.n_chunk_big, (unsigned long long)tc | ((unsigned long long)tb << 32));
-    const uint32_t bf = tf ? atomicAdd(L.n_finals, tf) : 0u;
-    for (int ww = 0; ww < WAVES; ++ww) {
-      wbase[ww][0] += (uint32_t)old;
-      wbase[ww][1] += (uint32_t)(old >> 32);
-      wbase[ww][2] += bf;
-    }
-  }
-  __syncthreads();
-  const uint32_t base_c = wbase[w][0], base_b = wbase[w][1], base_f = wbase[w][2];
-  bool overflow = false;
-  if (mode == 1) {
-    if (l == 0 && nx_list == 1) {
-      if (base_b < L.cap_big) L.big_next[base_b] = nx;
-      else overflow = true;
-    }
-    if (l == 0 && nx_list == 2) {
-      if (base_f < L.cap_finals) L.finals[base_f] = nx;
-      else overflow = true;
-    }
-  } else if (mode == 2) {
-    const uint8_t nbuf = (uint8_t)(sg.buf ^ 1);
-    for (uint32_t j = l; j < nc; j += 64) {
-      const uint32_t at = base_c + j;
-      if (at < L.cap_chunks) L.chunks[at] = Seg{sg.start + cstart[cw][j], clen[cw][j], sg.r, sg.d, nbuf, 0, 0, sg.coll};
-      else overflow = true;
-    }
-    const bool last = sg.d == 7;
-    uint32_t pb = 0, pf = 0;  // entries of the lower slots
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const uint32_t st = sg.start + bv[i];
-      if ((NB[i] >> l) & 1) {
-        const uint32_t at = base_b + pb + bits_below_lane(NB[i]);
-        const Seg e = last ? Seg{st, cv[i], (uint16_t)(sg.r + 1), 0, nbuf, 1, 0, sg.coll}
-                           : Seg{st, cv[i], sg.r, (uint8_t)(sg.d + 1), nbuf, 0, 0, sg.coll};
-        if (at < L.cap_big) L.big_next[at] = e;
-        else overflow = true;
-      }
-      if ((FIN[i] >> l) & 1) {
-        const uint32_t at = base_f + pf + bits_below_lane(FIN[i]);
-        if (at < L.cap_finals) L.finals[at] = Seg{st, cv[i], sg.r, (uint8_t)(sg.d + 1), nbuf, 0, 0, sg.coll};
-        else overflow = true;
-      }
-      pb += (uint32_t)__popcll(NB[i]);
-      pf += (uint32_t)__popcll(FIN[i]);
-    }
-  }
-  if (overflow) atomicOr(L.status, ST_LIST_OVERFLOW);
-  if (!PERSIST) break;
-  }
-}
-
-// Folds the level kinds of the statistics block into out[0..K_LEVEL_KINDS)
-// (sums, a maximum for the window) and clears them for the next scan.  One
-// wave.
-__global__ __launch_bounds__(64) void k_level_fold(unsigned long long *__restrict__ stats,
-                                                   unsigned long long *__restrict__ out,
-                                                   const uint32_t *__restrict__ flags) {
-  const uint32_t l = lane_id();
-  if (flags && (*flags & (FL_STALLED | FL_INCOMPLETE))) return;  // keep what the host resumes from
-  for (int k = K_LEVEL_FIRST; k < K_KINDS; ++k) {
-    unsigned long long *slot = stats + k * STAT_KIND + (uint64_t)l * STAT_STRIDE;
-    unsigned long long v = *slot;
-    *slot = 0;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const unsigned long long t = __shfl_xor(v, o, 64);
-      v = k == K_NEXT_MAXR ? max(v, t) : v + t;
-    }
-    if (l == 0) out[k - K_LEVEL_FIRST] = v;
-  }
-}
-
-// Clears the per-segment OR/AND words of the segments counted at *dev_n.
-__global__ void k_fill_seg(unsigned long long *__restrict__ seg_or, unsigned long long *__restrict__ seg_and,
-                           const uint32_t *__restrict__ dev_n) {
-  const uint32_t n = *dev_n;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    seg_or[i] = 0;
-    seg_and[i] = ~0ull;
-  }
-}
-
-// Between two levels of a build scheduled on the device (one thread): adds
-// the finished level's chunks and final groups to the running totals, then
-// makes the segments the level handed on the current ones (C_NCUR), or
-// flags the build for the host when they would not fit the scratch or when
-// no level is left.
-__global__ void k_level_step(uint32_t *__restrict__ c, uint64_t seg_slots, uint64_t max_tiles, uint64_t max_groups,
-                             int last) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const uint32_t fl = c[C_FLAGS];
-  if (fl & (FL_STALLED | FL_INCOMPLETE)) return;
-  const unsigned long long *f = reinterpret_cast<const unsigned long long *>(c + C_FOLD);
-  unsigned long long *g = reinterpret_cast<unsigned long long *>(c + C_CUM);
-  g[G_CHUNKS] += c[C_NCHUNK];
-  g[G_FINALS] += c[C_NFINAL];
-  g[G_FINLEN] += f[K_FINAL_LEN - K_LEVEL_FIRST];
-  c[C_NCHUNK] = 0;
-  c[C_NFINAL] = 0;
-  c[C_NCUR] = 0;
-  const uint32_t nbig = c[C_NBIG];
-  if (nbig == 0) return;
-  if (last) {
-    c[C_FLAGS] = fl | FL_INCOMPLETE;
-    return;
-  }
-  if (nbig > seg_slots || f[K_NEXT_TILES - K_LEVEL_FIRST] > max_tiles ||
-      f[K_NEXT_GROUPS - K_LEVEL_FIRST] > max_groups) {
-    c[C_FLAGS] = fl | FL_STALLED;
-    return;
-  }
-  c[C_NCUR] = nbig;
-  c[C_NBIG] = 0;
-  g[G_LEVELS] += 1;
-  g[G_BIGSEG] += nbig;
-  g[G_LEVSUF] += f[K_NEXT_LEN - K_LEVEL_FIRST];
-  g[G_REGATH] += f[K_NEXT_REGATHER - K_LEVEL_FIRST];
-  g[G_MAXWIN] = max(g[G_MAXWIN], f[K_NEXT_MAXR - K_LEVEL_FIRST]);
-  g[G_BATCHES] += 1;
-}
-
-// A replayed build checks that the collection bases are those it was
-// captured for.
-__global__ void k_check_bases(const uint64_t *__restrict__ got, const uint64_t *__restrict__ want, uint32_t count,
-                              uint32_t *status) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count && got[i] != want[i]) atomicOr(status, ST_PLAN_MISMATCH);
-}
-
-// Tile and group prefixes of a segment list on the device.  Entries sit
-// item_index<SEGP_ITEMS> in each workgroup of BLOCK threads; k_seg_count
-// writes per-workgroup totals (tiles, groups), k_seg_scan adds the totals
-// of the workgroups before it, writes tile_prefix[i] and group_prefix[i]
-// (and entry n: the totals) and, when copy is given, the list itself.
-constexpr int SEGP_ITEMS = 16;
-constexpr uint32_t SEGP_WG = BLOCK * SEGP_ITEMS;
-
-__device__ __forceinline__ void seg_tiles(const Seg *__restrict__ list, uint32_t n, uint32_t tile_len,
-                                          uint32_t (&t)[SEGP_ITEMS], uint32_t (&g)[SEGP_ITEMS]) {
-#pragma unroll
-  for (int i = 0; i < SEGP_ITEMS; ++i) {
-    const uint64_t at = (uint64_t)blockIdx.x * SEGP_WG + item_index<SEGP_ITEMS>(i);
-    const uint32_t len = at < n ? list[at].len : 0u;
-    t[i] = (len + tile_len - 1) / tile_len;
-    g[i] = (t[i] + GROUP_TILES - 1) / GROUP_TILES;
-  }
-}
-
-__global__ __launch_bounds__(BLOCK) void k_seg_count(const Seg *__restrict__ list, uint32_t n,
-                                                     const uint32_t *__restrict__ dev_n, uint32_t tile_len,
-                                                     uint32_t *__restrict__ wg_tot) {
-  __shared__ uint32_t tmp[WAVES];
-  if (dev_n) n = *dev_n;
-  if ((uint64_t)blockIdx.x * SEGP_WG >= n) return;
-  uint32_t t[SEGP_ITEMS], g[SEGP_ITEMS];
-  seg_tiles(list, n, tile_len, t, g);
-  uint32_t st = 0, sgr = 0;
-#pragma unroll
-  for (int i = 0; i < SEGP_ITEMS; ++i) {
-    st += t[i];
-    sgr += g[i];
-  }
-  uint32_t tt = 0, tg = 0;
-  (void)block_excl_sum(st, tmp, &tt);
-  (void)block_excl_sum(sgr, tmp, &tg);
-  if (threadIdx.x == 0) {
-    wg_tot[2 * blockIdx.x] = tt;
-    wg_tot[2 * blockIdx.x + 1] = tg;
-  }
-}
-
-__global__ __launch_bounds__(BLOCK) void k_seg_scan(const Seg *__restrict__ list, uint32_t n,
-                                                    const uint32_t *__restrict__ dev_n, uint32_t tile_len,
-                                                    const uint32_t *__restrict__ wg_tot, Seg *__restrict__ copy,
-                                                    uint32_t *__restrict__ tile_prefix,
-                                                    uint32_t *__restrict__ group_prefix) {
-  __shared__ uint32_t tmp[WAVES];
-  __shared__ uint32_t wt[WAVES][2];
-  if (dev_n) n = *dev_n;
-  if ((uint64_t)blockIdx.x * SEGP_WG >= n) return;
-  // base of this workgroup: the totals of the workgroups before it
-  uint32_t bt = 0, bg = 0;
-  for (uint32_t k = threadIdx.x; k < blockIdx.x; k += BLOCK) {
-    bt += wg_tot[2 * k];
-    bg += wg_tot[2 * k + 1];
-  }
-  uint32_t sum_t = 0, sum_g = 0;
-  (void)block_excl_sum(bt, tmp, &sum_t);
-  (void)block_excl_sum(bg, tmp, &sum_g);
-  uint32_t t[SEGP_ITEMS], g[SEGP_ITEMS];
-  seg_tiles(list, n, tile_len, t, g);
-  // exclusive prefixes inside the wave, items in item_index order
-  const uint32_t w = threadIdx.x >> 6;
-  uint32_t pt[SEGP_ITEMS], pg[SEGP_ITEMS];
-  uint32_t ct = 0, cg = 0;
-#pragma unroll
-  for (int i = 0; i < SEGP_ITEMS; ++i) {
-    const uint32_t it = wave_incl_sum(t[i]), ig = wave_incl_sum(g[i]);
-    pt[i] = ct + it - t[i];
-    pg[i] = cg + ig - g[i];
-    ct += (uint32_t)__builtin_amdgcn_readlane((int)it, 63);
-    cg += (uint32_t)__builtin_amdgcn_readlane((int)ig, 63);
-  }
-  if (lane_id() == 0) {
-    wt[w][0] = ct;
-    wt[w][1] = cg;
-  }
-  __syncthreads();
-  uint32_t wbt = sum_t, wbg = sum_g;
-  for (uint32_t ww = 0; ww < w; ++ww) {
-    wbt += wt[ww][0];
-    wbg += wt[ww][1];
-  }
-#pragma unroll
-  for (int i = 0; i < SEGP_ITEMS; ++i) {
-    const uint64_t at = (uint64_t)blockIdx.x * SEGP_WG + item_index<SEGP_ITEMS>(i);
-    if (at < n) {
-      tile_prefix[at] = wbt + pt[i];
-      if (group_prefix) group_prefix[at] = wbg + pg[i];
-      if (copy) copy[at] = list[at];
-      if (at == n - 1) {
-        tile_prefix[n] = wbt + pt[i] + t[i];
-        if (group_prefix) group_prefix[n] = wbg + pg[i] + g[i];
-      }
-    }
-  }
-}
-
-// Stable scatter of one tile by its segment's digit into the other buffer.
-template <int TI, int NW, bool PERSIST>
-__global__ __launch_bounds__(64 * NW) void k_level_scatter(const Seg *__restrict__ segs,
-                                                         const uint32_t *__restrict__ tile_prefix,
-                                                         const uint32_t *__restrict__ group_prefix, uint32_t nsegs,
-                                                         const uint32_t *__restrict__ dev_nsegs,
-                                                         const uint8_t *__restrict__ seg_split,
-                                                         const uint32_t *__restrict__ tile_hist,
-                                                         const uint32_t *__restrict__ gsum, uint64_t *keys0,
-                                                         uint64_t *keys1, uint32_t *hdl0, uint32_t *hdl1) {
-  constexpr uint32_t TL = 64 * NW * TI;
-  __shared__ ScatterSmem<TI, NW> S;
-  if (dev_nsegs) nsegs = *dev_nsegs;
-  if (nsegs == 0) return;
-  // virtual block v maps to a tile as a grid of ntiles would (neighbouring
-  // tiles on one XCD); a persistent grid is a multiple of the XCD count, so
-  // every workgroup stays on the XCD of its tiles
-  const uint32_t ntiles = PERSIST ? tile_prefix[nsegs] : gridDim.x;
-  for (uint32_t v = blockIdx.x; v < ntiles; v += gridDim.x) {
-  const uint32_t tile = xcd_tile(v, ntiles);
-  const uint32_t s = find_upper(tile_prefix, nsegs, tile);
-  if (!seg_split[s]) {
-    if (!PERSIST) break;
-    continue;
-  }
-  if (PERSIST) __syncthreads();  // the previous tile's LDS reads are done
-  const Seg sg = segs[s];
-  const uint32_t tl = tile - tile_prefix[s];
-  const uint64_t t0 = sg.start + (uint64_t)tl * TL;
-  const uint32_t m = (uint32_t)min((uint64_t)TL, sg.start + sg.len - t0);
-  const uint64_t *Ki = sg.buf ? keys1 : keys0;
-  const uint32_t *Hi = sg.buf ? hdl1 : hdl0;
-  uint64_t *Ko = sg.buf ? keys0 : keys1;
-  uint32_t *Ho = sg.buf ? hdl0 : hdl1;
-  const int d = sg.d;
-  uint64_t kr[TI];
-  uint32_t hr[TI], dig[TI];
-#pragma unroll
-  for (int i = 0; i < TI; ++i) {
-    const uint32_t li = item_index<TI>(i);
-    if (li < m) {
-      kr[i] = Ki[t0 + li];
-      hr[i] = Hi[t0 + li];
-      dig[i] = digit_of(kr[i], d);
-    } else {
-      kr[i] = 0;
-      hr[i] = 0;
-      dig[i] = NODIGIT;
-    }
-  }
-  const uint32_t g = group_prefix[s] + tl / GROUP_TILES;
-  if (threadIdx.x < 256)
-    S.goff[threadIdx.x] =
-        (uint64_t)gsum[(uint64_t)g * 256 + threadIdx.x] + tile_hist[(uint64_t)tile * 256 + threadIdx.x];
-  tile_scatter(S, kr, hr, dig, m, d, Ko, Ho);
-  if (!PERSIST) break;
-  }
-}
-
-// Groups of identical suffixes too large for one workgroup: emit in place.
-template <bool PERSIST>
-__global__ __launch_bounds__(BLOCK) void k_emit_final(const Seg *__restrict__ segs, const uint32_t *__restrict__ tile_prefix,
-                                                      uint32_t nsegs, const uint32_t *__restrict__ dev_nsegs,
-                                                      uint32_t tile_len, const uint64_t *__restrict__ keys0,
-                                                      const uint64_t *__restrict__ keys1, const uint32_t *__restrict__ hdl0,
-                                                      const uint32_t *__restrict__ hdl1, const TextRec *__restrict__ text,
-                                                      const uint32_t *__restrict__ srank,
-                                                      const CollMap *__restrict__ cmap, uint8_t *__restrict__ bwt,
-                                                      uint64_t *__restrict__ start_row) {
-  if (dev_nsegs) nsegs = *dev_nsegs;
-  if (nsegs == 0) return;
-  const uint32_t ntiles = PERSIST ? tile_prefix[nsegs] : blockIdx.x + 1;
-  for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const uint32_t s = find_upper(tile_prefix, nsegs, tile);
-    const Seg sg = segs[s];
-    const uint64_t t0 = sg.start + (uint64_t)(tile - tile_prefix[s]) * tile_len;
-    const uint64_t t1 = min(t0 + (uint64_t)tile_len, sg.start + sg.len);
-    const uint64_t *K = sg.buf ? keys1 : keys0;
-    const uint32_t *H = sg.buf ? hdl1 : hdl0;
-    const CollMap cm = cmap[sg.coll];
-    for (uint64_t j = t0 + threadIdx.x; j < t1; j += BLOCK) emit_row(j, cm, K[j], H[j], text, srank, bwt, start_row);
-    if (!PERSIST) break;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// a2/a3/a4 in one wave: finish a chunk of at most 64 LI suffixes in LDS.
-// A chunk is small enough that every group in it is ranked by all-pairs
-// comparison, so the kernel needs no multisplit and no cross-wave barrier;
-// many independent one-wave workgroups per CU hide each other's latency.
-// Each round works on the list of live positions only (the members of
-// groups that are not finished), so the rounds that refine a few tied
-// groups cost little.
-// ---------------------------------------------------------------------------
-template <int LI>
-struct LocalSmem {
-  static constexpr int CHUNK = LOCAL_WG * LI;
-  uint64_t K[CHUNK];  // key of each position
-  uint32_t H[CHUNK];  // handle of each position
-  union {
-    struct {
-      uint16_t live[CHUNK];    // live positions, ascending
-      uint16_t gr[CHUNK];      // group of each live-list entry
-      uint16_t hp[CHUNK + 1];  // first live-list entry of each group
-      uint16_t dst[CHUNK];     // new position of each live-list entry
-    };
-    struct {                   // while the chunk is split by digits
-      uint32_t cnt[256];
-      uint32_t dstart[256];
-    };
-  };
-  uint8_t head[CHUNK];  // position starts a group
-};
-
-constexpr int FETCH_BATCH = 2;  // window loads in flight per lane
-
-// Stable split of the m suffixes of a chunk by 8-bit digit sel, in place
-// (every suffix is held in registers before any moves).
-template <int LI>
-__device__ __forceinline__ void wave_split(LocalSmem<LI> &S, uint32_t m, int sel, uint32_t lane, uint64_t lt) {
-  for (uint32_t x = lane; x < 256; x += LOCAL_WG) S.cnt[x] = 0;
-  __syncthreads();
-  uint64_t kr[LI];
-  uint32_t hr[LI], dig[LI], pos[LI];
-#pragma unroll
-  for (int i = 0; i < LI; ++i) {
-    const uint32_t j = i * LOCAL_WG + lane;
-    const bool valid = j < m;
-    dig[i] = NODIGIT;
-    if (valid) {
-      kr[i] = S.K[j];
-      hr[i] = S.H[j];
-      dig[i] = digit_of(kr[i], sel);
-    }
-    if (i * LOCAL_WG >= (int)m) continue;
-    // rank among the lanes of this slot with the same digit
-    uint64_t peers = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const bool bit = (dig[i] >> b) & 1u;
-      const uint64_t v = __ballot(bit);
-      peers &= bit ? v : ~v;
-    }
-    if (valid) {
-      const uint32_t before = S.cnt[dig[i]];
-      pos[i] = before + (uint32_t)__popcll(peers & lt);
-      if ((peers & lt) == 0) S.cnt[dig[i]] = before + (uint32_t)__popcll(peers);
-    }
-    __syncthreads();
-  }
-  // digit starts: lane l sums digits 4l .. 4l+3
-  const uint32_t c0 = S.cnt[4 * lane], c1 = S.cnt[4 * lane + 1], c2 = S.cnt[4 * lane + 2], c3 = S.cnt[4 * lane + 3];
-  const uint32_t tot = c0 + c1 + c2 + c3;
-  const uint32_t ex = wave_incl_sum(tot) - tot;
-  S.dstart[4 * lane] = ex;
-  S.dstart[4 * lane + 1] = ex + c0;
-  S.dstart[4 * lane + 2] = ex + c0 + c1;
-  S.dstart[4 * lane + 3] = ex + c0 + c1 + c2;
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < LI; ++i) {
-    if (dig[i] != NODIGIT) {
-      const uint32_t q = S.dstart[dig[i]] + pos[i];
-      S.K[q] = kr[i];
-      S.H[q] = hr[i];
-    }
-  }
-  __syncthreads();
-}
-
-// Groups of the live list from the head flags of its positions: gr[x] and
-// hp[g] (hp[number of groups] = n).  One ballot per 64 entries.
-template <int LI>
-__device__ __forceinline__ void live_groups(LocalSmem<LI> &S, uint32_t n, uint32_t lane, uint64_t le) {
-  uint32_t run = 0;
-#pragma unroll
-  for (int i = 0; i < LI; ++i) {
-    const uint32_t x = i * LOCAL_WG + lane;
-    if (i * LOCAL_WG >= (int)n) break;
-    const bool in = x < n;
-    const bool h = in && S.head[S.live[x]];
-    const uint64_t hb = __ballot(h);
-    const uint32_t g = run + (uint32_t)__popcll(hb & le) - 1u;
-    if (in) {
-      S.gr[x] = (uint16_t)g;
-      if (h) S.hp[g] = (uint16_t)x;
-    }
-    run += (uint32_t)__popcll(hb);
-  }
-  if (lane == 0) S.hp[run] = (uint16_t)n;
-  __syncthreads();
-}
-
-// LI suffixes per lane; OCC waves per SIMD the kernel is compiled for;
-// PERSIST: a fixed grid loops over a chunk count on the device
-template <int LI, int OCC, bool PERSIST>
-__global__ __launch_bounds__(LOCAL_WG, OCC) void k_local(
-    const Seg *__restrict__ chunks, const uint64_t *__restrict__ keys0, const uint64_t *__restrict__ keys1,
-    const uint32_t *__restrict__ hdl0, const uint32_t *__restrict__ hdl1, const TextRec *__restrict__ text,
-    const uint32_t *__restrict__ srank, const CollMap *__restrict__ cmap, uint64_t nb, uint32_t rmax,
-    uint8_t *__restrict__ bwt, uint64_t *__restrict__ start_row, uint32_t *status, unsigned long long *fetches,
-    uint32_t n_chunks, const uint32_t *__restrict__ dev_nchunks, uint32_t first) {
-  __shared__ LocalSmem<LI> S;
-  const uint32_t lane = threadIdx.x;
-  const uint64_t le = lanemask_lt() | (1ull << lane);
-  // chunks first + blockIdx.x (+ k * gridDim.x when PERSIST) below the count
-  if (dev_nchunks) n_chunks = *dev_nchunks;
-  uint32_t nfetch = 0;
-  for (uint32_t c = first + blockIdx.x; c < n_chunks; c += gridDim.x) {
-  if (PERSIST) __syncthreads();  // the previous chunk's LDS reads are done
-  const Seg ch = chunks[c];
-  const uint32_t m = (uint32_t)ch.len;
-  const uint64_t *Kg = ch.buf ? keys1 : keys0;
-  const uint32_t *Hg = ch.buf ? hdl1 : hdl0;
-  // entry x of a list is handled by lane x % 64 in slot x / 64: neighbouring
-  // lanes hold neighbouring positions, which mostly share a group
-#pragma unroll
-  for (int i = 0; i < LI; ++i) {
-    const uint32_t j = i * LOCAL_WG + lane;
-    if (j < m) {
-      S.K[j] = Kg[ch.start + j];
-      S.H[j] = Hg[ch.start + j];
-    }
-  }
-  __syncthreads();
-  // The chunk is a run of buckets that differ in digit d and agree before
-  // it (or, unsplit, in read order, with d = 0).  Two stable splits, by digit
-  // d + 1 and then by digit d, leave it ordered by both digits; the groups of
-  // equal (d, d + 1) digits are then sorted on their current key, and after
-  // that groups are runs of equal keys, refined window by window.
-  const int d0 = ch.d;
-  const bool two = d0 < 7;
-  if (two) {
-    wave_split(S, m, d0 + 1, lane, le & ~(1ull << lane));
-    wave_split(S, m, d0, lane, le & ~(1ull << lane));
-  }
-#pragma unroll
-  for (int i = 0; i < LI; ++i) {
-    const uint32_t j = i * LOCAL_WG + lane;
-    if (j < m) {
-      bool h = j == 0;
-      if (!h && two) h = digit_of(S.K[j], d0) != digit_of(S.K[j - 1], d0) ||
-                         digit_of(S.K[j], d0 + 1) != digit_of(S.K[j - 1], d0 + 1);
-      else if (!h) h = !ch.unsplit && digit_of(S.K[j], d0) != digit_of(S.K[j - 1], d0);
-      S.head[j] = h;
-      S.live[j] = (uint16_t)j;
-    }
-  }
-  __syncthreads();
-  uint32_t n = m;  // live-list length
-  uint32_t r = ch.r;
-  bool fetch_round = false;
-  for (;;) {
-    // drop the finished groups: single suffixes, and (after the first sort)
-    // runs of equal keys that end inside the window, i.e. identical suffixes.
-    // A group is a run of live entries from a head to the next head, so an
-    // entry is alone in its group when it and the next live entry are both
-    // heads; the other test is the same for every member of a group of
-    // equal keys, so whole groups stay or go.
-    uint32_t kept = 0;
-#pragma unroll
-    for (int i = 0; i < LI; ++i) {
-      if (i * LOCAL_WG >= (int)n) break;
-      const uint32_t x = i * LOCAL_WG + lane;
-      bool keep = false;
-      uint16_t pos = 0;
-      if (x < n) {
-        pos = S.live[x];
-        // entry x + 1 is read before any slot writes an index above x
-        const bool alone = S.head[pos] && (x + 1 >= n || S.head[S.live[x + 1]]);
-        keep = !alone && (!fetch_round || clamp_of(S.K[pos]) == (uint32_t)W);
-      }
-      const uint64_t kb = __ballot(keep);
-      // compaction moves entries down only, so slot i never overwrites an
-      // entry a later slot still has to read
-      if (keep) S.live[kept + (uint32_t)__popcll(kb & (le >> 1))] = pos;
-      kept += (uint32_t)__popcll(kb);
-    }
-    n = kept;
-    if (n == 0) break;
-    __syncthreads();
-    live_groups(S, n, lane, le);
-    if (fetch_round) {
-      if (r + 1 > rmax) {
-        if (lane == 0) atomicOr(status, ST_WINDOW_BOUND);
-        break;
-      }
-      ++r;
-      // fetch the next window of every live suffix, FETCH_BATCH loads in
-      // flight per lane
-      for (uint32_t x0 = 0; x0 < n; x0 += FETCH_BATCH * LOCAL_WG) {
-        TextRec tr[FETCH_BATCH];
-        uint32_t tp[FETCH_BATCH];
-#pragma unroll
-        for (int i = 0; i < FETCH_BATCH; ++i) {
-          const uint32_t x = x0 + i * LOCAL_WG + lane;
-          if (x < n) {
-            tp[i] = S.live[x];
-            tr[i] = window_load(text, nb, S.H[tp[i]], r);
-          }
-        }
-#pragma unroll
-        for (int i = 0; i < FETCH_BATCH; ++i) {
-          const uint32_t x = x0 + i * LOCAL_WG + lane;
-          if (x < n) {
-            const uint32_t j = tp[i];
-            S.K[j] = window_combine(tr[i], nb, S.H[j], r, (uint32_t)S.K[j] & 7u);
-            ++nfetch;
-          }
-        }
-      }
-      __syncthreads();
-    }
-    // stable rank inside each live group by all-pairs comparison:
-    // rank = #{t < j : key_t <= key_j} + #{t > j : key_t < key_j}; every
-    // rank is taken before any entry moves.  The ordering bits oj are a
-    // multiple of 8, so (key_t & ~7) <= oj is key_t < oj + 8 and
-    // (key_t & ~7) < oj is key_t < oj: one 64-bit compare per key, on the
-    // raw keys (t = j adds nothing to the second count).
-    for (uint32_t x = lane; x < n; x += LOCAL_WG) {
-      const uint32_t j = S.live[x];
-      const uint32_t g = S.gr[x];
-      const uint32_t x0 = S.hp[g];
-      const uint32_t a = S.live[x0];
-      const uint32_t e = a + ((uint32_t)S.hp[g + 1] - x0);  // a group is a run of positions
-      const uint64_t oj = order_bits(S.K[j]);
-      const uint64_t below = oj + 8;  // cannot wrap: key bits 9..8 are zero
-      // four independent LDS reads per step keep the loops off the
-      // load-latency chain
-      uint32_t c = 0;
-      uint32_t t = a;
-      for (; t + 4 <= j; t += 4)
-        c += (uint32_t)(S.K[t] < below) + (uint32_t)(S.K[t + 1] < below) + (uint32_t)(S.K[t + 2] < below) +
-             (uint32_t)(S.K[t + 3] < below);
-      for (; t < j; ++t) c += (uint32_t)(S.K[t] < below);
-      for (; t + 4 <= e; t += 4)
-        c += (uint32_t)(S.K[t] < oj) + (uint32_t)(S.K[t + 1] < oj) + (uint32_t)(S.K[t + 2] < oj) +
-             (uint32_t)(S.K[t + 3] < oj);
-      for (; t < e; ++t) c += (uint32_t)(S.K[t] < oj);
-      S.dst[x] = (uint16_t)(a + c);
-    }
-    __syncthreads();
-    {
-      uint64_t sk[LI];
-      uint32_t sh[LI], sd[LI];
-#pragma unroll
-      for (int i = 0; i < LI; ++i) {
-        const uint32_t x = i * LOCAL_WG + lane;
-        if (x < n) {
-          const uint32_t j = S.live[x];
-          sk[i] = S.K[j];
-          sh[i] = S.H[j];
-          sd[i] = S.dst[x];
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int i = 0; i < LI; ++i) {
-        const uint32_t x = i * LOCAL_WG + lane;
-        if (x < n) {
-          S.K[sd[i]] = sk[i];
-          S.H[sd[i]] = sh[i];
-        }
-      }
-    }
-    __syncthreads();
-    // new group heads inside live groups: changes of the full key
-#pragma unroll
-    for (int i = 0; i < LI; ++i) {
-      const uint32_t x = i * LOCAL_WG + lane;
-      if (i * LOCAL_WG >= (int)n) break;
-      if (x >= n) continue;
-      const uint32_t j = S.live[x];
-      if (!S.head[j] && order_bits(S.K[j]) != order_bits(S.K[j - 1])) S.head[j] = 1;
-    }
-    __syncthreads();
-    fetch_round = true;
-  }
-  // a4: emit
-  const CollMap cm = cmap[ch.coll];
-#pragma unroll
-  for (int i = 0; i < LI; ++i) {
-    const uint32_t j = i * LOCAL_WG + lane;
-    if (j < m) emit_row(ch.start + j, cm, S.K[j], S.H[j], text, srank, bwt, start_row);
-  }
-  if (!PERSIST) break;
-  }
-  nfetch = wave_incl_sum(nfetch);
-  if (lane == 63 && nfetch) atomicAdd(stat_slot(fetches), (unsigned long long)nfetch);
-}
-
 
 // ---------------------------------------------------------------------------
 // host side
@@ -1680,6 +66,7 @@ thread_local int g_timing = 0;
 struct Tuning {
   uint32_t tile_items;   // 6, 8 or 16 suffixes per 256 threads' thread in a level tile (16: 8 waves x 8)
   uint32_t chunk_items;  // 3, 6 or 8 suffixes per lane in a chunk
+  uint32_t schedule = CXBWT_SCHEDULE_MSD;  // sort schedule of single-collection builds
   uint32_t tile_len() const { return BLOCK * tile_items; }
   uint32_t chunk() const { return LOCAL_WG * chunk_items; }
 };
@@ -1700,16 +87,34 @@ inline uint64_t align_up(uint64_t x) { return (x + 255) & ~255ull; }
 struct Layout {
   uint64_t keys0, keys1, hdl0, hdl1, text, srank, rank_blocks, start_row, tile_hist, gsum, segs, tile_prefix,
       group_prefix, seg_or, seg_and, seg_split, big_next, chunks, finals, coll_reads, coll_bases, cmap, counters,
-      stats, total;
+      stats, list_tiles, list_blocks, ph_counts, ph_prefixes, pos64, total;
   uint64_t cap_big, cap_chunks, cap_finals, seg_slots, max_tiles, max_groups, n_rec, n_rank_words, n_rank_blocks;
+  uint64_t sort_cap, n_cmap, n_list_tiles, n_list_blocks, tile_hist_bytes;
 };
 
 bool sizes_ok(uint64_t n_reads, uint64_t n_bases, uint32_t max_read_len) {
   return n_reads >= 1 && n_reads < (1ull << 32) && n_bases <= CXBWT_MAX_BASES && max_read_len <= CXBWT_MAX_READ_LEN;
 }
+// A build in ranges: the handles of one range are 32-bit (sort positions of
+// at most max_range_suffixes suffixes), so the collection may exceed 32-bit
+// base positions when they are kept in a 64-bit table.
+bool range_wide(uint64_t n_bases, uint32_t flags) {
+  return n_bases > CXBWT_MAX_BASES || (flags & CXBWT_RANGE_WIDE) != 0;
+}
+bool range_sizes_ok(uint64_t n_reads, uint64_t n_bases, uint32_t max_read_len, uint64_t m, uint32_t flags) {
+  (void)flags;
+  return n_reads >= 1 && n_reads < (1ull << 32) && n_bases <= CXBWT_MAX_RANGE_BASES &&
+         max_read_len <= CXBWT_MAX_READ_LEN && m >= 1 && m <= CXBWT_MAX_BASES;
+}
 
-Layout make_layout(uint64_t n_reads, uint64_t nb, uint32_t n_coll) {
+// Workspace of a build of nb bases in n_reads reads and n_coll collections
+// whose sort buffers hold at most m_sort suffixes at once (all nb of them,
+// or one range of a build in ranges).
+Layout make_layout(uint64_t n_reads, uint64_t nb_text, uint32_t n_coll, uint64_t m_sort = ~0ull, bool wide = false) {
   Layout L{};
+  const uint64_t nb = std::min(nb_text, m_sort);  // suffixes sorted at once
+  L.sort_cap = nb;
+  L.n_cmap = n_coll;  // a build in ranges rewrites its one entry per range
   // segments of one level are disjoint and each holds more than a chunk
   // (at least MIN_CHUNK) suffixes; level 1 starts with one segment per
   // collection
@@ -1727,7 +132,9 @@ Layout make_layout(uint64_t n_reads, uint64_t nb, uint32_t n_coll) {
   L.seg_slots = std::max<uint64_t>(nb / (SEG_BATCH_MIN + 1) + 2, (uint64_t)n_coll + 1);
   L.max_tiles = ceil_div(nb, MIN_TILE) + L.seg_slots + 1;
   L.max_groups = ceil_div(nb, (uint64_t)MIN_TILE * GROUP_TILES) + L.seg_slots + 1;
-  L.n_rec = nb / 16 + 2;
+  L.n_rec = nb_text / 16 + 2;
+  L.n_list_tiles = ceil_div(nb_text, LIST_TILE) + 1;
+  L.n_list_blocks = ceil_div(L.n_list_tiles, RANK_BLOCK_WORDS) + 1;
   L.n_rank_words = ceil_div(L.n_rec, 2);  // bitmap words covering the records
   L.n_rank_blocks = ceil_div(L.n_rank_words, RANK_BLOCK_WORDS);
   uint64_t off = 0;
@@ -1745,7 +152,9 @@ Layout make_layout(uint64_t n_reads, uint64_t nb, uint32_t n_coll) {
   L.srank = take(4 * L.n_rec);
   L.rank_blocks = take(4 * L.n_rank_blocks);
   L.start_row = take(8 * n_reads);
-  L.tile_hist = take(4 * 256 * L.max_tiles);
+  // the read-start bitmap (one bit per base) lives here before level 1
+  L.tile_hist_bytes = std::max<uint64_t>(4 * 256 * L.max_tiles, 4 * (nb_text / 32 + 4));
+  L.tile_hist = take(L.tile_hist_bytes);
   L.gsum = take(4 * 256 * L.max_groups);
   L.segs = take(sizeof(Seg) * seg_slots);
   // tile prefixes serve a batch of segments and, after it, the final groups
@@ -1760,9 +169,16 @@ Layout make_layout(uint64_t n_reads, uint64_t nb, uint32_t n_coll) {
   L.finals = take(sizeof(Seg) * L.cap_finals);
   L.coll_reads = take(8 * ((uint64_t)n_coll + 1));
   L.coll_bases = take(8 * ((uint64_t)n_coll + 1));
-  L.cmap = take(sizeof(CollMap) * (uint64_t)n_coll);
+  L.cmap = take(sizeof(CollMap) * L.n_cmap);
   L.counters = take(4 * C_COUNT);
   L.stats = take(8 * STAT_WORDS);
+  L.list_tiles = take(4 * L.n_list_tiles);
+  L.list_blocks = take(4 * L.n_list_blocks);
+  L.ph_counts = take(8 * 256 * PH_MAX_PREFIXES);
+  L.ph_prefixes = take(8 * PH_MAX_PREFIXES);
+  // wide positions: a 64-bit position per listed suffix; 0 = no table (the
+  // layout starts with keys0 at offset 0, so no other region sits there)
+  L.pos64 = wide ? take(8 * nb) : 0;
   L.total = off;
   return L;
 }
@@ -1864,7 +280,10 @@ struct PhaseTimer {
 
 
 struct Buffers {
-  uint64_t *keys0, *keys1, *start_row, *coll_reads, *coll_bases;
+  uint64_t *keys0, *keys1, *start_row, *coll_reads, *coll_bases, *ph_prefixes;
+  uint64_t *pos64;  // 64-bit positions of the listed range (wide builds in ranges), else null
+  uint32_t *list_tiles, *list_blocks;
+  unsigned long long *ph_counts;
   TextRec *text;
   uint32_t *hdl0, *hdl1, *srank, *rank_blocks, *tile_hist, *gsum, *tile_prefix, *group_prefix, *counters;
   Seg *segs, *big_next, *chunks, *finals;
@@ -2029,18 +448,18 @@ int launch_local(const Buffers &B, const Tuning &tu, uint64_t nb, uint32_t rmax,
 #define CX_LOCAL(LI, OCC, OCCP)                                                                                  \
   do {                                                                                                           \
     if (dev_nchunks && grid) {                                                                                   \
-      k_local<LI, OCC, false><<<grid, LOCAL_WG, 0, st>>>(B.chunks, B.keys0, B.keys1, B.hdl0, B.hdl1, B.text,      \
+      k_local<LI, OCC, false><<<grid, LOCAL_WG, 0, st>>>(B.chunks, B.keys0, B.keys1, B.hdl0, B.hdl1, B.pos64, B.text,\
                                                         B.srank, B.cmap, nb, rmax, bwt, B.start_row,             \
                                                         B.counters + C_STATUS, B.stats, 0, dev_nchunks, 0);      \
-      k_local<LI, OCCP, true><<<256u, LOCAL_WG, 0, st>>>(B.chunks, B.keys0, B.keys1, B.hdl0, B.hdl1, B.text,      \
+      k_local<LI, OCCP, true><<<256u, LOCAL_WG, 0, st>>>(B.chunks, B.keys0, B.keys1, B.hdl0, B.hdl1, B.pos64, B.text,\
                                                         B.srank, B.cmap, nb, rmax, bwt, B.start_row,             \
                                                         B.counters + C_STATUS, B.stats, 0, dev_nchunks, grid);   \
     } else if (dev_nchunks) {                                                                                    \
       k_local<LI, OCCP, true><<<256u * 4u * OCCP, LOCAL_WG, 0, st>>>(                                            \
-          B.chunks, B.keys0, B.keys1, B.hdl0, B.hdl1, B.text, B.srank, B.cmap, nb, rmax, bwt, B.start_row,      \
+          B.chunks, B.keys0, B.keys1, B.hdl0, B.hdl1, B.pos64, B.text, B.srank, B.cmap, nb, rmax, bwt, B.start_row,\
           B.counters + C_STATUS, B.stats, 0, dev_nchunks, 0);                                                    \
     } else {                                                                                                     \
-      k_local<LI, OCC, false><<<n_chunks, LOCAL_WG, 0, st>>>(B.chunks, B.keys0, B.keys1, B.hdl0, B.hdl1, B.text, \
+      k_local<LI, OCC, false><<<n_chunks, LOCAL_WG, 0, st>>>(B.chunks, B.keys0, B.keys1, B.hdl0, B.hdl1, B.pos64, B.text,\
                                                             B.srank, B.cmap, nb, rmax, bwt, B.start_row,         \
                                                             B.counters + C_STATUS, B.stats, n_chunks, nullptr,   \
                                                             0);                                                  \
@@ -2071,8 +490,8 @@ int finish_level(const Buffers &B, const Layout &Lo, const Tuning &tu, uint64_t 
     if ((rc = prefix_list(B, B.finals, n_finals, tu.tile_len(), nullptr, B.tile_prefix, nullptr, st))) return rc;
     T.begin();
     k_emit_final<false><<<(unsigned)final_tiles, BLOCK, 0, st>>>(B.finals, B.tile_prefix, n_finals, nullptr, tu.tile_len(),
-                                                          B.keys0, B.keys1, B.hdl0, B.hdl1, B.text, B.srank, B.cmap,
-                                                          bwt, B.start_row);
+                                                          B.keys0, B.keys1, B.hdl0, B.hdl1, B.pos64, B.text, B.srank,
+                                                          B.cmap, bwt, B.start_row);
     CX_LAUNCHED();
     T.end(PH_FINAL);
     g_stats.final_big += n_finals;
@@ -2098,7 +517,7 @@ int launch_level_kernels(const Buffers &B, const Tuning &tu, const Lists &Ls, ui
 #define CX_HIST(P, SUBT)                                                                                         \
   k_level_hist<P, SUBT><<<P ? g_hist : ntiles, BLOCK, 0, st>>>(B.segs, B.tile_prefix, nsg, dev_nsg, tu.tile_len(),  \
                                                                 B.keys0, B.keys1, B.hdl0, B.hdl1, B.text, nb,        \
-                                                                B.tile_hist, B.seg_or, B.seg_and)
+                                                                B.pos64, B.tile_hist, B.seg_or, B.seg_and)
   if (tu.tile_items == 16) {
     if (dev) CX_HIST(true, 2);
     else CX_HIST(false, 2);
@@ -2200,11 +619,17 @@ Buffers buffers_of(unsigned char *ws, const Layout &Lo) {
   B.cmap = (CollMap *)(ws + Lo.cmap);
   B.counters = (uint32_t *)(ws + Lo.counters);
   B.stats = (unsigned long long *)(ws + Lo.stats);
+  B.list_tiles = (uint32_t *)(ws + Lo.list_tiles);
+  B.list_blocks = (uint32_t *)(ws + Lo.list_blocks);
+  B.ph_counts = (unsigned long long *)(ws + Lo.ph_counts);
+  B.ph_prefixes = (uint64_t *)(ws + Lo.ph_prefixes);
+  B.pos64 = Lo.pos64 ? (uint64_t *)(ws + Lo.pos64) : nullptr;
   return B;
 }
 
 void build_init(Build &b, const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint64_t nb, uint32_t maxlen,
-                const uint64_t *coll_reads, uint32_t ncoll, uint8_t *bwt, uint64_t *term_pos, unsigned char *ws) {
+                const uint64_t *coll_reads, uint32_t ncoll, uint8_t *bwt, uint64_t *term_pos, unsigned char *ws,
+                uint64_t m_sort = ~0ull, bool wide = false) {
   b.packed = packed;
   b.offsets = offsets;
   b.n = n;
@@ -2213,7 +638,7 @@ void build_init(Build &b, const uint64_t *packed, const uint64_t *offsets, uint6
   b.ncoll = ncoll;
   b.bwt = bwt;
   b.term_pos = term_pos;
-  b.Lo = make_layout(n, nb, ncoll);
+  b.Lo = make_layout(n, nb, ncoll, m_sort, wide);
   b.B = buffers_of(ws, b.Lo);
   b.tu = g_tuning;
   b.rmax = maxlen / W + 1;
@@ -2233,7 +658,7 @@ int enqueue_prep(const Build &b, const uint64_t *coll_reads_src, const uint64_t 
   const Buffers &B = b.B;
   uint32_t *sbits = B.tile_hist;  // the tile histograms are not used before level 1
   const uint64_t n_sbits = b.nb / 32 + 4;
-  if (4 * n_sbits > 4 * 256 * b.Lo.max_tiles) return CXBWT_EDEVICE;
+  if (4 * n_sbits > b.Lo.tile_hist_bytes) return CXBWT_EDEVICE;
   int rc;
   if ((rc = fill_u32(B.counters, C_COUNT, 0, st))) return rc;
   if ((rc = fill_u64((uint64_t *)B.stats, STAT_WORDS, 0, st))) return rc;
@@ -2346,7 +771,7 @@ int finish_finals_dev(const Build &b, hipStream_t st, unsigned emit_grid = PG_EM
                         B.counters + C_NFINAL)))
     return rc;
   k_emit_final<true><<<emit_grid, BLOCK, 0, st>>>(B.finals, B.tile_prefix, 0, B.counters + C_NFINAL, b.tile_len, B.keys0,
-                                          B.keys1, B.hdl0, B.hdl1, B.text, B.srank, B.cmap, b.bwt, B.start_row);
+                                          B.keys1, B.hdl0, B.hdl1, B.pos64, B.text, B.srank, B.cmap, b.bwt, B.start_row);
   CX_LAUNCHED();
   return CXBWT_OK;
 }
@@ -2550,6 +975,80 @@ void level1_stats(const Build &b) {
   }
 }
 
+// The stringword schedule (Section 3.2) over one collection: for every
+// window from the last to the first, its keys in position order, permuted
+// into the current order, then one stable pass per varying digit, least
+// significant first; finally the rows and term_pos.
+int run_stringword(const Build &b, PhaseTimer &T, hipStream_t st) {
+  constexpr int TI = 8, NW = 4;
+  constexpr uint32_t TL = 64 * NW * TI;
+  const Buffers &B = b.B;
+  const Layout &Lo = b.Lo;
+  const uint64_t nb = b.nb;
+  g_stats.schedule = CXBWT_SCHEDULE_STRINGWORD;
+  if (b.ncoll) CX_CHECK(hipMemcpyAsync(B.cmap, b.cm.data(), sizeof(CollMap), hipMemcpyHostToDevice, st));
+  if (nb) {
+    const uint64_t ntiles = ceil_div(nb, TL), ngroups = ceil_div(ntiles, GROUP_TILES);
+    if (ntiles > Lo.max_tiles || ngroups > Lo.max_groups || ntiles > 0x7FFFFFFFull) return CXBWT_EDEVICE;
+    const uint32_t tp[2] = {0, (uint32_t)ntiles}, gp[2] = {0, (uint32_t)ngroups};
+    CX_CHECK(hipMemcpyAsync(B.tile_prefix, tp, sizeof(tp), hipMemcpyHostToDevice, st));
+    CX_CHECK(hipMemcpyAsync(B.group_prefix, gp, sizeof(gp), hipMemcpyHostToDevice, st));
+    uint64_t *K[2] = {B.keys0, B.keys1};
+    uint32_t *H[2] = {B.hdl0, B.hdl1};
+    unsigned long long *orand = B.seg_or;  // OR and AND of a window's ordering bits
+    const unsigned grid = (unsigned)std::min<uint64_t>(ceil_div(nb, BLOCK), 65536);
+    int cur = 0, rc;
+    for (int w = (int)b.rmax - 1; w >= 0; --w) {
+      if ((rc = fill_u64((uint64_t *)orand, 1, 0, st))) return rc;
+      if ((rc = fill_u64((uint64_t *)orand + 1, 1, ~0ull, st))) return rc;
+      T.begin();
+      k_sched_window<<<grid, BLOCK, 0, st>>>(B.text, B.srank, nb, (uint32_t)w, K[1 - cur], orand);
+      CX_LAUNCHED();
+      k_sched_gather<<<grid, BLOCK, 0, st>>>(K[1 - cur], nb, w == (int)b.rmax - 1, K[cur], H[cur]);
+      CX_LAUNCHED();
+      T.end(PH_GEN);
+      uint64_t oa[2];
+      CX_CHECK(hipMemcpyAsync(oa, orand, sizeof(oa), hipMemcpyDeviceToHost, st));
+      CX_CHECK(hipStreamSynchronize(st));
+      T.collect();
+      g_stats.window_fetches += nb;
+      for (int d = 7; d >= 0; --d) {
+        if (((oa[0] ^ oa[1]) & digit_mask(d)) == 0) continue;  // constant digit: the pass would not move anything
+        T.begin();
+        k_sched_hist<TL><<<(unsigned)ntiles, BLOCK, 0, st>>>(K[cur], nb, d, B.tile_hist);
+        CX_LAUNCHED();
+        T.end(PH_HIST);
+        T.begin();
+        k_group_scan<false><<<(unsigned)ngroups, BLOCK, 0, st>>>(B.tile_prefix, B.group_prefix, 1, nullptr,
+                                                                 B.tile_hist, B.gsum);
+        CX_LAUNCHED();
+        k_sched_top<<<1, 64, 0, st>>>(B.gsum, (uint32_t)ngroups);
+        CX_LAUNCHED();
+        T.end(PH_SCAN);
+        T.begin();
+        k_sched_scatter<TI, NW><<<(unsigned)ntiles, 64 * NW, 0, st>>>(K[cur], H[cur], nb, d, B.tile_hist, B.gsum,
+                                                                      K[1 - cur], H[1 - cur]);
+        CX_LAUNCHED();
+        T.end(PH_SCATTER);
+        cur = 1 - cur;
+        g_stats.levels++;
+        g_stats.scattered_suffixes += nb;
+        g_stats.level_suffixes += nb;
+      }
+      g_stats.max_window = std::max<uint32_t>(g_stats.max_window, (uint32_t)w);
+    }
+    T.begin();
+    k_sched_emit<<<grid, BLOCK, 0, st>>>(K[cur], H[cur], nb, B.cmap, B.text, B.srank, b.bwt, B.start_row);
+    CX_LAUNCHED();
+    T.end(PH_FINAL);
+  }
+  T.begin();
+  k_term<<<grid_for(b.n, 256), 256, 0, st>>>(b.offsets, b.n, b.nb, B.text, B.srank, B.start_row, b.term_pos);
+  CX_LAUNCHED();
+  T.end(PH_FINAL);
+  return CXBWT_OK;
+}
+
 // The whole build for ncoll collections laid end to end (a single build is
 // one collection).  coll_reads (host) holds ncoll + 1 read boundaries.
 int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint64_t nb, uint32_t maxlen,
@@ -2563,10 +1062,223 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
   if ((rc = enqueue_prep(b, b.coll_reads.data(), nullptr, T, st))) return rc;
   if ((rc = enqueue_records(b, T, st))) return rc;
   if ((rc = plan_level1(b, T, st))) return rc;
-  Level1Vectors v;
-  v.make(b);
-  level1_stats(b);
-  if ((rc = enqueue_body(b, v.src, 0, T, st))) return rc;
+  if (ncoll == 1 && b.tu.schedule == CXBWT_SCHEDULE_STRINGWORD) {
+    if ((rc = run_stringword(b, T, st))) return rc;
+  } else {
+    Level1Vectors v;
+    v.make(b);
+    level1_stats(b);
+    if ((rc = enqueue_body(b, v.src, 0, T, st))) return rc;
+  }
+  uint32_t hc[C_COUNT];
+  if ((rc = read_totals(b, T, st, hc))) return rc;
+  if (hc[C_STATUS]) return CXBWT_EDEVICE;
+  return CXBWT_OK;
+}
+
+// ---- the build in ranges of window-0 key prefixes -------------------------
+
+// A class of suffixes whose window-0 keys share their top `depth` digits
+// (`prefix`, ordering bits only), and its size.
+struct PrefixClass {
+  uint64_t prefix;
+  uint32_t depth;
+  uint64_t count;
+};
+// A range: consecutive classes, keys lo..hi (ordering bits, inclusive), the
+// rows after `before` suffixes of earlier ranges; its keys agree on their
+// first `common` digits.
+struct Range {
+  uint64_t lo, hi, count, before;
+  uint32_t common;
+  uint64_t skip = 0;  // a piece of one class of identical suffixes: its first member in read order
+};
+
+// Ordering bits of the smallest and largest key with this prefix.
+uint64_t class_lo(const PrefixClass &c) { return c.prefix; }
+uint64_t class_hi(const PrefixClass &c) {
+  if (c.depth >= 8) return c.prefix;
+  if (c.depth == 0) return ~7ull;
+  return (c.prefix | ((1ull << (64 - 8 * c.depth)) - 1)) & ~7ull;
+}
+
+// Counts the next digit of every class in `parents` (all of one depth, at
+// most PH_MAX_PREFIXES, ascending) on the device; returns the child classes.
+int count_children(const Build &b, const std::vector<PrefixClass> &parents, std::vector<PrefixClass> &children,
+                   hipStream_t st) {
+  const Buffers &B = b.B;
+  const uint32_t np = (uint32_t)parents.size();
+  const uint32_t depth = parents[0].depth;
+  std::vector<uint64_t> pf(np);
+  for (uint32_t i = 0; i < np; ++i) pf[i] = parents[i].prefix;
+  std::vector<unsigned long long> cnt((size_t)np * 256);
+  int rc;
+  if ((rc = fill_u64((uint64_t *)B.ph_counts, (uint64_t)np * 256, 0, st))) return rc;
+  CX_CHECK(hipMemcpyAsync(B.ph_prefixes, pf.data(), 8 * np, hipMemcpyHostToDevice, st));
+  const uint64_t nrec = ceil_div(b.nb, 16);
+  const unsigned grid = (unsigned)std::min<uint64_t>(ceil_div(nrec, BLOCK), 2048);
+  const size_t lds = (size_t)np * 256 * 4 + (size_t)np * 8;
+  k_prefix_hist<<<grid, BLOCK, lds, st>>>(B.text, b.nb, B.ph_prefixes, np, depth, B.ph_counts);
+  CX_LAUNCHED();
+  CX_CHECK(hipMemcpyAsync(cnt.data(), B.ph_counts, 8 * cnt.size(), hipMemcpyDeviceToHost, st));
+  CX_CHECK(hipStreamSynchronize(st));
+  const uint32_t nd = depth == 7 ? 32u : 256u;  // digit 7 is the 5-bit clamped length
+  for (uint32_t i = 0; i < np; ++i)
+    for (uint32_t v = 0; v < nd; ++v) {
+      const uint64_t c = cnt[(size_t)i * 256 + v];
+      if (!c) continue;
+      const uint64_t bits = depth < 7 ? (uint64_t)v << (56 - 8 * depth) : (uint64_t)v << 3;
+      children.push_back(PrefixClass{parents[i].prefix | bits, depth + 1, c});
+    }
+  return CXBWT_OK;
+}
+
+// Section 3.1's partitioning on the device: classes of window-0 key
+// prefixes, refined one digit at a time while larger than m, packed in key
+// order into ranges of at most m suffixes.  CXBWT_ERANGE when a class of
+// identical window-0 keys alone exceeds m.
+int plan_ranges(const Build &b, uint64_t m, std::vector<Range> &ranges, hipStream_t st) {
+  std::vector<PrefixClass> leaves, todo{PrefixClass{0, 0, b.nb}};
+  int rc;
+  while (!todo.empty()) {
+    // the shallowest classes first, up to PH_MAX_PREFIXES per counting pass
+    std::sort(todo.begin(), todo.end(), [](const PrefixClass &x, const PrefixClass &y) {
+      return x.depth != y.depth ? x.depth < y.depth : x.prefix < y.prefix;
+    });
+    size_t k = 1;
+    while (k < todo.size() && k < (size_t)PH_MAX_PREFIXES && todo[k].depth == todo[0].depth) ++k;
+    const std::vector<PrefixClass> parents(todo.begin(), todo.begin() + k);
+    todo.erase(todo.begin(), todo.begin() + k);
+    std::vector<PrefixClass> kids;
+    if ((rc = count_children(b, parents, kids, st))) return rc;
+    for (const PrefixClass &c : kids) {
+      if (c.count <= m) leaves.push_back(c);
+      else if (c.depth < 8) todo.push_back(c);
+      else if (clamp_of(c.prefix) < (uint32_t)W) leaves.push_back(c);  // identical suffixes: cut by read order below
+      else return CXBWT_ERANGE;  // equal whole first windows whose order depends on later windows
+    }
+  }
+  std::sort(leaves.begin(), leaves.end(),
+            [](const PrefixClass &x, const PrefixClass &y) { return x.prefix < y.prefix; });
+  ranges.clear();
+  uint64_t before = 0;
+  bool open = false;  // the last range takes more classes
+  for (const PrefixClass &c : leaves) {
+    if (c.count > m) {
+      // a class of identical suffixes (one whole first-window key that ends
+      // inside the window) above the budget: their order is the read order,
+      // so it is cut into pieces of m in that order, each a range of its own
+      for (uint64_t k = 0; k < c.count; k += m) {
+        Range r{c.prefix, c.prefix, std::min<uint64_t>(m, c.count - k), before, 0};
+        r.skip = k;
+        ranges.push_back(r);
+        before += r.count;
+      }
+      open = false;
+      continue;
+    }
+    if (!open || ranges.back().count + c.count > m) {
+      ranges.push_back(Range{class_lo(c), class_hi(c), 0, before, 0});
+      open = true;
+    }
+    Range &r = ranges.back();
+    r.hi = class_hi(c);
+    r.count += c.count;
+    before += c.count;
+  }
+  for (Range &r : ranges) {
+    uint32_t j = 0;
+    while (j < 8 && digit_of(r.lo, (int)j) == digit_of(r.hi, (int)j)) ++j;
+    r.common = j;
+  }
+  return CXBWT_OK;
+}
+
+// Lists the suffixes of range `r` into keys0 / hdl0 [0, count), in position
+// order.
+int list_range(const Build &b, const Range &r, PhaseTimer &T, hipStream_t st) {
+  const Buffers &B = b.B;
+  const Layout &Lo = b.Lo;
+  const uint64_t ntl = ceil_div(b.nb, LIST_TILE);
+  const uint64_t nlb = ceil_div(ntl, RANK_BLOCK_WORDS);
+  if (ntl + 1 > Lo.n_list_tiles || nlb + 1 > Lo.n_list_blocks || r.count > Lo.sort_cap) return CXBWT_EDEVICE;
+  T.begin();
+  k_range_count<<<(unsigned)ntl, BLOCK, 0, st>>>(B.text, b.nb, r.lo, r.hi, B.list_tiles);
+  CX_LAUNCHED();
+  k_count_blocks<<<(unsigned)nlb, BLOCK, 0, st>>>(B.list_tiles, ntl, B.list_blocks);
+  CX_LAUNCHED();
+  k_rank_top<<<1, BLOCK, 0, st>>>(B.list_blocks, (uint32_t)nlb);
+  CX_LAUNCHED();
+  k_count_prefix<<<(unsigned)nlb, BLOCK, 0, st>>>(B.list_tiles, ntl, B.list_blocks);
+  CX_LAUNCHED();
+  k_range_list<<<(unsigned)ntl, BLOCK, 0, st>>>(B.text, b.nb, r.lo, r.hi, B.list_tiles, r.skip, r.count, B.keys0,
+                                                 B.hdl0, B.pos64);
+  CX_LAUNCHED();
+  T.end(PH_GEN);
+  return CXBWT_OK;
+}
+
+// One collection built in ranges of at most m suffixes: the bare
+// terminators and text records as for a whole build, the ranges planned
+// from prefix counts, then each range listed, sorted (levels and chunks) and
+// emitted at its rows; term_pos at the end.
+int run_range_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint64_t nb, uint32_t maxlen,
+                    uint64_t m, bool wide, uint8_t *bwt, uint64_t *term_pos, unsigned char *ws, hipStream_t st) {
+  g_stats = cxbwt_stats{};
+  PhaseTimer T{st, g_timing != 0, {}};
+  Build b;
+  const uint64_t one[2] = {0, n};
+  build_init(b, packed, offsets, n, nb, maxlen, one, 1, bwt, term_pos, ws, m, wide);
+  int rc;
+  if ((rc = enqueue_prep(b, b.coll_reads.data(), nullptr, T, st))) return rc;
+  if ((rc = enqueue_records(b, T, st))) return rc;
+  {  // the offsets are checked on the device before anything is listed
+    uint32_t hc[C_COUNT];
+    CX_CHECK(hipMemcpyAsync(hc, b.B.counters, sizeof(hc), hipMemcpyDeviceToHost, st));
+    CX_CHECK(hipStreamSynchronize(st));
+    T.collect();
+    if (hc[C_STATUS] & (ST_BAD_OFFSETS | ST_TOO_LONG)) return CXBWT_EDATA;
+  }
+  g_stats.chunk_suffixes = nb;
+  std::vector<Range> ranges;
+  if (nb) {
+    if ((rc = plan_ranges(b, m, ranges, st))) return rc;
+  }
+  g_stats.ranges = (uint32_t)ranges.size();
+  // every range's rows follow the n bare-terminator rows and the earlier ranges
+  std::vector<CollMap> cm(ranges.size());
+  std::vector<Seg> seg(ranges.size());
+  for (size_t i = 0; i < ranges.size(); ++i) {
+    cm[i].out_shift = n + ranges[i].before;
+    cm[i].row_shift = (int64_t)(n + ranges[i].before);
+  }
+  for (size_t i = 0; i < ranges.size(); ++i) {
+    const Range &r = ranges[i];
+    // the row map of this range, in the one collection slot (stream order:
+    // after the previous range's kernels have read theirs)
+    CX_CHECK(hipMemcpyAsync(b.B.cmap, &cm[i], sizeof(CollMap), hipMemcpyHostToDevice, st));
+    if ((rc = list_range(b, r, T, st))) return rc;
+    const bool small = r.count <= (uint64_t)b.tu.chunk();
+    // a range that fits a chunk: one unsplit chunk; else one segment whose
+    // keys agree on their first `common` digits
+    seg[i] = Seg{0, (uint32_t)r.count, 0, (uint8_t)std::min<uint32_t>(r.common, small ? 6 : 7), 0, 0,
+                 (uint8_t)(small ? 1 : 0), 0};
+    if (small) {
+      CX_CHECK(hipMemcpyAsync(b.B.chunks, &seg[i], sizeof(Seg), hipMemcpyHostToDevice, st));
+      if ((rc = finish_level(b.B, b.Lo, b.tu, nb, b.rmax, bwt, 1, 0, 0, 0, T, st))) return rc;
+      continue;
+    }
+    CX_CHECK(hipMemcpyAsync(b.B.big_next, &seg[i], sizeof(Seg), hipMemcpyHostToDevice, st));
+    LevelOut acc{};
+    acc.next_len = r.count;
+    acc.next_tiles = ceil_div(r.count, b.tile_len);
+    acc.next_groups = ceil_div(acc.next_tiles, GROUP_TILES);
+    if ((rc = run_levels(b, acc, 1, T, st))) return rc;
+  }
+  T.begin();
+  k_term<<<grid_for(n, 256), 256, 0, st>>>(offsets, n, nb, b.B.text, b.B.srank, b.B.start_row, term_pos);
+  CX_LAUNCHED();
+  T.end(PH_FINAL);
   uint32_t hc[C_COUNT];
   if ((rc = read_totals(b, T, st, hc))) return rc;
   if (hc[C_STATUS]) return CXBWT_EDEVICE;
@@ -2747,7 +1459,7 @@ extern "C" {
 uint64_t cxbwt_packed_words(uint64_t n_bases) { return (n_bases + 31) / 32 + 1; }
 
 int cxbwt_pack(const uint8_t *ascii, uint64_t n_bases, uint64_t *packed, uint32_t *d_status, void *stream) {
-  if (n_bases > CXBWT_MAX_BASES) return CXBWT_ERANGE;
+  if (n_bases > CXBWT_MAX_RANGE_BASES) return CXBWT_ERANGE;
   if (!packed || (n_bases && !ascii)) return CXBWT_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   if (d_status) {
@@ -2794,6 +1506,26 @@ int cxbwt_build_noalloc(const uint64_t *packed, const uint64_t *offsets, uint64_
   // no kernel timing here: it would create HIP events
   return run_build(packed, offsets, n_reads, n_bases, max_read_len, one, 1, bwt, term_pos, ws, (hipStream_t)stream,
                    false);
+}
+
+size_t cxbwt_range_workspace_bytes(uint64_t n_reads, uint64_t n_bases, uint32_t max_read_len,
+                                   uint64_t max_range_suffixes, uint32_t flags) {
+  if (!range_sizes_ok(n_reads, n_bases, max_read_len, max_range_suffixes, flags)) return 0;
+  return (size_t)make_layout(n_reads, n_bases, 1, max_range_suffixes, range_wide(n_bases, flags)).total;
+}
+
+int cxbwt_build_ranges(const uint64_t *packed, const uint64_t *offsets, uint64_t n_reads, uint64_t n_bases,
+                       uint32_t max_read_len, uint64_t max_range_suffixes, uint32_t flags, uint8_t *bwt,
+                       uint64_t *term_pos, void *workspace, size_t workspace_bytes, void *stream) {
+  if (!packed || !offsets || !bwt || !term_pos || !workspace || n_reads == 0 || max_range_suffixes == 0 ||
+      (flags & ~(uint32_t)CXBWT_RANGE_WIDE))
+    return CXBWT_EINVAL;
+  if (!range_sizes_ok(n_reads, n_bases, max_read_len, max_range_suffixes, flags)) return CXBWT_ERANGE;
+  if (workspace_bytes < cxbwt_range_workspace_bytes(n_reads, n_bases, max_read_len, max_range_suffixes, flags))
+    return CXBWT_ENOMEM;
+  if (((uintptr_t)workspace & 255u) != 0) return CXBWT_EINVAL;
+  return run_range_build(packed, offsets, n_reads, n_bases, max_read_len, max_range_suffixes,
+                         range_wide(n_bases, flags), bwt, term_pos, (unsigned char *)workspace, (hipStream_t)stream);
 }
 
 int cxbwt_build_batch(const uint64_t *packed, const uint64_t *offsets, uint64_t n_reads, uint64_t n_bases,
@@ -2871,7 +1603,20 @@ int cxbwt_last_stats(cxbwt_stats *out) {
 
 int cxbwt_set_tuning(uint32_t tile_items, uint32_t chunk_items) {
   if (!tuning_ok(tile_items, chunk_items)) return CXBWT_EINVAL;
-  g_tuning = Tuning{tile_items, chunk_items};
+  g_tuning.tile_items = tile_items;
+  g_tuning.chunk_items = chunk_items;
+  return CXBWT_OK;
+}
+
+int cxbwt_set_schedule(uint32_t schedule) {
+  if (schedule != CXBWT_SCHEDULE_MSD && schedule != CXBWT_SCHEDULE_STRINGWORD) return CXBWT_EINVAL;
+  g_tuning.schedule = schedule;
+  return CXBWT_OK;
+}
+
+int cxbwt_get_schedule(uint32_t *schedule) {
+  if (!schedule) return CXBWT_EINVAL;
+  *schedule = g_tuning.schedule;
   return CXBWT_OK;
 }
 

@@ -25,13 +25,17 @@ NOALLOC_WORKSPACE_BYTES = 256 << 20
 
 # Names the C ABI exports (include/cxbwt.h).
 ABI_FUNCTIONS = ("cxbwt_packed_words", "cxbwt_pack", "cxbwt_workspace_bytes", "cxbwt_build", "cxbwt_build_noalloc",
-                 "cxbwt_batch_workspace_bytes", "cxbwt_build_batch", "cxbwt_last_stats", "cxbwt_set_timing",
-                 "cxbwt_set_tuning", "cxbwt_get_tuning", "cxbwt_graph_create", "cxbwt_graph_launch",
+                 "cxbwt_range_workspace_bytes", "cxbwt_build_ranges", "cxbwt_batch_workspace_bytes", "cxbwt_build_batch", "cxbwt_last_stats", "cxbwt_set_timing",
+                 "cxbwt_set_tuning", "cxbwt_get_tuning", "cxbwt_set_schedule", "cxbwt_get_schedule", "cxbwt_graph_create", "cxbwt_graph_launch",
                  "cxbwt_graph_finish", "cxbwt_graph_destroy", "cxbwt_status_str")
 
 # kernel instantiations the library holds: (suffixes per thread in a level
 # tile, suffixes per lane in a chunk); the first is the default
 TUNING_CHOICES = ((8, 6), (8, 8), (8, 3), (6, 6), (6, 8), (6, 3), (16, 6), (16, 8), (16, 3))
+
+# sort schedules (cxbwt_set_schedule): MSD with tie refinement (default), and
+# Section 3.2's LSD passes over every window
+SCHEDULE_MSD, SCHEDULE_STRINGWORD = 0, 1
 
 # kernel classes of cxbwt_stats.ms / launches
 KERNEL_CLASSES = ("prep", "gen", "level_hist", "level_scan", "level_scatter", "local", "final_emit", "unused")
@@ -53,7 +57,8 @@ class Stats(ctypes.Structure):
                 ("chunk_suffixes", ctypes.c_uint64), ("level_suffixes", ctypes.c_uint64),
                 ("scattered_suffixes", ctypes.c_uint64), ("regathered", ctypes.c_uint64),
                 ("window_fetches", ctypes.c_uint64), ("ms", ctypes.c_float * 8), ("launches", ctypes.c_uint32 * 8),
-                ("level_batches", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("level_batches", ctypes.c_uint32), ("ranges", ctypes.c_uint32), ("schedule", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 def lib():
@@ -76,6 +81,10 @@ def lib():
             L.cxbwt_build.restype = ctypes.c_int
             L.cxbwt_build_noalloc.argtypes = [vp, vp, u64, u64, u32, vp, vp, vp]
             L.cxbwt_build_noalloc.restype = ctypes.c_int
+            L.cxbwt_range_workspace_bytes.argtypes = [u64, u64, u32, u64, u32]
+            L.cxbwt_range_workspace_bytes.restype = ctypes.c_size_t
+            L.cxbwt_build_ranges.argtypes = [vp, vp, u64, u64, u32, u64, u32, vp, vp, vp, ctypes.c_size_t, vp]
+            L.cxbwt_build_ranges.restype = ctypes.c_int
             L.cxbwt_batch_workspace_bytes.argtypes = [u64, u64, u32, u32]
             L.cxbwt_batch_workspace_bytes.restype = ctypes.c_size_t
             L.cxbwt_build_batch.argtypes = [vp, vp, u64, u64, u32, vp, u32, vp, vp, vp, ctypes.c_size_t, vp]
@@ -88,6 +97,10 @@ def lib():
             L.cxbwt_set_tuning.restype = ctypes.c_int
             L.cxbwt_get_tuning.argtypes = [ctypes.POINTER(u32), ctypes.POINTER(u32)]
             L.cxbwt_get_tuning.restype = ctypes.c_int
+            L.cxbwt_set_schedule.argtypes = [u32]
+            L.cxbwt_set_schedule.restype = ctypes.c_int
+            L.cxbwt_get_schedule.argtypes = [ctypes.POINTER(u32)]
+            L.cxbwt_get_schedule.restype = ctypes.c_int
             L.cxbwt_graph_create.argtypes = [vp, vp, u64, u64, u32, vp, u32, vp, vp, vp, ctypes.c_size_t, u32, vp,
                                              ctypes.POINTER(vp)]
             L.cxbwt_graph_create.restype = ctypes.c_int
@@ -180,6 +193,62 @@ def build_noalloc(packed, offsets, n_reads: int, n_bases: int, max_read_len: int
                                    ctypes.c_void_p(term.data_ptr()), _stream_ptr(stream))
     if st != OK:
         raise CxbwtError(st, "cxbwt_build_noalloc")
+    return bwt, term
+
+
+RANGE_WIDE = 1  # CXBWT_RANGE_WIDE: 64-bit positions in a table per range
+MAX_BASES = (1 << 32) - 1  # CXBWT_MAX_BASES
+MAX_RANGE_BASES = 1 << 38  # CXBWT_MAX_RANGE_BASES
+
+
+def range_workspace_bytes(n_reads: int, n_bases: int, max_read_len: int, max_range_suffixes: int,
+                          wide: bool = False) -> int:
+    return int(lib().cxbwt_range_workspace_bytes(n_reads, n_bases, max_read_len, max_range_suffixes,
+                                                 RANGE_WIDE if wide else 0))
+
+
+def range_budget_for(n_reads: int, n_bases: int, max_read_len: int, workspace_bytes: int,
+                     wide: bool = False) -> int:
+    """Largest range budget (suffixes per range) whose workspace fits `workspace_bytes`,
+    or 0 when even one suffix per range does not fit (host arithmetic only)."""
+    def need(m):
+        return range_workspace_bytes(n_reads, n_bases, max_read_len, m, wide)
+    if need(1) == 0 or need(1) > workspace_bytes:
+        return 0
+    lo, hi = 1, max(1, min(n_bases, MAX_BASES))
+    while lo < hi:  # the workspace grows with the budget
+        mid = (lo + hi + 1) // 2
+        if need(mid) <= workspace_bytes:
+            lo = mid
+        else:
+            hi = mid - 1
+    return lo
+
+
+def build_ranges(packed, offsets, n_reads: int, n_bases: int, max_read_len: int, max_range_suffixes: int,
+                 workspace=None, out=None, stream=None, wide: bool = False):
+    """cxbwt_build_ranges: the BWT built in ranges of at most max_range_suffixes suffixes
+    (same result as `build`, a workspace sized by the largest range).  Collections above
+    MAX_BASES bases use 64-bit positions by themselves; wide=True asks for them below it."""
+    import torch
+    dev = packed.device
+    if workspace is None:
+        nbytes = range_workspace_bytes(n_reads, n_bases, max_read_len, max_range_suffixes, wide)
+        if nbytes == 0:
+            raise CxbwtError(ERANGE, "cxbwt_range_workspace_bytes")
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    if out is None:
+        bwt = torch.empty(n_bases + n_reads, dtype=torch.uint8, device=dev)
+        term = torch.empty(n_reads, dtype=torch.int64, device=dev)
+    else:
+        bwt, term = out
+    st = lib().cxbwt_build_ranges(ctypes.c_void_p(packed.data_ptr()), ctypes.c_void_p(offsets.data_ptr()), n_reads,
+                                  n_bases, max_read_len, int(max_range_suffixes), RANGE_WIDE if wide else 0,
+                                  ctypes.c_void_p(bwt.data_ptr()),
+                                  ctypes.c_void_p(term.data_ptr()), ctypes.c_void_p(workspace.data_ptr()),
+                                  workspace.numel(), _stream_ptr(stream))
+    if st != OK:
+        raise CxbwtError(st, "cxbwt_build_ranges")
     return bwt, term
 
 
@@ -354,13 +423,30 @@ def get_tuning() -> tuple:
     return int(t.value), int(c.value)
 
 
+def set_schedule(schedule: int) -> None:
+    """Sort schedule of later single-collection builds on this host thread."""
+    st = lib().cxbwt_set_schedule(int(schedule))
+    if st != 0:
+        raise CxbwtError(st, f"cxbwt_set_schedule({schedule})")
+
+
+def get_schedule() -> int:
+    v = ctypes.c_uint32()
+    st = lib().cxbwt_get_schedule(ctypes.byref(v))
+    if st != 0:
+        raise CxbwtError(st, "cxbwt_get_schedule")
+    return int(v.value)
+
+
 def set_timing(enable: bool) -> bool:
     """Per-kernel-class HIP-event timing of later builds on this host thread."""
     return bool(lib().cxbwt_set_timing(1 if enable else 0))
 
 
-def build_host(text: np.ndarray, offsets: np.ndarray, max_read_len: int | None = None, device="cuda"):
-    """Host arrays in, host arrays out: copy, pack and build on the device."""
+def build_host(text: np.ndarray, offsets: np.ndarray, max_read_len: int | None = None, device="cuda",
+               max_range_suffixes: int | None = None, wide: bool = False):
+    """Host arrays in, host arrays out: copy, pack and build on the device
+    (in ranges of at most max_range_suffixes suffixes when given)."""
     import torch
     text = np.ascontiguousarray(text, dtype=np.uint8)
     offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
@@ -371,7 +457,10 @@ def build_host(text: np.ndarray, offsets: np.ndarray, max_read_len: int | None =
     t_dev = torch.from_numpy(text).to(device) if nb else torch.empty(0, dtype=torch.uint8, device=device)
     o_dev = torch.from_numpy(offsets.view(np.int64)).to(device)
     packed, pstatus = pack(t_dev)
-    bwt, term = build(packed, o_dev, n, nb, max_read_len)
+    if max_range_suffixes is None:
+        bwt, term = build(packed, o_dev, n, nb, max_read_len)
+    else:
+        bwt, term = build_ranges(packed, o_dev, n, nb, max_read_len, max_range_suffixes, wide=wide)
     torch.cuda.synchronize()
     if int(pstatus.item()) != 0:
         raise CxbwtError(EDATA, "cxbwt_pack (non-ACGT byte)")

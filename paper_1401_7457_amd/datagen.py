@@ -213,30 +213,56 @@ def plain_config(k: int, scale: float = 1.0) -> Collection:
     return col
 
 
-def batch_collections(count: int = 256, scale: float = 1.0, seed: int = BASE_SEED + 3) -> list[Collection]:
-    """Independent collections of uneven size and read length.
+def length_sweep_config(read_len: int, total_bases: int = 2_000_000_000, coverage: int = 20) -> Collection:
+    """Reads of one length at a fixed total of bases (the read-length sweep of
+    Section 4.3, Table 4: 100, 200 and 400 bp at equal bases).
 
-    Reads per collection log-uniform on [5k, 2M] (times scale), read length
-    fixed per collection from {75, 100, 150}, genome uniform in [1, 10] Mb
-    (times scale), 0.5% substitutions.
+    n = total_bases / read_len reads from a uniform random genome of
+    total_bases / coverage bases, both strands, 0.5% substitutions.
     """
-    ss = np.random.SeedSequence(seed)
-    meta_ss, *col_ss = ss.spawn(count + 1)
+    ss = np.random.SeedSequence([BASE_SEED + 5, int(read_len)])
+    g_ss, r_ss = ss.spawn(2)
+    G = max(2 * read_len, total_bases // coverage)
+    n = max(1, total_bases // read_len)
+    genome = random_genome(np.random.Generator(np.random.PCG64(g_ss)), G)
+    col = sample_reads(np.random.Generator(np.random.PCG64(r_ss)), genome, n, read_len, 0.005)
+    col.seed = BASE_SEED + 5
+    col.label = f"sweep{read_len}"
+    return col
+
+
+def batch_specs(count: int = 256, scale: float = 1.0, seed: int = BASE_SEED + 3) -> list[tuple[int, int, int]]:
+    """(reads, read length, genome bases) of every collection of the batched
+    workload: reads log-uniform on [5k, 2M] (times scale), read length fixed
+    per collection from {75, 100, 150}, genome uniform in [1, 10] Mb (times
+    scale).  Cheap: no collection is generated."""
+    meta_ss = np.random.SeedSequence(seed).spawn(count + 1)[0]
     meta = np.random.Generator(np.random.PCG64(meta_ss))
     out = []
-    for j in range(count):
+    for _ in range(count):
         n = int(round(math.exp(meta.uniform(math.log(5_000), math.log(2_000_000))) * scale))
         L = int(meta.choice([75, 100, 150]))
         G = int(meta.integers(1_000_000, 10_000_001) * scale)
-        G = max(G, 2 * L)
-        n = max(n, 1)
-        rng = np.random.Generator(np.random.PCG64(col_ss[j]))
-        genome = random_genome(rng, G)
-        col = sample_reads(rng, genome, n, L, 0.005)
-        col.seed = seed
-        col.label = f"batch{j}"
-        out.append(col)
+        out.append((max(n, 1), L, max(G, 2 * L)))
     return out
+
+
+def batch_collection(j: int, count: int = 256, scale: float = 1.0, seed: int = BASE_SEED + 3) -> Collection:
+    """Collection j of the batched workload (the same as batch_collections()[j])."""
+    n, L, G = batch_specs(count, scale, seed)[j]
+    col_ss = np.random.SeedSequence(seed).spawn(count + 1)[1 + j]
+    rng = np.random.Generator(np.random.PCG64(col_ss))
+    genome = random_genome(rng, G)
+    col = sample_reads(rng, genome, n, L, 0.005)
+    col.seed = seed
+    col.label = f"batch{j}"
+    return col
+
+
+def batch_collections(count: int = 256, scale: float = 1.0, seed: int = BASE_SEED + 3) -> list[Collection]:
+    """Independent collections of uneven size and read length (batch_specs),
+    each from its own random genome at 0.5% substitutions."""
+    return [batch_collection(j, count, scale, seed) for j in range(count)]
 
 
 @dataclass

@@ -69,14 +69,25 @@ class Executor:
         raise NotImplementedError
 
 
-def state_bytes(n_reads: int, n_bases: int) -> int:
+def state_bytes(n_reads: int, n_bases: int, max_read_len: int = 255) -> int:
     """Device bytes a job holds while resident and while its batch runs.
 
-    ASCII reads (B) + packed (B/4) + offsets (8n) + its share of the batch
-    copies of reads and offsets (B + 8n) + outputs (B + n + 8n) + its share of
-    the batch workspace (about 24.5 B per base + 8 B per read).
+    Staged ASCII reads (B) + its part of the batch's concatenated reads (B),
+    packed words (B/4 + 16), offsets (8n + 8), outputs (B + n bytes of BWT,
+    8n of term_pos), and the library's workspace for the job alone
+    (cxbwt_batch_workspace_bytes for one collection, pure host arithmetic;
+    a batch's workspace is at most the sum of its jobs').  0 reads or bases
+    beyond one build's limit: the job cannot be built (None).
     """
-    return int(n_bases * (1 + 0.25 + 1 + 1 + 24.75) + n_reads * (8 + 8 + 1 + 8 + 8) + 4096)
+    from . import cxbwt
+    ws = cxbwt.batch_workspace_bytes(max(1, n_reads), n_bases, max(1, min(max_read_len, 65535)), 1)
+    if ws == 0:
+        return None
+    return int(ws + 2 * n_bases + n_bases // 4 + 16 + 8 * (n_reads + 1) + n_bases + n_reads + 8 * n_reads + 4096)
+
+
+def footprint_of(col) -> Optional[int]:
+    return state_bytes(col.n_reads, col.n_bases, col.max_read_len)
 
 
 class DeviceExecutor(Executor):
@@ -98,8 +109,8 @@ class DeviceExecutor(Executor):
         self.keep_on_device = keep_on_device
         cxbwt.lib()
 
-    def footprint(self, col) -> int:
-        return state_bytes(col.n_reads, col.n_bases)
+    def footprint(self, col) -> Optional[int]:
+        return footprint_of(col)
 
     def stage(self, job: Job) -> None:
         torch = self.torch
@@ -111,6 +122,7 @@ class DeviceExecutor(Executor):
         job.handle = (t_dev, ev)
 
     def run_batch(self, jobs: list[Job]) -> list[tuple]:
+        from . import autotune
         torch, cx = self.torch, self.cx
         stream = torch.cuda.current_stream(self.device)
         for j in jobs:
@@ -124,6 +136,8 @@ class DeviceExecutor(Executor):
         text = torch.cat(texts) if nb else torch.empty(0, dtype=torch.uint8, device=self.device)
         offsets = torch.from_numpy(offsets_h.view(np.int64)).to(self.device)
         packed, pstatus = cx.pack(text)
+        # the autotuner's remembered choice for this shape class, if it has one
+        autotune.select_for(n, nb, maxlen, len(jobs))
         bwt, term = cx.build_batch(packed, offsets, n, nb, maxlen, coll_reads)
         if int(pstatus.item()) != 0:
             raise cx.CxbwtError(cx.EDATA, "cxbwt_pack (non-ACGT byte)")
@@ -187,7 +201,10 @@ class Server:
             self._next_id += 1
             job.footprint = self.ex.footprint(collection)
             self.jobs.append(job)
-            if job.footprint > self.budget:
+            if job.footprint is None:
+                job.footprint = 0
+                self._finish(job, FAILED, error="collection above the size one build takes")
+            elif job.footprint > self.budget:
                 self._finish(job, FAILED, error="footprint exceeds the whole device budget")
             else:
                 self.queue.append(job)
@@ -387,15 +404,16 @@ def replay(arrivals, executor: Executor, budget_bytes: int, **server_kw):
         srv.close()
 
 
-def plan_waves(sizes: list[tuple[int, int]], max_bases: int = (1 << 32) - 1, budget_bytes: Optional[int] = None):
-    """Group collections (n_reads, n_bases) into consecutive waves for batched builds.
+def plan_waves(sizes: list[tuple], max_bases: int = (1 << 32) - 1, budget_bytes: Optional[int] = None):
+    """Group collections (n_reads, n_bases[, max_read_len]) into consecutive waves for batched builds.
 
     Each wave holds fewer than max_bases bases in total and, if budget_bytes is
     given, a footprint within it.  Returns lists of collection indices.
     """
     waves, cur, bases, foot = [], [], 0, 0
-    for i, (n, nb) in enumerate(sizes):
-        f = state_bytes(n, nb)
+    for i, size in enumerate(sizes):
+        n, nb = size[0], size[1]
+        f = state_bytes(n, nb, size[2] if len(size) > 2 else 255) or 0
         if cur and (bases + nb > max_bases or (budget_bytes is not None and foot + f > budget_bytes)):
             waves.append(cur)
             cur, bases, foot = [], 0, 0

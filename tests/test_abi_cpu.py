@@ -86,12 +86,67 @@ def test_noalloc_argument_validation_needs_no_gpu():
     assert b"fixed device array" in L.cxbwt_status_str(cxbwt.ESCRATCH)
 
 
+def test_range_argument_validation_needs_no_gpu():
+    """cxbwt_build_ranges checks its arguments before any HIP call."""
+    L = cxbwt.lib()
+    fake = ctypes.c_void_p(0x1000)
+    null = ctypes.c_void_p(0)
+
+    def call(**kw):
+        return L.cxbwt_build_ranges(kw.get("packed", fake), fake, kw.get("n", 3), kw.get("nb", 12), 4,
+                                    kw.get("m", 5), kw.get("flags", 0), fake, fake, kw.get("ws", fake),
+                                    kw.get("wsb", 1 << 40), null)
+
+    assert call(packed=null) == cxbwt.EINVAL
+    assert call(ws=null) == cxbwt.EINVAL
+    assert call(n=0) == cxbwt.EINVAL
+    assert call(m=0) == cxbwt.EINVAL
+    assert call(flags=2) == cxbwt.EINVAL
+    assert call(m=1 << 32) == cxbwt.ERANGE                      # a range must fit 32-bit handles
+    assert call(nb=(1 << 38) + 1) == cxbwt.ERANGE                # above the wide-position limit
+    assert call(wsb=10) == cxbwt.ENOMEM
+    assert call(ws=ctypes.c_void_p(0x1001)) == cxbwt.EINVAL      # misaligned workspace
+    # above 32-bit positions only in ranges, with 64-bit position tables
+    big = 5_000_000_000
+    assert cxbwt.workspace_bytes(50_000_000, big, 100) == 0
+    narrow = cxbwt.range_workspace_bytes(4_000_000, 400_000_000, 100, 10_000_000)
+    wide = cxbwt.range_workspace_bytes(4_000_000, 400_000_000, 100, 10_000_000, wide=True)
+    assert wide - narrow >= 8 * 10_000_000
+    assert cxbwt.range_workspace_bytes(50_000_000, big, 100, 1_000_000_000) > 0
+    assert cxbwt.range_workspace_bytes(50_000_000, big, 100, 0) == 0
+
+
+def test_range_workspace_is_smaller_and_monotone():
+    n, nb = 4_000_000, 400_000_000
+    whole = cxbwt.workspace_bytes(n, nb, 100)
+    part = cxbwt.range_workspace_bytes(n, nb, 100, 50_000_000)
+    assert part < whole / 3
+    assert cxbwt.range_workspace_bytes(n, nb, 100, 50_000_000, wide=True) > part
+    sizes = [cxbwt.range_workspace_bytes(n, nb, 100, m) for m in (1, 10, 1000, 10 ** 6, 10 ** 8, nb)]
+    assert sizes == sorted(sizes)                       # grows with the budget
+    assert sizes[0] > nb                                 # text records and ranks stay whole
+    assert cxbwt.range_budget_for(n, nb, 100, part) == 50_000_000
+    assert cxbwt.range_budget_for(n, nb, 100, 1000) == 0
+
+
+def test_schedule_set_and_get_without_gpu():
+    assert cxbwt.get_schedule() == cxbwt.SCHEDULE_MSD
+    try:
+        cxbwt.set_schedule(cxbwt.SCHEDULE_STRINGWORD)
+        assert cxbwt.get_schedule() == cxbwt.SCHEDULE_STRINGWORD
+        with pytest.raises(cxbwt.CxbwtError):
+            cxbwt.set_schedule(7)
+        assert cxbwt.get_schedule() == cxbwt.SCHEDULE_STRINGWORD
+    finally:
+        cxbwt.set_schedule(cxbwt.SCHEDULE_MSD)
+
+
 def test_pack_argument_validation_needs_no_gpu():
     L = cxbwt.lib()
     null = ctypes.c_void_p(0)
     assert L.cxbwt_pack(null, 10, ctypes.c_void_p(0x1000), null, null) == cxbwt.EINVAL
     assert L.cxbwt_pack(ctypes.c_void_p(0x1000), 10, null, null, null) == cxbwt.EINVAL
-    assert L.cxbwt_pack(ctypes.c_void_p(0x1000), 1 << 33, ctypes.c_void_p(0x1000), null, null) == cxbwt.ERANGE
+    assert L.cxbwt_pack(ctypes.c_void_p(0x1000), (1 << 38) + 1, ctypes.c_void_p(0x1000), null, null) == cxbwt.ERANGE
 
 
 def test_status_strings():

@@ -33,36 +33,46 @@ def test_algorithmic_bytes_model():
 
 
 def test_counter_runs_match_sources_and_instantiation(tmp_path, monkeypatch):
+    """Traffic per build from a counter record: raw FETCH_SIZE / WRITE_SIZE totals
+    over the record's builds, scaled by its calibration factors."""
     (tmp_path / "profiles").mkdir()
-    rec = {"kernel_sources_sha256_16": "abc", "tuning": "8x3",
-           "kernels": {"k_local": {"dispatches_per_build": 5, "fetch_MB_per_dispatch": 100.0,
-                                   "write_MB_per_dispatch": 10.0},
-                       "k_level_scatter": {"dispatches_per_build": 6, "fetch_MB_per_dispatch": 20.0,
-                                           "write_MB_per_dispatch": 20.0},
-                       "k_gen_scatter": {"dispatches_per_build": 1, "fetch_MB_per_dispatch": 6.0,
-                                         "write_MB_per_dispatch": 48.0}}}
+    cal = {"fetch_factor": 2.0, "write_factor": 1.0, "note": "neg over 1 GiB"}
+
+    def run(tuning, local_fetch, scatter):
+        return {"tuning": tuning, "kernels": {
+            "k_local": {"dispatches": 10, "fetch_MB": local_fetch, "write_MB": 20.0},
+            "k_level_scatter": {"dispatches": 12, "fetch_MB": scatter, "write_MB": scatter},
+            "k_gen_scatter": {"dispatches": 2, "fetch_MB": 6.0, "write_MB": 48.0}}}
+
+    rec = {"kernel_sources_sha256_16": "abc", "builds": 2, "calibration": cal,
+           "runs": [run("8x3", 100.0, 40.0), run("6x3", 200.0, 60.0)]}
     (tmp_path / "profiles" / "plain1_traffic.json").write_text(json.dumps(rec))
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     monkeypatch.setattr(bench, "kernel_sources_hash", lambda: "abc")
     # the chunk kernel's work depends on the chunk size only
-    assert bench.measured_traffic("plain1", "local", 5, "8x3") == 110e6
-    assert bench.measured_traffic("plain1", "local", 5, "16x3") == 110e6
-    assert bench.measured_traffic("plain1", "local", 5, "8x6") is None
+    assert bench.measured_traffic("plain1", "local", "8x3") == (100 * 2 + 20) * 1e6 / 2
+    assert bench.measured_traffic("plain1", "local", "16x3") == (100 * 2 + 20) * 1e6 / 2  # first run with chunk 3
+    assert bench.measured_traffic("plain1", "local", "6x3") == (200 * 2 + 20) * 1e6 / 2  # its own run first
+    assert bench.measured_traffic("plain1", "local", "8x6") is None
     # the scatters depend on both parts
-    assert bench.measured_traffic("plain1", "level_scatter", 7, "8x3") == (6 * 40e6 + 54e6) / 7
-    assert bench.measured_traffic("plain1", "level_scatter", 7, "16x3") is None
-    # counter runs of further instantiations of the same sources
-    rec["other_tunings"] = [{"tuning": "6x3", "kernels": {
-        "k_local": {"dispatches_per_build": 5, "fetch_MB_per_dispatch": 200.0, "write_MB_per_dispatch": 10.0},
-        "k_level_scatter": {"dispatches_per_build": 6, "fetch_MB_per_dispatch": 30.0,
-                            "write_MB_per_dispatch": 30.0}}}]
-    (tmp_path / "profiles" / "plain1_traffic.json").write_text(json.dumps(rec))
-    assert bench.measured_traffic("plain1", "level_scatter", 6, "6x3") == 360e6 / 6
-    assert bench.measured_traffic("plain1", "level_scatter", 7, "8x3") == (6 * 40e6 + 54e6) / 7
-    assert bench.measured_traffic("plain1", "local", 5, "6x3") == 210e6  # its own run first
-    assert bench.measured_traffic("plain1", "local", 5, "16x3") == 110e6
-    assert bench.measured_traffic("plain1", "level_scatter", 7, "16x3") is None
+    assert bench.measured_traffic("plain1", "level_scatter", "8x3") == (40 * 3 + 6 * 2 + 48) * 1e6 / 2
+    assert bench.measured_traffic("plain1", "level_scatter", "6x3") == (60 * 3 + 6 * 2 + 48) * 1e6 / 2
+    assert bench.measured_traffic("plain1", "level_scatter", "16x3") is None
     # other sources, or no counter run: nothing
     monkeypatch.setattr(bench, "kernel_sources_hash", lambda: "other")
-    assert bench.measured_traffic("plain1", "local", 5, "8x3") is None
-    assert bench.measured_traffic("plain2", "local", 5, "8x3") is None
+    assert bench.measured_traffic("plain1", "local", "8x3") is None
+    assert bench.traffic_record("plain1") is None
+    assert bench.measured_traffic("plain2", "local", "8x3") is None
+
+
+def test_host_info_names_cpu_and_ram():
+    info = bench.host_info()
+    assert info["threads"] >= 1
+    assert isinstance(info["cpu_model"], str) and info["cpu_model"]
+    assert info["host_ram_gib"] is None or info["host_ram_gib"] > 0
+
+
+def test_default_workload_is_the_largest_single_gpu_build():
+    assert bench.DEFAULT_WORKLOAD == "plain2"
+    assert bench.SECONDARY_WORKLOAD == "plain1"
+    assert set(bench.CPU_SAMPLE_SCALE) == set(bench.WORKLOADS)

@@ -67,11 +67,37 @@ def test_autotuner_selects_a_choice_and_output_is_unchanged():
     text = torch.from_numpy(col.text).cuda()
     off = torch.from_numpy(col.offsets.view(np.int64)).cuda()
     packed, _ = cxbwt.pack(text)
-    res = autotune.tune_build(packed, off, col.n_reads, col.n_bases, col.max_read_len, repeats=1)
-    assert set(res["ms"]) == set(cxbwt.TUNING_CHOICES)
-    assert res["choice"] in cxbwt.TUNING_CHOICES
-    assert cxbwt.get_tuning() == res["choice"]
+    res = autotune.tune_build(packed, off, col.n_reads, col.n_bases, col.max_read_len, repeats=3, persist=False)
+    # every instantiation with the MSD schedule, and the stringword schedule
+    assert set(res["ms"]) == set(autotune.choices_for(1))
+    assert {ch[:2] for ch in res["ms"]} == set(cxbwt.TUNING_CHOICES)
+    assert res["choice"] in res["ms"]
+    assert autotune.current() == res["choice"]
     assert autotune.select_for(col.n_reads, col.n_bases, col.max_read_len) == res["choice"]
-    b, t = cxbwt.build_host(col.text, col.offsets)
+    try:
+        b, t = cxbwt.build_host(col.text, col.offsets)
+    finally:
+        autotune.apply((*cxbwt.TUNING_CHOICES[0], cxbwt.SCHEDULE_MSD))
     eb, et = oracle.bwt(col.text, col.offsets)
     assert np.array_equal(b, eb) and np.array_equal(t, et)
+
+
+def test_tuner_choice_persists_across_processes(tmp_path, monkeypatch):
+    """A tuned choice is written to the cache file and found again by a fresh
+    in-memory cache (a later process)."""
+    import torch
+    monkeypatch.setenv("CXBWT_TUNE_CACHE", str(tmp_path / "tuning.json"))
+    col = datagen.plain_config(0, scale=0.2)
+    text = torch.from_numpy(col.text).cuda()
+    off = torch.from_numpy(col.offsets.view(np.int64)).cuda()
+    packed, _ = cxbwt.pack(text)
+    _say("autotune persistence")
+    choices = ((8, 3, cxbwt.SCHEDULE_MSD), (16, 6, cxbwt.SCHEDULE_MSD))
+    res = autotune.tune_build(packed, off, col.n_reads, col.n_bases, col.max_read_len, repeats=1, choices=choices)
+    try:
+        monkeypatch.setattr(autotune, "_cache", {})
+        autotune.apply((*cxbwt.TUNING_CHOICES[0], cxbwt.SCHEDULE_MSD))
+        assert autotune.select_for(col.n_reads, col.n_bases, col.max_read_len) == res["choice"]
+        assert autotune.current() == res["choice"]
+    finally:
+        autotune.apply((*cxbwt.TUNING_CHOICES[0], cxbwt.SCHEDULE_MSD))
