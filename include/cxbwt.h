@@ -244,6 +244,44 @@ int cxbwt_build_batch(const uint64_t *packed, const uint64_t *offsets, uint64_t 
                       uint64_t *term_pos, void *workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * Builds that return at once (for callers that overlap builds with other
+ * host work or with each other, such as a serving loop).
+ *
+ * cxbwt_build_start / cxbwt_build_batch_start -- arguments, checks and
+ *   results as cxbwt_build / cxbwt_build_batch, plus
+ *     job   (host, out) the started build, or NULL on an error returned here.
+ *   Argument errors are returned by the call, before any HIP call; a started
+ *   build's own status (CXBWT_EDATA and so on) comes from cxbwt_job_wait.  A
+ *   library worker thread enqueues the build's kernels and copies on
+ *   `stream`, in the order cxbwt_build would, and waits on that stream
+ *   between sort levels (the level counts are read back); the calling thread
+ *   does not wait.  The tuning, schedule and timing choices of the calling
+ *   thread at the call apply.  Until cxbwt_job_wait returns, the caller keeps
+ *   every buffer alive and unchanged and enqueues nothing on `stream` that
+ *   reads the outputs.  Builds started on distinct streams with distinct
+ *   workspaces run concurrently on the device; builds on one stream run one
+ *   after the other.
+ *
+ * cxbwt_job_done -- 1 once the build's device work has completed (the
+ *   outputs are final), else 0; never waits.  0 for NULL.
+ *
+ * cxbwt_job_wait -- wait for the build, return its status, copy its
+ *   statistics to *stats (host, may be NULL; cxbwt_last_stats on the waiting
+ *   thread also reads them) and free the job.  Every started job must be
+ *   waited for exactly once.  CXBWT_EINVAL for NULL.
+ */
+typedef struct cxbwt_job cxbwt_job;
+int cxbwt_build_start(const uint64_t *packed, const uint64_t *offsets, uint64_t n_reads, uint64_t n_bases,
+                      uint32_t max_read_len, uint8_t *bwt, uint64_t *term_pos, void *workspace,
+                      size_t workspace_bytes, void *stream, cxbwt_job **job);
+int cxbwt_build_batch_start(const uint64_t *packed, const uint64_t *offsets, uint64_t n_reads, uint64_t n_bases,
+                            uint32_t max_read_len, const uint64_t *coll_reads, uint32_t n_coll, uint8_t *bwt,
+                            uint64_t *term_pos, void *workspace, size_t workspace_bytes, void *stream,
+                            cxbwt_job **job);
+int cxbwt_job_done(const cxbwt_job *job);
+/* cxbwt_job_wait is declared after cxbwt_stats below. */
+
+/*
  * A build captured once in a hipGraph and replayed (the batched row of the
  * design: every level's launches cover all collections, and the launches of
  * the levels after the first are sized on the device, so the whole build is
@@ -360,6 +398,9 @@ int cxbwt_get_schedule(uint32_t *schedule);
 
 /* Copies the last build's counters (host) into *out; CXBWT_EINVAL on NULL. */
 int cxbwt_last_stats(cxbwt_stats *out);
+
+/* Waits for a started build (see cxbwt_build_start). */
+int cxbwt_job_wait(cxbwt_job *job, cxbwt_stats *stats);
 
 /*
  * cxbwt_set_timing -- for later cxbwt_build calls on the calling host thread,

@@ -45,8 +45,10 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <mutex>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "cxbwt.h"
@@ -1422,6 +1424,72 @@ struct cxbwt_graph {
   GraphPlan p;
 };
 
+// A build started by cxbwt_build_start / cxbwt_build_batch_start: a worker
+// thread enqueues it on the caller's stream and waits on that stream between
+// levels; the caller waits for the job instead of for the call.
+struct cxbwt_job {
+  std::thread worker;
+  std::atomic<int> done{0};
+  int status = CXBWT_OK;
+  cxbwt_stats stats{};
+};
+
+namespace {
+
+struct JobArgs {
+  const uint64_t *packed, *offsets;
+  uint64_t n, nb;
+  uint32_t maxlen;
+  std::vector<uint64_t> coll_reads;  // copied at the call: the caller's array may go away
+  uint8_t *bwt;
+  uint64_t *term_pos;
+  unsigned char *ws;
+  hipStream_t st;
+  int device;
+  Tuning tu;   // the calling thread's choices at the call
+  int timing;
+};
+
+void job_main(cxbwt_job *job, JobArgs a) {
+  int rc = CXBWT_OK;
+  try {
+    if (hipSetDevice(a.device) != hipSuccess) {
+      rc = CXBWT_EDEVICE;
+    } else {
+      g_tuning = a.tu;
+      g_timing = a.timing;
+      rc = run_build(a.packed, a.offsets, a.n, a.nb, a.maxlen, a.coll_reads.data(),
+                     (uint32_t)(a.coll_reads.size() - 1), a.bwt, a.term_pos, a.ws, a.st);
+      // a failed build may leave work in flight: the job ends when the stream has drained
+      if (rc && hipStreamSynchronize(a.st) != hipSuccess) rc = CXBWT_EDEVICE;
+    }
+  } catch (...) {
+    rc = CXBWT_EDEVICE;
+    (void)hipStreamSynchronize(a.st);
+  }
+  job->stats = g_stats;
+  job->status = rc;
+  job->done.store(1, std::memory_order_release);
+}
+
+int start_job(JobArgs &&a, cxbwt_job **out) {
+  if (hipGetDevice(&a.device) != hipSuccess) return CXBWT_EDEVICE;
+  a.tu = g_tuning;
+  a.timing = g_timing;
+  cxbwt_job *job = new (std::nothrow) cxbwt_job;
+  if (!job) return CXBWT_ENOMEM;
+  try {
+    job->worker = std::thread(job_main, job, std::move(a));
+  } catch (...) {
+    delete job;
+    return CXBWT_EDEVICE;
+  }
+  *out = job;
+  return CXBWT_OK;
+}
+
+}  // namespace
+
 // Workspace of cxbwt_build_noalloc: a fixed array in the code object, one
 // copy per device the library runs on, held until the process ends.  Host
 // code never passes the array's name to a kernel or a copy (on the host it
@@ -1526,6 +1594,53 @@ int cxbwt_build_ranges(const uint64_t *packed, const uint64_t *offsets, uint64_t
   if (((uintptr_t)workspace & 255u) != 0) return CXBWT_EINVAL;
   return run_range_build(packed, offsets, n_reads, n_bases, max_read_len, max_range_suffixes,
                          range_wide(n_bases, flags), bwt, term_pos, (unsigned char *)workspace, (hipStream_t)stream);
+}
+
+int cxbwt_build_start(const uint64_t *packed, const uint64_t *offsets, uint64_t n_reads, uint64_t n_bases,
+                      uint32_t max_read_len, uint8_t *bwt, uint64_t *term_pos, void *workspace,
+                      size_t workspace_bytes, void *stream, cxbwt_job **job) {
+  if (!job) return CXBWT_EINVAL;
+  *job = nullptr;
+  if (!packed || !offsets || !bwt || !term_pos || !workspace || n_reads == 0) return CXBWT_EINVAL;
+  if (!sizes_ok(n_reads, n_bases, max_read_len)) return CXBWT_ERANGE;
+  if (workspace_bytes < cxbwt_workspace_bytes(n_reads, n_bases, max_read_len)) return CXBWT_ENOMEM;
+  if (((uintptr_t)workspace & 255u) != 0) return CXBWT_EINVAL;
+  JobArgs a{packed, offsets, n_reads, n_bases, max_read_len, {0, n_reads}, bwt, term_pos,
+            (unsigned char *)workspace, (hipStream_t)stream, 0, Tuning{8, 6}, 0};
+  return start_job(std::move(a), job);
+}
+
+int cxbwt_build_batch_start(const uint64_t *packed, const uint64_t *offsets, uint64_t n_reads, uint64_t n_bases,
+                            uint32_t max_read_len, const uint64_t *coll_reads, uint32_t n_coll, uint8_t *bwt,
+                            uint64_t *term_pos, void *workspace, size_t workspace_bytes, void *stream,
+                            cxbwt_job **job) {
+  if (!job) return CXBWT_EINVAL;
+  *job = nullptr;
+  if (!packed || !offsets || !bwt || !term_pos || !workspace || !coll_reads || n_reads == 0 || n_coll == 0)
+    return CXBWT_EINVAL;
+  if (!sizes_ok(n_reads, n_bases, max_read_len)) return CXBWT_ERANGE;
+  if (n_coll > n_reads) return CXBWT_EINVAL;
+  if (coll_reads[0] != 0 || coll_reads[n_coll] != n_reads) return CXBWT_EINVAL;
+  for (uint32_t c = 0; c < n_coll; ++c)
+    if (coll_reads[c + 1] <= coll_reads[c]) return CXBWT_EINVAL;
+  if (workspace_bytes < cxbwt_batch_workspace_bytes(n_reads, n_bases, max_read_len, n_coll)) return CXBWT_ENOMEM;
+  if (((uintptr_t)workspace & 255u) != 0) return CXBWT_EINVAL;
+  JobArgs a{packed, offsets, n_reads, n_bases, max_read_len,
+            std::vector<uint64_t>(coll_reads, coll_reads + n_coll + 1), bwt, term_pos,
+            (unsigned char *)workspace, (hipStream_t)stream, 0, Tuning{8, 6}, 0};
+  return start_job(std::move(a), job);
+}
+
+int cxbwt_job_done(const cxbwt_job *job) { return job && job->done.load(std::memory_order_acquire) ? 1 : 0; }
+
+int cxbwt_job_wait(cxbwt_job *job, cxbwt_stats *stats) {
+  if (!job) return CXBWT_EINVAL;
+  if (job->worker.joinable()) job->worker.join();
+  const int rc = job->status;
+  if (stats) *stats = job->stats;
+  g_stats = job->stats;  // cxbwt_last_stats on the waiting thread
+  delete job;
+  return rc;
 }
 
 int cxbwt_build_batch(const uint64_t *packed, const uint64_t *offsets, uint64_t n_reads, uint64_t n_bases,

@@ -25,7 +25,8 @@ NOALLOC_WORKSPACE_BYTES = 256 << 20
 
 # Names the C ABI exports (include/cxbwt.h).
 ABI_FUNCTIONS = ("cxbwt_packed_words", "cxbwt_pack", "cxbwt_workspace_bytes", "cxbwt_build", "cxbwt_build_noalloc",
-                 "cxbwt_range_workspace_bytes", "cxbwt_build_ranges", "cxbwt_batch_workspace_bytes", "cxbwt_build_batch", "cxbwt_last_stats", "cxbwt_set_timing",
+                 "cxbwt_range_workspace_bytes", "cxbwt_build_ranges", "cxbwt_batch_workspace_bytes", "cxbwt_build_batch",
+                 "cxbwt_build_start", "cxbwt_build_batch_start", "cxbwt_job_done", "cxbwt_job_wait", "cxbwt_last_stats", "cxbwt_set_timing",
                  "cxbwt_set_tuning", "cxbwt_get_tuning", "cxbwt_set_schedule", "cxbwt_get_schedule", "cxbwt_graph_create", "cxbwt_graph_launch",
                  "cxbwt_graph_finish", "cxbwt_graph_destroy", "cxbwt_status_str")
 
@@ -89,6 +90,16 @@ def lib():
             L.cxbwt_batch_workspace_bytes.restype = ctypes.c_size_t
             L.cxbwt_build_batch.argtypes = [vp, vp, u64, u64, u32, vp, u32, vp, vp, vp, ctypes.c_size_t, vp]
             L.cxbwt_build_batch.restype = ctypes.c_int
+            L.cxbwt_build_start.argtypes = [vp, vp, u64, u64, u32, vp, vp, vp, ctypes.c_size_t, vp,
+                                            ctypes.POINTER(vp)]
+            L.cxbwt_build_start.restype = ctypes.c_int
+            L.cxbwt_build_batch_start.argtypes = [vp, vp, u64, u64, u32, vp, u32, vp, vp, vp, ctypes.c_size_t, vp,
+                                                  ctypes.POINTER(vp)]
+            L.cxbwt_build_batch_start.restype = ctypes.c_int
+            L.cxbwt_job_done.argtypes = [vp]
+            L.cxbwt_job_done.restype = ctypes.c_int
+            L.cxbwt_job_wait.argtypes = [vp, ctypes.POINTER(Stats)]
+            L.cxbwt_job_wait.restype = ctypes.c_int
             L.cxbwt_last_stats.argtypes = [ctypes.POINTER(Stats)]
             L.cxbwt_last_stats.restype = ctypes.c_int
             L.cxbwt_set_timing.argtypes = [ctypes.c_int]
@@ -287,6 +298,93 @@ def build_batch(packed, offsets, n_reads: int, n_bases: int, max_read_len: int, 
     return bwt, term
 
 
+class BuildJob:
+    """A build started with build_start / build_batch_start (cxbwt_job).
+
+    Holds every tensor the build reads or writes until wait() returns.
+    done(): the device work has completed.  wait(): its status (raises on a
+    failure) and (bwt, term).  A job must be waited for once.
+    """
+
+    def __init__(self, handle, what, tensors, out):
+        self._h = handle
+        self._what = what
+        self._tensors = tensors
+        self.bwt, self.term = out
+        self.stats = None
+
+    def done(self) -> bool:
+        return bool(self._h) and bool(lib().cxbwt_job_done(self._h))
+
+    def wait(self):
+        if not self._h:
+            raise RuntimeError("job already waited for")
+        s = Stats()
+        st = lib().cxbwt_job_wait(self._h, ctypes.byref(s))
+        self._h = ctypes.c_void_p()
+        self._tensors = None
+        self.stats = _stats_dict(s)
+        if st != OK:
+            raise CxbwtError(st, self._what)
+        return self.bwt, self.term
+
+    def __del__(self):
+        if self._h:  # never left running: wait (and drop the status)
+            try:
+                lib().cxbwt_job_wait(self._h, None)
+            except Exception:
+                pass
+
+
+def _out_tensors(out, n_reads, n_bases, dev):
+    import torch
+    if out is not None:
+        return out
+    return (torch.empty(n_bases + n_reads, dtype=torch.uint8, device=dev),
+            torch.empty(n_reads, dtype=torch.int64, device=dev))
+
+
+def build_start(packed, offsets, n_reads: int, n_bases: int, max_read_len: int, workspace=None, out=None,
+                stream=None) -> BuildJob:
+    """cxbwt_build_start: the build of `build`, returning at once (see BuildJob)."""
+    dev = packed.device
+    if workspace is None:
+        workspace = alloc_workspace(n_reads, n_bases, max_read_len, dev)
+    bwt, term = _out_tensors(out, n_reads, n_bases, dev)
+    h = ctypes.c_void_p()
+    st = lib().cxbwt_build_start(ctypes.c_void_p(packed.data_ptr()), ctypes.c_void_p(offsets.data_ptr()), n_reads,
+                                 n_bases, max_read_len, ctypes.c_void_p(bwt.data_ptr()),
+                                 ctypes.c_void_p(term.data_ptr()), ctypes.c_void_p(workspace.data_ptr()),
+                                 workspace.numel(), _stream_ptr(stream), ctypes.byref(h))
+    if st != OK:
+        raise CxbwtError(st, "cxbwt_build_start")
+    return BuildJob(h, "cxbwt_build_start", (packed, offsets, workspace), (bwt, term))
+
+
+def build_batch_start(packed, offsets, n_reads: int, n_bases: int, max_read_len: int, coll_reads, workspace=None,
+                      out=None, stream=None) -> BuildJob:
+    """cxbwt_build_batch_start: the build of `build_batch`, returning at once (see BuildJob)."""
+    import torch
+    cr = np.ascontiguousarray(np.asarray(coll_reads, dtype=np.uint64))
+    n_coll = cr.size - 1
+    dev = packed.device
+    if workspace is None:
+        nbytes = batch_workspace_bytes(n_reads, n_bases, max_read_len, n_coll)
+        if nbytes == 0:
+            raise CxbwtError(ERANGE, "cxbwt_batch_workspace_bytes")
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    bwt, term = _out_tensors(out, n_reads, n_bases, dev)
+    h = ctypes.c_void_p()
+    st = lib().cxbwt_build_batch_start(ctypes.c_void_p(packed.data_ptr()), ctypes.c_void_p(offsets.data_ptr()),
+                                       n_reads, n_bases, max_read_len, cr.ctypes.data_as(ctypes.c_void_p), n_coll,
+                                       ctypes.c_void_p(bwt.data_ptr()), ctypes.c_void_p(term.data_ptr()),
+                                       ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream_ptr(stream),
+                                       ctypes.byref(h))
+    if st != OK:
+        raise CxbwtError(st, "cxbwt_build_batch_start")
+    return BuildJob(h, "cxbwt_build_batch_start", (packed, offsets, workspace), (bwt, term))
+
+
 class BuildGraph:
     """A build captured once in a hipGraph and replayed (cxbwt_graph_*).
 
@@ -402,6 +500,10 @@ def build_batch_host(cols, device="cuda"):
 def last_stats() -> dict:
     s = Stats()
     lib().cxbwt_last_stats(ctypes.byref(s))
+    return _stats_dict(s)
+
+
+def _stats_dict(s) -> dict:
     out = {f: int(getattr(s, f)) for f, _ in Stats._fields_ if f not in ("ms", "launches", "reserved")}
     out["ms"] = {k: float(s.ms[i]) for i, k in enumerate(KERNEL_CLASSES) if s.launches[i]}
     out["launches"] = {k: int(s.launches[i]) for i, k in enumerate(KERNEL_CLASSES) if s.launches[i]}

@@ -5,10 +5,13 @@ Jobs (read collections) arrive over time.  The scheduler:
   * admits queued jobs in arrival order while the resident footprint stays
     within the budget (an admitted job's reads are staged on the device by a
     background stager thread, overlapping the build that is running);
-  * whenever the device is free, builds every staged job that fits the batch
-    limits in ONE cxbwt_build_batch call (continuous batching: jobs that
-    arrived while the previous batch ran join the next one);
-  * returns results per job, frees their memory and admits more.
+  * whenever fewer than `max_inflight` batches are building, starts every
+    staged job that fits the batch limits as ONE batched build that returns
+    at once (cxbwt_build_batch_start, on a stream of its own): continuous
+    batching, with the next batch's staging, packing and level launches
+    overlapping the running one on the device;
+  * collects finished batches, returns results per job, frees their memory
+    and admits more.
 A batch that fails is retried job by job so that a bad job fails alone.
 
 The executor is an interface: DeviceExecutor drives the HIP library; tests
@@ -68,6 +71,22 @@ class Executor:
     def release(self, job: Job) -> None:  # pragma: no cover - interface
         raise NotImplementedError
 
+    # Batches that return at once.  The defaults build synchronously.
+    def start_batch(self, jobs: list[Job]):
+        try:
+            return (self.run_batch(jobs), None)
+        except Exception as e:  # reported by finish_batch
+            return (None, e)
+
+    def batch_done(self, handle) -> bool:
+        return True
+
+    def finish_batch(self, handle) -> list[tuple]:
+        results, err = handle
+        if err is not None:
+            raise err
+        return results
+
 
 def state_bytes(n_reads: int, n_bases: int, max_read_len: int = 255) -> int:
     """Device bytes a job holds while resident and while its batch runs.
@@ -107,40 +126,63 @@ class DeviceExecutor(Executor):
         self.device = torch.device(device)
         self.copy_stream = torch.cuda.Stream(device=self.device)
         self.keep_on_device = keep_on_device
+        self.build_streams = [torch.cuda.Stream(device=self.device) for _ in range(2)]
+        self._next_stream = 0
         cxbwt.lib()
 
     def footprint(self, col) -> Optional[int]:
         return footprint_of(col)
 
     def stage(self, job: Job) -> None:
+        """Copy the job's reads to the device on the copy stream.  The reads may
+        be a numpy array or a torch CPU tensor; a client that receives reads
+        into pinned host memory (a tensor with pin_memory) gets an
+        asynchronous copy at full link speed."""
         torch = self.torch
         col = job.collection
+        src = col.text if isinstance(col.text, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(col.text))
         with torch.cuda.stream(self.copy_stream):
-            t_dev = torch.from_numpy(np.ascontiguousarray(col.text)).to(self.device, non_blocking=True)
+            t_dev = src.to(self.device, non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(self.copy_stream)
         job.handle = (t_dev, ev)
 
     def run_batch(self, jobs: list[Job]) -> list[tuple]:
+        return self.finish_batch(self.start_batch(jobs))
+
+    def start_batch(self, jobs: list[Job]):
+        """Concatenate the staged reads, pack them and start the batched build
+        on the next of two build streams; returns at once."""
         from . import autotune
         torch, cx = self.torch, self.cx
-        stream = torch.cuda.current_stream(self.device)
-        for j in jobs:
-            stream.wait_event(j.handle[1])
+        stream = self.build_streams[self._next_stream % len(self.build_streams)]
+        self._next_stream += 1
         cols = [j.collection for j in jobs]
         _, offsets_h, coll_reads, maxlen = cx.concat_collections([_Shape(c) for c in cols])
         nbs = [c.n_bases for c in cols]
         ns = [c.n_reads for c in cols]
         n, nb = int(coll_reads[-1]), int(offsets_h[-1])
-        texts = [j.handle[0] for j in jobs]
-        text = torch.cat(texts) if nb else torch.empty(0, dtype=torch.uint8, device=self.device)
-        offsets = torch.from_numpy(offsets_h.view(np.int64)).to(self.device)
-        packed, pstatus = cx.pack(text)
-        # the autotuner's remembered choice for this shape class, if it has one
-        autotune.select_for(n, nb, maxlen, len(jobs))
-        bwt, term = cx.build_batch(packed, offsets, n, nb, maxlen, coll_reads)
+        with torch.cuda.stream(stream):
+            for j in jobs:
+                stream.wait_event(j.handle[1])
+                j.handle[0].record_stream(stream)  # staged on the copy stream, read on this one
+            texts = [j.handle[0] for j in jobs]
+            text = torch.cat(texts) if nb else torch.empty(0, dtype=torch.uint8, device=self.device)
+            offsets = torch.from_numpy(offsets_h.view(np.int64)).to(self.device, non_blocking=False)
+            packed, pstatus = cx.pack(text, stream=stream)
+            # the autotuner's remembered choice for this shape class, if it has one
+            autotune.select_for(n, nb, maxlen, len(jobs))
+            job = cx.build_batch_start(packed, offsets, n, nb, maxlen, coll_reads, stream=stream)
+        return (job, pstatus, ns, nbs)
+
+    def batch_done(self, handle) -> bool:
+        return handle[0].done()
+
+    def finish_batch(self, handle) -> list[tuple]:
+        job, pstatus, ns, nbs = handle
+        bwt, term = job.wait()
         if int(pstatus.item()) != 0:
-            raise cx.CxbwtError(cx.EDATA, "cxbwt_pack (non-ACGT byte)")
+            raise self.cx.CxbwtError(self.cx.EDATA, "cxbwt_pack (non-ACGT byte)")
         if not self.keep_on_device:
             bwt = bwt.cpu().numpy()
             term = term.cpu().numpy().view(np.uint64)
@@ -153,6 +195,13 @@ class DeviceExecutor(Executor):
 
     def release(self, job: Job) -> None:
         job.handle = None
+
+
+class _Failed:
+    """A batch whose start raised: finished, failed, isolated job by job."""
+
+    def __init__(self, error):
+        self.error = error
 
 
 class _Shape:
@@ -168,16 +217,19 @@ class Server:
 
     budget_bytes      device memory the resident jobs may hold together
     max_batch_bases   bases per batch (the device path takes < 2^32)
-    max_batch_jobs    jobs per batch (1 = one job at a time, the baseline)
+    max_batch_jobs    jobs per batch (1 with max_inflight 1 = one job at a time, the baseline)
+    max_inflight      batches building at once (each on a stream of its own)
     """
 
     def __init__(self, executor: Executor, budget_bytes: int, max_batch_bases: int = (1 << 32) - 1,
                  max_batch_jobs: Optional[int] = None, clock: Callable[[], float] = time.monotonic,
-                 stage_in_background: bool = True):
+                 stage_in_background: bool = True, max_inflight: int = 2):
         self.ex = executor
         self.budget = int(budget_bytes)
         self.max_batch_bases = int(max_batch_bases)
         self.max_batch_jobs = max_batch_jobs
+        self.max_inflight = max(1, int(max_inflight))
+        self.inflight: list = []               # (batch, executor handle)
         self.clock = clock
         self.queue: deque[Job] = deque()       # arrived, not admitted
         self.staged: deque[Job] = deque()      # resident, waiting for a batch
@@ -301,20 +353,47 @@ class Server:
         return batch
 
     def step(self) -> int:
-        """Admit what fits, then build one batch of staged jobs.  Returns jobs built."""
-        with self._lock:
-            self._admit()
-            batch = self._take_batch()
-            for j in batch:
-                j.state = RUNNING
-                j.t_start = self.clock()
-                j.batch_id = len(self.batches)
-            if batch:
-                self.batches.append([j.id for j in batch])
-        if not batch:
-            return 0
+        """Collect finished batches, admit what fits, and start batches of
+        staged jobs while fewer than max_inflight are building.  Returns the
+        jobs finished or started (0: nothing to do yet)."""
+        progress = self._reap()
+        while len(self.inflight) < self.max_inflight:
+            with self._lock:
+                self._admit()
+                batch = self._take_batch()
+                for j in batch:
+                    j.state = RUNNING
+                    j.t_start = self.clock()
+                    j.batch_id = len(self.batches)
+                if batch:
+                    self.batches.append([j.id for j in batch])
+            if not batch:
+                break
+            try:
+                handle = self.ex.start_batch(batch)
+            except Exception as e:
+                handle = _Failed(e)  # finished (failed) at once: isolated when reaped
+            self.inflight.append((batch, handle))
+            progress += len(batch)
+            progress += self._reap()  # an executor that builds synchronously finishes at once
+        return progress
+
+    def _reap(self) -> int:
+        """Finish the in-flight batches whose builds are done."""
+        done = 0
+        for batch, handle in list(self.inflight):
+            if not isinstance(handle, _Failed) and not self.ex.batch_done(handle):
+                continue
+            self.inflight.remove((batch, handle))
+            self._complete(batch, handle)
+            done += len(batch)
+        return done
+
+    def _complete(self, batch, handle):
         try:
-            results = self.ex.run_batch(batch)
+            if isinstance(handle, _Failed):
+                raise handle.error
+            results = self.ex.finish_batch(handle)
             failures = {}
         except Exception:
             # isolate: rebuild one by one so only the bad job fails
@@ -335,7 +414,6 @@ class Server:
                     self._finish(j, FAILED, error=failures[j.id])
                 else:
                     self._finish(j, DONE, result=r)
-        return len(batch)
 
     def pending(self) -> int:
         with self._lock:

@@ -129,6 +129,40 @@ def test_range_workspace_is_smaller_and_monotone():
     assert cxbwt.range_budget_for(n, nb, 100, 1000) == 0
 
 
+def test_job_argument_validation_needs_no_gpu():
+    """cxbwt_build_start / cxbwt_build_batch_start check their arguments before
+    any HIP call (the job pointer is cleared); waiting on NULL is refused."""
+    L = cxbwt.lib()
+    fake = ctypes.c_void_p(0x1000)
+    null = ctypes.c_void_p(0)
+
+    def start(**kw):
+        h = ctypes.c_void_p(0x1234)
+        rc = L.cxbwt_build_start(kw.get("packed", fake), fake, kw.get("n", 3), kw.get("nb", 12), 4, fake, fake,
+                                 kw.get("ws", fake), kw.get("wsb", 1 << 40), null, ctypes.byref(h))
+        return rc, h.value
+
+    assert start(packed=null) == (cxbwt.EINVAL, None)
+    assert start(n=0)[0] == cxbwt.EINVAL
+    assert start(nb=1 << 32)[0] == cxbwt.ERANGE
+    assert start(wsb=10) == (cxbwt.ENOMEM, None)
+    assert start(ws=ctypes.c_void_p(0x1001))[0] == cxbwt.EINVAL
+    assert L.cxbwt_build_start(fake, fake, 3, 12, 4, fake, fake, fake, 1 << 40, null, None) == cxbwt.EINVAL
+
+    def bstart(coll, wsb=1 << 40):
+        h = ctypes.c_void_p(0x1234)
+        arr = (ctypes.c_uint64 * len(coll))(*coll)
+        rc = L.cxbwt_build_batch_start(fake, fake, 4, 40, 10, arr, len(coll) - 1, fake, fake, fake, wsb, null,
+                                       ctypes.byref(h))
+        return rc, h.value
+
+    assert bstart([0, 2, 3]) == (cxbwt.EINVAL, None)
+    assert bstart([0, 2, 2, 4])[0] == cxbwt.EINVAL
+    assert bstart([0, 2, 4], wsb=10)[0] == cxbwt.ENOMEM
+    assert L.cxbwt_job_wait(null, None) == cxbwt.EINVAL
+    assert L.cxbwt_job_done(null) == 0
+
+
 def test_schedule_set_and_get_without_gpu():
     assert cxbwt.get_schedule() == cxbwt.SCHEDULE_MSD
     try:

@@ -197,3 +197,54 @@ def test_plan_waves_respects_limits():
     assert waves == [[0, 1, 2], [3, 4]]
     assert all(sum(sizes[i][1] for i in w) <= 4500 for w in waves)
     assert sorted(i for w in waves for i in w) == list(range(5))
+
+
+class AsyncFakeExecutor(FakeExecutor):
+    """Batches that return at once and finish after their simulated build time
+    on the virtual clock; records how many were building together."""
+
+    def __init__(self, clock, **kw):
+        super().__init__(clock, **kw)
+        self.running = []
+        self.max_running = 0
+
+    def start_batch(self, jobs):
+        self.batches.append([j.id for j in jobs])
+        res = [oracle.bwt(j.collection.text, j.collection.offsets) for j in jobs]
+        end = self.clock.now + self.fixed_s + self.per_base_s * sum(j.collection.n_bases for j in jobs)
+        h = {"end": end, "res": res}
+        self.running.append(h)
+        self.max_running = max(self.max_running, len(self.running))
+        return h
+
+    def batch_done(self, h):
+        return self.clock.now >= h["end"]
+
+    def finish_batch(self, h):
+        self.running.remove(h)
+        return h["res"]
+
+
+def test_batches_overlap_up_to_max_inflight():
+    clk = VClock()
+    ex = AsyncFakeExecutor(clk, per_base_s=1e-6, fixed_s=0.01)
+    srv = serve.Server(ex, budget_bytes=1 << 40, max_batch_jobs=2, clock=clk, stage_in_background=False,
+                       max_inflight=2)
+    cols = _cols(8, seed=5)
+    jobs = [srv.submit(c, arrival_s=0.0) for c in cols]
+    srv.run_until_idle(sleep=clk.sleep)
+    assert ex.max_running == 2
+    for j, c in zip(jobs, cols):
+        assert j.state == serve.DONE
+        eb, et = oracle.bwt(c.text, c.offsets)
+        assert np.array_equal(j.result[0], eb) and np.array_equal(j.result[1], et)
+    # one at a time: never two building together
+    clk2 = VClock()
+    ex2 = AsyncFakeExecutor(clk2, per_base_s=1e-6, fixed_s=0.01)
+    srv2 = serve.Server(ex2, budget_bytes=1 << 40, max_batch_jobs=1, clock=clk2, stage_in_background=False,
+                        max_inflight=1)
+    for c in cols:
+        srv2.submit(c, arrival_s=0.0)
+    srv2.run_until_idle(sleep=clk2.sleep)
+    assert ex2.max_running == 1
+    assert srv2.report()["makespan_s"] > srv.report()["makespan_s"]
