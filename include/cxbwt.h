@@ -249,14 +249,17 @@ int cxbwt_build_batch(const uint64_t *packed, const uint64_t *offsets, uint64_t 
  *
  * cxbwt_build_start / cxbwt_build_batch_start -- arguments, checks and
  *   results as cxbwt_build / cxbwt_build_batch, plus
+ *     opts  (host, may be NULL) the kernel instantiation, sort schedule and
+ *           timing of this build (the values of cxbwt_set_tuning,
+ *           cxbwt_set_schedule and cxbwt_set_timing, checked the same way:
+ *           CXBWT_EINVAL for others); NULL takes the calling thread's.
  *     job   (host, out) the started build, or NULL on an error returned here.
  *   Argument errors are returned by the call, before any HIP call; a started
  *   build's own status (CXBWT_EDATA and so on) comes from cxbwt_job_wait.  A
  *   library worker thread enqueues the build's kernels and copies on
  *   `stream`, in the order cxbwt_build would, and waits on that stream
  *   between sort levels (the level counts are read back); the calling thread
- *   does not wait.  The tuning, schedule and timing choices of the calling
- *   thread at the call apply.  Until cxbwt_job_wait returns, the caller keeps
+ *   does not wait.  Until cxbwt_job_wait returns, the caller keeps
  *   every buffer alive and unchanged and enqueues nothing on `stream` that
  *   reads the outputs.  Builds started on distinct streams with distinct
  *   workspaces run concurrently on the device; builds on one stream run one
@@ -271,13 +274,19 @@ int cxbwt_build_batch(const uint64_t *packed, const uint64_t *offsets, uint64_t 
  *   waited for exactly once.  CXBWT_EINVAL for NULL.
  */
 typedef struct cxbwt_job cxbwt_job;
+typedef struct cxbwt_opts {
+  uint32_t tile_items;   /* 6, 8 or 16, as cxbwt_set_tuning          */
+  uint32_t chunk_items;  /* 3, 6 or 8, as cxbwt_set_tuning           */
+  uint32_t schedule;     /* CXBWT_SCHEDULE_MSD or _STRINGWORD       */
+  uint32_t timing;       /* nonzero: per-class kernel times in stats */
+} cxbwt_opts;
 int cxbwt_build_start(const uint64_t *packed, const uint64_t *offsets, uint64_t n_reads, uint64_t n_bases,
                       uint32_t max_read_len, uint8_t *bwt, uint64_t *term_pos, void *workspace,
-                      size_t workspace_bytes, void *stream, cxbwt_job **job);
+                      size_t workspace_bytes, const cxbwt_opts *opts, void *stream, cxbwt_job **job);
 int cxbwt_build_batch_start(const uint64_t *packed, const uint64_t *offsets, uint64_t n_reads, uint64_t n_bases,
                             uint32_t max_read_len, const uint64_t *coll_reads, uint32_t n_coll, uint8_t *bwt,
-                            uint64_t *term_pos, void *workspace, size_t workspace_bytes, void *stream,
-                            cxbwt_job **job);
+                            uint64_t *term_pos, void *workspace, size_t workspace_bytes,
+                            const cxbwt_opts *opts, void *stream, cxbwt_job **job);
 int cxbwt_job_done(const cxbwt_job *job);
 /* cxbwt_job_wait is declared after cxbwt_stats below. */
 
@@ -412,6 +421,14 @@ int cxbwt_set_timing(int enable);
 
 /* Static message for a status code. */
 const char *cxbwt_status_str(int status);
+
+/*
+ * cxbwt_last_error -- what lies behind the calling thread's last
+ * CXBWT_EDEVICE or CXBWT_EDATA: the HIP error text of a failed runtime call
+ * or launch, or the device's data checks that failed.  Empty after a build
+ * that succeeded.  Valid until the thread's next build.
+ */
+const char *cxbwt_last_error(void);
 
 #ifdef __cplusplus
 }

@@ -42,6 +42,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
@@ -185,13 +186,43 @@ Layout make_layout(uint64_t n_reads, uint64_t nb_text, uint32_t n_coll, uint64_t
   return L;
 }
 
-#define CX_CHECK(x)                              \
-  do {                                           \
-    if ((x) != hipSuccess) return CXBWT_EDEVICE; \
+// The text behind the calling thread's last CXBWT_EDEVICE or CXBWT_EDATA
+// (cxbwt_last_error).
+thread_local char g_last_error[256] = "";
+int fail_hip(hipError_t e, const char *what) {
+  snprintf(g_last_error, sizeof(g_last_error), "%s: %s", what, hipGetErrorString(e));
+  return CXBWT_EDEVICE;
+}
+// An internal size check that failed (a list or scratch area smaller than
+// the work handed to it).
+int fail_internal(const char *what) {
+  snprintf(g_last_error, sizeof(g_last_error), "internal check failed: %s", what);
+  return CXBWT_EDEVICE;
+}
+
+// A failure the device reported in its status word.
+int fail_status(uint32_t status) {
+  snprintf(g_last_error, sizeof(g_last_error), "device status 0x%x:%s%s%s%s%s%s", status,
+           (status & ST_BAD_OFFSETS) ? " offsets are not a non-decreasing partition of the bases;" : "",
+           (status & ST_TOO_LONG) ? " a read is longer than max_read_len;" : "",
+           (status & ST_BAD_CHAR) ? " a byte is not A/C/G/T;" : "",
+           (status & ST_LIST_OVERFLOW) ? " a work list overflowed its capacity;" : "",
+           (status & ST_WINDOW_BOUND) ? " a tie outlived the windows of max_read_len;" : "",
+           (status & ST_PLAN_MISMATCH) ? " collection bases differ from the captured plan;" : "");
+  if (status & (ST_BAD_OFFSETS | ST_TOO_LONG)) return CXBWT_EDATA;
+  if (status & ST_PLAN_MISMATCH) return CXBWT_EINVAL;
+  return CXBWT_EDEVICE;
+}
+
+#define CX_CHECK(x)                                                        \
+  do {                                                                     \
+    const hipError_t cx_e_ = (x);                                          \
+    if (cx_e_ != hipSuccess) return fail_hip(cx_e_, "HIP runtime call");   \
   } while (0)
-#define CX_LAUNCHED()                                          \
-  do {                                                         \
-    if (hipGetLastError() != hipSuccess) return CXBWT_EDEVICE; \
+#define CX_LAUNCHED()                                                      \
+  do {                                                                     \
+    const hipError_t cx_e_ = hipGetLastError();                            \
+    if (cx_e_ != hipSuccess) return fail_hip(cx_e_, "kernel launch");      \
   } while (0)
 
 unsigned grid_for(uint64_t n, unsigned block) {
@@ -316,7 +347,7 @@ int upload_segments(const Buffers &B, const Layout &Lo, const std::vector<Seg> &
                     std::vector<uint32_t> &tprefix, std::vector<uint32_t> &gprefix, uint32_t &ntiles,
                     uint32_t &ngroups, hipStream_t st) {
   const uint32_t ns = (uint32_t)segs.size();
-  if (ns > Lo.seg_slots) return CXBWT_EDEVICE;
+  if (ns > Lo.seg_slots) return fail_internal("work exceeds a workspace list or scratch area");
   tprefix.assign(ns + 1, 0);
   gprefix.assign(ns + 1, 0);
   for (uint32_t i = 0; i < ns; ++i) {
@@ -326,7 +357,7 @@ int upload_segments(const Buffers &B, const Layout &Lo, const std::vector<Seg> &
   }
   ntiles = tprefix[ns];
   ngroups = gprefix[ns];
-  if (ntiles > Lo.max_tiles || ngroups > Lo.max_groups) return CXBWT_EDEVICE;
+  if (ntiles > Lo.max_tiles || ngroups > Lo.max_groups) return fail_internal("work exceeds a workspace list or scratch area");
   CX_CHECK(hipMemcpyAsync(B.segs, segs.data(), sizeof(Seg) * ns, hipMemcpyHostToDevice, st));
   CX_CHECK(hipMemcpyAsync(B.tile_prefix, tprefix.data(), 4 * (ns + 1), hipMemcpyHostToDevice, st));
   CX_CHECK(hipMemcpyAsync(B.group_prefix, gprefix.data(), 4 * (ns + 1), hipMemcpyHostToDevice, st));
@@ -479,7 +510,7 @@ int launch_local(const Buffers &B, const Tuning &tu, uint64_t nb, uint32_t rmax,
 int finish_level(const Buffers &B, const Layout &Lo, const Tuning &tu, uint64_t nb, uint32_t rmax, uint8_t *bwt,
                  uint32_t n_chunks, uint32_t n_finals, uint64_t final_tiles, uint64_t final_len, PhaseTimer &T,
                  hipStream_t st) {
-  if (n_chunks > Lo.cap_chunks || n_finals > Lo.cap_finals) return CXBWT_EDEVICE;
+  if (n_chunks > Lo.cap_chunks || n_finals > Lo.cap_finals) return fail_internal("work exceeds a workspace list or scratch area");
   int rc;
   if (n_chunks) {
     T.begin();
@@ -488,7 +519,7 @@ int finish_level(const Buffers &B, const Layout &Lo, const Tuning &tu, uint64_t 
     g_stats.chunks += n_chunks;
   }
   if (n_finals) {
-    if (final_tiles == 0 || final_tiles > 0xFFFFFFFFull) return CXBWT_EDEVICE;
+    if (final_tiles == 0 || final_tiles > 0xFFFFFFFFull) return fail_internal("work exceeds a workspace list or scratch area");
     if ((rc = prefix_list(B, B.finals, n_finals, tu.tile_len(), nullptr, B.tile_prefix, nullptr, st))) return rc;
     T.begin();
     k_emit_final<false><<<(unsigned)final_tiles, BLOCK, 0, st>>>(B.finals, B.tile_prefix, n_finals, nullptr, tu.tile_len(),
@@ -660,7 +691,7 @@ int enqueue_prep(const Build &b, const uint64_t *coll_reads_src, const uint64_t 
   const Buffers &B = b.B;
   uint32_t *sbits = B.tile_hist;  // the tile histograms are not used before level 1
   const uint64_t n_sbits = b.nb / 32 + 4;
-  if (4 * n_sbits > b.Lo.tile_hist_bytes) return CXBWT_EDEVICE;
+  if (4 * n_sbits > b.Lo.tile_hist_bytes) return fail_internal("work exceeds a workspace list or scratch area");
   int rc;
   if ((rc = fill_u32(B.counters, C_COUNT, 0, st))) return rc;
   if ((rc = fill_u64((uint64_t *)B.stats, STAT_WORDS, 0, st))) return rc;
@@ -715,7 +746,7 @@ int plan_level1(Build &b, PhaseTimer &T, hipStream_t st) {
   CX_CHECK(hipMemcpyAsync(b.cbase.data(), b.B.coll_bases, 8 * ((uint64_t)b.ncoll + 1), hipMemcpyDeviceToHost, st));
   CX_CHECK(hipStreamSynchronize(st));
   T.collect();
-  if (hc[C_STATUS] & (ST_BAD_OFFSETS | ST_TOO_LONG)) return CXBWT_EDATA;
+  if (hc[C_STATUS] & (ST_BAD_OFFSETS | ST_TOO_LONG)) return fail_status(hc[C_STATUS]);
   // offsets are valid, so the collection bases are non-decreasing and end at nb
   b.cm.assign(b.ncoll, CollMap{});
   b.big.clear();
@@ -758,7 +789,7 @@ void seg_prefixes(const std::vector<Seg> &segs, uint32_t tile_len, std::vector<u
 }
 
 int upload_src(const Buffers &B, const Layout &Lo, const SegSrc &s, hipStream_t st) {
-  if (s.ns > Lo.seg_slots || s.ntiles > Lo.max_tiles || s.ngroups > Lo.max_groups) return CXBWT_EDEVICE;
+  if (s.ns > Lo.seg_slots || s.ntiles > Lo.max_tiles || s.ngroups > Lo.max_groups) return fail_internal("work exceeds a workspace list or scratch area");
   CX_CHECK(hipMemcpyAsync(B.segs, s.segs, sizeof(Seg) * s.ns, hipMemcpyHostToDevice, st));
   CX_CHECK(hipMemcpyAsync(B.tile_prefix, s.tprefix, 4 * ((uint64_t)s.ns + 1), hipMemcpyHostToDevice, st));
   CX_CHECK(hipMemcpyAsync(B.group_prefix, s.gprefix, 4 * ((uint64_t)s.ns + 1), hipMemcpyHostToDevice, st));
@@ -793,7 +824,7 @@ int run_levels(const Build &b, LevelOut acc, uint32_t nbig, PhaseTimer &T, hipSt
   LevelOut o{};
   int rc;
   while (nbig) {
-    if (nbig > Lo.cap_big) return CXBWT_EDEVICE;
+    if (nbig > Lo.cap_big) return fail_internal("work exceeds a workspace list or scratch area");
     g_stats.levels++;
     g_stats.big_segments += nbig;
     g_stats.level_suffixes += acc.next_len;
@@ -991,7 +1022,7 @@ int run_stringword(const Build &b, PhaseTimer &T, hipStream_t st) {
   if (b.ncoll) CX_CHECK(hipMemcpyAsync(B.cmap, b.cm.data(), sizeof(CollMap), hipMemcpyHostToDevice, st));
   if (nb) {
     const uint64_t ntiles = ceil_div(nb, TL), ngroups = ceil_div(ntiles, GROUP_TILES);
-    if (ntiles > Lo.max_tiles || ngroups > Lo.max_groups || ntiles > 0x7FFFFFFFull) return CXBWT_EDEVICE;
+    if (ntiles > Lo.max_tiles || ngroups > Lo.max_groups || ntiles > 0x7FFFFFFFull) return fail_internal("work exceeds a workspace list or scratch area");
     const uint32_t tp[2] = {0, (uint32_t)ntiles}, gp[2] = {0, (uint32_t)ngroups};
     CX_CHECK(hipMemcpyAsync(B.tile_prefix, tp, sizeof(tp), hipMemcpyHostToDevice, st));
     CX_CHECK(hipMemcpyAsync(B.group_prefix, gp, sizeof(gp), hipMemcpyHostToDevice, st));
@@ -1057,6 +1088,7 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
               const uint64_t *coll_reads, uint32_t ncoll, uint8_t *bwt, uint64_t *term_pos, unsigned char *ws,
               hipStream_t st, bool allow_timing = true) {
   g_stats = cxbwt_stats{};
+  g_last_error[0] = 0;
   PhaseTimer T{st, allow_timing && g_timing != 0, {}};
   Build b;
   build_init(b, packed, offsets, n, nb, maxlen, coll_reads, ncoll, bwt, term_pos, ws);
@@ -1074,7 +1106,7 @@ int run_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint6
   }
   uint32_t hc[C_COUNT];
   if ((rc = read_totals(b, T, st, hc))) return rc;
-  if (hc[C_STATUS]) return CXBWT_EDEVICE;
+  if (hc[C_STATUS]) return fail_status(hc[C_STATUS]);
   return CXBWT_OK;
 }
 
@@ -1203,7 +1235,7 @@ int list_range(const Build &b, const Range &r, PhaseTimer &T, hipStream_t st) {
   const Layout &Lo = b.Lo;
   const uint64_t ntl = ceil_div(b.nb, LIST_TILE);
   const uint64_t nlb = ceil_div(ntl, RANK_BLOCK_WORDS);
-  if (ntl + 1 > Lo.n_list_tiles || nlb + 1 > Lo.n_list_blocks || r.count > Lo.sort_cap) return CXBWT_EDEVICE;
+  if (ntl + 1 > Lo.n_list_tiles || nlb + 1 > Lo.n_list_blocks || r.count > Lo.sort_cap) return fail_internal("work exceeds a workspace list or scratch area");
   T.begin();
   k_range_count<<<(unsigned)ntl, BLOCK, 0, st>>>(B.text, b.nb, r.lo, r.hi, B.list_tiles);
   CX_LAUNCHED();
@@ -1227,6 +1259,7 @@ int list_range(const Build &b, const Range &r, PhaseTimer &T, hipStream_t st) {
 int run_range_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n, uint64_t nb, uint32_t maxlen,
                     uint64_t m, bool wide, uint8_t *bwt, uint64_t *term_pos, unsigned char *ws, hipStream_t st) {
   g_stats = cxbwt_stats{};
+  g_last_error[0] = 0;
   PhaseTimer T{st, g_timing != 0, {}};
   Build b;
   const uint64_t one[2] = {0, n};
@@ -1239,7 +1272,7 @@ int run_range_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n,
     CX_CHECK(hipMemcpyAsync(hc, b.B.counters, sizeof(hc), hipMemcpyDeviceToHost, st));
     CX_CHECK(hipStreamSynchronize(st));
     T.collect();
-    if (hc[C_STATUS] & (ST_BAD_OFFSETS | ST_TOO_LONG)) return CXBWT_EDATA;
+    if (hc[C_STATUS] & (ST_BAD_OFFSETS | ST_TOO_LONG)) return fail_status(hc[C_STATUS]);
   }
   g_stats.chunk_suffixes = nb;
   std::vector<Range> ranges;
@@ -1283,7 +1316,7 @@ int run_range_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n,
   T.end(PH_FINAL);
   uint32_t hc[C_COUNT];
   if ((rc = read_totals(b, T, st, hc))) return rc;
-  if (hc[C_STATUS]) return CXBWT_EDEVICE;
+  if (hc[C_STATUS]) return fail_status(hc[C_STATUS]);
   return CXBWT_OK;
 }
 
@@ -1325,7 +1358,7 @@ int graph_capture(GraphPlan &P, hipStream_t st) {
   uint32_t hc[C_COUNT];
   if (!rc) rc = read_totals(b, T, st, hc);
   if (rc) return rc;
-  if (hc[C_STATUS]) return CXBWT_EDEVICE;
+  if (hc[C_STATUS]) return fail_status(hc[C_STATUS]);
   // pinned copies of everything the captured copies read
   const size_t nc1 = (size_t)b.ncoll + 1;
   const size_t nbg = b.big.size(), nsm = b.small.size();
@@ -1369,7 +1402,7 @@ int graph_capture(GraphPlan &P, hipStream_t st) {
     if (g) (void)hipGraphDestroy(g);
     return rc;
   }
-  if (ec != hipSuccess || !g) return CXBWT_EDEVICE;
+  if (ec != hipSuccess || !g) return fail_hip(ec, "graph capture");
   P.graph = g;
   CX_CHECK(hipGraphInstantiate(&P.exec, P.graph, nullptr, nullptr, 0));
   return CXBWT_OK;
@@ -1383,9 +1416,8 @@ int graph_finish(GraphPlan &P, hipStream_t st) {
   uint32_t hc[C_COUNT];
   int rc;
   if ((rc = read_totals(b, T, st, hc))) return rc;
-  if (hc[C_STATUS] & (ST_BAD_OFFSETS | ST_TOO_LONG)) return CXBWT_EDATA;
-  if (hc[C_STATUS] & ST_PLAN_MISMATCH) return CXBWT_EINVAL;
-  if (hc[C_STATUS]) return CXBWT_EDEVICE;
+  if (hc[C_STATUS] & (ST_BAD_OFFSETS | ST_TOO_LONG)) return fail_status(hc[C_STATUS]);
+  if (hc[C_STATUS]) return fail_status(hc[C_STATUS]);
   uint64_t g[G_COUNT], f[K_LEVEL_KINDS];
   memcpy(g, hc + C_CUM, sizeof(g));
   memcpy(f, hc + C_FOLD, sizeof(f));
@@ -1414,7 +1446,7 @@ int graph_finish(GraphPlan &P, hipStream_t st) {
   g_stats.window_fetches = 0;
   g_stats.scattered_suffixes = 0;
   if ((rc = read_totals(b, T, st, hc))) return rc;
-  if (hc[C_STATUS]) return CXBWT_EDEVICE;
+  if (hc[C_STATUS]) return fail_status(hc[C_STATUS]);
   return CXBWT_OK;
 }
 
@@ -1432,6 +1464,7 @@ struct cxbwt_job {
   std::atomic<int> done{0};
   int status = CXBWT_OK;
   cxbwt_stats stats{};
+  char error[256] = "";
 };
 
 namespace {
@@ -1469,13 +1502,28 @@ void job_main(cxbwt_job *job, JobArgs a) {
   }
   job->stats = g_stats;
   job->status = rc;
+  memcpy(job->error, g_last_error, sizeof(job->error));
   job->done.store(1, std::memory_order_release);
+}
+
+// The choices a started build runs with: opts, or the calling thread's.
+bool job_choices(const cxbwt_opts *opts, Tuning &tu, int &timing) {
+  if (!opts) {
+    tu = g_tuning;
+    timing = g_timing;
+    return true;
+  }
+  if (!tuning_ok(opts->tile_items, opts->chunk_items)) return false;
+  if (opts->schedule != CXBWT_SCHEDULE_MSD && opts->schedule != CXBWT_SCHEDULE_STRINGWORD) return false;
+  tu.tile_items = opts->tile_items;
+  tu.chunk_items = opts->chunk_items;
+  tu.schedule = opts->schedule;
+  timing = opts->timing ? 1 : 0;
+  return true;
 }
 
 int start_job(JobArgs &&a, cxbwt_job **out) {
   if (hipGetDevice(&a.device) != hipSuccess) return CXBWT_EDEVICE;
-  a.tu = g_tuning;
-  a.timing = g_timing;
   cxbwt_job *job = new (std::nothrow) cxbwt_job;
   if (!job) return CXBWT_ENOMEM;
   try {
@@ -1511,7 +1559,7 @@ int scratch_address(unsigned char **out) {
   if (!g_scratch_addr[dev]) {
     void *p = nullptr;
     if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return CXBWT_EDEVICE;
-    if (((uintptr_t)p & 255u) != 0) return CXBWT_EDEVICE;
+    if (((uintptr_t)p & 255u) != 0) return fail_internal("work exceeds a workspace list or scratch area");
     g_scratch_addr[dev] = (unsigned char *)p;
   }
   *out = g_scratch_addr[dev];
@@ -1536,7 +1584,7 @@ int cxbwt_pack(const uint8_t *ascii, uint64_t n_bases, uint64_t *packed, uint32_
   }
   const uint64_t nw = cxbwt_packed_words(n_bases);
   k_pack<<<grid_for(nw, 256), 256, 0, st>>>(ascii, n_bases, packed, nw, d_status);
-  if (hipGetLastError() != hipSuccess) return CXBWT_EDEVICE;
+  CX_LAUNCHED();
   return CXBWT_OK;
 }
 
@@ -1598,7 +1646,7 @@ int cxbwt_build_ranges(const uint64_t *packed, const uint64_t *offsets, uint64_t
 
 int cxbwt_build_start(const uint64_t *packed, const uint64_t *offsets, uint64_t n_reads, uint64_t n_bases,
                       uint32_t max_read_len, uint8_t *bwt, uint64_t *term_pos, void *workspace,
-                      size_t workspace_bytes, void *stream, cxbwt_job **job) {
+                      size_t workspace_bytes, const cxbwt_opts *opts, void *stream, cxbwt_job **job) {
   if (!job) return CXBWT_EINVAL;
   *job = nullptr;
   if (!packed || !offsets || !bwt || !term_pos || !workspace || n_reads == 0) return CXBWT_EINVAL;
@@ -1607,13 +1655,14 @@ int cxbwt_build_start(const uint64_t *packed, const uint64_t *offsets, uint64_t 
   if (((uintptr_t)workspace & 255u) != 0) return CXBWT_EINVAL;
   JobArgs a{packed, offsets, n_reads, n_bases, max_read_len, {0, n_reads}, bwt, term_pos,
             (unsigned char *)workspace, (hipStream_t)stream, 0, Tuning{8, 6}, 0};
+  if (!job_choices(opts, a.tu, a.timing)) return CXBWT_EINVAL;
   return start_job(std::move(a), job);
 }
 
 int cxbwt_build_batch_start(const uint64_t *packed, const uint64_t *offsets, uint64_t n_reads, uint64_t n_bases,
                             uint32_t max_read_len, const uint64_t *coll_reads, uint32_t n_coll, uint8_t *bwt,
-                            uint64_t *term_pos, void *workspace, size_t workspace_bytes, void *stream,
-                            cxbwt_job **job) {
+                            uint64_t *term_pos, void *workspace, size_t workspace_bytes,
+                            const cxbwt_opts *opts, void *stream, cxbwt_job **job) {
   if (!job) return CXBWT_EINVAL;
   *job = nullptr;
   if (!packed || !offsets || !bwt || !term_pos || !workspace || !coll_reads || n_reads == 0 || n_coll == 0)
@@ -1628,6 +1677,7 @@ int cxbwt_build_batch_start(const uint64_t *packed, const uint64_t *offsets, uin
   JobArgs a{packed, offsets, n_reads, n_bases, max_read_len,
             std::vector<uint64_t>(coll_reads, coll_reads + n_coll + 1), bwt, term_pos,
             (unsigned char *)workspace, (hipStream_t)stream, 0, Tuning{8, 6}, 0};
+  if (!job_choices(opts, a.tu, a.timing)) return CXBWT_EINVAL;
   return start_job(std::move(a), job);
 }
 
@@ -1638,7 +1688,8 @@ int cxbwt_job_wait(cxbwt_job *job, cxbwt_stats *stats) {
   if (job->worker.joinable()) job->worker.join();
   const int rc = job->status;
   if (stats) *stats = job->stats;
-  g_stats = job->stats;  // cxbwt_last_stats on the waiting thread
+  g_stats = job->stats;  // cxbwt_last_stats and cxbwt_last_error on the waiting thread
+  memcpy(g_last_error, job->error, sizeof(g_last_error));
   delete job;
   return rc;
 }
@@ -1747,6 +1798,8 @@ int cxbwt_set_timing(int enable) {
   g_timing = enable ? 1 : 0;
   return prev;
 }
+
+const char *cxbwt_last_error(void) { return g_last_error; }
 
 const char *cxbwt_status_str(int status) {
   switch (status) {

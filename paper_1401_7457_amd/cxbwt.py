@@ -28,7 +28,7 @@ ABI_FUNCTIONS = ("cxbwt_packed_words", "cxbwt_pack", "cxbwt_workspace_bytes", "c
                  "cxbwt_range_workspace_bytes", "cxbwt_build_ranges", "cxbwt_batch_workspace_bytes", "cxbwt_build_batch",
                  "cxbwt_build_start", "cxbwt_build_batch_start", "cxbwt_job_done", "cxbwt_job_wait", "cxbwt_last_stats", "cxbwt_set_timing",
                  "cxbwt_set_tuning", "cxbwt_get_tuning", "cxbwt_set_schedule", "cxbwt_get_schedule", "cxbwt_graph_create", "cxbwt_graph_launch",
-                 "cxbwt_graph_finish", "cxbwt_graph_destroy", "cxbwt_status_str")
+                 "cxbwt_graph_finish", "cxbwt_graph_destroy", "cxbwt_status_str", "cxbwt_last_error")
 
 # kernel instantiations the library holds: (suffixes per thread in a level
 # tile, suffixes per lane in a chunk); the first is the default
@@ -46,10 +46,20 @@ _lib = None
 
 
 class CxbwtError(RuntimeError):
-    def __init__(self, status: int, what: str):
+    def __init__(self, status: int, what: str, detail: str | None = None):
         self.status = status
         msg = lib().cxbwt_status_str(status).decode() if _lib is not None else ""
-        super().__init__(f"{what}: {STATUS_NAMES.get(status, status)} ({msg})")
+        if detail is None and _lib is not None and status in (EDEVICE, EDATA):
+            detail = lib().cxbwt_last_error().decode()
+        self.detail = detail or ""
+        super().__init__(f"{what}: {STATUS_NAMES.get(status, status)} ({msg})" +
+                         (f": {self.detail}" if self.detail else ""))
+
+
+class Opts(ctypes.Structure):
+    """cxbwt_opts: the choices of one started build."""
+    _fields_ = [("tile_items", ctypes.c_uint32), ("chunk_items", ctypes.c_uint32), ("schedule", ctypes.c_uint32),
+                ("timing", ctypes.c_uint32)]
 
 
 class Stats(ctypes.Structure):
@@ -90,11 +100,11 @@ def lib():
             L.cxbwt_batch_workspace_bytes.restype = ctypes.c_size_t
             L.cxbwt_build_batch.argtypes = [vp, vp, u64, u64, u32, vp, u32, vp, vp, vp, ctypes.c_size_t, vp]
             L.cxbwt_build_batch.restype = ctypes.c_int
-            L.cxbwt_build_start.argtypes = [vp, vp, u64, u64, u32, vp, vp, vp, ctypes.c_size_t, vp,
-                                            ctypes.POINTER(vp)]
+            L.cxbwt_build_start.argtypes = [vp, vp, u64, u64, u32, vp, vp, vp, ctypes.c_size_t,
+                                            ctypes.POINTER(Opts), vp, ctypes.POINTER(vp)]
             L.cxbwt_build_start.restype = ctypes.c_int
-            L.cxbwt_build_batch_start.argtypes = [vp, vp, u64, u64, u32, vp, u32, vp, vp, vp, ctypes.c_size_t, vp,
-                                                  ctypes.POINTER(vp)]
+            L.cxbwt_build_batch_start.argtypes = [vp, vp, u64, u64, u32, vp, u32, vp, vp, vp, ctypes.c_size_t,
+                                                  ctypes.POINTER(Opts), vp, ctypes.POINTER(vp)]
             L.cxbwt_build_batch_start.restype = ctypes.c_int
             L.cxbwt_job_done.argtypes = [vp]
             L.cxbwt_job_done.restype = ctypes.c_int
@@ -123,6 +133,8 @@ def lib():
             L.cxbwt_graph_destroy.restype = None
             L.cxbwt_status_str.argtypes = [ctypes.c_int]
             L.cxbwt_status_str.restype = ctypes.c_char_p
+            L.cxbwt_last_error.argtypes = []
+            L.cxbwt_last_error.restype = ctypes.c_char_p
             _lib = L
         return _lib
 
@@ -325,7 +337,7 @@ class BuildJob:
         self._tensors = None
         self.stats = _stats_dict(s)
         if st != OK:
-            raise CxbwtError(st, self._what)
+            raise CxbwtError(st, self._what)  # cxbwt_last_error now holds the job's text
         return self.bwt, self.term
 
     def __del__(self):
@@ -344,9 +356,18 @@ def _out_tensors(out, n_reads, n_bases, dev):
             torch.empty(n_reads, dtype=torch.int64, device=dev))
 
 
+def _opts(opts):
+    """None, or (tile_items, chunk_items, schedule[, timing]) -> a cxbwt_opts pointer."""
+    if opts is None:
+        return None
+    t, c, sched = opts[:3]
+    return ctypes.byref(Opts(int(t), int(c), int(sched), int(opts[3]) if len(opts) > 3 else 0))
+
+
 def build_start(packed, offsets, n_reads: int, n_bases: int, max_read_len: int, workspace=None, out=None,
-                stream=None) -> BuildJob:
-    """cxbwt_build_start: the build of `build`, returning at once (see BuildJob)."""
+                stream=None, opts=None) -> BuildJob:
+    """cxbwt_build_start: the build of `build`, returning at once (see BuildJob).
+    opts: (tile_items, chunk_items, schedule[, timing]) for this build, else the thread's choices."""
     dev = packed.device
     if workspace is None:
         workspace = alloc_workspace(n_reads, n_bases, max_read_len, dev)
@@ -355,14 +376,14 @@ def build_start(packed, offsets, n_reads: int, n_bases: int, max_read_len: int, 
     st = lib().cxbwt_build_start(ctypes.c_void_p(packed.data_ptr()), ctypes.c_void_p(offsets.data_ptr()), n_reads,
                                  n_bases, max_read_len, ctypes.c_void_p(bwt.data_ptr()),
                                  ctypes.c_void_p(term.data_ptr()), ctypes.c_void_p(workspace.data_ptr()),
-                                 workspace.numel(), _stream_ptr(stream), ctypes.byref(h))
+                                 workspace.numel(), _opts(opts), _stream_ptr(stream), ctypes.byref(h))
     if st != OK:
         raise CxbwtError(st, "cxbwt_build_start")
     return BuildJob(h, "cxbwt_build_start", (packed, offsets, workspace), (bwt, term))
 
 
 def build_batch_start(packed, offsets, n_reads: int, n_bases: int, max_read_len: int, coll_reads, workspace=None,
-                      out=None, stream=None) -> BuildJob:
+                      out=None, stream=None, opts=None) -> BuildJob:
     """cxbwt_build_batch_start: the build of `build_batch`, returning at once (see BuildJob)."""
     import torch
     cr = np.ascontiguousarray(np.asarray(coll_reads, dtype=np.uint64))
@@ -378,8 +399,8 @@ def build_batch_start(packed, offsets, n_reads: int, n_bases: int, max_read_len:
     st = lib().cxbwt_build_batch_start(ctypes.c_void_p(packed.data_ptr()), ctypes.c_void_p(offsets.data_ptr()),
                                        n_reads, n_bases, max_read_len, cr.ctypes.data_as(ctypes.c_void_p), n_coll,
                                        ctypes.c_void_p(bwt.data_ptr()), ctypes.c_void_p(term.data_ptr()),
-                                       ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream_ptr(stream),
-                                       ctypes.byref(h))
+                                       ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _opts(opts),
+                                       _stream_ptr(stream), ctypes.byref(h))
     if st != OK:
         raise CxbwtError(st, "cxbwt_build_batch_start")
     return BuildJob(h, "cxbwt_build_batch_start", (packed, offsets, workspace), (bwt, term))
@@ -495,6 +516,11 @@ def build_batch_host(cols, device="cuda"):
     if int(pstatus.item()) != 0:
         raise CxbwtError(EDATA, "cxbwt_pack (non-ACGT byte)")
     return split_batch_output(bwt.cpu().numpy(), term.cpu().numpy().view(np.uint64), cols)
+
+
+def last_error() -> str:
+    """cxbwt_last_error: the text behind this thread's last EDEVICE / EDATA."""
+    return lib().cxbwt_last_error().decode()
 
 
 def last_stats() -> dict:

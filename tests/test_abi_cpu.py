@@ -139,7 +139,7 @@ def test_job_argument_validation_needs_no_gpu():
     def start(**kw):
         h = ctypes.c_void_p(0x1234)
         rc = L.cxbwt_build_start(kw.get("packed", fake), fake, kw.get("n", 3), kw.get("nb", 12), 4, fake, fake,
-                                 kw.get("ws", fake), kw.get("wsb", 1 << 40), null, ctypes.byref(h))
+                                 kw.get("ws", fake), kw.get("wsb", 1 << 40), kw.get("opts"), null, ctypes.byref(h))
         return rc, h.value
 
     assert start(packed=null) == (cxbwt.EINVAL, None)
@@ -147,13 +147,19 @@ def test_job_argument_validation_needs_no_gpu():
     assert start(nb=1 << 32)[0] == cxbwt.ERANGE
     assert start(wsb=10) == (cxbwt.ENOMEM, None)
     assert start(ws=ctypes.c_void_p(0x1001))[0] == cxbwt.EINVAL
-    assert L.cxbwt_build_start(fake, fake, 3, 12, 4, fake, fake, fake, 1 << 40, null, None) == cxbwt.EINVAL
+    assert L.cxbwt_build_start(fake, fake, 3, 12, 4, fake, fake, fake, 1 << 40, None, null, None) == cxbwt.EINVAL
+    # per-call options: an instantiation the library does not hold, or an unknown schedule
+    t, c = cxbwt.TUNING_CHOICES[0]
+    assert start(opts=ctypes.byref(cxbwt.Opts(t + 1, c, cxbwt.SCHEDULE_MSD, 0))) == (cxbwt.EINVAL, None)
+    assert start(opts=ctypes.byref(cxbwt.Opts(t, c, 7, 0))) == (cxbwt.EINVAL, None)
+    # with valid options the other checks still apply
+    assert start(opts=ctypes.byref(cxbwt.Opts(t, c, cxbwt.SCHEDULE_STRINGWORD, 1)), wsb=10) == (cxbwt.ENOMEM, None)
 
     def bstart(coll, wsb=1 << 40):
         h = ctypes.c_void_p(0x1234)
         arr = (ctypes.c_uint64 * len(coll))(*coll)
-        rc = L.cxbwt_build_batch_start(fake, fake, 4, 40, 10, arr, len(coll) - 1, fake, fake, fake, wsb, null,
-                                       ctypes.byref(h))
+        rc = L.cxbwt_build_batch_start(fake, fake, 4, 40, 10, arr, len(coll) - 1, fake, fake, fake, wsb, None,
+                                       null, ctypes.byref(h))
         return rc, h.value
 
     assert bstart([0, 2, 3]) == (cxbwt.EINVAL, None)

@@ -119,3 +119,44 @@ def test_started_build_reports_bad_offsets_at_the_wait():
     job = cxbwt.build_start(packed, offs, col.n_reads, col.n_bases, col.max_read_len, stream=s)
     b, t = job.wait()
     _against_oracle(col, b, t, "after the failure")
+
+
+def test_started_builds_with_their_own_options():
+    """Per-call options: the same input built with every instantiation and
+    both schedules, all started before any wait, each on its own stream; the
+    thread's own choices are left alone."""
+    import torch
+    col = datagen.plain_config(0, scale=0.2)
+    before = (cxbwt.get_tuning(), cxbwt.get_schedule())
+    choices = [(t, c, cxbwt.SCHEDULE_MSD, 1) for t, c in cxbwt.TUNING_CHOICES[:3]]
+    choices.append((*cxbwt.TUNING_CHOICES[0], cxbwt.SCHEDULE_STRINGWORD, 1))
+    _say(f"started builds with options {choices}: {col.n_bases} bases")
+    streams = [torch.cuda.Stream() for _ in choices]
+    jobs = []
+    for ch, s in zip(choices, streams):
+        _, offs, packed, _ = _device(col, s)
+        jobs.append((ch, cxbwt.build_start(packed, offs, col.n_reads, col.n_bases, col.max_read_len, stream=s,
+                                           opts=ch)))
+    for ch, j in jobs:
+        b, t = j.wait()
+        assert j.stats["schedule"] == ch[2]
+        assert sum(j.stats["ms"].values()) > 0  # timing was asked for
+        _against_oracle(col, b, t, f"options {ch}")
+    assert (cxbwt.get_tuning(), cxbwt.get_schedule()) == before
+
+
+def test_device_failure_text():
+    """An EDATA from the device comes with the library's text."""
+    import torch
+    col = datagen.plain_config(0, scale=0.05)
+    s = torch.cuda.Stream()
+    _, offs, packed, _ = _device(col, s)
+    with torch.cuda.stream(s):
+        bad = offs.clone()
+        bad[3] = bad[9] + 1
+    _say("blocking build with invalid offsets: error text")
+    with pytest.raises(cxbwt.CxbwtError) as e:
+        with torch.cuda.stream(s):
+            cxbwt.build(packed, bad, col.n_reads, col.n_bases, col.max_read_len, stream=s)
+    assert e.value.status == cxbwt.EDATA
+    assert e.value.detail, "no text for EDATA"
