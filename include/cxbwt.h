@@ -361,7 +361,8 @@ typedef struct cxbwt_stats {
   uint32_t level_batches;      /* batches the levels after the first ran in            */
   uint32_t ranges;             /* key ranges of a build in ranges (0 otherwise)        */
   uint32_t schedule;           /* CXBWT_SCHEDULE_* the build ran                       */
-  uint32_t reserved;
+  uint32_t host_levels;        /* levels the host scheduled from counts it read back
+                                * (0: the device scheduled every level)                 */
 } cxbwt_stats;
 
 /*

@@ -826,6 +826,7 @@ int run_levels(const Build &b, LevelOut acc, uint32_t nbig, PhaseTimer &T, hipSt
   while (nbig) {
     if (nbig > Lo.cap_big) return fail_internal("work exceeds a workspace list or scratch area");
     g_stats.levels++;
+    g_stats.host_levels++;
     g_stats.big_segments += nbig;
     g_stats.level_suffixes += acc.next_len;
     g_stats.regathered += acc.next_regather;
@@ -944,10 +945,14 @@ int enqueue_body(const Build &b, const Level1Src &src, uint32_t device_levels, P
         // the level just scanned: fold, finish its chunks and final groups
         k_level_fold<<<1, 64, 0, st>>>(B.stats, (unsigned long long *)(counters + C_FOLD), counters + C_FLAGS);
         CX_LAUNCHED();
+        T.begin();
         if ((rc = launch_local(B, b.tu, nb, b.rmax, b.bwt, (uint32_t)Lo.cap_chunks, counters + C_NCHUNK, st,
                                grid_from(seen(lv).nchunks, 0))))
           return rc;
+        T.end(PH_LOCAL);
+        T.begin();
         if ((rc = finish_finals_dev(b, st, grid_from(seen(lv).ftiles, PG_EMIT)))) return rc;
+        T.end(PH_FINAL);
         const int last = lv == device_levels - 1;
         k_level_step<<<1, 64, 0, st>>>(counters, Lo.seg_slots, Lo.max_tiles, Lo.max_groups, last);
         CX_LAUNCHED();
@@ -1079,6 +1084,47 @@ int run_stringword(const Build &b, PhaseTimer &T, hipStream_t st) {
   k_term<<<grid_for(b.n, 256), 256, 0, st>>>(b.offsets, b.n, b.nb, B.text, B.srank, B.start_row, b.term_pos);
   CX_LAUNCHED();
   T.end(PH_FINAL);
+  return CXBWT_OK;
+}
+
+// After a run of levels the device scheduled (a graph replay): the status,
+// the statistics the device counted, and the levels it left to the host.
+// hc0 holds the counters read after the run.
+int finish_device_levels(const Build &b, const uint32_t (&hc0)[C_COUNT], PhaseTimer &T, hipStream_t st) {
+  uint32_t hc[C_COUNT];
+  memcpy(hc, hc0, sizeof(hc));
+  int rc;
+  if (hc[C_STATUS] & (ST_BAD_OFFSETS | ST_TOO_LONG)) return fail_status(hc[C_STATUS]);
+  if (hc[C_STATUS]) return fail_status(hc[C_STATUS]);
+  uint64_t g[G_COUNT], f[K_LEVEL_KINDS];
+  memcpy(g, hc + C_CUM, sizeof(g));
+  memcpy(f, hc + C_FOLD, sizeof(f));
+  g_stats.levels += (uint32_t)g[G_LEVELS];
+  g_stats.big_segments += g[G_BIGSEG];
+  g_stats.level_suffixes += g[G_LEVSUF];
+  g_stats.regathered += g[G_REGATH];
+  g_stats.max_window = std::max<uint32_t>(g_stats.max_window, (uint32_t)g[G_MAXWIN]);
+  g_stats.chunks += g[G_CHUNKS];
+  g_stats.final_big += g[G_FINALS];
+  g_stats.chunk_suffixes -= g[G_FINLEN];
+  g_stats.level_batches += (uint32_t)g[G_BATCHES];
+  if (!(hc[C_FLAGS] & (FL_STALLED | FL_INCOMPLETE))) return CXBWT_OK;
+  // the device schedule did not cover the build: the host finishes it
+  LevelOut acc{};
+  acc.next_len = f[K_NEXT_LEN - K_LEVEL_FIRST];
+  acc.next_regather = f[K_NEXT_REGATHER - K_LEVEL_FIRST];
+  acc.next_maxr = f[K_NEXT_MAXR - K_LEVEL_FIRST];
+  acc.next_tiles = f[K_NEXT_TILES - K_LEVEL_FIRST];
+  acc.next_groups = f[K_NEXT_GROUPS - K_LEVEL_FIRST];
+  if ((rc = run_levels(b, acc, hc[C_NBIG], T, st))) return rc;
+  k_term<<<grid_for(b.n, 256), 256, 0, st>>>(b.offsets, b.n, b.nb, b.B.text, b.B.srank, b.B.start_row,
+                                              b.term_pos);
+  CX_LAUNCHED();
+  // the statistics block still holds the device levels' counts: take the rest only
+  g_stats.window_fetches = 0;
+  g_stats.scattered_suffixes = 0;
+  if ((rc = read_totals(b, T, st, hc))) return rc;
+  if (hc[C_STATUS]) return fail_status(hc[C_STATUS]);
   return CXBWT_OK;
 }
 
@@ -1410,44 +1456,12 @@ int graph_capture(GraphPlan &P, hipStream_t st) {
 
 // After a replay: status, statistics, and the levels left to the host.
 int graph_finish(GraphPlan &P, hipStream_t st) {
-  Build &b = P.b;
   PhaseTimer T{st, false, {}};
   g_stats = P.base;
   uint32_t hc[C_COUNT];
   int rc;
-  if ((rc = read_totals(b, T, st, hc))) return rc;
-  if (hc[C_STATUS] & (ST_BAD_OFFSETS | ST_TOO_LONG)) return fail_status(hc[C_STATUS]);
-  if (hc[C_STATUS]) return fail_status(hc[C_STATUS]);
-  uint64_t g[G_COUNT], f[K_LEVEL_KINDS];
-  memcpy(g, hc + C_CUM, sizeof(g));
-  memcpy(f, hc + C_FOLD, sizeof(f));
-  g_stats.levels += (uint32_t)g[G_LEVELS];
-  g_stats.big_segments += g[G_BIGSEG];
-  g_stats.level_suffixes += g[G_LEVSUF];
-  g_stats.regathered += g[G_REGATH];
-  g_stats.max_window = std::max<uint32_t>(g_stats.max_window, (uint32_t)g[G_MAXWIN]);
-  g_stats.chunks += g[G_CHUNKS];
-  g_stats.final_big += g[G_FINALS];
-  g_stats.chunk_suffixes -= g[G_FINLEN];
-  g_stats.level_batches += (uint32_t)g[G_BATCHES];
-  if (!(hc[C_FLAGS] & (FL_STALLED | FL_INCOMPLETE))) return CXBWT_OK;
-  // the device schedule did not cover the build: the host finishes it
-  LevelOut acc{};
-  acc.next_len = f[K_NEXT_LEN - K_LEVEL_FIRST];
-  acc.next_regather = f[K_NEXT_REGATHER - K_LEVEL_FIRST];
-  acc.next_maxr = f[K_NEXT_MAXR - K_LEVEL_FIRST];
-  acc.next_tiles = f[K_NEXT_TILES - K_LEVEL_FIRST];
-  acc.next_groups = f[K_NEXT_GROUPS - K_LEVEL_FIRST];
-  if ((rc = run_levels(b, acc, hc[C_NBIG], T, st))) return rc;
-  k_term<<<grid_for(b.n, 256), 256, 0, st>>>(b.offsets, b.n, b.nb, b.B.text, b.B.srank, b.B.start_row,
-                                              b.term_pos);
-  CX_LAUNCHED();
-  // the statistics block still holds the replay's counts: take the rest only
-  g_stats.window_fetches = 0;
-  g_stats.scattered_suffixes = 0;
-  if ((rc = read_totals(b, T, st, hc))) return rc;
-  if (hc[C_STATUS]) return fail_status(hc[C_STATUS]);
-  return CXBWT_OK;
+  if ((rc = read_totals(P.b, T, st, hc))) return rc;
+  return finish_device_levels(P.b, hc, T, st);
 }
 
 }  // namespace

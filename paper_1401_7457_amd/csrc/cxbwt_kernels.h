@@ -247,6 +247,9 @@ __global__ void k_prep(const uint64_t *__restrict__ packed, const uint64_t *__re
     else chi = mid;
   }
   const uint64_t first_read = coll_reads[clo];
+  // the end of the text ends every window, also when offsets are invalid
+  // (the levels of a device-scheduled build still run over [0, nb))
+  if (i == n - 1) atomicOr(&sbits[nb >> 5], 1u << (nb & 31));
   const uint64_t a = offsets[i], b = offsets[i + 1];
   const bool bad = b < a || b > nb || (i == 0 && a != 0) || (i == n - 1 && b != nb);
   if (bad) {
@@ -268,7 +271,6 @@ __global__ void k_prep(const uint64_t *__restrict__ packed, const uint64_t *__re
     return;
   }
   const uint64_t out = ob + i;
-  if (i == n - 1) atomicOr(&sbits[nb >> 5], 1u << (nb & 31));  // end of the text
   if (b > a) {
     const uint64_t e = b - 1;
     atomicOr(&sbits[a >> 5], 1u << (a & 31));

@@ -69,7 +69,7 @@ class Stats(ctypes.Structure):
                 ("scattered_suffixes", ctypes.c_uint64), ("regathered", ctypes.c_uint64),
                 ("window_fetches", ctypes.c_uint64), ("ms", ctypes.c_float * 8), ("launches", ctypes.c_uint32 * 8),
                 ("level_batches", ctypes.c_uint32), ("ranges", ctypes.c_uint32), ("schedule", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("host_levels", ctypes.c_uint32)]
 
 
 def lib():
@@ -530,7 +530,7 @@ def last_stats() -> dict:
 
 
 def _stats_dict(s) -> dict:
-    out = {f: int(getattr(s, f)) for f, _ in Stats._fields_ if f not in ("ms", "launches", "reserved")}
+    out = {f: int(getattr(s, f)) for f, _ in Stats._fields_ if f not in ("ms", "launches")}
     out["ms"] = {k: float(s.ms[i]) for i, k in enumerate(KERNEL_CLASSES) if s.launches[i]}
     out["launches"] = {k: int(s.launches[i]) for i, k in enumerate(KERNEL_CLASSES) if s.launches[i]}
     return out
