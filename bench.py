@@ -570,10 +570,10 @@ def _serve_mode(args) -> dict:
 def _ceilings_mode(args) -> dict:
     """Memory-system ceilings the kernels are measured against, with torch's own
     kernels: a streaming copy, random 16-byte gathers (the window fetches'
-    access pattern) and writes in runs of 8 and 16 consecutive records per
-    bucket per tile (the level scatters' write pattern; index_copy_ also
-    reads its 8-byte indices), each timed with events over several
-    repetitions."""
+    access pattern) and writes in runs of consecutive records per bucket per
+    tile (the level scatters' write pattern, for 256 buckets and for the
+    wider digits a 10- or 12-bit digit would give; index_copy_ also reads its
+    8-byte indices), each timed with events over several repetitions."""
     import torch
     out = {}
     reps = max(3, args.steps)
@@ -605,12 +605,15 @@ def _ceilings_mode(args) -> dict:
         out[f"random_16B_loads_per_s_table_{table_mib}MiB"] = idx.numel() / t
         del table, idx
     # the write pattern of a level scatter: ~400M (key u64, handle u32)
-    # records in tiles of 256 r, each tile writing a run of r records to each
-    # of 256 evenly filled buckets at the bucket's running position
-    for r in (8, 16):
-        ntiles = 400_000_000 // (256 * r)
+    # records in tiles of nb * r, each tile writing a run of r records to
+    # each of nb evenly filled buckets at the bucket's running position.  The
+    # 8-bit digit of the library is nb = 256 (runs of 16 for its 4096-suffix
+    # tile); a 10-bit digit over the same tile would write runs of 4 to 1024
+    # buckets, over a tile twice as long runs of 8.
+    for nbk, r in ((256, 8), (256, 16), (1024, 4), (1024, 8), (4096, 2)):
+        ntiles = 400_000_000 // (nbk * r)
         t_ = torch.arange(ntiles, device="cuda").view(-1, 1, 1)
-        b_ = torch.arange(256, device="cuda").view(1, -1, 1)
+        b_ = torch.arange(nbk, device="cuda").view(1, -1, 1)
         k_ = torch.arange(r, device="cuda").view(1, 1, -1)
         pos = (b_ * (ntiles * r) + t_ * r + k_).reshape(-1)
         m = pos.numel()
@@ -623,8 +626,9 @@ def _ceilings_mode(args) -> dict:
             ko.index_copy_(0, pos, keys)
             ho.index_copy_(0, pos, hdl)
         t = timed(scat)
-        out[f"scatter_runs_of_{r}_ms_per_400M"] = t * 1e3 * 400_000_000 / m
-        out[f"scatter_runs_of_{r}_gb_per_s"] = m * 24 / t / 1e9
+        name = f"scatter_runs_of_{r}" if nbk == 256 else f"scatter_{nbk}_buckets_runs_of_{r}"
+        out[f"{name}_ms_per_400M"] = t * 1e3 * 400_000_000 / m
+        out[f"{name}_gb_per_s"] = m * 24 / t / 1e9
         del pos, keys, hdl, ko, ho, t_, b_, k_
     return {"metric": "memory-system ceilings at 1 GPU (torch kernels)", "unit": "various", "n_gpus": 1,
             "data": "synthetic", "reps": reps, "ceilings": out}

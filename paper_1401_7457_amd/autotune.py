@@ -142,14 +142,23 @@ def tune_build(packed, offsets, n_reads: int, n_bases: int, max_read_len: int, c
     return {"choice": best, "ms": times}
 
 
-def select_for(n_reads: int, n_bases: int, max_read_len: int, n_coll: int = 1) -> tuple | None:
-    """Select the remembered choice for this shape class, if any (returns it)."""
+def remembered(n_reads: int, n_bases: int, max_read_len: int, n_coll: int = 1) -> tuple | None:
+    """The remembered (tile_items, chunk_items, schedule) choice for this
+    shape class, if any; selects nothing (pass it as a started build's opts)."""
     key = shape_key(n_reads, n_bases, max_read_len, n_coll)
     best = _cache.get(key)
     if best is None:
         best = _load_file().get(_key_str(key))
+        if best is not None and len(best) != 3:
+            best = None  # written before the schedule was a choice
         if best is not None:
             _cache[key] = best
+    return best
+
+
+def select_for(n_reads: int, n_bases: int, max_read_len: int, n_coll: int = 1) -> tuple | None:
+    """Select the remembered choice for this shape class on this thread, if any (returns it)."""
+    best = remembered(n_reads, n_bases, max_read_len, n_coll)
     if best is not None:
         apply(best)
     return best

@@ -170,9 +170,10 @@ class DeviceExecutor(Executor):
             text = torch.cat(texts) if nb else torch.empty(0, dtype=torch.uint8, device=self.device)
             offsets = torch.from_numpy(offsets_h.view(np.int64)).to(self.device, non_blocking=False)
             packed, pstatus = cx.pack(text, stream=stream)
-            # the autotuner's remembered choice for this shape class, if it has one
-            autotune.select_for(n, nb, maxlen, len(jobs))
-            job = cx.build_batch_start(packed, offsets, n, nb, maxlen, coll_reads, stream=stream)
+            # the autotuner's remembered choice for this shape class, if it has
+            # one, as this build's own options (the thread's choices otherwise)
+            opts = autotune.remembered(n, nb, maxlen, len(jobs))
+            job = cx.build_batch_start(packed, offsets, n, nb, maxlen, coll_reads, stream=stream, opts=opts)
         return (job, pstatus, ns, nbs)
 
     def batch_done(self, handle) -> bool:
