@@ -58,6 +58,21 @@ extern "C" {
 #define CXBWT_MAX_READ_LEN 65535u
 
 /*
+ * The choices of one build (cxbwt_build, cxbwt_build_batch and the builds
+ * that return at once): the kernel instantiation, the sort schedule and
+ * per-class kernel timing, as cxbwt_set_tuning, cxbwt_set_schedule and
+ * cxbwt_set_timing would set them, and checked the same way (CXBWT_EINVAL
+ * for values those calls refuse).  A NULL opts takes the calling thread's
+ * choices.  The result of a build never depends on them, only its speed.
+ */
+typedef struct cxbwt_opts {
+  uint32_t tile_items;   /* 6, 8 or 16, as cxbwt_set_tuning          */
+  uint32_t chunk_items;  /* 3, 6 or 8, as cxbwt_set_tuning           */
+  uint32_t schedule;     /* CXBWT_SCHEDULE_MSD or _STRINGWORD       */
+  uint32_t timing;       /* nonzero: per-class kernel times in stats */
+} cxbwt_opts;
+
+/*
  * Packed read layout (input of cxbwt_build), fixed by this library:
  * base t of the reads concatenated in read order is the 2-bit code
  * A=0, C=1, G=2, T=3 stored in 64-bit word t/32 at bits
@@ -118,6 +133,10 @@ size_t cxbwt_workspace_bytes(uint64_t n_reads, uint64_t n_bases, uint32_t max_re
  * Workspace
  *   workspace     (device) at least cxbwt_workspace_bytes(...) bytes, aligned
  *                 to 256 bytes; contents on entry are ignored.
+ * Options
+ *   opts          (host, may be NULL) this build's choices (cxbwt_opts); NULL
+ *                 takes the calling thread's.  The thread's choices are left
+ *                 as they were.
  * Behaviour
  *   Work is enqueued on `stream`; the call reads a few counters back between
  *   sort levels, so it returns only after the device work is complete.
@@ -128,7 +147,7 @@ size_t cxbwt_workspace_bytes(uint64_t n_reads, uint64_t n_bases, uint32_t max_re
  */
 int cxbwt_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n_reads, uint64_t n_bases,
                 uint32_t max_read_len, uint8_t *bwt, uint64_t *term_pos, void *workspace,
-                size_t workspace_bytes, void *stream);
+                size_t workspace_bytes, const cxbwt_opts *opts, void *stream);
 
 /*
  * cxbwt_build_noalloc -- cxbwt_build without a caller workspace and without
@@ -235,13 +254,16 @@ size_t cxbwt_batch_workspace_bytes(uint64_t n_reads, uint64_t n_bases, uint32_t 
  *   term_pos      (device, out) n_reads uint64: for global read i of
  *                 collection c, the row inside collection c's BWT of the '$'
  *                 standing for read i - coll_reads[c].
- * Workspace, stream, return codes: as cxbwt_build, with CXBWT_EINVAL also
- * for inconsistent coll_reads and CXBWT_ENOMEM below
- * cxbwt_batch_workspace_bytes().  Returns after the device work completes.
+ * Workspace, options, stream, return codes: as cxbwt_build, with CXBWT_EINVAL
+ * also for inconsistent coll_reads and CXBWT_ENOMEM below
+ * cxbwt_batch_workspace_bytes().  The stringword schedule applies to a
+ * single collection only; a batch sorts most significant digit first.
+ * Returns after the device work completes.
  */
 int cxbwt_build_batch(const uint64_t *packed, const uint64_t *offsets, uint64_t n_reads, uint64_t n_bases,
                       uint32_t max_read_len, const uint64_t *coll_reads, uint32_t n_coll, uint8_t *bwt,
-                      uint64_t *term_pos, void *workspace, size_t workspace_bytes, void *stream);
+                      uint64_t *term_pos, void *workspace, size_t workspace_bytes, const cxbwt_opts *opts,
+                      void *stream);
 
 /*
  * Builds that return at once (for callers that overlap builds with other
@@ -249,10 +271,6 @@ int cxbwt_build_batch(const uint64_t *packed, const uint64_t *offsets, uint64_t 
  *
  * cxbwt_build_start / cxbwt_build_batch_start -- arguments, checks and
  *   results as cxbwt_build / cxbwt_build_batch, plus
- *     opts  (host, may be NULL) the kernel instantiation, sort schedule and
- *           timing of this build (the values of cxbwt_set_tuning,
- *           cxbwt_set_schedule and cxbwt_set_timing, checked the same way:
- *           CXBWT_EINVAL for others); NULL takes the calling thread's.
  *     job   (host, out) the started build, or NULL on an error returned here.
  *   Argument errors are returned by the call, before any HIP call; a started
  *   build's own status (CXBWT_EDATA and so on) comes from cxbwt_job_wait.  A
@@ -274,12 +292,6 @@ int cxbwt_build_batch(const uint64_t *packed, const uint64_t *offsets, uint64_t 
  *   waited for exactly once.  CXBWT_EINVAL for NULL.
  */
 typedef struct cxbwt_job cxbwt_job;
-typedef struct cxbwt_opts {
-  uint32_t tile_items;   /* 6, 8 or 16, as cxbwt_set_tuning          */
-  uint32_t chunk_items;  /* 3, 6 or 8, as cxbwt_set_tuning           */
-  uint32_t schedule;     /* CXBWT_SCHEDULE_MSD or _STRINGWORD       */
-  uint32_t timing;       /* nonzero: per-class kernel times in stats */
-} cxbwt_opts;
 int cxbwt_build_start(const uint64_t *packed, const uint64_t *offsets, uint64_t n_reads, uint64_t n_bases,
                       uint32_t max_read_len, uint8_t *bwt, uint64_t *term_pos, void *workspace,
                       size_t workspace_bytes, const cxbwt_opts *opts, void *stream, cxbwt_job **job);

@@ -1536,6 +1536,20 @@ bool job_choices(const cxbwt_opts *opts, Tuning &tu, int &timing) {
   return true;
 }
 
+// A blocking build's choices: set for the call, the thread's restored after.
+struct ChoiceScope {
+  Tuning saved_tu;
+  int saved_timing;
+  ChoiceScope(const Tuning &tu, int timing) : saved_tu(g_tuning), saved_timing(g_timing) {
+    g_tuning = tu;
+    g_timing = timing;
+  }
+  ~ChoiceScope() {
+    g_tuning = saved_tu;
+    g_timing = saved_timing;
+  }
+};
+
 int start_job(JobArgs &&a, cxbwt_job **out) {
   if (hipGetDevice(&a.device) != hipSuccess) return CXBWT_EDEVICE;
   cxbwt_job *job = new (std::nothrow) cxbwt_job;
@@ -1614,11 +1628,15 @@ size_t cxbwt_batch_workspace_bytes(uint64_t n_reads, uint64_t n_bases, uint32_t 
 
 int cxbwt_build(const uint64_t *packed, const uint64_t *offsets, uint64_t n_reads, uint64_t n_bases,
                 uint32_t max_read_len, uint8_t *bwt, uint64_t *term_pos, void *workspace, size_t workspace_bytes,
-                void *stream) {
+                const cxbwt_opts *opts, void *stream) {
   if (!packed || !offsets || !bwt || !term_pos || !workspace || n_reads == 0) return CXBWT_EINVAL;
   if (!sizes_ok(n_reads, n_bases, max_read_len)) return CXBWT_ERANGE;
   if (workspace_bytes < cxbwt_workspace_bytes(n_reads, n_bases, max_read_len)) return CXBWT_ENOMEM;
   if (((uintptr_t)workspace & 255u) != 0) return CXBWT_EINVAL;
+  Tuning tu;
+  int timing = 0;
+  if (!job_choices(opts, tu, timing)) return CXBWT_EINVAL;
+  ChoiceScope scope(tu, timing);
   const uint64_t one[2] = {0, n_reads};
   return run_build(packed, offsets, n_reads, n_bases, max_read_len, one, 1, bwt, term_pos, (unsigned char *)workspace,
                    (hipStream_t)stream);
@@ -1710,7 +1728,8 @@ int cxbwt_job_wait(cxbwt_job *job, cxbwt_stats *stats) {
 
 int cxbwt_build_batch(const uint64_t *packed, const uint64_t *offsets, uint64_t n_reads, uint64_t n_bases,
                       uint32_t max_read_len, const uint64_t *coll_reads, uint32_t n_coll, uint8_t *bwt,
-                      uint64_t *term_pos, void *workspace, size_t workspace_bytes, void *stream) {
+                      uint64_t *term_pos, void *workspace, size_t workspace_bytes, const cxbwt_opts *opts,
+                      void *stream) {
   if (!packed || !offsets || !bwt || !term_pos || !workspace || !coll_reads || n_reads == 0 || n_coll == 0)
     return CXBWT_EINVAL;
   if (!sizes_ok(n_reads, n_bases, max_read_len)) return CXBWT_ERANGE;
@@ -1720,6 +1739,10 @@ int cxbwt_build_batch(const uint64_t *packed, const uint64_t *offsets, uint64_t 
     if (coll_reads[c + 1] <= coll_reads[c]) return CXBWT_EINVAL;  // every collection holds a read
   if (workspace_bytes < cxbwt_batch_workspace_bytes(n_reads, n_bases, max_read_len, n_coll)) return CXBWT_ENOMEM;
   if (((uintptr_t)workspace & 255u) != 0) return CXBWT_EINVAL;
+  Tuning tu;
+  int timing = 0;
+  if (!job_choices(opts, tu, timing)) return CXBWT_EINVAL;
+  ChoiceScope scope(tu, timing);
   return run_build(packed, offsets, n_reads, n_bases, max_read_len, coll_reads, n_coll, bwt, term_pos,
                    (unsigned char *)workspace, (hipStream_t)stream);
 }

@@ -88,7 +88,7 @@ def lib():
             L.cxbwt_pack.restype = ctypes.c_int
             L.cxbwt_workspace_bytes.argtypes = [u64, u64, u32]
             L.cxbwt_workspace_bytes.restype = ctypes.c_size_t
-            L.cxbwt_build.argtypes = [vp, vp, u64, u64, u32, vp, vp, vp, ctypes.c_size_t, vp]
+            L.cxbwt_build.argtypes = [vp, vp, u64, u64, u32, vp, vp, vp, ctypes.c_size_t, ctypes.POINTER(Opts), vp]
             L.cxbwt_build.restype = ctypes.c_int
             L.cxbwt_build_noalloc.argtypes = [vp, vp, u64, u64, u32, vp, vp, vp]
             L.cxbwt_build_noalloc.restype = ctypes.c_int
@@ -98,7 +98,8 @@ def lib():
             L.cxbwt_build_ranges.restype = ctypes.c_int
             L.cxbwt_batch_workspace_bytes.argtypes = [u64, u64, u32, u32]
             L.cxbwt_batch_workspace_bytes.restype = ctypes.c_size_t
-            L.cxbwt_build_batch.argtypes = [vp, vp, u64, u64, u32, vp, u32, vp, vp, vp, ctypes.c_size_t, vp]
+            L.cxbwt_build_batch.argtypes = [vp, vp, u64, u64, u32, vp, u32, vp, vp, vp, ctypes.c_size_t,
+                                            ctypes.POINTER(Opts), vp]
             L.cxbwt_build_batch.restype = ctypes.c_int
             L.cxbwt_build_start.argtypes = [vp, vp, u64, u64, u32, vp, vp, vp, ctypes.c_size_t,
                                             ctypes.POINTER(Opts), vp, ctypes.POINTER(vp)]
@@ -181,10 +182,12 @@ def alloc_workspace(n_reads: int, n_bases: int, max_read_len: int, device="cuda"
     return torch.empty(nbytes, dtype=torch.uint8, device=device)
 
 
-def build(packed, offsets, n_reads: int, n_bases: int, max_read_len: int, workspace=None, out=None, stream=None):
+def build(packed, offsets, n_reads: int, n_bases: int, max_read_len: int, workspace=None, out=None, stream=None,
+          opts=None):
     """BWT (uint8 CUDA tensor, n_bases + n_reads) and term_pos (int64 CUDA tensor, n_reads).
 
     packed: int64 CUDA tensor of packed words; offsets: int64 CUDA tensor of n_reads + 1 base offsets.
+    opts: (tile_items, chunk_items, schedule[, timing]) for this build, else the thread's choices.
     """
     import torch
     dev = packed.device
@@ -197,7 +200,8 @@ def build(packed, offsets, n_reads: int, n_bases: int, max_read_len: int, worksp
         bwt, term = out
     st = lib().cxbwt_build(ctypes.c_void_p(packed.data_ptr()), ctypes.c_void_p(offsets.data_ptr()), n_reads, n_bases,
                            max_read_len, ctypes.c_void_p(bwt.data_ptr()), ctypes.c_void_p(term.data_ptr()),
-                           ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream_ptr(stream))
+                           ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _opts(opts),
+                           _stream_ptr(stream))
     if st != OK:
         raise CxbwtError(st, "cxbwt_build")
     return bwt, term
@@ -280,8 +284,9 @@ def batch_workspace_bytes(n_reads: int, n_bases: int, max_read_len: int, n_coll:
 
 
 def build_batch(packed, offsets, n_reads: int, n_bases: int, max_read_len: int, coll_reads, workspace=None,
-                out=None, stream=None):
+                out=None, stream=None, opts=None):
     """BWTs of several collections laid end to end (see cxbwt_build_batch).
+    opts: as for build.
 
     coll_reads: host sequence of n_coll + 1 read boundaries.  Returns the
     concatenated BWTs (uint8 CUDA tensor) and per-read term_pos rows local to
@@ -304,7 +309,8 @@ def build_batch(packed, offsets, n_reads: int, n_bases: int, max_read_len: int, 
     st = lib().cxbwt_build_batch(ctypes.c_void_p(packed.data_ptr()), ctypes.c_void_p(offsets.data_ptr()), n_reads,
                                  n_bases, max_read_len, cr.ctypes.data_as(ctypes.c_void_p), n_coll,
                                  ctypes.c_void_p(bwt.data_ptr()), ctypes.c_void_p(term.data_ptr()),
-                                 ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream_ptr(stream))
+                                 ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _opts(opts),
+                                 _stream_ptr(stream))
     if st != OK:
         raise CxbwtError(st, "cxbwt_build_batch")
     return bwt, term

@@ -52,7 +52,7 @@ def test_build_argument_validation_needs_no_gpu():
     null = ctypes.c_void_p(0)
     args = lambda **kw: [kw.get("packed", fake), kw.get("offsets", fake), kw.get("n", 3), kw.get("nb", 12),
                          kw.get("maxlen", 4), kw.get("bwt", fake), kw.get("term", fake), kw.get("ws", fake),
-                         kw.get("wsb", 1 << 40), null]
+                         kw.get("wsb", 1 << 40), kw.get("opts"), null]
     assert L.cxbwt_build(*args(packed=null)) == cxbwt.EINVAL
     assert L.cxbwt_build(*args(bwt=null)) == cxbwt.EINVAL
     assert L.cxbwt_build(*args(term=null)) == cxbwt.EINVAL
@@ -62,6 +62,11 @@ def test_build_argument_validation_needs_no_gpu():
     assert L.cxbwt_build(*args(maxlen=1 << 20)) == cxbwt.ERANGE
     assert L.cxbwt_build(*args(wsb=10)) == cxbwt.ENOMEM
     assert L.cxbwt_build(*args(ws=ctypes.c_void_p(0x1001))) == cxbwt.EINVAL  # misaligned workspace
+    # options the library does not hold are refused before any HIP call (the
+    # buffers here are fake, so a call that got further would not return)
+    t, c = cxbwt.TUNING_CHOICES[0]
+    assert L.cxbwt_build(*args(opts=ctypes.byref(cxbwt.Opts(t, c + 1, cxbwt.SCHEDULE_MSD, 0)))) == cxbwt.EINVAL
+    assert L.cxbwt_build(*args(opts=ctypes.byref(cxbwt.Opts(t, c, 2, 0)))) == cxbwt.EINVAL
 
 
 def test_noalloc_argument_validation_needs_no_gpu():
@@ -210,7 +215,7 @@ def test_batch_argument_validation_needs_no_gpu():
 
     def call(coll, n=4, nb=40, wsb=1 << 40, ws=fake):
         arr = (ctypes.c_uint64 * len(coll))(*coll)
-        return L.cxbwt_build_batch(fake, fake, n, nb, 10, arr, len(coll) - 1, fake, fake, ws, wsb, null)
+        return L.cxbwt_build_batch(fake, fake, n, nb, 10, arr, len(coll) - 1, fake, fake, ws, wsb, None, null)
 
     assert call([0, 2, 3]) == cxbwt.EINVAL          # does not end at n_reads
     assert call([1, 2, 4]) == cxbwt.EINVAL          # does not start at 0

@@ -160,3 +160,33 @@ def test_device_failure_text():
             cxbwt.build(packed, bad, col.n_reads, col.n_bases, col.max_read_len, stream=s)
     assert e.value.status == cxbwt.EDATA
     assert e.value.detail, "no text for EDATA"
+
+
+def test_blocking_builds_take_options():
+    """cxbwt_build / cxbwt_build_batch with their own options: the result is the
+    oracle's for every choice, the statistics name the schedule run, and the
+    thread's own choices are left as they were."""
+    import torch
+    col = datagen.plain_config(0, scale=0.1)
+    before = (cxbwt.get_tuning(), cxbwt.get_schedule())
+    s = torch.cuda.current_stream()
+    _, offs, packed, _ = _device(col, s)
+    for ch in ((*cxbwt.TUNING_CHOICES[-1], cxbwt.SCHEDULE_MSD, 1), (*cxbwt.TUNING_CHOICES[0], cxbwt.SCHEDULE_STRINGWORD, 0)):
+        _say(f"blocking build with options {ch}")
+        b, t = cxbwt.build(packed, offs, col.n_reads, col.n_bases, col.max_read_len, opts=ch)
+        assert cxbwt.last_stats()["schedule"] == ch[2]
+        _against_oracle(col, b, t, f"options {ch}")
+    cols = datagen.batch_collections(count=5, scale=0.002)
+    text, offsets, coll_reads, maxlen = cxbwt.concat_collections(cols)
+    t_dev = torch.from_numpy(text).cuda()
+    o_dev = torch.from_numpy(offsets.view(np.int64)).cuda()
+    packed_b, _ = cxbwt.pack(t_dev)
+    n, nb = offsets.size - 1, int(offsets[-1])
+    _say(f"blocking batch with options: {len(cols)} collections, {nb} bases")
+    bwt, term = cxbwt.build_batch(packed_b, o_dev, n, nb, maxlen, coll_reads,
+                                  opts=(*cxbwt.TUNING_CHOICES[-1], cxbwt.SCHEDULE_MSD))
+    outs = cxbwt.split_batch_output(bwt.cpu().numpy(), term.cpu().numpy().view(np.uint64), cols)
+    for c, (b, t) in zip(cols, outs):
+        eb, et = oracle.bwt(c.text, c.offsets)
+        assert np.array_equal(b, eb) and np.array_equal(t, et)
+    assert (cxbwt.get_tuning(), cxbwt.get_schedule()) == before
