@@ -498,9 +498,12 @@ int launch_local(const Buffers &B, const Tuning &tu, uint64_t nb, uint32_t rmax,
                                                             0);                                                  \
     }                                                                                                            \
   } while (0)
-  if (tu.chunk_items == 8) CX_LOCAL(8, 3, 3);
+  // waves per SIMD: the most that neither spill much nor lose time (measured:
+  // 8 per lane at 4, 6 per lane at 4 (5 spills 14 registers and is slower),
+  // 3 per lane at 7 (8 spills and is slower))
+  if (tu.chunk_items == 8) CX_LOCAL(8, 4, 3);
   else if (tu.chunk_items == 6) CX_LOCAL(6, 4, 4);
-  else CX_LOCAL(3, 6, 5);
+  else CX_LOCAL(3, 7, 5);
 #undef CX_LOCAL
   CX_LAUNCHED();
   return CXBWT_OK;
