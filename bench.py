@@ -569,8 +569,9 @@ def _serve_mode(args) -> dict:
 
 def _ceilings_mode(args) -> dict:
     """Memory-system ceilings the kernels are measured against, with torch's own
-    kernels: a streaming copy, random 16-byte gathers (the window fetches'
-    access pattern) and writes in runs of consecutive records per bucket per
+    kernels (torch's, and one gather kernel of this package): a streaming
+    copy, random 16-byte gathers (the window fetches' access pattern) and
+    32-byte ones (two windows a load), and writes in runs of consecutive records per bucket per
     tile (the level scatters' write pattern, for 256 buckets and for the
     wider digits a 10- or 12-bit digit would give; index_copy_ also reads its
     8-byte indices), each timed with events over several repetitions."""
@@ -595,15 +596,28 @@ def _ceilings_mode(args) -> dict:
     t = timed(lambda: dst.copy_(src))
     out["copy_gb_per_s"] = 2 * 8 * n / t / 1e9
     del src, dst
-    g = torch.Generator(device="cuda")
-    g.manual_seed(14017457)
-    for table_mib in (256, 4096):
-        rows = (table_mib << 20) // 16
-        table = torch.zeros(rows, dtype=torch.complex128, device="cuda")  # one 16-byte element a row
-        idx = torch.randint(0, rows, (1 << 24,), device="cuda", generator=g)
-        t = timed(lambda: table.index_select(0, idx))
-        out[f"random_16B_loads_per_s_table_{table_mib}MiB"] = idx.numel() / t
-        del table, idx
+    # random row gathers with the library's measurement kernel (hashed
+    # indices, four loads in flight per thread, 2^26 loads a launch)
+    import ctypes
+    cl = ctypes.CDLL(os.path.join(ROOT, "paper_1401_7457_amd", "libcxbwt_ceilings.so"))
+    cl.cxbwt_ceiling_gather.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64,
+                                        ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]
+    cl.cxbwt_ceiling_gather.restype = ctypes.c_int
+    table = torch.zeros(8 << 30, dtype=torch.uint8, device="cuda")
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    n_loads = 1 << 26
+    for table_mib, row_bytes in ((256, 16), (4096, 16), (8192, 16), (4096, 32), (8192, 32)):
+        rows = (table_mib << 20) // row_bytes
+        stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+        def gather():
+            rc = cl.cxbwt_ceiling_gather(ctypes.c_void_p(table.data_ptr()), rows, row_bytes, n_loads, 14017457,
+                                         ctypes.c_void_p(sink.data_ptr()), stream)
+            if rc != 0:
+                raise RuntimeError(f"cxbwt_ceiling_gather: {rc}")
+        t = timed(gather)
+        out[f"random_{row_bytes}B_loads_per_s_table_{table_mib}MiB"] = n_loads / t
+    del table, sink
     # the write pattern of a level scatter: ~400M (key u64, handle u32)
     # records in tiles of nb * r, each tile writing a run of r records to
     # each of nb evenly filled buckets at the bucket's running position.  The
@@ -630,7 +644,7 @@ def _ceilings_mode(args) -> dict:
         out[f"{name}_ms_per_400M"] = t * 1e3 * 400_000_000 / m
         out[f"{name}_gb_per_s"] = m * 24 / t / 1e9
         del pos, keys, hdl, ko, ho, t_, b_, k_
-    return {"metric": "memory-system ceilings at 1 GPU (torch kernels)", "unit": "various", "n_gpus": 1,
+    return {"metric": "memory-system ceilings at 1 GPU", "unit": "various", "n_gpus": 1,
             "data": "synthetic", "reps": reps, "ceilings": out}
 
 

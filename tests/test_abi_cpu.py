@@ -276,3 +276,19 @@ def test_autotune_shape_key_classes():
     assert a == autotune.shape_key(4_100_000, 410_000_000, 100)
     assert a != autotune.shape_key(40_000_000, 4_000_000_000, 100)
     assert a != autotune.shape_key(2_000_000, 400_000_000, 250)
+
+
+def test_ceilings_gather_library_checks_arguments_without_a_gpu():
+    """The measurement kernel of bench.py --mode ceilings is built beside the
+    library; invalid arguments are refused before any HIP call."""
+    path = os.path.join(os.path.dirname(cxbwt.LIB_PATH), "libcxbwt_ceilings.so")
+    L = ctypes.CDLL(path)
+    f = L.cxbwt_ceiling_gather
+    f.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64,
+                  ctypes.c_void_p, ctypes.c_void_p]
+    f.restype = ctypes.c_int
+    fake, sink = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000)
+    assert f(None, 1 << 20, 16, 10, 1, sink, None) == -1          # no table
+    assert f(fake, 1000, 16, 10, 1, sink, None) == -1             # rows not a power of two
+    assert f(fake, 1 << 20, 24, 10, 1, sink, None) == -1          # row size
+    assert f(ctypes.c_void_p(0x1008), 1 << 20, 16, 10, 1, sink, None) == -1  # misaligned table
