@@ -1447,6 +1447,75 @@ __device__ __forceinline__ void live_groups(LocalSmem<LI> &S, uint32_t n, uint32
   __syncthreads();
 }
 
+// Live groups of more than BIG_GROUP suffixes are sorted in place by a
+// bitonic network instead of the all-pairs ranking, whose cost grows with
+// the square of the group.  Equal ordering bits keep the suffixes in handle
+// order, which is their order in the group: the first order was read-major
+// (handles are base positions, or indices of a position-ordered table) and
+// every pass since was stable.  So the network sorts by (ordering bits,
+// handle), which are distinct, and gives the same order as a stable rank.
+constexpr uint32_t BIG_GROUP = 128;
+
+__device__ __forceinline__ bool rec_after(uint64_t ka, uint32_t ha, uint64_t kb, uint32_t hb) {
+  const uint64_t oa = order_bits(ka), ob = order_bits(kb);
+  return oa > ob || (oa == ob && ha > hb);
+}
+
+// One group of positions [a, a + m): the network for the next power of two
+// P >= m with the missing entries taken as larger than all, so that every
+// compare-exchange puts the smaller entry first and a pair reaching past the
+// group is left as it is.  Each merge of blocks of k starts by comparing
+// mirrored entries (i with the entry k - 1 - (i mod k) of its block), then
+// halves the distance.
+template <int LI>
+__device__ __forceinline__ void bitonic_group(LocalSmem<LI> &S, uint32_t a, uint32_t m, uint32_t lane) {
+  uint32_t P = 2;
+  while (P < m) P <<= 1;
+  for (uint32_t k = 2; k <= P; k <<= 1) {
+    for (uint32_t d = k >> 1; d > 0; d >>= 1) {
+      for (uint32_t q = lane; q < P / 2; q += LOCAL_WG) {
+        uint32_t i, l;
+        if (d == k >> 1) {  // mirrored pairs of a block of k
+          const uint32_t blk = q / d, off = q % d;
+          i = blk * k + off;
+          l = blk * k + (k - 1 - off);
+        } else {
+          i = (q / d) * 2 * d + (q % d);
+          l = i + d;
+        }
+        if (l < m) {
+          const uint64_t ki = S.K[a + i], kl = S.K[a + l];
+          const uint32_t hi = S.H[a + i], hl = S.H[a + l];
+          if (rec_after(ki, hi, kl, hl)) {
+            S.K[a + i] = kl;
+            S.K[a + l] = ki;
+            S.H[a + i] = hl;
+            S.H[a + l] = hi;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Every live group above BIG_GROUP suffixes, one after another.
+template <int LI>
+__device__ __forceinline__ void sort_big_groups(LocalSmem<LI> &S, uint32_t n, uint32_t lane) {
+  const uint32_t ngroups = (uint32_t)S.gr[n - 1] + 1u;
+  for (uint32_t g0 = 0; g0 < ngroups; g0 += LOCAL_WG) {
+    const uint32_t g = g0 + lane;
+    const bool big = g < ngroups && (uint32_t)S.hp[g + 1] - S.hp[g] > BIG_GROUP;
+    uint64_t todo = __ballot(big);
+    while (todo) {
+      const uint32_t b = g0 + (uint32_t)__builtin_ctzll(todo);
+      todo &= todo - 1;
+      const uint32_t x0 = S.hp[b];
+      bitonic_group(S, (uint32_t)S.live[x0], (uint32_t)S.hp[b + 1] - x0, lane);
+    }
+  }
+}
+
 // LI suffixes per lane; OCC waves per SIMD the kernel is compiled for;
 // PERSIST: a fixed grid loops over a chunk count on the device
 template <int LI, int OCC, bool PERSIST>
@@ -1458,6 +1527,10 @@ __global__ __launch_bounds__(LOCAL_WG, OCC) void k_local(
     uint8_t *__restrict__ bwt, uint64_t *__restrict__ start_row, uint32_t *status, unsigned long long *fetches,
     uint32_t n_chunks, const uint32_t *__restrict__ dev_nchunks, uint32_t first) {
   __shared__ LocalSmem<LI> S;
+  // chunks of up to twice BIG_GROUP suffixes keep the all-pairs ranking for
+  // every group (and the registers the network would take)
+  constexpr bool SORT_BIG = LI * LOCAL_WG > 2 * (int)BIG_GROUP;
+  constexpr bool SPLIT_CHUNKS = LI > 3;
   const uint32_t lane = threadIdx.x;
   const uint64_t le = lanemask_lt() | (1ull << lane);
   // chunks first + blockIdx.x (+ k * gridDim.x when PERSIST) below the count
@@ -1486,7 +1559,9 @@ __global__ __launch_bounds__(LOCAL_WG, OCC) void k_local(
   // equal (d, d + 1) digits are then sorted on their current key, and after
   // that groups are runs of equal keys, refined window by window.
   const int d0 = ch.d;
-  const bool two = d0 < 7;
+  // (chunks of up to 3 suffixes a lane hold buckets small enough that the
+  // ranking alone is cheaper than the two splits)
+  const bool two = SPLIT_CHUNKS && d0 < 7;
   if (two) {
     wave_split(S, m, d0 + 1, lane, le & ~(1ull << lane));
     wave_split(S, m, d0, lane, le & ~(1ull << lane));
@@ -1576,12 +1651,19 @@ __global__ __launch_bounds__(LOCAL_WG, OCC) void k_local(
     // multiple of 8, so (key_t & ~7) <= oj is key_t < oj + 8 and
     // (key_t & ~7) < oj is key_t < oj: one 64-bit compare per key, on the
     // raw keys (t = j adds nothing to the second count).
+    bool big_groups = false;
     for (uint32_t x = lane; x < n; x += LOCAL_WG) {
       const uint32_t j = S.live[x];
       const uint32_t g = S.gr[x];
       const uint32_t x0 = S.hp[g];
       const uint32_t a = S.live[x0];
       const uint32_t e = a + ((uint32_t)S.hp[g + 1] - x0);  // a group is a run of positions
+      if (SORT_BIG && e - a > BIG_GROUP) {
+        // sorted in place below: stays where it is for now
+        S.dst[x] = (uint16_t)j;
+        big_groups = true;
+        continue;
+      }
       const uint64_t oj = order_bits(S.K[j]);
       const uint64_t below = oj + 8;  // cannot wrap: key bits 9..8 are zero
       // four independent LDS reads per step keep the loops off the
@@ -1623,6 +1705,7 @@ __global__ __launch_bounds__(LOCAL_WG, OCC) void k_local(
       }
     }
     __syncthreads();
+    if (SORT_BIG && __ballot(big_groups)) sort_big_groups(S, n, lane);
     // new group heads inside live groups: changes of the full key
 #pragma unroll
     for (int i = 0; i < LI; ++i) {
