@@ -501,11 +501,19 @@ __global__ __launch_bounds__(64 * NW) void k_gen_scatter(const Seg *__restrict__
   const uint32_t m = (uint32_t)min((uint64_t)TL, sg.start + sg.len - t0);
   uint64_t kr[TI];
   uint32_t hr[TI], dig[TI];
+  // the records of every item are loaded before any key is formed (an item
+  // past the tile reads the last one's record, m >= 1)
+  TextRec tr[TI];
+#pragma unroll
+  for (int i = 0; i < TI; ++i) {
+    const uint32_t li = item_index<TI>(i);
+    tr[i] = text[(t0 + (li < m ? li : m - 1)) >> 4];
+  }
 #pragma unroll
   for (int i = 0; i < TI; ++i) {
     const uint32_t li = item_index<TI>(i);
     if (li < m) {
-      kr[i] = first_key(text, nb, t0 + li);
+      kr[i] = first_key_from(tr[i], nb, t0 + li);
       hr[i] = (uint32_t)(t0 + li);
       dig[i] = digit_of(kr[i], 0);
     } else {
@@ -1289,12 +1297,18 @@ __global__ __launch_bounds__(64 * NW) void k_level_scatter(const Seg *__restrict
   const int d = sg.d;
   uint64_t kr[TI];
   uint32_t hr[TI], dig[TI];
+  // every load of the tile is issued before any is used (an item past the
+  // tile reads the last one, m >= 1, and is then cleared)
 #pragma unroll
   for (int i = 0; i < TI; ++i) {
     const uint32_t li = item_index<TI>(i);
-    if (li < m) {
-      kr[i] = Ki[t0 + li];
-      hr[i] = Hi[t0 + li];
+    const uint64_t at = t0 + (li < m ? li : m - 1);
+    kr[i] = Ki[at];
+    hr[i] = Hi[at];
+  }
+#pragma unroll
+  for (int i = 0; i < TI; ++i) {
+    if (item_index<TI>(i) < m) {
       dig[i] = digit_of(kr[i], d);
     } else {
       kr[i] = 0;
@@ -1544,12 +1558,25 @@ __global__ __launch_bounds__(LOCAL_WG, OCC) void k_local(
   const uint32_t *Hg = ch.buf ? hdl1 : hdl0;
   // entry x of a list is handled by lane x % 64 in slot x / 64: neighbouring
   // lanes hold neighbouring positions, which mostly share a group
+  // every load of the chunk is issued before the first store to LDS (an
+  // entry past the chunk reads the last one, m >= 1)
+  {
+    uint64_t lk[LI];
+    uint32_t lh[LI];
 #pragma unroll
-  for (int i = 0; i < LI; ++i) {
-    const uint32_t j = i * LOCAL_WG + lane;
-    if (j < m) {
-      S.K[j] = Kg[ch.start + j];
-      S.H[j] = Hg[ch.start + j];
+    for (int i = 0; i < LI; ++i) {
+      const uint32_t j = i * LOCAL_WG + lane;
+      const uint64_t at = ch.start + (j < m ? j : m - 1);
+      lk[i] = Kg[at];
+      lh[i] = Hg[at];
+    }
+#pragma unroll
+    for (int i = 0; i < LI; ++i) {
+      const uint32_t j = i * LOCAL_WG + lane;
+      if (j < m) {
+        S.K[j] = lk[i];
+        S.H[j] = lh[i];
+      }
     }
   }
   __syncthreads();
@@ -2000,12 +2027,18 @@ __global__ __launch_bounds__(64 * NW) void k_sched_scatter(const uint64_t *__res
   const uint32_t m = (uint32_t)min((uint64_t)TL, nb - t0);
   uint64_t kr[TI];
   uint32_t hr[TI], dig[TI];
+  // every load of the tile is issued before any is used (an item past the
+  // tile reads the last one, m >= 1, and is then cleared)
 #pragma unroll
   for (int i = 0; i < TI; ++i) {
     const uint32_t li = item_index<TI>(i);
-    if (li < m) {
-      kr[i] = Ki[t0 + li];
-      hr[i] = Hi[t0 + li];
+    const uint64_t at = t0 + (li < m ? li : m - 1);
+    kr[i] = Ki[at];
+    hr[i] = Hi[at];
+  }
+#pragma unroll
+  for (int i = 0; i < TI; ++i) {
+    if (item_index<TI>(i) < m) {
       dig[i] = digit_of(kr[i], d);
     } else {
       kr[i] = 0;

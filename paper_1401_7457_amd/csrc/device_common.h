@@ -98,13 +98,16 @@ __host__ __device__ __forceinline__ uint64_t window_key(const TextRec *__restric
 }
 
 // Window-0 key of the suffix starting at base p, with its preceding symbol:
-// '$' when p starts a read, else base p-1.
-__host__ __device__ __forceinline__ uint64_t first_key(const TextRec *__restrict__ text, uint64_t nb, uint64_t p) {
-  const TextRec t = window_load(text, nb, p, 0);
+// '$' when p starts a read, else base p-1; t is the record of p (text[p/16]).
+__host__ __device__ __forceinline__ uint64_t first_key_from(const TextRec &t, uint64_t nb, uint64_t p) {
   const uint32_t o = (uint32_t)(p & 15);
   uint32_t prev3 = 4;
   if (!((t.lo >> o) & 1u)) prev3 = o ? rec_base_at(t, o - 1) : (uint32_t)(t.lo >> 42) & 3u;
   return window_combine(t, nb, p, 0, prev3);
+}
+
+__host__ __device__ __forceinline__ uint64_t first_key(const TextRec *__restrict__ text, uint64_t nb, uint64_t p) {
+  return first_key_from(window_load(text, nb, p, 0), nb, p);
 }
 
 // ---------------------------------------------------------------------------
