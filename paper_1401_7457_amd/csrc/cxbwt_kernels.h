@@ -421,19 +421,22 @@ __global__ __launch_bounds__(BLOCK) void k_gen_hist(const Seg *__restrict__ segs
   const uint64_t t1 = min(t0 + (uint64_t)tile_len, sg.start + sg.len);
   hist[threadIdx.x] = 0;
   __syncthreads();
-  // every record load of a sub-tile is issued before its first count
+  // every record load of a sub-tile is issued before its first key is formed
+  // (an item past the tile reads the last one's record, t1 > t0)
 #pragma unroll
   for (int sub = 0; sub < SUBT; ++sub) {
     const uint64_t u0 = t0 + (uint64_t)sub * BLOCK * MAX_TILE_ITEMS;
-    uint64_t kk[MAX_TILE_ITEMS];
+    TextRec tr[MAX_TILE_ITEMS];
 #pragma unroll
     for (int i = 0; i < MAX_TILE_ITEMS; ++i) {
       const uint64_t p = u0 + (uint64_t)i * BLOCK + threadIdx.x;
-      if (p < t1) kk[i] = first_key(text, nb, p);
+      tr[i] = text[(p < t1 ? p : t1 - 1) >> 4];
     }
 #pragma unroll
-    for (int i = 0; i < MAX_TILE_ITEMS; ++i)
-      if (u0 + (uint64_t)i * BLOCK + threadIdx.x < t1) atomicAdd(&hist[digit_of(kk[i], 0)], 1u);
+    for (int i = 0; i < MAX_TILE_ITEMS; ++i) {
+      const uint64_t p = u0 + (uint64_t)i * BLOCK + threadIdx.x;
+      if (p < t1) atomicAdd(&hist[digit_of(first_key_from(tr[i], nb, p), 0)], 1u);
+    }
   }
   __syncthreads();
   tile_hist[(uint64_t)tile * 256 + threadIdx.x] = hist[threadIdx.x];
@@ -565,7 +568,9 @@ __global__ __launch_bounds__(BLOCK) void k_level_hist(const Seg *__restrict__ se
   hist[threadIdx.x] = 0;
   __syncthreads();
   // all loads of a sub-tile (keys, and for a re-keyed segment handles and
-  // then records) are issued before any result is used
+  // then records) are issued before any result is used; the sub-tiles one
+  // after the other (holding both sets of keys at once costs more in
+  // occupancy than the second wait)
   uint64_t o = 0, a = ~0ull;
   // SUBT sub-tiles of BLOCK * MAX_TILE_ITEMS (two for the wide tile)
 #pragma unroll
