@@ -1651,7 +1651,9 @@ __global__ __launch_bounds__(LOCAL_WG, OCC) void k_local(
       }
       ++r;
       // fetch the next window of every live suffix, FETCH_BATCH loads in
-      // flight per lane
+      // flight per lane: the positions of a batch first (a table load in a
+      // build with wide positions), then every record load, then their use
+      // (an entry past the list loads record 0 and is not used)
       for (uint32_t x0 = 0; x0 < n; x0 += FETCH_BATCH * LOCAL_WG) {
         TextRec tr[FETCH_BATCH];
         uint32_t tp[FETCH_BATCH];
@@ -1659,11 +1661,17 @@ __global__ __launch_bounds__(LOCAL_WG, OCC) void k_local(
 #pragma unroll
         for (int i = 0; i < FETCH_BATCH; ++i) {
           const uint32_t x = x0 + i * LOCAL_WG + lane;
-          if (x < n) {
-            tp[i] = S.live[x];
-            pp[i] = position_of(pos64, S.H[tp[i]]);
-            tr[i] = window_load(text, nb, pp[i], r);
-          }
+          tp[i] = S.live[x < n ? x : 0];
+          pp[i] = S.H[tp[i]];
+        }
+        if (pos64) {
+#pragma unroll
+          for (int i = 0; i < FETCH_BATCH; ++i) pp[i] = pos64[pp[i]];
+        }
+#pragma unroll
+        for (int i = 0; i < FETCH_BATCH; ++i) {
+          const uint32_t x = x0 + i * LOCAL_WG + lane;
+          tr[i] = window_load(text, nb, x < n ? pp[i] : 0, x < n ? r : 0);
         }
 #pragma unroll
         for (int i = 0; i < FETCH_BATCH; ++i) {
