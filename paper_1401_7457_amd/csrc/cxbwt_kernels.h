@@ -1558,6 +1558,7 @@ __global__ __launch_bounds__(LOCAL_WG, OCC) void k_local(
   for (uint32_t c = first + blockIdx.x; c < n_chunks; c += gridDim.x) {
   if (PERSIST) __syncthreads();  // the previous chunk's LDS reads are done
   const Seg ch = chunks[c];
+  const CollMap cm = cmap[ch.coll];  // loaded with the chunk, used at the emit
   const uint32_t m = (uint32_t)ch.len;
   const uint64_t *Kg = ch.buf ? keys1 : keys0;
   const uint32_t *Hg = ch.buf ? hdl1 : hdl0;
@@ -1758,12 +1759,43 @@ __global__ __launch_bounds__(LOCAL_WG, OCC) void k_local(
     __syncthreads();
     fetch_round = true;
   }
-  // a4: emit
-  const CollMap cm = cmap[ch.coll];
+  // a4: emit, as emit_row does, in phases: the BWT bytes; the positions of
+  // the offset-0 suffixes (preceded by '$'); every load of their read ranks;
+  // the rows.  Entries that are not offset-0 suffixes load position 0 and
+  // write nothing.
+  {
+    const uint32_t lut = 'A' | ('C' << 8) | ('G' << 16) | ('T' << 24);
+    uint64_t ep[LI];
+    bool first[LI];
 #pragma unroll
-  for (int i = 0; i < LI; ++i) {
-    const uint32_t j = i * LOCAL_WG + lane;
-    if (j < m) emit_row(ch.start + j, cm, S.K[j], S.H[j], pos64, text, srank, bwt, start_row);
+    for (int i = 0; i < LI; ++i) {
+      const uint32_t j = i * LOCAL_WG + lane;
+      first[i] = false;
+      ep[i] = 0;
+      if (j < m) {
+        const uint32_t pv = (uint32_t)S.K[j] & 7u;
+        bwt[ch.start + j + cm.out_shift] = pv == 4 ? (uint8_t)'$' : (uint8_t)((lut >> (8 * pv)) & 0xFFu);
+        first[i] = pv == 4;
+        if (first[i]) ep[i] = S.H[j];
+      }
+    }
+    if (pos64) {
+#pragma unroll
+      for (int i = 0; i < LI; ++i) ep[i] = first[i] ? pos64[ep[i]] : 0;
+    }
+    uint64_t lo[LI];
+    uint32_t sr[LI];
+#pragma unroll
+    for (int i = 0; i < LI; ++i) {
+      lo[i] = text[ep[i] >> 4].lo;
+      sr[i] = srank[ep[i] >> 4];
+    }
+#pragma unroll
+    for (int i = 0; i < LI; ++i)
+      if (first[i]) {
+        const uint32_t rank = sr[i] + (uint32_t)__popcll(lo[i] & ((1ull << (ep[i] & 15)) - 1ull));
+        start_row[rank] = (uint64_t)((int64_t)(ch.start + i * LOCAL_WG + lane) + cm.row_shift);
+      }
   }
   if (!PERSIST) break;
   }
