@@ -30,6 +30,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+DIGIT_BITS = 8  # radix digit of every level (a wider one loses on its write pattern: --mode ceilings)
 
 WORKLOADS = {
     "plain0": (0, "plain single build: 10k reads x 100 bp, 100 kb genome, 1% subst, both strands"),
@@ -220,8 +221,8 @@ def choice_name(ch) -> str:
 
 def tuning_record(res: dict, repeats: int) -> dict:
     a, b, sched = res["choice"]
-    return {"tile_items": a, "chunk_items": b, "schedule": SCHEDULE_NAMES[sched], "repeats": repeats,
-            "ms_per_choice": {choice_name(ch): round(v, 3) for ch, v in res["ms"].items()}}
+    return {"tile_items": a, "chunk_items": b, "schedule": SCHEDULE_NAMES[sched], "digit_bits": DIGIT_BITS,
+            "repeats": repeats, "ms_per_choice": {choice_name(ch): round(v, 3) for ch, v in res["ms"].items()}}
 
 
 def _tune(args, packed, offsets, n, nb, maxlen, ws, bwt, term, pstatus, text):
@@ -231,7 +232,8 @@ def _tune(args, packed, offsets, n, nb, maxlen, ws, bwt, term, pstatus, text):
         a, b = (int(v) for v in args.tuning.split("x")[:2])
         sched = cxbwt.SCHEDULE_STRINGWORD if args.tuning.endswith("sw") else cxbwt.SCHEDULE_MSD
         autotune.apply((a, b, sched))
-        return {"tile_items": a, "chunk_items": b, "schedule": SCHEDULE_NAMES[sched], "forced": True}
+        return {"tile_items": a, "chunk_items": b, "schedule": SCHEDULE_NAMES[sched], "digit_bits": DIGIT_BITS,
+                "forced": True}
     if args.no_tune:
         return None
     cxbwt.pack(text, out=packed, status=pstatus)
