@@ -133,6 +133,36 @@ def test_identical_reads_beyond_one_workgroup():
     assert b.tobytes().decode() == "".join(ch * n for ch in single_b)
 
 
+@pytest.mark.parametrize("copies", [140, 250, 380, 500])
+def test_tie_groups_sorted_by_the_network(copies):
+    """Tie groups of 140-500 suffixes inside chunks of 384 and 512 (6 and 8
+    suffixes a lane), where groups above 128 are sorted by a bitonic network
+    on (ordering bits, handle): families of near-identical reads (a few
+    substitutions apart, so that groups split at different windows) mixed
+    with their exact copies and with random reads, for both chunk sizes."""
+    rng = np.random.default_rng(copies)
+    base = datagen.ASCII[rng.integers(0, 4, size=120)].tobytes().decode()
+    reads = []
+    for k in range(copies):
+        r = list(base)
+        if k % 3:  # two of three copies carry one substitution past the first window
+            pos = int(rng.integers(30, 120))
+            r[pos] = "ACGT"[int(rng.integers(0, 4))]
+        reads.append("".join(r)[: int(rng.integers(60, 121))])
+    reads += [datagen.ASCII[rng.integers(0, 4, size=int(rng.integers(0, 150)))].tobytes().decode()
+              for _ in range(400)]
+    order = rng.permutation(len(reads))
+    col = datagen.from_reads([reads[i] for i in order])
+    before = (cxbwt.get_tuning(), cxbwt.get_schedule())
+    try:
+        for tile, chunk in ((16, 6), (8, 8)):
+            cxbwt.set_tuning(tile, chunk)
+            _check(col, f"tie groups of {copies}, {tile}x{chunk}")
+    finally:
+        cxbwt.set_tuning(*before[0])
+        cxbwt.set_schedule(before[1])
+
+
 def test_homopolymers_beyond_one_workgroup():
     col = datagen.from_reads(["A" * 100] * 6000 + ["C" * 57] * 5000)
     _check(col, "homopolymers")
