@@ -2009,12 +2009,30 @@ __global__ __launch_bounds__(BLOCK) void k_sched_window(const TextRec *__restric
 // window's handles are the positions in order: H[j] = j).
 __global__ __launch_bounds__(BLOCK) void k_sched_gather(const uint64_t *__restrict__ keyw, uint64_t nb, bool first,
                                                         uint64_t *__restrict__ K, uint32_t *__restrict__ H) {
-  for (uint64_t j = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; j < nb; j += (uint64_t)gridDim.x * BLOCK) {
-    if (first) {
+  const uint64_t stride = (uint64_t)gridDim.x * BLOCK;
+  if (first) {
+    for (uint64_t j = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; j < nb; j += stride) {
       H[j] = (uint32_t)j;
       K[j] = keyw[j];
-    } else {
-      K[j] = keyw[H[j]];
+    }
+    return;
+  }
+  // four gathers in flight per thread: the handles, then the keys they name
+  constexpr int G = 4;
+  for (uint64_t j0 = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; j0 < nb; j0 += G * stride) {
+    uint32_t h[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const uint64_t j = j0 + g * stride;
+      h[g] = H[j < nb ? j : nb - 1];
+    }
+    uint64_t k[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) k[g] = keyw[h[g]];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const uint64_t j = j0 + g * stride;
+      if (j < nb) K[j] = k[g];
     }
   }
 }
@@ -2028,15 +2046,17 @@ __global__ __launch_bounds__(BLOCK) void k_sched_hist(const uint64_t *__restrict
   __syncthreads();
   const uint64_t t0 = (uint64_t)blockIdx.x * TL;
   constexpr int PER = TL / BLOCK;
-  uint32_t dg[PER];
+  // every key load of the tile first (an item past the end reads the last
+  // key, nb > t0), then the counts
+  uint64_t kk[PER];
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const uint64_t j = t0 + (uint64_t)i * BLOCK + threadIdx.x;
-    dg[i] = j < nb ? digit_of(K[j], d) : NODIGIT;
+    kk[i] = K[j < nb ? j : nb - 1];
   }
 #pragma unroll
   for (int i = 0; i < PER; ++i)
-    if (dg[i] != NODIGIT) atomicAdd(&hist[dg[i]], 1u);
+    if (t0 + (uint64_t)i * BLOCK + threadIdx.x < nb) atomicAdd(&hist[digit_of(kk[i], d)], 1u);
   __syncthreads();
   tile_hist[(uint64_t)blockIdx.x * 256 + threadIdx.x] = hist[threadIdx.x];
 }
