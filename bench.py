@@ -403,6 +403,72 @@ def _sweep_mode(args) -> dict:
     }
 
 
+def _ranges_mode(args) -> dict:
+    """The 4 Gbase build in key ranges (Section 3.1, Fig. 2): budgets of about
+    1/2, 1/4 and 1/8 of its suffixes, against the build of all of it at once
+    (the same instantiation): ms per step, ranges, workspace, and whether the
+    output equals the build's."""
+    import hashlib
+
+    import numpy as np
+    import torch
+
+    from paper_1401_7457_amd import autotune, cxbwt, datagen
+    k, label = WORKLOADS[args.workload]
+    col = datagen.plain_config(k)
+    n, nb, maxlen = col.n_reads, col.n_bases, col.max_read_len
+    print(f"[bench] ranges: {args.workload} reads={n} bases={nb}", file=sys.stderr, flush=True)
+    text = torch.from_numpy(col.text).cuda()
+    offsets = torch.from_numpy(col.offsets.view(np.int64)).cuda()
+    packed, _ = cxbwt.pack(text)
+    bwt = torch.empty(nb + n, dtype=torch.uint8, device="cuda")
+    term = torch.empty(n, dtype=torch.int64, device="cuda")
+    if args.tuning:
+        a, b = (int(v) for v in args.tuning.split("x")[:2])
+        autotune.apply((a, b, cxbwt.SCHEDULE_MSD))
+
+    def digest():
+        return hashlib.sha256(bwt.cpu().numpy().tobytes() + term.cpu().numpy().tobytes()).hexdigest()[:16]
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps
+
+    ws = cxbwt.alloc_workspace(n, nb, maxlen)
+    ms_all = timed(lambda: cxbwt.build(packed, offsets, n, nb, maxlen, workspace=ws, out=(bwt, term)))
+    ref = digest()
+    ws_all = ws.numel()
+    del ws
+    torch.cuda.empty_cache()
+    lines = [{"ranges": 1, "budget_suffixes": nb, "ms_per_step": ms_all, "gbases_per_s": nb / ms_all / 1e6,
+              "workspace_bytes": ws_all, "same_output": True, "form": "cxbwt_build"}]
+    for parts in (2, 4, 8):
+        m = nb // parts + 1
+        wsb = cxbwt.range_workspace_bytes(n, nb, maxlen, m)
+        ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+        ms = timed(lambda: cxbwt.build_ranges(packed, offsets, n, nb, maxlen, m, workspace=ws, out=(bwt, term)))
+        st = cxbwt.last_stats()
+        lines.append({"ranges": st["ranges"], "budget_suffixes": m, "ms_per_step": ms, "gbases_per_s": nb / ms / 1e6,
+                      "workspace_bytes": wsb, "same_output": digest() == ref, "form": "cxbwt_build_ranges"})
+        print(f"[bench] ranges budget {m}: {st['ranges']} ranges, {ms:.1f} ms/step", file=sys.stderr, flush=True)
+        del ws
+        torch.cuda.empty_cache()
+    return {
+        "metric": "BWT build Gbases/s at 1 GPU in key ranges", "value": lines[-1]["gbases_per_s"], "unit": "Gbases/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "data": "synthetic",
+        "config": {"workload": label, "reads": n, "bases": nb, "tuning": "x".join(map(str, cxbwt.get_tuning()))},
+        "lines": lines,
+    }
+
+
 def _batch_mode(args) -> dict:
     """Many collections: one batched build per wave against one build per collection."""
     import numpy as np
@@ -653,9 +719,10 @@ def _ceilings_mode(args) -> dict:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve", "sweep", "ceilings"],
+    ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve", "sweep", "ceilings", "ranges"],
                     help="plain: one collection (the headline line); batch / serve: the batched and served forms; "
-                         "sweep: 100/200/400-base reads at equal total bases")
+                         "sweep: 100/200/400-base reads at equal total bases; ranges: the --workload build in "
+                         "1/2/4/8 key ranges")
     ap.add_argument("--scale", type=float, default=0.05, help="batch/serve: size scale of the collections")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--jobs", type=int, default=60)
@@ -698,9 +765,9 @@ def main() -> int:
     cxbwt.lib()
     if args.copy_calibration_mib:
         calibration_kernels(args.copy_calibration_mib)
-    if args.mode in ("batch", "serve", "sweep", "ceilings"):
+    if args.mode in ("batch", "serve", "sweep", "ceilings", "ranges"):
         res = {"batch": _batch_mode, "serve": _serve_mode, "sweep": _sweep_mode,
-               "ceilings": _ceilings_mode}[args.mode](args)
+               "ceilings": _ceilings_mode, "ranges": _ranges_mode}[args.mode](args)
         print(json.dumps(res), flush=True)
         return 0
 
