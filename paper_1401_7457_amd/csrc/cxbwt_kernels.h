@@ -1443,29 +1443,6 @@ __device__ __forceinline__ void wave_split(LocalSmem<LI> &S, uint32_t m, int sel
   __syncthreads();
 }
 
-// Groups of the live list from the head flags of its positions: gr[x] and
-// hp[g] (hp[number of groups] = n).  One ballot per 64 entries.
-template <int LI>
-__device__ __forceinline__ void live_groups(LocalSmem<LI> &S, uint32_t n, uint32_t lane, uint64_t le) {
-  uint32_t run = 0;
-#pragma unroll
-  for (int i = 0; i < LI; ++i) {
-    const uint32_t x = i * LOCAL_WG + lane;
-    if (i * LOCAL_WG >= (int)n) break;
-    const bool in = x < n;
-    const bool h = in && S.head[S.live[x]];
-    const uint64_t hb = __ballot(h);
-    const uint32_t g = run + (uint32_t)__popcll(hb & le) - 1u;
-    if (in) {
-      S.gr[x] = (uint16_t)g;
-      if (h) S.hp[g] = (uint16_t)x;
-    }
-    run += (uint32_t)__popcll(hb);
-  }
-  if (lane == 0) S.hp[run] = (uint16_t)n;
-  __syncthreads();
-}
-
 // Live groups of more than BIG_GROUP suffixes are sorted in place by a
 // bitonic network instead of the all-pairs ranking, whose cost grows with
 // the square of the group.  Equal ordering bits keep the suffixes in handle
@@ -1622,29 +1599,41 @@ __global__ __launch_bounds__(LOCAL_WG, OCC) void k_local(
     // entry is alone in its group when it and the next live entry are both
     // heads; the other test is the same for every member of a group of
     // equal keys, so whole groups stay or go.
-    uint32_t kept = 0;
+    // The groups of the kept list are made in the same pass: a group is kept
+    // or dropped whole, so its head is the first kept entry of it; gr[x] is
+    // the group of kept entry x and hp[g] its first entry (hp[groups] = n).
+    uint32_t kept = 0, run = 0;
 #pragma unroll
     for (int i = 0; i < LI; ++i) {
       if (i * LOCAL_WG >= (int)n) break;
       const uint32_t x = i * LOCAL_WG + lane;
-      bool keep = false;
+      bool keep = false, hd = false;
       uint16_t pos = 0;
       if (x < n) {
         pos = S.live[x];
+        hd = S.head[pos];
         // entry x + 1 is read before any slot writes an index above x
-        const bool alone = S.head[pos] && (x + 1 >= n || S.head[S.live[x + 1]]);
+        const bool alone = hd && (x + 1 >= n || S.head[S.live[x + 1]]);
         keep = !alone && (!fetch_round || clamp_of(S.K[pos]) == (uint32_t)W);
       }
       const uint64_t kb = __ballot(keep);
+      const uint64_t hb = __ballot(keep && hd);
       // compaction moves entries down only, so slot i never overwrites an
       // entry a later slot still has to read
-      if (keep) S.live[kept + (uint32_t)__popcll(kb & (le >> 1))] = pos;
+      if (keep) {
+        const uint32_t xn = kept + (uint32_t)__popcll(kb & (le >> 1));
+        const uint32_t g = run + (uint32_t)__popcll(hb & le) - 1u;
+        S.live[xn] = pos;
+        S.gr[xn] = (uint16_t)g;
+        if (hd) S.hp[g] = (uint16_t)xn;
+      }
       kept += (uint32_t)__popcll(kb);
+      run += (uint32_t)__popcll(hb);
     }
     n = kept;
     if (n == 0) break;
+    if (lane == 0) S.hp[run] = (uint16_t)n;
     __syncthreads();
-    live_groups(S, n, lane, le);
     if (fetch_round) {
       if (r + 1 > rmax) {
         if (lane == 0) atomicOr(status, ST_WINDOW_BOUND);
