@@ -1409,13 +1409,7 @@ __device__ __forceinline__ void wave_split(LocalSmem<LI> &S, uint32_t m, int sel
     }
     if (i * LOCAL_WG >= (int)m) continue;
     // rank among the lanes of this slot with the same digit
-    uint64_t peers = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const bool bit = (dig[i] >> b) & 1u;
-      const uint64_t v = __ballot(bit);
-      peers &= bit ? v : ~v;
-    }
+    const uint64_t peers = wave_match8(dig[i], __ballot(valid));
     if (valid) {
       const uint32_t before = S.cnt[dig[i]];
       pos[i] = before + (uint32_t)__popcll(peers & lt);

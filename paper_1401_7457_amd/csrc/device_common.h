@@ -199,6 +199,22 @@ __device__ __forceinline__ uint32_t item_index(int i) {
   return (uint32_t)((threadIdx.x >> 6) * (64 * NI) + i * 64) + lane_id();
 }
 
+// The lanes among `live` whose 8-bit value d equals this lane's: one ballot
+// per bit, each lane keeping the lanes that agree with its own bit.  The bit
+// is sign-extended to a 32-bit mask t (all ones when set), so the agreeing
+// lanes are ~(ballot ^ t), one three-input bit operation per mask half.
+__device__ __forceinline__ uint64_t wave_match8(uint32_t d, uint64_t live) {
+  uint32_t lo = (uint32_t)live, hi = (uint32_t)(live >> 32);
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const uint32_t t = (uint32_t)((int32_t)(d << (31 - b)) >> 31);
+    const uint64_t v = __ballot(t != 0u);
+    lo &= ~((uint32_t)v ^ t);
+    hi &= ~((uint32_t)(v >> 32) ^ t);
+  }
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // Stable 256-way split of up to 64*NW*NI items held in registers by a
 // workgroup of NW waves (layout of item_index<NI>).  On return pos[i] is the
 // destination of item i in [0, count) and dstart[d] the first destination of
@@ -218,13 +234,7 @@ __device__ __forceinline__ void block_multisplit(const uint32_t (&dig)[NI], uint
   for (int i = 0; i < NI; ++i) {
     const uint32_t d = dig[i];
     const bool valid = d != NODIGIT;
-    uint64_t peers = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const uint64_t v = __ballot(bit);
-      peers &= bit ? v : ~v;
-    }
+    const uint64_t peers = wave_match8(d, __ballot(valid));
     if (valid) {
       const uint32_t before = wc[d];
       pos[i] = before + (uint32_t)__popcll(peers & lt);
