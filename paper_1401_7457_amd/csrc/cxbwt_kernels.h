@@ -1596,19 +1596,32 @@ __global__ __launch_bounds__(LOCAL_WG, OCC) void k_local(
     // The groups of the kept list are made in the same pass: a group is kept
     // or dropped whole, so its head is the first kept entry of it; gr[x] is
     // the group of kept entry x and hp[g] its first entry (hp[groups] = n).
+    // After a sort the heads of the new groups are found here too: a live
+    // entry that is not a head has its group's entry at the position before
+    // it, and starts a new group where the two keys differ.  An entry that
+    // is not a head and follows entry x in the list is at the position after
+    // it.  A new head is written for the later rounds; every lane that reads
+    // that flag in this pass finds the same result from the keys.
     uint32_t kept = 0, run = 0;
 #pragma unroll
     for (int i = 0; i < LI; ++i) {
       if (i * LOCAL_WG >= (int)n) break;
       const uint32_t x = i * LOCAL_WG + lane;
-      bool keep = false, hd = false;
+      bool keep = false, hd = false, fresh = false;
       uint16_t pos = 0;
       if (x < n) {
         pos = S.live[x];
+        const uint64_t kp = S.K[pos];
         hd = S.head[pos];
+        if (fetch_round && !hd) fresh = hd = order_bits(kp) != order_bits(S.K[pos - 1]);
         // entry x + 1 is read before any slot writes an index above x
-        const bool alone = hd && (x + 1 >= n || S.head[S.live[x + 1]]);
-        keep = !alone && (!fetch_round || clamp_of(S.K[pos]) == (uint32_t)W);
+        bool next_hd = true;
+        if (x + 1 < n) {
+          const uint32_t p1 = S.live[x + 1];
+          next_hd = S.head[p1];
+          if (fetch_round && !next_hd) next_hd = order_bits(S.K[p1]) != order_bits(kp);
+        }
+        keep = !(hd && next_hd) && (!fetch_round || clamp_of(kp) == (uint32_t)W);
       }
       const uint64_t kb = __ballot(keep);
       const uint64_t hb = __ballot(keep && hd);
@@ -1620,6 +1633,7 @@ __global__ __launch_bounds__(LOCAL_WG, OCC) void k_local(
         S.live[xn] = pos;
         S.gr[xn] = (uint16_t)g;
         if (hd) S.hp[g] = (uint16_t)xn;
+        if (fresh) S.head[pos] = 1;
       }
       kept += (uint32_t)__popcll(kb);
       run += (uint32_t)__popcll(hb);
@@ -1730,16 +1744,8 @@ __global__ __launch_bounds__(LOCAL_WG, OCC) void k_local(
     }
     __syncthreads();
     if (SORT_BIG && __ballot(big_groups)) sort_big_groups(S, n, lane);
-    // new group heads inside live groups: changes of the full key
-#pragma unroll
-    for (int i = 0; i < LI; ++i) {
-      const uint32_t x = i * LOCAL_WG + lane;
-      if (i * LOCAL_WG >= (int)n) break;
-      if (x >= n) continue;
-      const uint32_t j = S.live[x];
-      if (!S.head[j] && order_bits(S.K[j]) != order_bits(S.K[j - 1])) S.head[j] = 1;
-    }
-    __syncthreads();
+    // (the new group heads, changes of the full key, are found by the next
+    // pass over the list)
     fetch_round = true;
   }
   // a4: emit, as emit_row does, in phases: the BWT bytes; the positions of
