@@ -1506,6 +1506,27 @@ __device__ __forceinline__ void sort_big_groups(LocalSmem<LI> &S, uint32_t n, ui
   }
 }
 
+// #{t in [a, j) : k_t < below} + #{t in [j, e) : k_t < oj} for the keys
+// k_t = p0[STRIDE * t] of one group.  The LDS address is the loop variable,
+// tested against a bound three entries early: one add and one compare per
+// step of four independent reads.
+template <typename T, int STRIDE>
+__device__ __forceinline__ uint32_t count_below(const T *p0, uint32_t a, uint32_t j, uint32_t e, T below, T oj) {
+  uint32_t c = 0;
+  const T *p = p0 + STRIDE * a;
+  const T *const pj = p0 + STRIDE * j, *const pe = p0 + STRIDE * e;
+  const T *const pj3 = p0 + STRIDE * (j >= 3 ? j - 3 : 0), *const pe3 = p0 + STRIDE * (e >= 3 ? e - 3 : 0);
+  for (; p < pj3; p += 4 * STRIDE)
+    c += (uint32_t)(p[0] < below) + (uint32_t)(p[STRIDE] < below) + (uint32_t)(p[2 * STRIDE] < below) +
+         (uint32_t)(p[3 * STRIDE] < below);
+  for (; p < pj; p += STRIDE) c += (uint32_t)(*p < below);
+  for (; p < pe3; p += 4 * STRIDE)
+    c += (uint32_t)(p[0] < oj) + (uint32_t)(p[STRIDE] < oj) + (uint32_t)(p[2 * STRIDE] < oj) +
+         (uint32_t)(p[3 * STRIDE] < oj);
+  for (; p < pe; p += STRIDE) c += (uint32_t)(*p < oj);
+  return c;
+}
+
 // LI suffixes per lane; OCC waves per SIMD the kernel is compiled for;
 // PERSIST: a fixed grid loops over a chunk count on the device
 template <int LI, int OCC, bool PERSIST>
@@ -1689,7 +1710,11 @@ __global__ __launch_bounds__(LOCAL_WG, OCC) void k_local(
     // multiple of 8, so (key_t & ~7) <= oj is key_t < oj + 8 and
     // (key_t & ~7) < oj is key_t < oj: one 64-bit compare per key, on the
     // raw keys (t = j adds nothing to the second count).
+    // In the first sort after two splits from digit d >= 2 every group
+    // agrees in digits 0..3, the high words of its keys: the low words decide
+    // (oj + 8 does not carry out of them, its bits 9..8 being zero).
     bool big_groups = false;
+    const bool low_words = !fetch_round && two && d0 >= 2;
     for (uint32_t x = lane; x < n; x += LOCAL_WG) {
       const uint32_t j = S.live[x];
       const uint32_t g = S.gr[x];
@@ -1707,15 +1732,22 @@ __global__ __launch_bounds__(LOCAL_WG, OCC) void k_local(
       // four independent LDS reads per step keep the loops off the
       // load-latency chain
       uint32_t c = 0;
-      uint32_t t = a;
-      for (; t + 4 <= j; t += 4)
-        c += (uint32_t)(S.K[t] < below) + (uint32_t)(S.K[t + 1] < below) + (uint32_t)(S.K[t + 2] < below) +
-             (uint32_t)(S.K[t + 3] < below);
-      for (; t < j; ++t) c += (uint32_t)(S.K[t] < below);
-      for (; t + 4 <= e; t += 4)
-        c += (uint32_t)(S.K[t] < oj) + (uint32_t)(S.K[t + 1] < oj) + (uint32_t)(S.K[t + 2] < oj) +
-             (uint32_t)(S.K[t + 3] < oj);
-      for (; t < e; ++t) c += (uint32_t)(S.K[t] < oj);
+      if (low_words) {
+        c = count_below<uint32_t, 2>((const uint32_t *)S.K, a, j, e, (uint32_t)below, (uint32_t)oj);
+      } else if (LI > 3) {
+        c = count_below<uint64_t, 1>(S.K, a, j, e, below, oj);
+      } else {
+        // (small chunks, small groups: index loops measure faster here)
+        uint32_t t = a;
+        for (; t + 4 <= j; t += 4)
+          c += (uint32_t)(S.K[t] < below) + (uint32_t)(S.K[t + 1] < below) + (uint32_t)(S.K[t + 2] < below) +
+               (uint32_t)(S.K[t + 3] < below);
+        for (; t < j; ++t) c += (uint32_t)(S.K[t] < below);
+        for (; t + 4 <= e; t += 4)
+          c += (uint32_t)(S.K[t] < oj) + (uint32_t)(S.K[t + 1] < oj) + (uint32_t)(S.K[t + 2] < oj) +
+               (uint32_t)(S.K[t + 3] < oj);
+        for (; t < e; ++t) c += (uint32_t)(S.K[t] < oj);
+      }
       S.dst[x] = (uint16_t)(a + c);
     }
     __syncthreads();
