@@ -1444,7 +1444,7 @@ __device__ __forceinline__ void wave_split(LocalSmem<LI> &S, uint32_t m, int sel
 // (handles are base positions, or indices of a position-ordered table) and
 // every pass since was stable.  So the network sorts by (ordering bits,
 // handle), which are distinct, and gives the same order as a stable rank.
-constexpr uint32_t BIG_GROUP = 128;
+constexpr uint32_t BIG_GROUP = 96;
 
 __device__ __forceinline__ bool rec_after(uint64_t ka, uint32_t ha, uint64_t kb, uint32_t hb) {
   const uint64_t oa = order_bits(ka), ob = order_bits(kb);
@@ -1588,8 +1588,11 @@ __global__ __launch_bounds__(LOCAL_WG, OCC) void k_local(
   // ranking alone is cheaper than the two splits)
   const bool two = SPLIT_CHUNKS && d0 < 7;
   if (two) {
+    // a chunk of one bucket (its first and last suffixes share digit d) is
+    // ordered by both digits after the first split
+    const bool one_bucket = !ch.unsplit && digit_of(S.K[0], d0) == digit_of(S.K[m - 1], d0);
     wave_split(S, m, d0 + 1, lane, le & ~(1ull << lane));
-    wave_split(S, m, d0, lane, le & ~(1ull << lane));
+    if (!one_bucket) wave_split(S, m, d0, lane, le & ~(1ull << lane));
   }
 #pragma unroll
   for (int i = 0; i < LI; ++i) {

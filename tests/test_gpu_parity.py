@@ -133,10 +133,10 @@ def test_identical_reads_beyond_one_workgroup():
     assert b.tobytes().decode() == "".join(ch * n for ch in single_b)
 
 
-@pytest.mark.parametrize("copies", [140, 250, 380, 500])
+@pytest.mark.parametrize("copies", [110, 140, 250, 380, 500])
 def test_tie_groups_sorted_by_the_network(copies):
-    """Tie groups of 140-500 suffixes inside chunks of 384 and 512 (6 and 8
-    suffixes a lane), where groups above 128 are sorted by a bitonic network
+    """Tie groups of 110-500 suffixes inside chunks of 384 and 512 (6 and 8
+    suffixes a lane), where groups above 96 are sorted by a bitonic network
     on (ordering bits, handle): families of near-identical reads (a few
     substitutions apart, so that groups split at different windows) mixed
     with their exact copies and with random reads, for both chunk sizes."""
