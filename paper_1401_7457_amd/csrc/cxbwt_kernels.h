@@ -1594,78 +1594,115 @@ __global__ __launch_bounds__(LOCAL_WG, OCC) void k_local(
     wave_split(S, m, d0 + 1, lane, le & ~(1ull << lane));
     if (!one_bucket) wave_split(S, m, d0, lane, le & ~(1ull << lane));
   }
-#pragma unroll
-  for (int i = 0; i < LI; ++i) {
-    const uint32_t j = i * LOCAL_WG + lane;
-    if (j < m) {
-      bool h = j == 0;
-      if (!h && two) h = digit_of(S.K[j], d0) != digit_of(S.K[j - 1], d0) ||
-                         digit_of(S.K[j], d0 + 1) != digit_of(S.K[j - 1], d0 + 1);
-      else if (!h) h = !ch.unsplit && digit_of(S.K[j], d0) != digit_of(S.K[j - 1], d0);
-      S.head[j] = h;
-      S.live[j] = (uint16_t)j;
-    }
-  }
-  __syncthreads();
-  uint32_t n = m;  // live-list length
-  uint32_t r = ch.r;
-  bool fetch_round = false;
-  for (;;) {
-    // drop the finished groups: single suffixes, and (after the first sort)
-    // runs of equal keys that end inside the window, i.e. identical suffixes.
-    // A group is a run of live entries from a head to the next head, so an
-    // entry is alone in its group when it and the next live entry are both
-    // heads; the other test is the same for every member of a group of
-    // equal keys, so whole groups stay or go.
-    // The groups of the kept list are made in the same pass: a group is kept
-    // or dropped whole, so its head is the first kept entry of it; gr[x] is
-    // the group of kept entry x and hp[g] its first entry (hp[groups] = n).
-    // After a sort the heads of the new groups are found here too: a live
-    // entry that is not a head has its group's entry at the position before
-    // it, and starts a new group where the two keys differ.  An entry that
-    // is not a head and follows entry x in the list is at the position after
-    // it.  A new head is written for the later rounds; every lane that reads
-    // that flag in this pass finds the same result from the keys.
-    uint32_t kept = 0, run = 0;
+  // The first groups: runs of equal digits d and d + 1 after two splits, of
+  // equal digit d in a chunk of buckets, the whole chunk when unsplit; a
+  // suffix alone in its group is finished.  The kept suffixes form the live
+  // list (positions ascending): gr[x] is the group of entry x, hp[g] the
+  // first entry of group g (hp[groups] = n), head[j] marks group starts.
+  // (In chunks of 3 a lane the first drop is left to the loop, with a pass
+  // of its own for the heads: that measures faster there.)
+  const uint64_t hmask = two ? (digit_mask(d0) | digit_mask(d0 + 1)) : (ch.unsplit ? 0ull : digit_mask(d0));
+  uint32_t n = 0;  // live-list length
+  if (!SPLIT_CHUNKS) {
 #pragma unroll
     for (int i = 0; i < LI; ++i) {
-      if (i * LOCAL_WG >= (int)n) break;
-      const uint32_t x = i * LOCAL_WG + lane;
-      bool keep = false, hd = false, fresh = false;
-      uint16_t pos = 0;
-      if (x < n) {
-        pos = S.live[x];
-        const uint64_t kp = S.K[pos];
-        hd = S.head[pos];
-        if (fetch_round && !hd) fresh = hd = order_bits(kp) != order_bits(S.K[pos - 1]);
-        // entry x + 1 is read before any slot writes an index above x
-        bool next_hd = true;
-        if (x + 1 < n) {
-          const uint32_t p1 = S.live[x + 1];
-          next_hd = S.head[p1];
-          if (fetch_round && !next_hd) next_hd = order_bits(S.K[p1]) != order_bits(kp);
-        }
-        keep = !(hd && next_hd) && (!fetch_round || clamp_of(kp) == (uint32_t)W);
+      const uint32_t j = i * LOCAL_WG + lane;
+      if (j < m) {
+        S.head[j] = j == 0 || (!ch.unsplit && digit_of(S.K[j], d0) != digit_of(S.K[j - 1], d0));
+        S.live[j] = (uint16_t)j;
+      }
+    }
+    n = m;
+  } else {
+    uint32_t run = 0;
+#pragma unroll
+    for (int i = 0; i < LI; ++i) {
+      if (i * LOCAL_WG >= (int)m) break;
+      const uint32_t j = i * LOCAL_WG + lane;
+      bool keep = false, h = false;
+      if (j < m) {
+        const uint64_t kj = S.K[j];
+        h = j == 0 || ((kj ^ S.K[j - 1]) & hmask) != 0;
+        const bool hn = j + 1 >= m || ((S.K[j + 1] ^ kj) & hmask) != 0;
+        keep = !(h && hn);
+        S.head[j] = h;
       }
       const uint64_t kb = __ballot(keep);
-      const uint64_t hb = __ballot(keep && hd);
-      // compaction moves entries down only, so slot i never overwrites an
-      // entry a later slot still has to read
+      const uint64_t hb = __ballot(keep && h);
       if (keep) {
-        const uint32_t xn = kept + (uint32_t)__popcll(kb & (le >> 1));
+        const uint32_t xn = n + (uint32_t)__popcll(kb & (le >> 1));
         const uint32_t g = run + (uint32_t)__popcll(hb & le) - 1u;
-        S.live[xn] = pos;
+        S.live[xn] = (uint16_t)j;
         S.gr[xn] = (uint16_t)g;
-        if (hd) S.hp[g] = (uint16_t)xn;
-        if (fresh) S.head[pos] = 1;
+        if (h) S.hp[g] = (uint16_t)xn;
       }
-      kept += (uint32_t)__popcll(kb);
+      n += (uint32_t)__popcll(kb);
       run += (uint32_t)__popcll(hb);
     }
-    n = kept;
-    if (n == 0) break;
     if (lane == 0) S.hp[run] = (uint16_t)n;
-    __syncthreads();
+  }
+  __syncthreads();
+  uint32_t r = ch.r;
+  bool fetch_round = false;  // every round after the first sort fetches a window
+  for (;;) {
+    if (SPLIT_CHUNKS && !fetch_round) {
+      if (n == 0) break;
+    } else {
+      // drop the finished groups: single suffixes, and (after a sort) runs of
+      // equal keys that end inside the window, i.e. identical suffixes.  A group is a
+      // run of live entries from a head to the next head, so an entry is
+      // alone in its group when it and the next live entry are both heads;
+      // the other test is the same for every member of a group of equal
+      // keys, so whole groups stay or go.  The groups of the kept list are
+      // made in the same pass (a group is kept or dropped whole, so its head
+      // is its first kept entry).  The heads of the groups the last sort
+      // made are found here too: a live entry that is not a head has its
+      // group's entry at the position before it, and starts a new group
+      // where the two keys differ; an entry that is not a head and follows
+      // entry x in the list is at the position after it.  A new head is
+      // written for the later rounds; every lane that reads that flag in
+      // this pass finds the same result from the keys.
+      uint32_t kept = 0, run = 0;
+#pragma unroll
+      for (int i = 0; i < LI; ++i) {
+        if (i * LOCAL_WG >= (int)n) break;
+        const uint32_t x = i * LOCAL_WG + lane;
+        bool keep = false, hd = false, fresh = false;
+        uint16_t pos = 0;
+        if (x < n) {
+          pos = S.live[x];
+          const uint64_t kp = S.K[pos];
+          hd = S.head[pos];
+          if (fetch_round && !hd) fresh = hd = order_bits(kp) != order_bits(S.K[pos - 1]);
+          // entry x + 1 is read before any slot writes an index above x
+          bool next_hd = true;
+          if (x + 1 < n) {
+            const uint32_t p1 = S.live[x + 1];
+            next_hd = S.head[p1];
+            if (fetch_round && !next_hd) next_hd = order_bits(S.K[p1]) != order_bits(kp);
+          }
+          keep = !(hd && next_hd) && (!fetch_round || clamp_of(kp) == (uint32_t)W);
+        }
+        const uint64_t kb = __ballot(keep);
+        const uint64_t hb = __ballot(keep && hd);
+        // compaction moves entries down only, so slot i never overwrites an
+        // entry a later slot still has to read
+        if (keep) {
+          const uint32_t xn = kept + (uint32_t)__popcll(kb & (le >> 1));
+          const uint32_t g = run + (uint32_t)__popcll(hb & le) - 1u;
+          S.live[xn] = pos;
+          S.gr[xn] = (uint16_t)g;
+          if (hd) S.hp[g] = (uint16_t)xn;
+          if (fresh) S.head[pos] = 1;
+        }
+        kept += (uint32_t)__popcll(kb);
+        run += (uint32_t)__popcll(hb);
+      }
+      n = kept;
+      if (n == 0) break;
+      if (lane == 0) S.hp[run] = (uint16_t)n;
+      __syncthreads();
+    }
     if (fetch_round) {
       if (r + 1 > rmax) {
         if (lane == 0) atomicOr(status, ST_WINDOW_BOUND);
