@@ -498,11 +498,11 @@ int launch_local(const Buffers &B, const Tuning &tu, uint64_t nb, uint32_t rmax,
                                                             0);                                                  \
     }                                                                                                            \
   } while (0)
-  // waves per SIMD: the most that neither spill much nor lose time (measured:
-  // 8 per lane at 4, 6 per lane at 4 (5 spills 14 registers and is slower),
-  // 3 per lane at 7 (8 spills and is slower))
+  // waves per SIMD the register allocation is held to: 8 per lane at 4, 6 per
+  // lane at 6 (70 registers; the LDS of a 384-suffix chunk, 6.4 KB, also
+  // allows six), 3 per lane at 7 (8 spills and is slower)
   if (tu.chunk_items == 8) CX_LOCAL(8, 4, 3);
-  else if (tu.chunk_items == 6) CX_LOCAL(6, 4, 4);
+  else if (tu.chunk_items == 6) CX_LOCAL(6, 6, 4);
   else CX_LOCAL(3, 7, 5);
 #undef CX_LOCAL
   CX_LAUNCHED();

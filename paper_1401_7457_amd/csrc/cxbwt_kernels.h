@@ -1367,6 +1367,7 @@ __global__ __launch_bounds__(BLOCK) void k_emit_final(const Seg *__restrict__ se
 // groups that are not finished), so the rounds that refine a few tied
 // groups cost little.
 // ---------------------------------------------------------------------------
+// (about 6.4 KB for 384 suffixes: six one-wave workgroups per SIMD)
 template <int LI>
 struct LocalSmem {
   static constexpr int CHUNK = LOCAL_WG * LI;
@@ -1374,18 +1375,26 @@ struct LocalSmem {
   uint32_t H[CHUNK];  // handle of each position
   union {
     struct {
-      uint16_t live[CHUNK];    // live positions, ascending
-      uint16_t gr[CHUNK];      // group of each live-list entry
-      uint16_t hp[CHUNK + 1];  // first live-list entry of each group
-      uint16_t dst[CHUNK];     // new position of each live-list entry
+      uint16_t live[CHUNK];  // live positions, ascending
+      // group of each live-list entry; while a sort moves the entries, the
+      // entry's new position (each entry's own lane reads the group first)
+      uint16_t gr[CHUNK];
+      // first live-list entry of each group, then the list length: a kept
+      // group has two entries or more
+      uint16_t hp[CHUNK / 2 + 1];
     };
-    struct {                   // while the chunk is split by digits
-      uint32_t cnt[256];
-      uint32_t dstart[256];
+    struct {  // while the chunk is split by digits
+      uint16_t cnt[256];
+      uint16_t dstart[256];
     };
   };
-  uint8_t head[CHUNK];  // position starts a group
+  uint32_t headw[CHUNK / 32];  // bit j % 32 of word j / 32: position j starts a group
 };
+
+template <int LI>
+__device__ __forceinline__ bool head_at(const LocalSmem<LI> &S, uint32_t j) {
+  return (S.headw[j >> 5] >> (j & 31u)) & 1u;
+}
 
 constexpr int FETCH_BATCH = 2;  // window loads in flight per lane
 
@@ -1491,8 +1500,7 @@ __device__ __forceinline__ void bitonic_group(LocalSmem<LI> &S, uint32_t a, uint
 
 // Every live group above BIG_GROUP suffixes, one after another.
 template <int LI>
-__device__ __forceinline__ void sort_big_groups(LocalSmem<LI> &S, uint32_t n, uint32_t lane) {
-  const uint32_t ngroups = (uint32_t)S.gr[n - 1] + 1u;
+__device__ __forceinline__ void sort_big_groups(LocalSmem<LI> &S, uint32_t ngroups, uint32_t lane) {
   for (uint32_t g0 = 0; g0 < ngroups; g0 += LOCAL_WG) {
     const uint32_t g = g0 + lane;
     const bool big = g < ngroups && (uint32_t)S.hp[g + 1] - S.hp[g] > BIG_GROUP;
@@ -1602,14 +1610,21 @@ __global__ __launch_bounds__(LOCAL_WG, OCC) void k_local(
   // (In chunks of 3 a lane the first drop is left to the loop, with a pass
   // of its own for the heads: that measures faster there.)
   const uint64_t hmask = two ? (digit_mask(d0) | digit_mask(d0 + 1)) : (ch.unsplit ? 0ull : digit_mask(d0));
-  uint32_t n = 0;  // live-list length
+  uint32_t n = 0;        // live-list length
+  uint32_t ngroups = 0;  // groups of the live list
   if (!SPLIT_CHUNKS) {
 #pragma unroll
     for (int i = 0; i < LI; ++i) {
       const uint32_t j = i * LOCAL_WG + lane;
+      bool h = false;
       if (j < m) {
-        S.head[j] = j == 0 || (!ch.unsplit && digit_of(S.K[j], d0) != digit_of(S.K[j - 1], d0));
+        h = j == 0 || (!ch.unsplit && digit_of(S.K[j], d0) != digit_of(S.K[j - 1], d0));
         S.live[j] = (uint16_t)j;
+      }
+      const uint64_t hm = __ballot(h);
+      if (lane == 0) {
+        S.headw[2 * i] = (uint32_t)hm;
+        S.headw[2 * i + 1] = (uint32_t)(hm >> 32);
       }
     }
     n = m;
@@ -1625,7 +1640,11 @@ __global__ __launch_bounds__(LOCAL_WG, OCC) void k_local(
         h = j == 0 || ((kj ^ S.K[j - 1]) & hmask) != 0;
         const bool hn = j + 1 >= m || ((S.K[j + 1] ^ kj) & hmask) != 0;
         keep = !(h && hn);
-        S.head[j] = h;
+      }
+      const uint64_t hm = __ballot(h);
+      if (lane == 0) {
+        S.headw[2 * i] = (uint32_t)hm;
+        S.headw[2 * i + 1] = (uint32_t)(hm >> 32);
       }
       const uint64_t kb = __ballot(keep);
       const uint64_t hb = __ballot(keep && h);
@@ -1640,6 +1659,7 @@ __global__ __launch_bounds__(LOCAL_WG, OCC) void k_local(
       run += (uint32_t)__popcll(hb);
     }
     if (lane == 0) S.hp[run] = (uint16_t)n;
+    ngroups = run;
   }
   __syncthreads();
   uint32_t r = ch.r;
@@ -1672,13 +1692,13 @@ __global__ __launch_bounds__(LOCAL_WG, OCC) void k_local(
         if (x < n) {
           pos = S.live[x];
           const uint64_t kp = S.K[pos];
-          hd = S.head[pos];
+          hd = head_at(S, pos);
           if (fetch_round && !hd) fresh = hd = order_bits(kp) != order_bits(S.K[pos - 1]);
           // entry x + 1 is read before any slot writes an index above x
           bool next_hd = true;
           if (x + 1 < n) {
             const uint32_t p1 = S.live[x + 1];
-            next_hd = S.head[p1];
+            next_hd = head_at(S, p1);
             if (fetch_round && !next_hd) next_hd = order_bits(S.K[p1]) != order_bits(kp);
           }
           keep = !(hd && next_hd) && (!fetch_round || clamp_of(kp) == (uint32_t)W);
@@ -1693,12 +1713,13 @@ __global__ __launch_bounds__(LOCAL_WG, OCC) void k_local(
           S.live[xn] = pos;
           S.gr[xn] = (uint16_t)g;
           if (hd) S.hp[g] = (uint16_t)xn;
-          if (fresh) S.head[pos] = 1;
+          if (fresh) atomicOr(&S.headw[pos >> 5], 1u << (pos & 31u));
         }
         kept += (uint32_t)__popcll(kb);
         run += (uint32_t)__popcll(hb);
       }
       n = kept;
+      ngroups = run;
       if (n == 0) break;
       if (lane == 0) S.hp[run] = (uint16_t)n;
       __syncthreads();
@@ -1763,7 +1784,7 @@ __global__ __launch_bounds__(LOCAL_WG, OCC) void k_local(
       const uint32_t e = a + ((uint32_t)S.hp[g + 1] - x0);  // a group is a run of positions
       if (SORT_BIG && e - a > BIG_GROUP) {
         // sorted in place below: stays where it is for now
-        S.dst[x] = (uint16_t)j;
+        S.gr[x] = (uint16_t)j;
         big_groups = true;
         continue;
       }
@@ -1788,7 +1809,7 @@ __global__ __launch_bounds__(LOCAL_WG, OCC) void k_local(
                (uint32_t)(S.K[t + 3] < oj);
         for (; t < e; ++t) c += (uint32_t)(S.K[t] < oj);
       }
-      S.dst[x] = (uint16_t)(a + c);
+      S.gr[x] = (uint16_t)(a + c);
     }
     __syncthreads();
     {
@@ -1801,7 +1822,7 @@ __global__ __launch_bounds__(LOCAL_WG, OCC) void k_local(
           const uint32_t j = S.live[x];
           sk[i] = S.K[j];
           sh[i] = S.H[j];
-          sd[i] = S.dst[x];
+          sd[i] = S.gr[x];
         }
       }
       __syncthreads();
@@ -1815,7 +1836,7 @@ __global__ __launch_bounds__(LOCAL_WG, OCC) void k_local(
       }
     }
     __syncthreads();
-    if (SORT_BIG && __ballot(big_groups)) sort_big_groups(S, n, lane);
+    if (SORT_BIG && __ballot(big_groups)) sort_big_groups(S, ngroups, lane);
     // (the new group heads, changes of the full key, are found by the next
     // pass over the list)
     fetch_round = true;
