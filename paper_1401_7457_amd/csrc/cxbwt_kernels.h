@@ -1606,7 +1606,8 @@ __global__ __launch_bounds__(LOCAL_WG, OCC) void k_local(
   // equal digit d in a chunk of buckets, the whole chunk when unsplit; a
   // suffix alone in its group is finished.  The kept suffixes form the live
   // list (positions ascending): gr[x] is the group of entry x, hp[g] the
-  // first entry of group g (hp[groups] = n), head[j] marks group starts.
+  // first entry of group g (hp[groups] = n), bit j of headw marks a group
+  // starting at position j.
   // (In chunks of 3 a lane the first drop is left to the loop, with a pass
   // of its own for the heads: that measures faster there.)
   const uint64_t hmask = two ? (digit_mask(d0) | digit_mask(d0 + 1)) : (ch.unsplit ? 0ull : digit_mask(d0));
@@ -1668,10 +1669,10 @@ __global__ __launch_bounds__(LOCAL_WG, OCC) void k_local(
     if (SPLIT_CHUNKS && !fetch_round) {
       if (n == 0) break;
     } else {
-      // drop the finished groups: single suffixes, and (after a sort) runs of
-      // equal keys that end inside the window, i.e. identical suffixes.  A group is a
-      // run of live entries from a head to the next head, so an entry is
-      // alone in its group when it and the next live entry are both heads;
+      // drop the finished groups: single suffixes, and (after a sort) runs
+      // of equal keys that end inside the window, i.e. identical suffixes.
+      // A group is a run of live entries from a head to the next head, so an
+      // entry is alone in its group when it and the next live entry are both heads;
       // the other test is the same for every member of a group of equal
       // keys, so whole groups stay or go.  The groups of the kept list are
       // made in the same pass (a group is kept or dropped whole, so its head
